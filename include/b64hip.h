@@ -1,0 +1,119 @@
+/*
+ * b64hip.h -- C ABI of libb64hip.so, a base64 codec for AMD Instinct MI355X
+ * (gfx950), after W. Mula and D. Lemire, "Base64 encoding and decoding at
+ * almost the speed of a memory copy".
+ *
+ * Conventions for every entry point
+ *   - Data pointers (src, dst, in_off, out_off, out_len, first_bad, status
+ *     words) are DEVICE pointers on the current HIP device, owned by the
+ *     caller.  The library never frees them and keeps no reference to them
+ *     once the enqueued work has completed.  No alignment is required.
+ *   - `alphabet` is a HOST pointer to 64 bytes, copied by value into the
+ *     kernel arguments of the launch (Section "Encoding", step 2: any 64-byte
+ *     mapping may be used, even one chosen at run time).  It must hold 64
+ *     distinct bytes, none equal to '='; bytes >= 0x80 are allowed.
+ *   - Work is enqueued on the caller's `stream` (a hipStream_t; 0 means the
+ *     null stream).  Functions marked "asynchronous" return as soon as the
+ *     work is enqueued; functions marked "blocking" synchronize `stream`.
+ *   - Errors never abort or throw.  Bad arguments return B64_EARG; a failing
+ *     HIP call returns B64_EHIP.  b64_last_error() then gives a message.
+ *     Invalid base64 CONTENT is not an API error: it is reported as a first
+ *     invalid offset (below).
+ *   - Lengths, offsets and counts are int64 bytes.
+ *
+ * Output format (Section "Base64"): groups of three bytes s1,s2,s3 become the
+ * characters of the four 6-bit values s1 div 4, (s2 div 16) + (s1*16 mod 64),
+ * (s2*4 mod 64) + (s3 div 64), s3 mod 64; a last group of one or two bytes is
+ * zero-filled and padded with '=' to four characters.  Decoding inverts this
+ * with the 4 -> 3 byte closed form of the same section.
+ *
+ * First invalid offset.  Decoding validates its input (Section "Decoding":
+ * characters outside the alphabet are detected).  For an input that is not a
+ * valid padded encoding, the reported offset `off` in [0, n] is the length of
+ * the longest prefix of the input that is still a prefix of some valid
+ * encoding: the position of the first character outside the alphabet, of a
+ * misplaced '=', of a '=' after a value with nonzero trailing bits, of any
+ * character after the final padded quantum; off == n means the input is
+ * truncated (n not a multiple of 4).  Whitespace is invalid.  The output
+ * bytes written for an invalid input are unspecified.
+ */
+#ifndef B64HIP_H
+#define B64HIP_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define B64_EARG INT64_MIN         /* bad argument                              */
+#define B64_EHIP (INT64_MIN + 1)   /* a HIP runtime call failed                 */
+
+/* Table tab:base64table: A-Z a-z 0-9 + /  (64 bytes, not NUL-terminated use). */
+extern const char b64_alphabet_std[64];
+/* base64url (Section "Base64"): '+' -> '-', '/' -> '_'.                       */
+extern const char b64_alphabet_url[64];
+
+/* 4*ceil(n/3): characters produced by encoding n bytes; B64_EARG if n < 0.    */
+int64_t b64_encoded_len(int64_t n);
+/* 3*(n/4): capacity to allocate for decoding n characters; B64_EARG if n < 0. */
+int64_t b64_decoded_max_len(int64_t n);
+
+/* Encode src[0..n) to dst[0..4*ceil(n/3)).  Asynchronous.
+ * Returns the encoded length (known on the host) or B64_EARG / B64_EHIP.
+ * dst must hold b64_encoded_len(n) bytes; src and dst must not overlap.
+ * Encoding cannot fail on content.  (Section "Encoding".) */
+int64_t b64_encode(const uint8_t *src, int64_t n, uint8_t *dst,
+                   const char *alphabet, hipStream_t stream);
+
+/* Decode src[0..n) into dst (capacity b64_decoded_max_len(n)).  Blocking.
+ * Returns the decoded length r >= 0 for a valid input, ~off (= -off-1) for an
+ * invalid one (off as defined above), or B64_EARG / B64_EHIP (both below
+ * -2^62).  (Section "Decoding".) */
+int64_t b64_decode(const uint8_t *src, int64_t n, uint8_t *dst,
+                   const char *alphabet, hipStream_t stream);
+
+/* Decode, asynchronous form.  Results land in device memory once `stream`
+ * reaches them: *out_len = decoded length (or -1 if invalid), *first_bad = -1
+ * if valid (else the first invalid offset).  Returns 0 or B64_EARG /
+ * B64_EHIP.  Safe to capture in a HIP graph.  (Section "Decoding".) */
+int64_t b64_decode_async(const uint8_t *src, int64_t n, uint8_t *dst,
+                         int64_t *out_len, int64_t *first_bad,
+                         const char *alphabet, hipStream_t stream);
+
+/* Batched encode of nbuf ragged buffers packed back to back.  Asynchronous.
+ * Buffer b is src[in_off[b] .. in_off[b+1]); in_off has nbuf+1 non-decreasing
+ * entries.  Output b is written at dst + out_off[b] (capacity
+ * b64_encoded_len(length_b); out_off has nbuf entries; outputs must not
+ * overlap each other or the input).  out_len[b] receives 4*ceil(length_b/3).
+ * Returns 0 or B64_EARG / B64_EHIP.  One launch covers every buffer.
+ * Safe to capture in a HIP graph.  (Section "Encoding", applied per buffer.) */
+int64_t b64_encode_batch(const uint8_t *src, const int64_t *in_off, int64_t nbuf,
+                         uint8_t *dst, const int64_t *out_off, int64_t *out_len,
+                         const char *alphabet, hipStream_t stream);
+
+/* Batched decode, asynchronous; layout as b64_encode_batch (output capacity
+ * b64_decoded_max_len(length_b)).  Per buffer: first_bad[b] = -1 and
+ * out_len[b] = decoded length if valid, else first_bad[b] = the first invalid
+ * offset within buffer b and out_len[b] = -1.  Returns 0 or B64_EARG /
+ * B64_EHIP.  Safe to capture in a HIP graph.  (Section "Decoding", per buffer.) */
+int64_t b64_decode_batch(const uint8_t *src, const int64_t *in_off, int64_t nbuf,
+                         uint8_t *dst, const int64_t *out_off, int64_t *out_len,
+                         int64_t *first_bad, const char *alphabet, hipStream_t stream);
+
+/* Launch shape used by the kernels of operation `op` (0 encode, 1 decode,
+ * 2 encode_batch, 3 decode_batch): `unroll` wave rounds in flight per thread
+ * (1, 2, 4 or 8) and `blocks_per_cu` workgroups of 256 threads per compute
+ * unit (1..64).  Process-wide; meant for the autotuner.  Returns 0 or B64_EARG. */
+int64_t b64_tune_set(int op, int unroll, int blocks_per_cu);
+/* Current shape of `op` packed as unroll*1000 + blocks_per_cu, or B64_EARG.   */
+int64_t b64_tune_get(int op);
+
+/* Message for the last B64_EARG / B64_EHIP returned on this thread.          */
+const char *b64_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* B64HIP_H */

@@ -1,0 +1,196 @@
+"""Base64 codec for AMD MI355X (gfx950): HIP kernels behind a C ABI.
+
+After W. Mula and D. Lemire, "Base64 encoding and decoding at almost the
+speed of a memory copy".  PyTorch is used only for device memory and streams;
+every step of the codec runs in libb64hip.so.
+
+  encode(x)                -> uint8 CUDA tensor of 4*ceil(n/3) characters
+  decode(s)                -> (uint8 tensor, None) or (None, first_invalid_offset)
+  decode_async(s)          -> (out, status) with status = int64[2] on the device:
+                              [decoded length or -1, -1 or first invalid offset]
+  encode_batch(src, in_off)-> (dst, out_off, out_len)
+  decode_batch(src, in_off)-> (dst, out_off, out_len, first_bad)
+
+Tensors are torch.uint8 (data) / torch.int64 (offsets) on the current CUDA
+(HIP) device; work is enqueued on torch's current stream.
+"""
+from __future__ import annotations
+
+import ctypes
+
+from . import _lib
+from ._lib import B64Error, check, load
+
+STD = b"ABCDEFGHIJKLMNOPQRSTUVWXYZabcdefghijklmnopqrstuvwxyz0123456789+/"
+URL = b"ABCDEFGHIJKLMNOPQRSTUVWXYZabcdefghijklmnopqrstuvwxyz0123456789-_"
+
+OPS = {"encode": 0, "decode": 1, "encode_batch": 2, "decode_batch": 3}
+
+__all__ = ["STD", "URL", "B64Error", "load", "encoded_len", "decoded_max_len", "encode",
+           "decode", "decode_async", "encode_batch", "decode_batch", "tune_set", "tune_get",
+           "stream_ptr"]
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def stream_ptr(stream=None) -> int:
+    torch = _torch()
+    s = torch.cuda.current_stream() if stream is None else stream
+    return int(s.cuda_stream)
+
+
+def _alpha(alphabet) -> ctypes.Array:
+    a = bytes(alphabet)
+    if len(a) != 64:
+        raise ValueError("alphabet must have 64 bytes")
+    return ctypes.create_string_buffer(a, 64)
+
+
+def _check_u8(t, what):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or t.dtype != torch.uint8 or not t.is_cuda:
+        raise TypeError(f"{what} must be a torch.uint8 CUDA tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{what} must be contiguous")
+
+
+def _check_i64(t, what):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or t.dtype != torch.int64 or not t.is_cuda:
+        raise TypeError(f"{what} must be a torch.int64 CUDA tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{what} must be contiguous")
+
+
+def encoded_len(n: int) -> int:
+    return check(load().b64_encoded_len(n), "encoded_len")
+
+
+def decoded_max_len(n: int) -> int:
+    return check(load().b64_decoded_max_len(n), "decoded_max_len")
+
+
+def encode(x, alphabet=STD, out=None, stream=None):
+    """Encode a uint8 CUDA tensor; returns out[:4*ceil(n/3)] (asynchronous)."""
+    torch = _torch()
+    _check_u8(x, "x")
+    n = x.numel()
+    m = encoded_len(n)
+    if out is None:
+        out = torch.empty(m, dtype=torch.uint8, device=x.device)
+    else:
+        _check_u8(out, "out")
+        if out.numel() < m:
+            raise ValueError("out too small")
+    r = check(load().b64_encode(x.data_ptr(), n, out.data_ptr(), _alpha(alphabet),
+                                stream_ptr(stream)), "b64_encode")
+    return out[:r]
+
+
+def decode(s, alphabet=STD, out=None, stream=None):
+    """Blocking decode: (bytes_tensor, None) if valid, (None, first_bad) if not."""
+    torch = _torch()
+    _check_u8(s, "s")
+    n = s.numel()
+    cap = decoded_max_len(n)
+    if out is None:
+        out = torch.empty(max(cap, 1), dtype=torch.uint8, device=s.device)
+    else:
+        _check_u8(out, "out")
+        if out.numel() < cap:
+            raise ValueError("out too small")
+    r = check(load().b64_decode(s.data_ptr(), n, out.data_ptr(), _alpha(alphabet),
+                                stream_ptr(stream)), "b64_decode")
+    if r < 0:
+        return None, ~r
+    return out[:r], None
+
+
+def decode_async(s, alphabet=STD, out=None, status=None, stream=None):
+    """Asynchronous decode.  Returns (out, status), status = int64[2] on the
+    device: [decoded length or -1, -1 or first invalid offset]."""
+    torch = _torch()
+    _check_u8(s, "s")
+    n = s.numel()
+    cap = decoded_max_len(n)
+    if out is None:
+        out = torch.empty(max(cap, 1), dtype=torch.uint8, device=s.device)
+    if status is None:
+        status = torch.empty(2, dtype=torch.int64, device=s.device)
+    _check_u8(out, "out")
+    _check_i64(status, "status")
+    if out.numel() < cap or status.numel() < 2:
+        raise ValueError("out or status too small")
+    sp = status.data_ptr()
+    check(load().b64_decode_async(s.data_ptr(), n, out.data_ptr(), sp, sp + 8, _alpha(alphabet),
+                                  stream_ptr(stream)), "b64_decode_async")
+    return out, status
+
+
+def _batch_layout(in_off, per_len):
+    torch = _torch()
+    lens = in_off[1:] - in_off[:-1]
+    out_off = torch.zeros_like(in_off)
+    torch.cumsum(per_len(lens), 0, out=out_off[1:])
+    return out_off
+
+
+def encode_batch(src, in_off, alphabet=STD, dst=None, out_off=None, out_len=None, stream=None):
+    """Encode nbuf = len(in_off)-1 packed buffers in one launch (asynchronous).
+    Returns (dst, out_off, out_len); out_off has nbuf+1 entries."""
+    torch = _torch()
+    _check_u8(src, "src")
+    _check_i64(in_off, "in_off")
+    nbuf = in_off.numel() - 1
+    if out_off is None:
+        out_off = _batch_layout(in_off, lambda L: 4 * torch.div(L + 2, 3, rounding_mode="floor"))
+    _check_i64(out_off, "out_off")
+    if dst is None:
+        dst = torch.empty(max(int(out_off[-1].item()), 1), dtype=torch.uint8, device=src.device)
+    if out_len is None:
+        out_len = torch.empty(max(nbuf, 1), dtype=torch.int64, device=src.device)
+    _check_u8(dst, "dst")
+    _check_i64(out_len, "out_len")
+    check(load().b64_encode_batch(src.data_ptr(), in_off.data_ptr(), nbuf, dst.data_ptr(),
+                                  out_off.data_ptr(), out_len.data_ptr(), _alpha(alphabet),
+                                  stream_ptr(stream)), "b64_encode_batch")
+    return dst, out_off, out_len[:nbuf]
+
+
+def decode_batch(src, in_off, alphabet=STD, dst=None, out_off=None, out_len=None,
+                 first_bad=None, stream=None):
+    """Decode nbuf packed buffers in one launch (asynchronous).  Returns
+    (dst, out_off, out_len, first_bad): out_len[b] = length or -1,
+    first_bad[b] = -1 or the first invalid offset within buffer b."""
+    torch = _torch()
+    _check_u8(src, "src")
+    _check_i64(in_off, "in_off")
+    nbuf = in_off.numel() - 1
+    if out_off is None:
+        out_off = _batch_layout(in_off, lambda L: 3 * torch.div(L, 4, rounding_mode="floor"))
+    _check_i64(out_off, "out_off")
+    if dst is None:
+        dst = torch.empty(max(int(out_off[-1].item()), 1), dtype=torch.uint8, device=src.device)
+    if out_len is None:
+        out_len = torch.empty(max(nbuf, 1), dtype=torch.int64, device=src.device)
+    if first_bad is None:
+        first_bad = torch.empty(max(nbuf, 1), dtype=torch.int64, device=src.device)
+    _check_u8(dst, "dst")
+    _check_i64(out_len, "out_len")
+    _check_i64(first_bad, "first_bad")
+    check(load().b64_decode_batch(src.data_ptr(), in_off.data_ptr(), nbuf, dst.data_ptr(),
+                                  out_off.data_ptr(), out_len.data_ptr(), first_bad.data_ptr(),
+                                  _alpha(alphabet), stream_ptr(stream)), "b64_decode_batch")
+    return dst, out_off, out_len[:nbuf], first_bad[:nbuf]
+
+
+def tune_set(op: str, unroll: int, blocks_per_cu: int) -> None:
+    check(load().b64_tune_set(OPS[op], unroll, blocks_per_cu), "b64_tune_set")
+
+
+def tune_get(op: str) -> tuple[int, int]:
+    v = check(load().b64_tune_get(OPS[op]), "b64_tune_get")
+    return v // 1000, v % 1000

@@ -1,0 +1,74 @@
+"""ctypes binding of libb64hip.so (C ABI declared in include/b64hip.h).
+
+Argument marshalling only: pointers, sizes and the HIP stream go across; every
+step of encoding, decoding and validation runs in the library's HIP kernels.
+The library must have been built (python -m paper_1910_05109_amd.build); if it
+is missing this module raises instead of falling back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libb64hip.so")
+
+EARG = -(2 ** 63)
+EHIP = -(2 ** 63) + 1
+
+# entry points and their signatures, in the order of include/b64hip.h
+_P, _I64, _INT = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int
+SIGNATURES = {
+    "b64_encoded_len": ([_I64], _I64),
+    "b64_decoded_max_len": ([_I64], _I64),
+    "b64_encode": ([_P, _I64, _P, _P, _P], _I64),
+    "b64_decode": ([_P, _I64, _P, _P, _P], _I64),
+    "b64_decode_async": ([_P, _I64, _P, _P, _P, _P, _P], _I64),
+    "b64_encode_batch": ([_P, _P, _I64, _P, _P, _P, _P, _P], _I64),
+    "b64_decode_batch": ([_P, _P, _I64, _P, _P, _P, _P, _P, _P], _I64),
+    "b64_tune_set": ([_INT, _INT, _INT], _I64),
+    "b64_tune_get": ([_INT], _I64),
+    "b64_last_error": ([], ctypes.c_char_p),
+}
+DATA_SYMBOLS = ("b64_alphabet_std", "b64_alphabet_url")
+
+_lib = None
+
+
+class B64Error(RuntimeError):
+    """Raised when the library returns B64_EARG or B64_EHIP."""
+
+
+def load() -> ctypes.CDLL:
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(
+                f"{LIB_PATH} is not built; run `python -m paper_1910_05109_amd.build` "
+                "(there is no fallback codec)")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (args, res) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = res
+        _lib = L
+    return _lib
+
+
+def last_error() -> str:
+    msg = load().b64_last_error()
+    return msg.decode(errors="replace") if msg else ""
+
+
+def check(ret: int, what: str) -> int:
+    if ret in (EARG, EHIP):
+        kind = "bad argument" if ret == EARG else "HIP error"
+        raise B64Error(f"{what}: {kind}: {last_error()}")
+    return ret
+
+
+def alphabet_bytes(name: str) -> bytes:
+    """The library's own 64-byte alphabet constant ('std' or 'url')."""
+    sym = {"std": "b64_alphabet_std", "url": "b64_alphabet_url"}[name]
+    arr = (ctypes.c_char * 64).in_dll(load(), sym)
+    return bytes(arr.raw)

@@ -1,0 +1,105 @@
+"""The C-ABI library loads and exports every symbol that include/b64hip.h
+declares; host-side argument checks work without a GPU (CPU only: nothing
+here launches a kernel)."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+from conftest import ROOT
+
+HEADER = os.path.join(ROOT, "include", "b64hip.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    funcs = re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(b64_\w+)\s*\(", text, flags=re.M)
+    data = re.findall(r"extern\s+const\s+char\s+(b64_\w+)\s*\[", text)
+    return funcs, data
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_1910_05109_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.skip("libb64hip.so not built")
+    return _lib.load()
+
+
+def test_header_declares_the_boundary():
+    funcs, data = _declared()
+    assert set(funcs) == {
+        "b64_encoded_len", "b64_decoded_max_len", "b64_encode", "b64_decode", "b64_decode_async",
+        "b64_encode_batch", "b64_decode_batch", "b64_tune_set", "b64_tune_get", "b64_last_error"}
+    assert set(data) == {"b64_alphabet_std", "b64_alphabet_url"}
+
+
+def test_library_exports_every_declared_symbol(lib):
+    from paper_1910_05109_amd import _lib
+    funcs, data = _declared()
+    for name in funcs + data:
+        assert hasattr(lib, name), name
+    assert set(funcs) == set(_lib.SIGNATURES)
+    out = subprocess.run(["nm", "-D", "--defined-only", _lib.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = {line.split()[-1] for line in out.splitlines() if line.strip()}
+    for name in funcs + data:
+        assert name in exported, name
+
+
+def test_alphabet_constants(lib, golden_dir):
+    from paper_1910_05109_amd import _lib, STD, URL
+    rows = [l.split() for l in open(os.path.join(golden_dir, "table_base64.txt"))
+            if not l.startswith("#")]
+    table = bytes(int(h, 16) for _, h, _ in rows)
+    assert _lib.alphabet_bytes("std") == table == STD
+    assert _lib.alphabet_bytes("url") == table[:62] + b"-_" == URL
+
+
+def test_length_helpers(lib):
+    for n in range(0, 100):
+        assert lib.b64_encoded_len(n) == 4 * ((n + 2) // 3)
+        assert lib.b64_decoded_max_len(n) == 3 * (n // 4)
+    assert lib.b64_encoded_len(-1) == -(2 ** 63)
+    assert lib.b64_decoded_max_len(-5) == -(2 ** 63)
+    big = (1 << 40) + 1
+    assert lib.b64_encoded_len(big) == 4 * ((big + 2) // 3)
+
+
+def test_argument_errors_without_gpu(lib):
+    """Bad arguments are rejected on the host, before any HIP call."""
+    EARG = -(2 ** 63)
+    std = ctypes.create_string_buffer(b"ABCDEFGHIJKLMNOPQRSTUVWXYZabcdefghijklmnopqrstuvwxyz0123456789+/", 64)
+    dup = ctypes.create_string_buffer(b"A" * 64, 64)
+    with_pad = ctypes.create_string_buffer(b"=" + std.raw[1:], 64)
+    fake = ctypes.c_void_p(0x1000)
+    assert lib.b64_encode(fake, -1, fake, std, None) == EARG
+    assert lib.b64_encode(None, 10, fake, std, None) == EARG
+    assert lib.b64_encode(fake, 10, fake, dup, None) == EARG
+    assert lib.b64_encode(fake, 10, fake, with_pad, None) == EARG
+    assert lib.b64_encode(fake, 10, fake, None, None) == EARG
+    assert lib.b64_decode(fake, 10, fake, with_pad, None) == EARG
+    assert lib.b64_decode(fake, -3, fake, std, None) == EARG
+    assert lib.b64_decode_async(fake, 10, fake, None, fake, std, None) == EARG
+    assert lib.b64_encode_batch(fake, fake, -1, fake, fake, fake, std, None) == EARG
+    assert lib.b64_encode_batch(fake, None, 3, fake, fake, fake, std, None) == EARG
+    assert lib.b64_decode_batch(fake, fake, 3, fake, fake, fake, None, std, None) == EARG
+    assert lib.b64_decode_batch(fake, fake, 3, fake, fake, fake, fake, dup, None) == EARG
+    assert b"alphabet" in lib.b64_last_error()
+    # zero-size work needs no device
+    assert lib.b64_encode(None, 0, None, std, None) == 0
+    assert lib.b64_encode_batch(None, None, 0, None, None, None, std, None) == 0
+
+
+def test_tuning_interface(lib):
+    EARG = -(2 ** 63)
+    old = lib.b64_tune_get(0)
+    assert lib.b64_tune_set(0, 3, 8) == EARG
+    assert lib.b64_tune_set(0, 4, 0) == EARG
+    assert lib.b64_tune_set(7, 4, 8) == EARG
+    assert lib.b64_tune_set(0, 8, 16) == 0
+    assert lib.b64_tune_get(0) == 8016
+    assert lib.b64_tune_set(0, old // 1000, old % 1000) == 0
