@@ -191,19 +191,244 @@ def run_single(args, torch, b64):
     print(json.dumps(rec), flush=True)
 
 
+def _events_time(torch, fn, reps, before=None):
+    """Median / min / p90 ms of `fn` over `reps` runs, HIP events on the
+    launch stream; `before` (untimed) runs ahead of each timed call."""
+    pairs = []
+    for _ in range(reps):
+        if before is not None:
+            before()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        fn()
+        b.record()
+        pairs.append((a, b))
+    torch.cuda.synchronize()
+    ms = sorted(x.elapsed_time(y) for x, y in pairs)
+    return {"median": ms[len(ms) // 2], "min": ms[0], "p90": ms[min(len(ms) - 1, int(0.9 * len(ms)))]}
+
+
+def _graph_time(torch, fn, reps):
+    """Median ms per replay of `fn` captured in a HIP graph (launch overhead
+    amortised the way a captured serving loop would see it)."""
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        fn()
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        for _ in range(10):
+            fn()
+    g.replay()
+    torch.cuda.synchronize()
+    r = _events_time(torch, g.replay, reps)
+    return {k: v / 10 for k, v in r.items()}
+
+
+def run_small(args, torch, b64):
+    """The 3 MiB workload: launch-latency regime, warm in L2 / MALL."""
+    n = workloads.SINGLE_3MIB
+    x = torch.from_numpy(workloads.random_bytes(workloads.SEED_BASE + 1, n)).cuda()
+    N = 4 * ((n + 2) // 3)
+    text = torch.empty(N, dtype=torch.uint8, device="cuda")
+    dec = torch.empty(n, dtype=torch.uint8, device="cuda")
+    st = torch.empty(2, dtype=torch.int64, device="cuda")
+    enc = lambda: b64.encode(x, out=text)
+    dcd = lambda: b64.decode_async(text, out=dec, status=st)
+    for _ in range(5):
+        enc(); dcd()
+    mc = lambda: dec.copy_(x)
+    res = {"workload": "single 3 MiB buffer", "n_bytes": n, "n_chars": N,
+           "encode_ms": _events_time(torch, enc, 50), "decode_ms": _events_time(torch, dcd, 50),
+           "encode_graph_ms": _graph_time(torch, enc, 20), "decode_graph_ms": _graph_time(torch, dcd, 20),
+           "memcpy_n_ms": _events_time(torch, mc, 50)}
+    t0 = time.perf_counter()
+    for _ in range(200):
+        r = b64.decode(text, out=dec)
+    res["decode_blocking_us"] = (time.perf_counter() - t0) / 200 * 1e6
+    assert r[1] is None
+    print(json.dumps(res), flush=True)
+
+
+def run_sweep(args, torch, b64):
+    """Size sweep 2^k + r (k = 10..26, r = 0..2) plus the paper's four file
+    sizes as lengths of random data; warm (back-to-back) and cold (the 256 MiB
+    last-level cache flushed by a 512 MiB write before each run)."""
+    lengths = workloads.sweep_lengths() + list(workloads.TABLE_PERF_LENGTHS)
+    big = max(lengths)
+    x = torch.from_numpy(workloads.random_bytes(workloads.SEED_BASE + 3, big)).cuda()
+    text = torch.empty(4 * ((big + 2) // 3), dtype=torch.uint8, device="cuda")
+    dec = torch.empty(big + 3, dtype=torch.uint8, device="cuda")
+    mc_dst = torch.empty(4 * ((big + 2) // 3), dtype=torch.uint8, device="cuda")
+    st = torch.empty(2, dtype=torch.int64, device="cuda")
+    scratch = torch.empty(512 << 20, dtype=torch.uint8, device="cuda")
+    flush = lambda: scratch.fill_(1)
+    rows = []
+    for n in sorted(lengths):
+        N = 4 * ((n + 2) // 3)
+        xs, ts = x[:n], text[:N]
+        enc = lambda: b64.encode(xs, out=ts)
+        dcd = lambda: b64.decode_async(ts, out=dec, status=st)
+        mcN = lambda: mc_dst[:N].copy_(ts)
+        for _ in range(3):
+            enc(); dcd(); mcN()
+        row = {"n": n, "N": N}
+        for name, fn in (("encode", enc), ("decode", dcd), ("memcpy_N", mcN)):
+            w = _events_time(torch, fn, 20)
+            c = _events_time(torch, fn, 10, before=flush)
+            row[name] = {"warm_ms": w["median"], "cold_ms": c["median"]}
+        for name in ("encode", "decode"):
+            for reg in ("warm", "cold"):
+                t = row[name][f"{reg}_ms"]
+                row[name][f"{reg}_gbps_b64"] = N / t / 1e6
+                row[name][f"{reg}_pct_memcpy_N"] = 100 * row["memcpy_N"][f"{reg}_ms"] / t
+        if n <= (1 << 20) + 2:
+            row["encode"]["graph_ms"] = _graph_time(torch, enc, 10)["median"]
+            row["decode"]["graph_ms"] = _graph_time(torch, dcd, 10)["median"]
+        working = n + 2 * N
+        row["regime"] = ("latency" if N < (1 << 20) else
+                         "on-chip" if working <= (256 << 20) else "hbm")
+        assert st.cpu().tolist() == [n, -1]
+        rows.append(row)
+        log("sweep", n, row["regime"], f"enc {row['encode']['warm_gbps_b64']:.0f} GB/s",
+            f"dec {row['decode']['warm_gbps_b64']:.0f} GB/s")
+    print(json.dumps({"workload": "size sweep", "rows": rows}), flush=True)
+
+
+def run_batch(args, torch, b64):
+    """100,000 ragged buffers (log-uniform 16 B .. 1 MiB): one graph-captured
+    batched launch per direction vs one launch per buffer on one stream."""
+    import ctypes
+    from paper_1910_05109_amd import _lib
+    from paper_1910_05109_amd.batch import GraphBatch
+    seed = workloads.SEED_BASE + 4
+    lens = workloads.batch_lengths(seed, args.nbuf)
+    in_off = workloads.offsets(lens)
+    total = int(in_off[-1])
+    log("batch: generate", total, "bytes in", lens.size, "buffers")
+    src = torch.from_numpy(workloads.random_bytes(seed, total)).cuda()
+    genc = GraphBatch("encode", lens.size, total)
+    genc.load(lens, src)
+    genc.replay()
+    torch.cuda.synchronize()
+    enc_dst, enc_off, enc_len, _ = genc.results()
+    tlens = 4 * ((lens + 2) // 3)
+    assert np.array_equal(enc_len.cpu().numpy(), tlens)
+    ntext = int(tlens.sum())
+    gdec = GraphBatch("decode", lens.size, ntext)
+    gdec.load(tlens, enc_dst[:ntext])
+    gdec.replay()
+    torch.cuda.synchronize()
+    _, _, dlen, dbad = gdec.results()
+    assert np.array_equal(dlen.cpu().numpy(), lens) and (dbad.cpu().numpy() == -1).all()
+    t_enc = _events_time(torch, genc.replay, args.steps)
+    t_dec = _events_time(torch, gdec.replay, args.steps)
+    # one launch per buffer, same stream, no graph
+    L = _lib.load()
+    alpha = ctypes.create_string_buffer(b64.STD, 64)
+    stream = b64.stream_ptr()
+    sp, dp = src.data_ptr(), enc_dst.data_ptr()
+    eo = genc.host_out_off
+    per_dst = torch.empty(int(gdec.host_out_off[-1]) + 1, dtype=torch.uint8, device="cuda")
+    stat = torch.empty(2 * lens.size, dtype=torch.int64, device="cuda")
+    pp, stp = per_dst.data_ptr(), stat.data_ptr()
+    do = gdec.host_out_off
+    ioff = in_off.tolist(); eol = eo.tolist(); dol = do.tolist(); ll = lens.tolist(); tl = tlens.tolist()
+
+    def per_enc():
+        for b in range(len(ll)):
+            L.b64_encode(sp + ioff[b], ll[b], dp + eol[b], alpha, stream)
+
+    def per_dec():
+        for b in range(len(ll)):
+            L.b64_decode_async(dp + eol[b], tl[b], pp + dol[b], stp + 16 * b, stp + 16 * b + 8,
+                               alpha, stream)
+
+    res = {"workload": "ragged batch", "buffers": int(lens.size), "bytes": total, "chars": ntext}
+    for name, fn, tb in (("encode", per_enc, t_enc), ("decode", per_dec, t_dec)):
+        fn()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        a.record()
+        fn()
+        b.record()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        gpu_ms = a.elapsed_time(b)
+        res[name] = {"batched_ms": tb["median"], "batched_gbps_b64": ntext / tb["median"] / 1e6,
+                     "batched_hbm_gbps": (total + ntext) / tb["median"] / 1e6,
+                     "per_buffer_ms": gpu_ms, "per_buffer_wall_ms": wall * 1e3,
+                     "per_buffer_gbps_b64": ntext / gpu_ms / 1e6,
+                     "speedup": gpu_ms / tb["median"]}
+        log("batch", name, json.dumps(res[name]))
+    st = stat.view(-1, 2).cpu().numpy()
+    assert np.array_equal(st[:, 0], lens) and (st[:, 1] == -1).all()
+    print(json.dumps(res), flush=True)
+
+
+def run_serve(args, torch, b64):
+    """Poisson arrivals of mixed encode/decode requests at swept rates."""
+    from paper_1910_05109_amd import serve
+    out = []
+    for rate in args.rates:
+        count = int(min(args.requests, max(2000, rate * args.seconds)))
+        seed = workloads.SEED_BASE + 5
+        sizes = workloads.serve_sizes(seed, count)
+        is_dec, is_bad = workloads.serve_kinds(seed + 1, count)
+        arrival = workloads.serve_arrivals(seed + 2, count, rate)
+        kinds = is_dec.astype(np.int64)
+        enc_idx, dec_idx = np.nonzero(~is_dec)[0], np.nonzero(is_dec)[0]
+        pos = np.zeros(count, dtype=np.int64)
+        pos[enc_idx] = np.arange(enc_idx.size)
+        pos[dec_idx] = np.arange(dec_idx.size)
+        raw = workloads.random_bytes(seed + 3, int(sizes.sum()))
+        roff = workloads.offsets(sizes)
+        enc_lens = sizes[enc_idx]
+        enc_data = torch.from_numpy(np.concatenate([raw[roff[i]:roff[i + 1]] for i in enc_idx])
+                                    if enc_idx.size else np.zeros(1, np.uint8)).cuda()
+        # decode payloads: encodings of their raw bytes, 1% spoiled by one byte
+        dsrc = torch.from_numpy(np.concatenate([raw[roff[i]:roff[i + 1]] for i in dec_idx])
+                                if dec_idx.size else np.zeros(1, np.uint8)).cuda()
+        dtext, doff, _ = b64.encode_batch(dsrc, torch.from_numpy(workloads.offsets(sizes[dec_idx])).cuda())
+        doff_h = doff.cpu().numpy()
+        g = workloads.rng(seed + 4)
+        bad_bytes = workloads.non_alphabet_bytes(b64.STD)
+        spoil = np.nonzero(is_bad[dec_idx])[0]
+        for j in spoil:
+            p = int(doff_h[j] + g.integers(0, doff_h[j + 1] - doff_h[j]))
+            dtext[p] = int(bad_bytes[g.integers(0, bad_bytes.size)])
+        enc_pool = serve.make_pool(serve.ENC, enc_data, enc_lens)
+        dec_pool = serve.make_pool(serve.DEC, dtext, np.diff(doff_h))
+        srv = serve.Server(enc_pool, dec_pool, budget_bytes=32 << 30)
+        torch.cuda.synchronize()
+        stats = srv.run(kinds, arrival, pos)
+        dl, db = srv.results(serve.DEC)
+        assert (db[spoil] >= 0).all() and (np.delete(db, spoil) == -1).all()
+        summ = {"rate": rate, **stats.summary(), "invalid": int(spoil.size)}
+        log("serve", json.dumps(summ))
+        out.append(summ)
+    print(json.dumps({"workload": "serving", "sigma": workloads.SERVE_SIGMA, "rows": out}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--mode", default="single", choices=["single"])
+    ap.add_argument("--mode", default="single", choices=["single", "small", "sweep", "batch", "serve"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--cpu-sample", type=int, default=512 << 20)
     ap.add_argument("--cpu-reps", type=int, default=5)
+    ap.add_argument("--nbuf", type=int, default=workloads.BATCH_BUFFERS)
+    ap.add_argument("--rates", type=float, nargs="+", default=[1e3, 3e3, 1e4, 3e4, 1e5, 3e5])
+    ap.add_argument("--requests", type=int, default=100_000)
+    ap.add_argument("--seconds", type=float, default=2.0)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on one GPU only: this codec shards without exchanging payload "
-              "(see the design notes); run it with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU only; run it with --gpus 1", file=sys.stderr)
         sys.exit(2)
     import torch
     import paper_1910_05109_amd as b64
@@ -211,8 +436,8 @@ def main():
     if not torch.cuda.is_available():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
-    if args.mode == "single":
-        run_single(args, torch, b64)
+    {"single": run_single, "small": run_small, "sweep": run_sweep, "batch": run_batch,
+     "serve": run_serve}[args.mode](args, torch, b64)
 
 
 if __name__ == "__main__":

@@ -103,11 +103,14 @@ int64_t b64_decode_batch(const uint8_t *src, const int64_t *in_off, int64_t nbuf
                          int64_t *first_bad, const char *alphabet, hipStream_t stream);
 
 /* Launch shape used by the kernels of operation `op` (0 encode, 1 decode,
- * 2 encode_batch, 3 decode_batch): `unroll` wave rounds in flight per thread
- * (1, 2, 4 or 8) and `blocks_per_cu` workgroups of 256 threads per compute
- * unit (1..64).  Process-wide; meant for the autotuner.  Returns 0 or B64_EARG. */
-int64_t b64_tune_set(int op, int unroll, int blocks_per_cu);
-/* Current shape of `op` packed as unroll*1000 + blocks_per_cu, or B64_EARG.   */
+ * 2 encode_batch, 3 decode_batch): `unroll` lane chunks in flight per lane
+ * (1, 2, 4 or 8; a lane chunk is 12 bytes -> 16 characters or back),
+ * `blocks_per_cu` workgroups of 256 threads per compute unit (1..64), and
+ * `nontemporal` (0 or 1) for streaming loads and stores.  Process-wide; meant
+ * for the autotuner.  Does not change results.  Returns 0 or B64_EARG. */
+int64_t b64_tune_set(int op, int unroll, int blocks_per_cu, int nontemporal);
+/* Current shape of `op` packed as nontemporal*10000 + unroll*100 +
+ * blocks_per_cu, or B64_EARG.                                                */
 int64_t b64_tune_get(int op);
 
 /* Message for the last B64_EARG / B64_EHIP returned on this thread.          */

@@ -130,6 +130,35 @@ def decode_async(s, alphabet=STD, out=None, status=None, stream=None):
     return out, status
 
 
+def _validate_layout(src, in_off, dst, out_off, cap_of, what):
+    """Host-side bounds check of a batch layout before launching: offsets
+    non-decreasing and inside `src`, every output region inside `dst`.  The
+    kernels trust the offsets, so a bad layout must be stopped here."""
+    torch = _torch()
+    nbuf = in_off.numel() - 1
+    if nbuf <= 0:
+        return
+    if out_off.numel() < nbuf:
+        raise ValueError(f"{what}: out_off needs {nbuf} entries")
+    lens = in_off[1:] - in_off[:-1]
+    ends = out_off[:nbuf] + cap_of(lens)
+    stats = torch.stack([in_off[0], in_off[-1], lens.min(), out_off[:nbuf].min(), ends.max()]).cpu()
+    first, last, min_len, min_out, max_end = (int(v) for v in stats)
+    if first < 0 or min_len < 0 or last > src.numel():
+        raise ValueError(f"{what}: in_off must be non-decreasing within src "
+                         f"(first {first}, last {last}, src has {src.numel()} bytes)")
+    if min_out < 0 or max_end > dst.numel():
+        raise ValueError(f"{what}: outputs end at {max_end}, dst has {dst.numel()} bytes")
+
+
+def _enc_cap(L):
+    return 4 * _torch().div(L + 2, 3, rounding_mode="floor")
+
+
+def _dec_cap(L):
+    return 3 * _torch().div(L, 4, rounding_mode="floor")
+
+
 def _batch_layout(in_off, per_len):
     torch = _torch()
     lens = in_off[1:] - in_off[:-1]
@@ -138,15 +167,17 @@ def _batch_layout(in_off, per_len):
     return out_off
 
 
-def encode_batch(src, in_off, alphabet=STD, dst=None, out_off=None, out_len=None, stream=None):
-    """Encode nbuf = len(in_off)-1 packed buffers in one launch (asynchronous).
+def encode_batch(src, in_off, alphabet=STD, dst=None, out_off=None, out_len=None, stream=None,
+                 validate=True):
+    """Encode nbuf = len(in_off)-1 packed buffers in one launch (asynchronous
+    unless `validate`, which checks the layout on the host first).
     Returns (dst, out_off, out_len); out_off has nbuf+1 entries."""
     torch = _torch()
     _check_u8(src, "src")
     _check_i64(in_off, "in_off")
     nbuf = in_off.numel() - 1
     if out_off is None:
-        out_off = _batch_layout(in_off, lambda L: 4 * torch.div(L + 2, 3, rounding_mode="floor"))
+        out_off = _batch_layout(in_off, _enc_cap)
     _check_i64(out_off, "out_off")
     if dst is None:
         dst = torch.empty(max(int(out_off[-1].item()), 1), dtype=torch.uint8, device=src.device)
@@ -154,6 +185,10 @@ def encode_batch(src, in_off, alphabet=STD, dst=None, out_off=None, out_len=None
         out_len = torch.empty(max(nbuf, 1), dtype=torch.int64, device=src.device)
     _check_u8(dst, "dst")
     _check_i64(out_len, "out_len")
+    if out_len.numel() < nbuf:
+        raise ValueError("out_len too small")
+    if validate:
+        _validate_layout(src, in_off, dst, out_off, _enc_cap, "encode_batch")
     check(load().b64_encode_batch(src.data_ptr(), in_off.data_ptr(), nbuf, dst.data_ptr(),
                                   out_off.data_ptr(), out_len.data_ptr(), _alpha(alphabet),
                                   stream_ptr(stream)), "b64_encode_batch")
@@ -161,7 +196,7 @@ def encode_batch(src, in_off, alphabet=STD, dst=None, out_off=None, out_len=None
 
 
 def decode_batch(src, in_off, alphabet=STD, dst=None, out_off=None, out_len=None,
-                 first_bad=None, stream=None):
+                 first_bad=None, stream=None, validate=True):
     """Decode nbuf packed buffers in one launch (asynchronous).  Returns
     (dst, out_off, out_len, first_bad): out_len[b] = length or -1,
     first_bad[b] = -1 or the first invalid offset within buffer b."""
@@ -170,7 +205,7 @@ def decode_batch(src, in_off, alphabet=STD, dst=None, out_off=None, out_len=None
     _check_i64(in_off, "in_off")
     nbuf = in_off.numel() - 1
     if out_off is None:
-        out_off = _batch_layout(in_off, lambda L: 3 * torch.div(L, 4, rounding_mode="floor"))
+        out_off = _batch_layout(in_off, _dec_cap)
     _check_i64(out_off, "out_off")
     if dst is None:
         dst = torch.empty(max(int(out_off[-1].item()), 1), dtype=torch.uint8, device=src.device)
@@ -181,16 +216,21 @@ def decode_batch(src, in_off, alphabet=STD, dst=None, out_off=None, out_len=None
     _check_u8(dst, "dst")
     _check_i64(out_len, "out_len")
     _check_i64(first_bad, "first_bad")
+    if out_len.numel() < nbuf or first_bad.numel() < nbuf:
+        raise ValueError("out_len / first_bad too small")
+    if validate:
+        _validate_layout(src, in_off, dst, out_off, _dec_cap, "decode_batch")
     check(load().b64_decode_batch(src.data_ptr(), in_off.data_ptr(), nbuf, dst.data_ptr(),
                                   out_off.data_ptr(), out_len.data_ptr(), first_bad.data_ptr(),
                                   _alpha(alphabet), stream_ptr(stream)), "b64_decode_batch")
     return dst, out_off, out_len[:nbuf], first_bad[:nbuf]
 
 
-def tune_set(op: str, unroll: int, blocks_per_cu: int) -> None:
-    check(load().b64_tune_set(OPS[op], unroll, blocks_per_cu), "b64_tune_set")
+def tune_set(op: str, unroll: int, blocks_per_cu: int, nontemporal: int = 1) -> None:
+    check(load().b64_tune_set(OPS[op], unroll, blocks_per_cu, int(nontemporal)), "b64_tune_set")
 
 
-def tune_get(op: str) -> tuple[int, int]:
+def tune_get(op: str) -> tuple[int, int, int]:
+    """(unroll, blocks_per_cu, nontemporal) of `op`."""
     v = check(load().b64_tune_get(OPS[op]), "b64_tune_get")
-    return v // 1000, v % 1000
+    return (v // 100) % 100, v % 100, v // 10000

@@ -26,7 +26,7 @@ SIGNATURES = {
     "b64_decode_async": ([_P, _I64, _P, _P, _P, _P, _P], _I64),
     "b64_encode_batch": ([_P, _P, _I64, _P, _P, _P, _P, _P], _I64),
     "b64_decode_batch": ([_P, _P, _I64, _P, _P, _P, _P, _P, _P], _I64),
-    "b64_tune_set": ([_INT, _INT, _INT], _I64),
+    "b64_tune_set": ([_INT, _INT, _INT, _INT], _I64),
     "b64_tune_get": ([_INT], _I64),
     "b64_last_error": ([], ctypes.c_char_p),
 }

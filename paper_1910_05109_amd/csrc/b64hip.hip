@@ -57,6 +57,8 @@ constexpr int kWaves = kThreads / 64;
 constexpr uint32_t kPad = '=';
 constexpr uint32_t kBad = 0xFF;        // decode-map value of a non-alphabet byte
 constexpr int64_t kNoError = INT64_MAX;
+constexpr int kXcds = 8;               // MI355X: 8 accelerator dies, each with its own L2
+constexpr int kLine = 128;             // L2 cache line, bytes
 
 // Runtime alphabet, passed by value as a kernel argument.
 struct EncTab { uint32_t w[16]; };     // byte v = character of value v
@@ -68,6 +70,34 @@ struct DecMap { uint32_t w[64]; };     // byte c = value of character c, or kBad
 typedef uint32_t u32x3 __attribute__((ext_vector_type(3), aligned(1)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4), aligned(1)));
 typedef uint32_t u32a1 __attribute__((aligned(1)));
+
+// Streaming loads and stores of 12 or 16 bytes at any byte address; NT marks
+// them nontemporal (each byte is touched once, so nothing is worth keeping in
+// the caches).  The pointer types carry the byte alignment explicitly.
+template <bool NT>
+__device__ __forceinline__ u32x3 load12(const uint8_t *p)
+{
+    if constexpr (NT) return __builtin_nontemporal_load((const u32x3 *)p);
+    else return *(const u32x3 *)p;
+}
+template <bool NT>
+__device__ __forceinline__ u32x4 load16(const uint8_t *p)
+{
+    if constexpr (NT) return __builtin_nontemporal_load((const u32x4 *)p);
+    else return *(const u32x4 *)p;
+}
+template <bool NT>
+__device__ __forceinline__ void store12(uint8_t *p, u32x3 v)
+{
+    if constexpr (NT) __builtin_nontemporal_store(v, (u32x3 *)p);
+    else *(u32x3 *)p = v;
+}
+template <bool NT>
+__device__ __forceinline__ void store16(uint8_t *p, u32x4 v)
+{
+    if constexpr (NT) __builtin_nontemporal_store(v, (u32x4 *)p);
+    else *(u32x4 *)p = v;
+}
 
 // ---------------------------------------------------------------- encode --
 
@@ -121,10 +151,24 @@ __device__ __forceinline__ void stage_enc_table(uint32_t *s_tab, const EncTab &t
     __syncthreads();
 }
 
-// Single buffer: lane chunk c covers input [12c, 12c+12) and output
-// [16c, 16c+16).  Grid-stride over chunks, U chunks in flight per lane; the
-// n mod 12 leftover bytes go through the scalar path on one lane.
-template <int U>
+// Workgroups are dealt round-robin over the XCDs.  Renumber them so that
+// consecutive logical blocks, which write adjacent output spans, run on the
+// same XCD: a cache line shared by two spans is then completed in one L2
+// instead of being written back in two partial halves from two L2s.
+__device__ __forceinline__ int64_t logical_block()
+{
+    const int64_t G = gridDim.x, b = blockIdx.x;
+    if (G % kXcds != 0) return b;
+    return (b % kXcds) * (G / kXcds) + b / kXcds;
+}
+
+// Single buffer.  `head` whole groups are set aside so that the chunk outputs
+// start on a 128-byte line (when dst is 4-byte aligned); then lane chunk c
+// covers input [3*head + 12c, +12) and output [4*head + 16c, +16), grid-stride
+// with U chunks in flight per lane.  Threads t < head encode one head group
+// each; the last thread encodes the at most three whole groups and the
+// partial group left after the chunks.
+template <int U, bool NT>
 __global__ __launch_bounds__(kThreads) void k_encode(const uint8_t *__restrict__ src, int64_t n,
                                                      uint8_t *__restrict__ dst, EncTab tab)
 {
@@ -132,23 +176,33 @@ __global__ __launch_bounds__(kThreads) void k_encode(const uint8_t *__restrict__
     stage_enc_table(s_tab, tab);
     const uint8_t *a = (const uint8_t *)s_tab;
 
-    const int64_t nch = n / 12;
+    const int64_t ng = n / 3;
+    const uint64_t da = (uint64_t)(uintptr_t)dst;
+    int64_t head = (da & 3) ? 0 : (int64_t)((((uint64_t)kLine - (da & (kLine - 1))) & (kLine - 1)) >> 2);
+    if (head > ng) head = ng;
+    const int64_t nch = (ng - head) >> 2;
+    const uint8_t *s0 = src + 3 * head;
+    uint8_t *d0 = dst + 4 * head;
     const int64_t T = (int64_t)gridDim.x * kThreads;
-    const int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    const int64_t t = logical_block() * kThreads + threadIdx.x;
     for (int64_t c0 = t; c0 < nch; c0 += U * T) {
         u32x3 in[U];
 #pragma unroll
         for (int j = 0; j < U; ++j) {
             const int64_t c = c0 + j * T;
-            if (c < nch) in[j] = *(const u32x3 *)(src + 12 * c);
+            if (c < nch) in[j] = load12<NT>(s0 + 12 * c);
         }
 #pragma unroll
         for (int j = 0; j < U; ++j) {
             const int64_t c = c0 + j * T;
-            if (c < nch) *(u32x4 *)(dst + 16 * c) = enc_chunk(in[j], a);
+            if (c < nch) store16<NT>(d0 + 16 * c, enc_chunk(in[j], a));
         }
     }
-    if (t == 0) enc_scalar(src + 12 * nch, n - 12 * nch, dst + 16 * nch, a);
+    if (t < head) enc_scalar(src + 3 * t, 3, dst + 4 * t, a);
+    if (t == kThreads - 1) {
+        const int64_t g = head + 4 * nch;
+        enc_scalar(src + 3 * g, n - 3 * g, dst + 4 * g, a);
+    }
 }
 
 // ---------------------------------------------------------------- decode --
@@ -263,12 +317,15 @@ __device__ __forceinline__ void atomic_min_i64(int64_t *p, int64_t v)
     atomicMin((unsigned long long *)p, (unsigned long long)v);
 }
 
-// Single buffer: the body is every quantum but the last (4*floor((n-1)/4)
-// characters); lane chunk c covers characters [16c, 16c+16) and bytes
-// [12c, 12c+12) of the body.  Characters from 16*floor(body/16) to n (at most
-// 16) go through dec_tail on one lane.  first_bad must hold kNoError before
-// the launch; out_len is written only when the tail is valid.
-template <int U>
+// Single buffer.  The body is every quantum but the last (nbq quanta).
+// `head` body quanta are set aside so that the chunk outputs start on a
+// 128-byte line (3*head = -dst mod 128; 43 is the inverse of 3 mod 128); then
+// lane chunk c covers characters [4*head + 16c, +16) and bytes
+// [3*head + 12c, +12).  Threads t < head decode one head quantum each; the
+// last thread runs dec_tail over the (at most three) body quanta left after
+// the chunks and the last quantum.  first_bad must hold kNoError before the
+// launch; out_len is written only when the tail is valid.
+template <int U, bool NT>
 __global__ __launch_bounds__(kThreads) void k_decode(const uint8_t *__restrict__ src, int64_t n,
                                                      uint8_t *__restrict__ dst, DecMap map,
                                                      int64_t *__restrict__ out_len,
@@ -278,40 +335,56 @@ __global__ __launch_bounds__(kThreads) void k_decode(const uint8_t *__restrict__
     stage_dec_map(s_map, map);
     const uint8_t *m = (const uint8_t *)s_map;
 
-    const int64_t body = n >= 1 ? ((n - 1) >> 2) << 2 : 0;
-    const int64_t nch = body >> 4;
+    const int64_t nbq = n >= 1 ? (n - 1) >> 2 : 0;
+    const uint64_t da = (uint64_t)(uintptr_t)dst;
+    int64_t head = (int64_t)(((0 - da) * 43u) & (uint64_t)(kLine - 1));
+    if (head > nbq) head = nbq;
+    const int64_t nch = (nbq - head) >> 2;
+    const uint8_t *s0 = src + 4 * head;
+    uint8_t *d0 = dst + 3 * head;
     const int64_t T = (int64_t)gridDim.x * kThreads;
-    const int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    const int64_t t = logical_block() * kThreads + threadIdx.x;
     uint32_t err = 0;
     for (int64_t c0 = t; c0 < nch; c0 += U * T) {
         u32x4 in[U];
 #pragma unroll
         for (int j = 0; j < U; ++j) {
             const int64_t c = c0 + j * T;
-            if (c < nch) in[j] = *(const u32x4 *)(src + 16 * c);
+            if (c < nch) in[j] = load16<NT>(s0 + 16 * c);
         }
 #pragma unroll
         for (int j = 0; j < U; ++j) {
             const int64_t c = c0 + j * T;
-            if (c < nch) *(u32x3 *)(dst + 12 * c) = dec_chunk(in[j], m, err);
+            if (c < nch) store12<NT>(d0 + 12 * c, dec_chunk(in[j], m, err));
         }
     }
     // One test per lane for its whole share (bit 7 is set only by kBad).
     if (__ballot(err & 0x80)) {
         if (err & 0x80) {
             for (int64_t c = t; c < nch; c += T) {
-                const int64_t bad = dec_check_inner(src + 16 * c, 16, m);
+                const int64_t bad = dec_check_inner(s0 + 16 * c, 16, m);
                 if (bad >= 0) {
-                    atomic_min_i64(first_bad, 16 * c + bad);
+                    atomic_min_i64(first_bad, 4 * head + 16 * c + bad);
                     break;   // later chunks of this lane have larger offsets
                 }
             }
         }
     }
-    if (t == 0) {
-        const int64_t t0 = 16 * nch;
-        const int64_t bad = dec_tail(src + t0, n - t0, n, dst + 12 * nch, m, out_len);
-        if (bad >= 0) atomic_min_i64(first_bad, t0 + bad);
+    if (t < head) {
+        uint32_t qerr = 0;
+        const uint32_t v = dec_quantum(*(const u32a1 *)(src + 4 * t), m, qerr);
+        dst[3 * t] = (uint8_t)(v >> 16);
+        dst[3 * t + 1] = (uint8_t)(v >> 8);
+        dst[3 * t + 2] = (uint8_t)v;
+        if (qerr & 0x80) {
+            const int64_t bad = dec_check_inner(src + 4 * t, 4, m);
+            if (bad >= 0) atomic_min_i64(first_bad, 4 * t + bad);
+        }
+    }
+    if (t == kThreads - 1) {
+        const int64_t q = head + 4 * nch;
+        const int64_t bad = dec_tail(src + 4 * q, n - 4 * q, n, dst + 3 * q, m, out_len);
+        if (bad >= 0) atomic_min_i64(first_bad, 4 * q + bad);
     }
 }
 
@@ -355,7 +428,7 @@ __device__ WaveSpan wave_span(const int64_t *__restrict__ in_off, int64_t nbuf, 
     const int64_t nwaves = (int64_t)gridDim.x * kWaves;
     // the wave index is uniform across the wave; say so, so that the span and
     // the per-buffer offsets live in scalar registers
-    const int64_t w = (int64_t)blockIdx.x * kWaves +
+    const int64_t w = logical_block() * kWaves +
                       __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int64_t base = in_off[0], end = in_off[nbuf];
     const int64_t per = (end - base + nwaves - 1) / nwaves;
@@ -375,7 +448,7 @@ __device__ WaveSpan wave_span(const int64_t *__restrict__ in_off, int64_t nbuf, 
     return s;
 }
 
-template <int U>
+template <int U, bool NT>
 __global__ __launch_bounds__(kThreads) void k_encode_batch(
     const uint8_t *__restrict__ src, const int64_t *__restrict__ in_off, int64_t nbuf,
     uint8_t *__restrict__ dst, const int64_t *__restrict__ out_off, int64_t *__restrict__ out_len,
@@ -408,12 +481,12 @@ __global__ __launch_bounds__(kThreads) void k_encode_batch(
 #pragma unroll
             for (int j = 0; j < U; ++j) {
                 const int64_t k = k0 + j * 64 + lane;
-                if (k < nchunk) in[j] = *(const u32x3 *)(sp + 12 * k);
+                if (k < nchunk) in[j] = load12<NT>(sp + 12 * k);
             }
 #pragma unroll
             for (int j = 0; j < U; ++j) {
                 const int64_t k = k0 + j * 64 + lane;
-                if (k < nchunk) *(u32x4 *)(dp + 16 * k) = enc_chunk(in[j], a);
+                if (k < nchunk) store16<NT>(dp + 16 * k, enc_chunk(in[j], a));
             }
         }
         // at most three whole groups and the buffer's partial last group
@@ -428,7 +501,7 @@ __global__ __launch_bounds__(kThreads) void k_encode_batch(
 // Decode: the body of buffer b is its quanta but the last; chunks of four
 // body quanta go to lanes, then lanes 0..3 take up to three leftover body
 // quanta and the last quantum (lane 3 at most, via dec_tail).
-template <int U>
+template <int U, bool NT>
 __global__ __launch_bounds__(kThreads) void k_decode_batch(
     const uint8_t *__restrict__ src, const int64_t *__restrict__ in_off, int64_t nbuf,
     uint8_t *__restrict__ dst, const int64_t *__restrict__ out_off, int64_t *__restrict__ out_len,
@@ -465,12 +538,12 @@ __global__ __launch_bounds__(kThreads) void k_decode_batch(
 #pragma unroll
             for (int j = 0; j < U; ++j) {
                 const int64_t k = k0 + j * 64 + lane;
-                if (k < nchunk) in[j] = *(const u32x4 *)(sp + 16 * k);
+                if (k < nchunk) in[j] = load16<NT>(sp + 16 * k);
             }
 #pragma unroll
             for (int j = 0; j < U; ++j) {
                 const int64_t k = k0 + j * 64 + lane;
-                if (k < nchunk) *(u32x3 *)(dp + 12 * k) = dec_chunk(in[j], m, err);
+                if (k < nchunk) store12<NT>(dp + 12 * k, dec_chunk(in[j], m, err));
             }
         }
         if (__ballot(err & 0x80)) {
@@ -552,9 +625,11 @@ DecMap make_dec(const char *alphabet)
     return d;
 }
 
-// Launch shapes per operation: {unroll, blocks per CU}.
-struct Shape { int unroll, bpc; };
-Shape g_shape[4] = {{4, 8}, {4, 8}, {4, 8}, {4, 8}};
+// Launch shapes per operation: {unroll, blocks per CU, nontemporal}; the
+// defaults are the autotuner's choices on MI355X (1 GiB single buffers, 2 GiB
+// log-uniform ragged batches).
+struct Shape { int unroll, bpc, nt; };
+Shape g_shape[4] = {{4, 2, 1}, {4, 2, 1}, {2, 4, 0}, {4, 32, 1}};
 std::mutex g_mu;
 
 constexpr int kMaxDevices = 64;
@@ -589,17 +664,27 @@ int64_t grid_for(int64_t nch, Shape sh, int cus)
     int64_t need = (nch + per_block - 1) / per_block;
     const int64_t cap = (int64_t)cus * sh.bpc;
     if (need > cap) need = cap;
+    if (need >= kXcds) need -= need % kXcds;   // a whole number of blocks per XCD
     return need < 1 ? 1 : need;
 }
 
-#define B64_DISPATCH_U(U_, KERNEL, GRID, STREAM, ...)                                         \
-    do {                                                                                      \
-        switch (U_) {                                                                         \
-        case 1: hipLaunchKernelGGL(KERNEL<1>, dim3(GRID), dim3(kThreads), 0, STREAM, __VA_ARGS__); break; \
-        case 2: hipLaunchKernelGGL(KERNEL<2>, dim3(GRID), dim3(kThreads), 0, STREAM, __VA_ARGS__); break; \
-        case 8: hipLaunchKernelGGL(KERNEL<8>, dim3(GRID), dim3(kThreads), 0, STREAM, __VA_ARGS__); break; \
-        default: hipLaunchKernelGGL(KERNEL<4>, dim3(GRID), dim3(kThreads), 0, STREAM, __VA_ARGS__); break; \
-        }                                                                                     \
+#define B64_LAUNCH(KERNEL, U_, NT_, GRID, STREAM, ...) \
+    hipLaunchKernelGGL((KERNEL<U_, NT_>), dim3(GRID), dim3(kThreads), 0, STREAM, __VA_ARGS__)
+#define B64_DISPATCH_NT(KERNEL, U_, SH, GRID, STREAM, ...)                 \
+    do {                                                                  \
+        if ((SH).nt) B64_LAUNCH(KERNEL, U_, true, GRID, STREAM, __VA_ARGS__);  \
+        else B64_LAUNCH(KERNEL, U_, false, GRID, STREAM, __VA_ARGS__);         \
+    } while (0)
+// Instantiates KERNEL for every (unroll, nontemporal) shape and launches the
+// one `SH` selects.
+#define B64_DISPATCH(KERNEL, SH, GRID, STREAM, ...)                                  \
+    do {                                                                            \
+        switch ((SH).unroll) {                                                      \
+        case 1: B64_DISPATCH_NT(KERNEL, 1, SH, GRID, STREAM, __VA_ARGS__); break;   \
+        case 2: B64_DISPATCH_NT(KERNEL, 2, SH, GRID, STREAM, __VA_ARGS__); break;   \
+        case 8: B64_DISPATCH_NT(KERNEL, 8, SH, GRID, STREAM, __VA_ARGS__); break;   \
+        default: B64_DISPATCH_NT(KERNEL, 4, SH, GRID, STREAM, __VA_ARGS__); break;  \
+        }                                                                           \
     } while (0)
 
 int64_t launch_fill(int64_t *p, int64_t count, int64_t value, hipStream_t stream)
@@ -646,6 +731,28 @@ hipError_t status_slot(StatusSlot **out)
     return hipSuccess;
 }
 
+// Enqueue one single-buffer decode: reset first_bad, run k_decode, and (with
+// `finish`) turn the raw status into the public form.
+int64_t decode_launch(const uint8_t *src, int64_t n, uint8_t *dst, int64_t *out_len,
+                      int64_t *first_bad, const char *alphabet, hipStream_t stream, bool finish)
+{
+    if (n < 0) return fail(B64_EARG, "negative length%s", "");
+    if (!alphabet_ok(alphabet))
+        return fail(B64_EARG, "alphabet must be 64 distinct bytes without '='%s", "");
+    int cus = 0;
+    hipError_t e = cu_count(&cus);
+    if (e != hipSuccess) return hip_fail(e, "device query");
+    int64_t r = launch_fill(first_bad, 1, kNoError, stream);
+    if (r) return r;
+    const Shape sh = shape_of(1);
+    const int64_t nbq = n >= 1 ? (n - 1) >> 2 : 0;
+    const int64_t grid = grid_for(nbq >> 2, sh, cus);
+    B64_DISPATCH(k_decode, sh, grid, stream, src, n, dst, make_dec(alphabet), out_len, first_bad);
+    e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "decode launch");
+    return finish ? launch_finish(out_len, first_bad, 1, stream) : 0;
+}
+
 }  // namespace
 
 extern "C" {
@@ -664,14 +771,15 @@ int64_t b64_decoded_max_len(int64_t n)
 
 const char *b64_last_error(void) { return g_err; }
 
-int64_t b64_tune_set(int op, int unroll, int blocks_per_cu)
+int64_t b64_tune_set(int op, int unroll, int blocks_per_cu, int nontemporal)
 {
     if (op < 0 || op > 3) return fail(B64_EARG, "bad op%s", "");
     if (!(unroll == 1 || unroll == 2 || unroll == 4 || unroll == 8))
         return fail(B64_EARG, "unroll must be 1, 2, 4 or 8%s", "");
     if (blocks_per_cu < 1 || blocks_per_cu > 64) return fail(B64_EARG, "blocks_per_cu out of range%s", "");
+    if (nontemporal != 0 && nontemporal != 1) return fail(B64_EARG, "nontemporal must be 0 or 1%s", "");
     std::lock_guard<std::mutex> lk(g_mu);
-    g_shape[op] = Shape{unroll, blocks_per_cu};
+    g_shape[op] = Shape{unroll, blocks_per_cu, nontemporal};
     return 0;
 }
 
@@ -679,7 +787,7 @@ int64_t b64_tune_get(int op)
 {
     if (op < 0 || op > 3) return fail(B64_EARG, "bad op%s", "");
     Shape s = shape_of(op);
-    return (int64_t)s.unroll * 1000 + s.bpc;
+    return (int64_t)s.nt * 10000 + (int64_t)s.unroll * 100 + s.bpc;
 }
 
 int64_t b64_encode(const uint8_t *src, int64_t n, uint8_t *dst, const char *alphabet,
@@ -695,7 +803,7 @@ int64_t b64_encode(const uint8_t *src, int64_t n, uint8_t *dst, const char *alph
     if (e != hipSuccess) return hip_fail(e, "device query");
     const Shape sh = shape_of(0);
     const int64_t grid = grid_for(n / 12, sh, cus);
-    B64_DISPATCH_U(sh.unroll, k_encode, grid, stream, src, n, dst, make_enc(alphabet));
+    B64_DISPATCH(k_encode, sh, grid, stream, src, n, dst, make_enc(alphabet));
     e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "encode launch");
     return 4 * ((n + 2) / 3);
@@ -704,44 +812,31 @@ int64_t b64_encode(const uint8_t *src, int64_t n, uint8_t *dst, const char *alph
 int64_t b64_decode_async(const uint8_t *src, int64_t n, uint8_t *dst, int64_t *out_len,
                          int64_t *first_bad, const char *alphabet, hipStream_t stream)
 {
-    if (n < 0) return fail(B64_EARG, "negative length%s", "");
     if ((n > 0 && (!src || !dst)) || !out_len || !first_bad)
         return fail(B64_EARG, "null pointer%s", "");
-    if (!alphabet_ok(alphabet))
-        return fail(B64_EARG, "alphabet must be 64 distinct bytes without '='%s", "");
-    int cus = 0;
-    hipError_t e = cu_count(&cus);
-    if (e != hipSuccess) return hip_fail(e, "device query");
-    int64_t r = launch_fill(first_bad, 1, kNoError, stream);
-    if (r) return r;
-    const Shape sh = shape_of(1);
-    const int64_t body = n >= 1 ? ((n - 1) >> 2) << 2 : 0;
-    const int64_t grid = grid_for(body >> 4, sh, cus);
-    B64_DISPATCH_U(sh.unroll, k_decode, grid, stream, src, n, dst, make_dec(alphabet), out_len,
-                   first_bad);
-    e = hipGetLastError();
-    if (e != hipSuccess) return hip_fail(e, "decode launch");
-    return launch_finish(out_len, first_bad, 1, stream);
+    return decode_launch(src, n, dst, out_len, first_bad, alphabet, stream, true);
 }
 
 int64_t b64_decode(const uint8_t *src, int64_t n, uint8_t *dst, const char *alphabet,
                    hipStream_t stream)
 {
     StatusSlot *slot = nullptr;
-    if (n < 0) return fail(B64_EARG, "negative length%s", "");
     if (n > 0 && (!src || !dst)) return fail(B64_EARG, "null buffer%s", "");
+    if (n < 0) return fail(B64_EARG, "negative length%s", "");
     if (!alphabet_ok(alphabet))
         return fail(B64_EARG, "alphabet must be 64 distinct bytes without '='%s", "");
     hipError_t e = status_slot(&slot);
     if (e != hipSuccess) return hip_fail(e, "status slot");
-    int64_t r = b64_decode_async(src, n, dst, slot->d, slot->d + 1, alphabet, stream);
+    // raw status: slot->d[0] = length if the tail is valid, slot->d[1] = the
+    // smallest invalid offset or kNoError; read back and combined here.
+    int64_t r = decode_launch(src, n, dst, slot->d, slot->d + 1, alphabet, stream, false);
     if (r) return r;
     e = hipMemcpyAsync(slot->h, slot->d, 2 * sizeof(int64_t), hipMemcpyDeviceToHost, stream);
     if (e != hipSuccess) return hip_fail(e, "status copy");
     e = hipStreamSynchronize(stream);
     if (e != hipSuccess) return hip_fail(e, "stream synchronize");
     const int64_t len = slot->h[0], bad = slot->h[1];
-    return bad < 0 ? len : ~bad;
+    return bad == kNoError ? len : ~bad;
 }
 
 int64_t b64_encode_batch(const uint8_t *src, const int64_t *in_off, int64_t nbuf, uint8_t *dst,
@@ -758,7 +853,7 @@ int64_t b64_encode_batch(const uint8_t *src, const int64_t *in_off, int64_t nbuf
     if (e != hipSuccess) return hip_fail(e, "device query");
     const Shape sh = shape_of(2);
     const int64_t grid = (int64_t)cus * sh.bpc;
-    B64_DISPATCH_U(sh.unroll, k_encode_batch, grid, stream, src, in_off, nbuf, dst, out_off, out_len,
+    B64_DISPATCH(k_encode_batch, sh, grid, stream, src, in_off, nbuf, dst, out_off, out_len,
                    make_enc(alphabet));
     e = hipGetLastError();
     return e == hipSuccess ? 0 : hip_fail(e, "encode_batch launch");
@@ -781,7 +876,7 @@ int64_t b64_decode_batch(const uint8_t *src, const int64_t *in_off, int64_t nbuf
     if (r) return r;
     const Shape sh = shape_of(3);
     const int64_t grid = (int64_t)cus * sh.bpc;
-    B64_DISPATCH_U(sh.unroll, k_decode_batch, grid, stream, src, in_off, nbuf, dst, out_off, out_len,
+    B64_DISPATCH(k_decode_batch, sh, grid, stream, src, in_off, nbuf, dst, out_off, out_len,
                    first_bad, make_dec(alphabet));
     e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "decode_batch launch");

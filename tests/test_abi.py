@@ -97,9 +97,11 @@ def test_argument_errors_without_gpu(lib):
 def test_tuning_interface(lib):
     EARG = -(2 ** 63)
     old = lib.b64_tune_get(0)
-    assert lib.b64_tune_set(0, 3, 8) == EARG
-    assert lib.b64_tune_set(0, 4, 0) == EARG
-    assert lib.b64_tune_set(7, 4, 8) == EARG
-    assert lib.b64_tune_set(0, 8, 16) == 0
-    assert lib.b64_tune_get(0) == 8016
-    assert lib.b64_tune_set(0, old // 1000, old % 1000) == 0
+    assert lib.b64_tune_set(0, 3, 8, 0) == EARG
+    assert lib.b64_tune_set(0, 4, 0, 0) == EARG
+    assert lib.b64_tune_set(7, 4, 8, 0) == EARG
+    assert lib.b64_tune_set(0, 4, 8, 2) == EARG
+    assert lib.b64_tune_set(0, 8, 16, 1) == 0
+    assert lib.b64_tune_get(0) == 10816
+    assert lib.b64_tune_set(0, (old // 100) % 100, old % 100, old // 10000) == 0
+    assert lib.b64_tune_get(0) == old

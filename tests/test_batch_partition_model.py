@@ -1,0 +1,175 @@
+"""CPU model of the batched kernels' work partition (no GPU).
+
+The batched kernels split the packed input into one span per wave and let
+each wave walk the buffers its span touches.  This test re-traces that index
+arithmetic on the host for many layouts and grid sizes and checks, before any
+launch, that:
+  - every group (encode) / quantum (decode) of every buffer is handled exactly
+    once, by a lane chunk or by one of the (at most four) leftover lanes;
+  - every read stays inside its buffer and every write inside its output
+    capacity;
+  - exactly one wave writes each encode out_len, and exactly one lane runs the
+    tail path of each non-empty decode buffer.
+"""
+import numpy as np
+import pytest
+
+import workloads
+
+WAVES_PER_BLOCK = 4
+XCDS = 8
+
+
+def logical_block(b, G):
+    if G % XCDS:
+        return b
+    return (b % XCDS) * (G // XCDS) + b // XCDS
+
+
+def wave_span(in_off, nbuf, quantum, w, nwaves):
+    base, end = int(in_off[0]), int(in_off[nbuf])
+    per = (end - base + nwaves - 1) // nwaves
+    span = (per + quantum - 1) // quantum * quantum
+    last = w == nwaves - 1
+    lo = min(base + w * span, end)
+    hi = end if last else min(lo + span, end)
+    # first b with in_off[b+1] >= lo
+    l, r = 0, nbuf
+    while l < r:
+        mid = (l + r) >> 1
+        if in_off[mid + 1] < lo:
+            l = mid + 1
+        else:
+            r = mid
+    return lo, hi, l, last
+
+
+def trace_encode(in_off, out_off, nbuf, grid):
+    nwaves = grid * WAVES_PER_BLOCK
+    seen = [np.zeros((int(in_off[b + 1] - in_off[b]) + 2) // 3, dtype=np.int64) for b in range(nbuf)]
+    owners = np.zeros(nbuf, dtype=np.int64)
+    for blk in range(grid):
+        for wv in range(WAVES_PER_BLOCK):
+            w = logical_block(blk, grid) * WAVES_PER_BLOCK + wv
+            lo, hi, b0, last = wave_span(in_off, nbuf, 768, w, nwaves)
+            if lo >= hi and not last:
+                continue
+            for b in range(b0, nbuf):
+                s, e = int(in_off[b]), int(in_off[b + 1])
+                if s >= hi and not (last and s == hi):
+                    break
+                length = e - s
+                ngroups, nfull = (length + 2) // 3, length // 3
+                if s >= lo:
+                    owners[b] += 1
+                g_lo = 0 if s >= lo else (lo - s + 2) // 3
+                g_hi = 0 if hi <= s else (hi - s + 2) // 3
+                g_hi = min(g_hi, ngroups)
+                if g_lo >= g_hi:
+                    continue
+                g_full = min(g_hi, nfull)
+                nchunk = (g_full - g_lo) >> 2 if g_full > g_lo else 0
+                if nchunk:
+                    seen[b][g_lo: g_lo + 4 * nchunk] += 1
+                    # reads [s + 3 g_lo, s + 3 g_lo + 12 nchunk), writes 16 per chunk
+                    assert s + 3 * g_lo + 12 * nchunk <= e
+                    assert 4 * g_lo + 16 * nchunk <= 4 * ngroups
+                left = g_hi - (g_lo + 4 * nchunk)
+                assert 0 <= left <= 4
+                for lane in range(left):
+                    g = g_lo + 4 * nchunk + lane
+                    rem = length - 3 * g
+                    assert rem > 0 and 3 * g + min(rem, 3) <= length
+                    seen[b][g] += 1
+    for b in range(nbuf):
+        assert (seen[b] == 1).all(), (b, seen[b])
+    assert (owners == 1).all(), np.nonzero(owners != 1)
+
+
+def trace_decode(in_off, nbuf, grid):
+    nwaves = grid * WAVES_PER_BLOCK
+    seen = [np.zeros((int(in_off[b + 1] - in_off[b]) + 3) // 4, dtype=np.int64) for b in range(nbuf)]
+    tails = np.zeros(nbuf, dtype=np.int64)
+    empty_owner = np.zeros(nbuf, dtype=np.int64)
+    for blk in range(grid):
+        for wv in range(WAVES_PER_BLOCK):
+            w = logical_block(blk, grid) * WAVES_PER_BLOCK + wv
+            lo, hi, b0, last = wave_span(in_off, nbuf, 1024, w, nwaves)
+            if lo >= hi and not last:
+                continue
+            for b in range(b0, nbuf):
+                s, e = int(in_off[b]), int(in_off[b + 1])
+                if s >= hi and not (last and s == hi):
+                    break
+                length = e - s
+                if length == 0:
+                    if s >= lo:
+                        empty_owner[b] += 1
+                    continue
+                nq, nbody = (length + 3) >> 2, (length - 1) >> 2
+                q_lo = 0 if s >= lo else (lo - s + 3) >> 2
+                q_hi = min(0 if hi <= s else (hi - s + 3) >> 2, nq)
+                if q_lo >= q_hi:
+                    continue
+                q_body = min(q_hi, nbody)
+                nchunk = (q_body - q_lo) >> 2 if q_body > q_lo else 0
+                if nchunk:
+                    seen[b][q_lo: q_lo + 4 * nchunk] += 1
+                    assert 4 * q_lo + 16 * nchunk <= 4 * nbody < length
+                    assert 3 * q_lo + 12 * nchunk <= 3 * (length // 4)
+                left = q_hi - (q_lo + 4 * nchunk)
+                assert 0 <= left <= 4
+                for lane in range(left):
+                    q = q_lo + 4 * nchunk + lane
+                    seen[b][q] += 1
+                    if q < nbody:
+                        assert 4 * q + 4 <= length and 3 * q + 3 <= 3 * (length // 4)
+                    else:
+                        assert q == nq - 1
+                        tails[b] += 1
+    for b in range(nbuf):
+        assert (seen[b] == 1).all(), (b, seen[b])
+        n = int(in_off[b + 1] - in_off[b])
+        assert tails[b] == (1 if n else 0)
+        assert empty_owner[b] == (0 if n else 1)
+
+
+def _layouts():
+    g = workloads.rng(77)
+    yield np.array([0, 0], dtype=np.int64)                         # one empty buffer
+    yield np.array([5, 5, 5, 5], dtype=np.int64)                   # all empty, offset base
+    yield np.array([0, 1 << 20], dtype=np.int64)                   # one big buffer
+    yield workloads.offsets(np.arange(0, 40, dtype=np.int64)) + 3  # every tiny length
+    for k in range(6):
+        nbuf = int(g.integers(1, 400))
+        lens = g.integers(0, 20_000, size=nbuf)
+        lens[g.random(nbuf) < 0.2] = 0
+        yield workloads.offsets(lens.astype(np.int64)) + int(g.integers(0, 17))
+    lens = workloads.batch_lengths(78, 300)
+    yield workloads.offsets(lens)
+
+
+@pytest.mark.parametrize("grid", [1, 2, 3, 8, 16, 40])
+def test_encode_partition(grid):
+    for in_off in _layouts():
+        nbuf = in_off.size - 1
+        out_off = workloads.offsets(4 * ((np.diff(in_off) + 2) // 3))
+        trace_encode(in_off, out_off, nbuf, grid)
+
+
+@pytest.mark.parametrize("grid", [1, 2, 3, 8, 16, 40])
+def test_decode_partition(grid):
+    for in_off in _layouts():
+        trace_decode(in_off, in_off.size - 1, grid)
+
+
+def test_single_buffer_heads_align_outputs():
+    """Single-buffer kernels set aside `head` groups / quanta so that chunk
+    outputs start on a 128-byte line, and never more than the body holds."""
+    for addr in range(0, 512):
+        ehead = 0 if addr & 3 else ((128 - (addr & 127)) & 127) >> 2
+        assert ehead < 32
+        if addr % 4 == 0:
+            assert (addr + 4 * ehead) % 128 == 0
+        dhead = (-addr * 43) & 127
+        assert (addr + 3 * dhead) % 128 == 0 and dhead < 128

@@ -261,3 +261,23 @@ def test_batch_workload_full_size(b64, oracle):
         assert oracle.decode_raw(text) == ~exp_bad[b]
     del d_enc, d_dec, d_src
     torch.cuda.empty_cache()
+
+
+def test_layout_validation_rejects_out_of_bounds(b64):
+    """The binding checks a batch layout against the tensor sizes on the host
+    and raises before any launch."""
+    import torch
+    src = torch.zeros(1000, dtype=torch.uint8, device="cuda")
+    too_long = to_dev(np.array([0, 600, 1200], dtype=np.int64))
+    with pytest.raises(ValueError):
+        b64.encode_batch(src, too_long)
+    with pytest.raises(ValueError):
+        b64.decode_batch(src, too_long)
+    decreasing = to_dev(np.array([0, 600, 500], dtype=np.int64))
+    with pytest.raises(ValueError):
+        b64.encode_batch(src, decreasing)
+    ok = to_dev(np.array([0, 600, 1000], dtype=np.int64))
+    small_dst = torch.zeros(100, dtype=torch.uint8, device="cuda")
+    with pytest.raises(ValueError):
+        b64.encode_batch(src, ok, dst=small_dst)
+    torch.cuda.synchronize()
