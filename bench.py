@@ -37,7 +37,9 @@ import workloads  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
 METRIC = "encode/decode GB/s as % of D2D memcpy; batched vs per-buffer GB/s; p99"
-KERNEL_SRC = os.path.join(ROOT, "paper_1910_05109_amd", "csrc", "b64hip.hip")
+# sources of the single-buffer kernels; a change to them voids the recorded HBM traffic
+KERNEL_SRCS = [os.path.join(ROOT, "paper_1910_05109_amd", "csrc", f)
+               for f in ("b64_device.h", "b64_single.hip")]
 
 
 def log(*a):
@@ -45,8 +47,11 @@ def log(*a):
 
 
 def kernel_hash() -> str:
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for path in KERNEL_SRCS:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def measured_traffic(kernel: str, n_launch_bytes: float):

@@ -10,7 +10,8 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SRC = os.path.join(HERE, "csrc", "b64hip.hip")
+CSRC = os.path.join(HERE, "csrc")
+SOURCES = [os.path.join(CSRC, f) for f in ("b64_single.hip", "b64_batch.hip", "b64_abi.hip")]
 LIB = os.path.join(HERE, "libb64hip.so")
 INCLUDE = os.path.join(ROOT, "include")
 ARCH = "gfx950"
@@ -20,7 +21,7 @@ FLAGS = [
     "-Wall", "-Wextra", "-Wno-unused-parameter",
     # no packed-FP32 instructions anywhere
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-    f"-I{INCLUDE}",
+    f"-I{INCLUDE}", f"-I{CSRC}",
 ]
 
 
@@ -33,7 +34,7 @@ def hipcc() -> str:
 def build(extra: list[str] | None = None, out: str = LIB) -> str:
     """Compile every HIP source of the package into `out` (always recompiles)."""
     tmp = out + ".tmp"
-    cmd = [hipcc(), *FLAGS, *(extra or []), SRC, "-o", tmp]
+    cmd = [hipcc(), *FLAGS, *(extra or []), *SOURCES, "-o", tmp]
     subprocess.check_call(cmd)
     os.replace(tmp, out)
     return out

@@ -1,0 +1,269 @@
+// b64_abi.hip -- the C ABI of libb64hip.so (declared in include/b64hip.h):
+// argument checks, the alphabet tables passed to the kernels, launch shapes,
+// per-device queries and the blocking decode's status slot.
+#include <stdio.h>
+#include <string.h>
+
+#include <mutex>
+
+#include "b64_launch.h"
+#include "b64hip.h"
+
+extern "C" {
+const char b64_alphabet_std[64] = {
+    'A', 'B', 'C', 'D', 'E', 'F', 'G', 'H', 'I', 'J', 'K', 'L', 'M', 'N', 'O', 'P',
+    'Q', 'R', 'S', 'T', 'U', 'V', 'W', 'X', 'Y', 'Z', 'a', 'b', 'c', 'd', 'e', 'f',
+    'g', 'h', 'i', 'j', 'k', 'l', 'm', 'n', 'o', 'p', 'q', 'r', 's', 't', 'u', 'v',
+    'w', 'x', 'y', 'z', '0', '1', '2', '3', '4', '5', '6', '7', '8', '9', '+', '/'};
+const char b64_alphabet_url[64] = {
+    'A', 'B', 'C', 'D', 'E', 'F', 'G', 'H', 'I', 'J', 'K', 'L', 'M', 'N', 'O', 'P',
+    'Q', 'R', 'S', 'T', 'U', 'V', 'W', 'X', 'Y', 'Z', 'a', 'b', 'c', 'd', 'e', 'f',
+    'g', 'h', 'i', 'j', 'k', 'l', 'm', 'n', 'o', 'p', 'q', 'r', 's', 't', 'u', 'v',
+    'w', 'x', 'y', 'z', '0', '1', '2', '3', '4', '5', '6', '7', '8', '9', '-', '_'};
+}
+
+using namespace b64hip;
+
+namespace {
+
+thread_local char g_err[256];
+
+int64_t fail(int64_t code, const char *msg)
+{
+    snprintf(g_err, sizeof g_err, "%s", msg);
+    return code;
+}
+
+int64_t hip_fail(hipError_t e, const char *where)
+{
+    snprintf(g_err, sizeof g_err, "%s: %s", where, hipGetErrorString(e));
+    return B64_EHIP;
+}
+
+// An alphabet must be invertible and may not contain the pad character.
+bool alphabet_ok(const char *alphabet)
+{
+    if (!alphabet) return false;
+    bool seen[256] = {false};
+    for (int v = 0; v < 64; ++v) {
+        const uint8_t c = (uint8_t)alphabet[v];
+        if (c == kPad || seen[c]) return false;
+        seen[c] = true;
+    }
+    return true;
+}
+
+EncTab make_enc(const char *alphabet)
+{
+    EncTab t;
+    memcpy(t.w, alphabet, 64);
+    return t;
+}
+
+DecMap make_dec(const char *alphabet)
+{
+    DecMap d;
+    uint8_t *b = (uint8_t *)d.w;
+    memset(b, (int)kBad, 256);
+    for (int v = 0; v < 64; ++v) b[(uint8_t)alphabet[v]] = (uint8_t)v;
+    return d;
+}
+
+// Launch shapes per operation (encode, decode, encode_batch, decode_batch);
+// the defaults are the autotuner's choices on MI355X (1 GiB single buffers,
+// 1 GiB log-uniform ragged batches).
+Shape g_shape[4] = {{4, 2, 1}, {4, 2, 1}, {2, 4, 1}, {2, 4, 1}};
+std::mutex g_mu;
+
+Shape shape_of(int op)
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    return g_shape[op];
+}
+
+constexpr int kMaxDevices = 64;
+int g_cus[kMaxDevices];
+
+hipError_t cu_count(int *cus)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    if (g_cus[dev] == 0) {
+        int v = 0;
+        e = hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev);
+        if (e != hipSuccess) return e;
+        g_cus[dev] = v > 0 ? v : 1;
+    }
+    *cus = g_cus[dev];
+    return hipSuccess;
+}
+
+// Per thread and device: 2 int64 of device memory and of pinned host memory
+// for the blocking b64_decode (held until the process ends).
+struct StatusSlot { int64_t *d = nullptr; int64_t *h = nullptr; };
+thread_local StatusSlot g_slot[kMaxDevices];
+
+hipError_t status_slot(StatusSlot **out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    StatusSlot &s = g_slot[dev];
+    if (!s.d) {
+        e = hipMalloc((void **)&s.d, 2 * sizeof(int64_t));
+        if (e != hipSuccess) return e;
+        e = hipHostMalloc((void **)&s.h, 2 * sizeof(int64_t), hipHostMallocDefault);
+        if (e != hipSuccess) {
+            (void)hipFree(s.d);
+            s.d = nullptr;
+            return e;
+        }
+    }
+    *out = &s;
+    return hipSuccess;
+}
+
+const char *const kBadAlphabet = "alphabet must be 64 distinct bytes without '='";
+
+// Enqueue one single-buffer decode: reset first_bad, run k_decode, and (with
+// `finish`) turn the raw status into the public form.
+int64_t decode_enqueue(const uint8_t *src, int64_t n, uint8_t *dst, int64_t *out_len,
+                       int64_t *first_bad, const char *alphabet, hipStream_t stream, bool finish)
+{
+    int cus = 0;
+    hipError_t e = cu_count(&cus);
+    if (e != hipSuccess) return hip_fail(e, "device query");
+    e = launch_fill(first_bad, 1, kNoError, stream);
+    if (e != hipSuccess) return hip_fail(e, "fill launch");
+    e = launch_decode(src, n, dst, make_dec(alphabet), out_len, first_bad, shape_of(1), cus, stream);
+    if (e != hipSuccess) return hip_fail(e, "decode launch");
+    if (finish) {
+        e = launch_finish(out_len, first_bad, 1, stream);
+        if (e != hipSuccess) return hip_fail(e, "status launch");
+    }
+    return 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+int64_t b64_encoded_len(int64_t n)
+{
+    if (n < 0) return fail(B64_EARG, "negative length");
+    return 4 * ((n + 2) / 3);
+}
+
+int64_t b64_decoded_max_len(int64_t n)
+{
+    if (n < 0) return fail(B64_EARG, "negative length");
+    return 3 * (n / 4);
+}
+
+const char *b64_last_error(void) { return g_err; }
+
+int64_t b64_tune_set(int op, int unroll, int blocks_per_cu, int nontemporal)
+{
+    if (op < 0 || op > 3) return fail(B64_EARG, "bad op");
+    if (!(unroll == 1 || unroll == 2 || unroll == 4 || unroll == 8))
+        return fail(B64_EARG, "unroll must be 1, 2, 4 or 8");
+    if (blocks_per_cu < 1 || blocks_per_cu > 64) return fail(B64_EARG, "blocks_per_cu out of range");
+    if (nontemporal != 0 && nontemporal != 1) return fail(B64_EARG, "nontemporal must be 0 or 1");
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_shape[op] = Shape{unroll, blocks_per_cu, nontemporal};
+    return 0;
+}
+
+int64_t b64_tune_get(int op)
+{
+    if (op < 0 || op > 3) return fail(B64_EARG, "bad op");
+    const Shape s = shape_of(op);
+    return (int64_t)s.nt * 10000 + (int64_t)s.unroll * 100 + s.bpc;
+}
+
+int64_t b64_encode(const uint8_t *src, int64_t n, uint8_t *dst, const char *alphabet,
+                   hipStream_t stream)
+{
+    if (n < 0) return fail(B64_EARG, "negative length");
+    if (n > 0 && (!src || !dst)) return fail(B64_EARG, "null buffer");
+    if (!alphabet_ok(alphabet)) return fail(B64_EARG, kBadAlphabet);
+    if (n == 0) return 0;
+    int cus = 0;
+    hipError_t e = cu_count(&cus);
+    if (e != hipSuccess) return hip_fail(e, "device query");
+    e = launch_encode(src, n, dst, make_enc(alphabet), shape_of(0), cus, stream);
+    if (e != hipSuccess) return hip_fail(e, "encode launch");
+    return 4 * ((n + 2) / 3);
+}
+
+int64_t b64_decode_async(const uint8_t *src, int64_t n, uint8_t *dst, int64_t *out_len,
+                         int64_t *first_bad, const char *alphabet, hipStream_t stream)
+{
+    if (n < 0) return fail(B64_EARG, "negative length");
+    if ((n > 0 && (!src || !dst)) || !out_len || !first_bad) return fail(B64_EARG, "null pointer");
+    if (!alphabet_ok(alphabet)) return fail(B64_EARG, kBadAlphabet);
+    return decode_enqueue(src, n, dst, out_len, first_bad, alphabet, stream, true);
+}
+
+int64_t b64_decode(const uint8_t *src, int64_t n, uint8_t *dst, const char *alphabet,
+                   hipStream_t stream)
+{
+    if (n < 0) return fail(B64_EARG, "negative length");
+    if (n > 0 && (!src || !dst)) return fail(B64_EARG, "null buffer");
+    if (!alphabet_ok(alphabet)) return fail(B64_EARG, kBadAlphabet);
+    StatusSlot *slot = nullptr;
+    hipError_t e = status_slot(&slot);
+    if (e != hipSuccess) return hip_fail(e, "status slot");
+    // raw status: slot->d[0] = length if the tail is valid, slot->d[1] = the
+    // smallest invalid offset or kNoError; read back and combined here.
+    const int64_t r = decode_enqueue(src, n, dst, slot->d, slot->d + 1, alphabet, stream, false);
+    if (r) return r;
+    e = hipMemcpyAsync(slot->h, slot->d, 2 * sizeof(int64_t), hipMemcpyDeviceToHost, stream);
+    if (e != hipSuccess) return hip_fail(e, "status copy");
+    e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return hip_fail(e, "stream synchronize");
+    const int64_t len = slot->h[0], bad = slot->h[1];
+    return bad == kNoError ? len : ~bad;
+}
+
+int64_t b64_encode_batch(const uint8_t *src, const int64_t *in_off, int64_t nbuf, uint8_t *dst,
+                         const int64_t *out_off, int64_t *out_len, const char *alphabet,
+                         hipStream_t stream)
+{
+    if (nbuf < 0) return fail(B64_EARG, "negative buffer count");
+    if (nbuf == 0) return 0;
+    if (!src || !in_off || !dst || !out_off || !out_len) return fail(B64_EARG, "null pointer");
+    if (!alphabet_ok(alphabet)) return fail(B64_EARG, kBadAlphabet);
+    int cus = 0;
+    hipError_t e = cu_count(&cus);
+    if (e != hipSuccess) return hip_fail(e, "device query");
+    e = launch_encode_batch(src, in_off, nbuf, dst, out_off, out_len, make_enc(alphabet),
+                            shape_of(2), cus, stream);
+    return e == hipSuccess ? 0 : hip_fail(e, "encode_batch launch");
+}
+
+int64_t b64_decode_batch(const uint8_t *src, const int64_t *in_off, int64_t nbuf, uint8_t *dst,
+                         const int64_t *out_off, int64_t *out_len, int64_t *first_bad,
+                         const char *alphabet, hipStream_t stream)
+{
+    if (nbuf < 0) return fail(B64_EARG, "negative buffer count");
+    if (nbuf == 0) return 0;
+    if (!src || !in_off || !dst || !out_off || !out_len || !first_bad)
+        return fail(B64_EARG, "null pointer");
+    if (!alphabet_ok(alphabet)) return fail(B64_EARG, kBadAlphabet);
+    int cus = 0;
+    hipError_t e = cu_count(&cus);
+    if (e != hipSuccess) return hip_fail(e, "device query");
+    e = launch_fill(first_bad, nbuf, kNoError, stream);
+    if (e != hipSuccess) return hip_fail(e, "fill launch");
+    e = launch_decode_batch(src, in_off, nbuf, dst, out_off, out_len, first_bad,
+                            make_dec(alphabet), shape_of(3), cus, stream);
+    if (e != hipSuccess) return hip_fail(e, "decode_batch launch");
+    e = launch_finish(out_len, first_bad, nbuf, stream);
+    return e == hipSuccess ? 0 : hip_fail(e, "status launch");
+}
+
+}  // extern "C"

@@ -1,0 +1,258 @@
+// b64_device.h -- device-side building blocks of the base64 kernels (gfx950).
+//
+// Method: W. Mula and D. Lemire, "Base64 encoding and decoding at almost the
+// speed of a memory copy".  The paper's AVX-512 kernels process 48 input
+// bytes (encode) or 64 characters (decode) per register; here every lane of a
+// 64-wide wavefront processes a 12-byte -> 16-character (encode) or
+// 16-character -> 12-byte (decode) chunk, and consecutive lanes own
+// consecutive chunks, so that every wave-wide load and store is one contiguous
+// 768- or 1024-byte span.
+//
+// Encode (Section "Encoding"): the byte gather (s1,s2,s3) -> (s2,s1,s3,s2) is
+// one v_perm_b32 per group; the four 6-bit indices are the low six bits of
+// that word shifted right by 10, 4, 22 and 16 (the paper's multishift
+// amounts), and each index selects its character from the runtime alphabet
+// staged in LDS (the paper's second vpermb).
+//
+// Decode (Section "Decoding"): each character goes through a 256-entry map in
+// LDS holding its 6-bit value or 0xFF (the paper's 0x80 "invalid" value; the
+// 256-entry map also covers bytes >= 0x80 directly).  The map values are ORed
+// into a per-lane error word that is tested once, after the lane's share of
+// the input (the paper's deferred vpternlogd/vpmovb2m check); a wave-wide
+// ballot skips the slow path when every lane is clean.  A lane that saw an
+// invalid character (or a '=') rescans its chunks to find the first invalid
+// offset and publishes it with an atomic minimum.  Four 6-bit values are
+// packed as a<<18 | b<<12 | c<<6 | d (the paper's two multiply-adds) and the
+// three bytes of four quanta are packed into three dwords by v_perm_b32 (the
+// paper's final vpermb).  The last quantum, with its '=' rules, goes through
+// a separate single-lane path (the paper's "conventional code path").
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace b64hip {
+
+constexpr int kThreads = 256;          // 4 waves of 64 lanes per workgroup
+constexpr int kWaves = kThreads / 64;
+constexpr uint32_t kPad = '=';
+constexpr uint32_t kBad = 0xFF;        // decode-map value of a non-alphabet byte
+constexpr int64_t kNoError = INT64_MAX;
+constexpr int kXcds = 8;               // MI355X: 8 accelerator dies, each with its own L2
+constexpr int kLine = 128;             // L2 cache line, bytes
+
+// Runtime alphabet, passed by value as a kernel argument.
+struct EncTab { uint32_t w[16]; };     // byte v = character of value v
+struct DecMap { uint32_t w[64]; };     // byte c = value of character c, or kBad
+
+// Byte-aligned vector types: the amdhsa ABI runs with unaligned global access
+// enabled, so these compile to single dwordx3 / dwordx4 accesses whatever the
+// address; packed ragged buffers start at arbitrary byte offsets.
+typedef uint32_t u32x3 __attribute__((ext_vector_type(3), aligned(1)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4), aligned(1)));
+typedef uint32_t u32a1 __attribute__((aligned(1)));
+
+// Streaming loads and stores of 12 or 16 bytes at any byte address; NT marks
+// them nontemporal (each byte is touched once, so nothing is worth keeping in
+// the caches).  The pointer types carry the byte alignment explicitly.
+template <bool NT>
+__device__ __forceinline__ u32x3 load12(const uint8_t *p)
+{
+    if constexpr (NT) return __builtin_nontemporal_load((const u32x3 *)p);
+    else return *(const u32x3 *)p;
+}
+template <bool NT>
+__device__ __forceinline__ u32x4 load16(const uint8_t *p)
+{
+    if constexpr (NT) return __builtin_nontemporal_load((const u32x4 *)p);
+    else return *(const u32x4 *)p;
+}
+template <bool NT>
+__device__ __forceinline__ void store12(uint8_t *p, u32x3 v)
+{
+    if constexpr (NT) __builtin_nontemporal_store(v, (u32x3 *)p);
+    else *(u32x3 *)p = v;
+}
+template <bool NT>
+__device__ __forceinline__ void store16(uint8_t *p, u32x4 v)
+{
+    if constexpr (NT) __builtin_nontemporal_store(v, (u32x4 *)p);
+    else *(u32x4 *)p = v;
+}
+
+// ---------------------------------------------------------------- encode --
+
+// Four characters of one group.  g holds the gathered bytes
+// s2 | s1<<8 | s3<<16 | s2<<24; shifting right by 10, 4, 22, 16 and keeping
+// six bits gives s1 div 4, (s2 div 16)+(s1*16 mod 64), (s2*4 mod 64)+(s3 div 64)
+// and s3 mod 64 (Section "Encoding", step 1; Section "Base64" closed form).
+__device__ __forceinline__ uint32_t enc_group(uint32_t g, const uint8_t *tab)
+{
+    uint32_t c0 = tab[(g >> 10) & 63];
+    uint32_t c1 = tab[(g >> 4) & 63];
+    uint32_t c2 = tab[(g >> 22) & 63];
+    uint32_t c3 = tab[(g >> 16) & 63];
+    return c0 | (c1 << 8) | (c2 << 16) | (c3 << 24);
+}
+
+// 12 input bytes b0..b11 (little-endian in three dwords) -> 16 characters.
+// v_perm_b32(hi, lo, sel) picks bytes of the 8-byte value hi:lo.
+__device__ __forceinline__ u32x4 enc_chunk(u32x3 in, const uint8_t *tab)
+{
+    u32x4 o;
+    o.x = enc_group(__builtin_amdgcn_perm(in.x, in.x, 0x01020001u), tab);  // b1 b0 b2 b1
+    o.y = enc_group(__builtin_amdgcn_perm(in.y, in.x, 0x04050304u), tab);  // b4 b3 b5 b4
+    o.z = enc_group(__builtin_amdgcn_perm(in.z, in.y, 0x03040203u), tab);  // b7 b6 b8 b7
+    o.w = enc_group(__builtin_amdgcn_perm(in.z, in.z, 0x02030102u), tab);  // b10 b9 b11 b10
+    return o;
+}
+
+// Scalar path for 0..r bytes: whole groups, then a last group of one or two
+// bytes zero-filled and padded with '=' (Section "Base64").
+__device__ inline void enc_scalar(const uint8_t *p, int64_t r, uint8_t *o, const uint8_t *tab)
+{
+    int64_t i = 0;
+    for (; i + 3 <= r; i += 3, o += 4) {
+        uint32_t s1 = p[i], s2 = p[i + 1], s3 = p[i + 2];
+        *(u32a1 *)o = enc_group(s2 | (s1 << 8) | (s3 << 16) | (s2 << 24), tab);
+    }
+    if (r - i == 1) {
+        uint32_t q = enc_group((uint32_t)p[i] << 8, tab);
+        *(u32a1 *)o = (q & 0xFFFFu) | (kPad << 16) | (kPad << 24);
+    } else if (r - i == 2) {
+        uint32_t s1 = p[i], s2 = p[i + 1];
+        uint32_t q = enc_group(s2 | (s1 << 8) | (s2 << 24), tab);
+        *(u32a1 *)o = (q & 0xFFFFFFu) | (kPad << 24);
+    }
+}
+
+__device__ __forceinline__ void stage_enc_table(uint32_t *s_tab, const EncTab &tab)
+{
+    if (threadIdx.x < 16) s_tab[threadIdx.x] = tab.w[threadIdx.x];
+    __syncthreads();
+}
+
+// Workgroups are dealt round-robin over the XCDs.  Renumber them so that
+// consecutive logical blocks, which write adjacent output spans, run on the
+// same XCD: a cache line shared by two spans is then completed in one L2
+// instead of being written back in two partial halves from two L2s.
+__device__ __forceinline__ int64_t logical_block()
+{
+    const int64_t G = gridDim.x, b = blockIdx.x;
+    if (G % kXcds != 0) return b;
+    return (b % kXcds) * (G / kXcds) + b / kXcds;
+}
+
+// ---------------------------------------------------------------- decode --
+
+// Values of four characters (one quantum, little-endian in q) packed as
+// a<<18 | b<<12 | c<<6 | d; their map entries are ORed into err.
+__device__ __forceinline__ uint32_t dec_quantum(uint32_t q, const uint8_t *map, uint32_t &err)
+{
+    uint32_t m0 = map[q & 0xFF];
+    uint32_t m1 = map[(q >> 8) & 0xFF];
+    uint32_t m2 = map[(q >> 16) & 0xFF];
+    uint32_t m3 = map[q >> 24];
+    err |= m0 | m1 | m2 | m3;
+    return (m0 << 18) | (m1 << 12) | (m2 << 6) | m3;
+}
+
+// 16 characters -> 12 bytes.  Quantum value v holds its three output bytes
+// as v.b2 v.b1 v.b0; v_perm_b32 lays four quanta out as 12 consecutive bytes.
+__device__ __forceinline__ u32x3 dec_chunk(u32x4 in, const uint8_t *map, uint32_t &err)
+{
+    uint32_t v0 = dec_quantum(in.x, map, err);
+    uint32_t v1 = dec_quantum(in.y, map, err);
+    uint32_t v2 = dec_quantum(in.z, map, err);
+    uint32_t v3 = dec_quantum(in.w, map, err);
+    u32x3 o;
+    o.x = __builtin_amdgcn_perm(v1, v0, 0x06000102u);   // v0.b2 v0.b1 v0.b0 v1.b2
+    o.y = __builtin_amdgcn_perm(v2, v1, 0x05060001u);   // v1.b1 v1.b0 v2.b2 v2.b1
+    o.z = __builtin_amdgcn_perm(v3, v2, 0x04050600u);   // v2.b0 v3.b2 v3.b1 v3.b0
+    return o;
+}
+
+enum { kData = 0, kPad1 = 1, kDone = 2 };
+
+// Validate characters p[0..len) that start at a quantum boundary in the data
+// state.  Returns the offset (relative to p) of the first character that
+// cannot extend a valid encoding, or -1; *state gets the state after p[len-1]:
+// kPad1 after a '=' at quantum position 2, kDone after the final '='.
+// Rules: a non-alphabet character is invalid; '=' may stand only at quantum
+// positions 2 and 3; before "==" the last value needs four zero low bits,
+// before a single '=' two; nothing may follow the padded quantum.
+__device__ inline int64_t dec_validate(const uint8_t *p, int64_t len, const uint8_t *map, int *state)
+{
+    int st = kData;
+    for (int64_t i = 0; i < len; ++i) {
+        const uint32_t c = p[i];
+        const int pos = (int)(i & 3);
+        if (st == kDone) return i;
+        if (c != kPad) {
+            if (map[c] == kBad || st == kPad1) return i;
+            continue;
+        }
+        if (pos < 2) return i;
+        if (pos == 2) {
+            if (map[p[i - 1]] & 15) return i;
+            st = kPad1;
+        } else {
+            if (st != kPad1 && (map[p[i - 1]] & 3)) return i;
+            st = kDone;
+        }
+    }
+    *state = st;
+    return -1;
+}
+
+// First invalid offset (relative to p) inside a run of whole quanta that is
+// known to be followed by at least one more character, or -1 if the run is
+// clean.  A run ending with its padded quantum makes the next character the
+// first invalid one.
+__device__ __forceinline__ int64_t dec_check_inner(const uint8_t *p, int64_t len, const uint8_t *map)
+{
+    int st = kData;
+    int64_t bad = dec_validate(p, len, map, &st);
+    if (bad >= 0) return bad;
+    return st == kDone ? len : -1;
+}
+
+// The last (up to 19) characters of a buffer: validate as the end of the
+// input and, when valid, decode them.  Returns -1 and sets *out_len (the
+// buffer's whole decoded length) when valid, else the first invalid offset
+// relative to p.  `n_total` is the buffer length, p starts at a quantum
+// boundary.
+__device__ inline int64_t dec_tail(const uint8_t *p, int64_t len, int64_t n_total, uint8_t *o,
+                            const uint8_t *map, int64_t *out_len)
+{
+    int st = kData;
+    int64_t bad = dec_validate(p, len, map, &st);
+    if (bad >= 0) return bad;
+    if (st == kPad1 || ((n_total & 3) != 0 && st != kDone)) return len;
+    int npad = 0;
+    for (int64_t q = 0; q < len; q += 4) {
+        const uint32_t a = map[p[q]], b = map[p[q + 1]];
+        const bool pc = p[q + 2] == kPad, pd = p[q + 3] == kPad;
+        const uint32_t c = pc ? 0u : map[p[q + 2]], d = pd ? 0u : map[p[q + 3]];
+        const uint32_t v = (a << 18) | (b << 12) | (c << 6) | d;
+        *o++ = (uint8_t)(v >> 16);
+        if (!pc) *o++ = (uint8_t)(v >> 8);
+        if (!pd) *o++ = (uint8_t)v;
+        npad = (int)pc + (int)pd;
+    }
+    *out_len = 3 * (n_total >> 2) - npad;
+    return -1;
+}
+
+__device__ __forceinline__ void stage_dec_map(uint32_t *s_map, const DecMap &map)
+{
+    if (threadIdx.x < 64) s_map[threadIdx.x] = map.w[threadIdx.x];
+    __syncthreads();
+}
+
+__device__ __forceinline__ void atomic_min_i64(int64_t *p, int64_t v)
+{
+    atomicMin((unsigned long long *)p, (unsigned long long)v);
+}
+
+}  // namespace b64hip

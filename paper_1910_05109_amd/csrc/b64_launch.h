@@ -1,0 +1,55 @@
+// b64_launch.h -- host-side launchers shared by the C ABI (b64_abi.hip) and
+// the kernel translation units (b64_single.hip, b64_batch.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "b64_device.h"
+
+namespace b64hip {
+
+// Launch shape: lane chunks in flight per lane, workgroups per CU, and
+// whether streaming loads / stores carry the nontemporal hint.
+struct Shape { int unroll, bpc, nt; };
+
+// Blocks for a grid-stride launch over `nch` lane chunks: enough to cover
+// them with `unroll` chunks per lane, at most `bpc` per CU, a whole number
+// per XCD.
+int64_t grid_for(int64_t nch, Shape sh, int cus);
+
+hipError_t launch_encode(const uint8_t *src, int64_t n, uint8_t *dst, const EncTab &tab, Shape sh,
+                         int cus, hipStream_t stream);
+hipError_t launch_decode(const uint8_t *src, int64_t n, uint8_t *dst, const DecMap &map,
+                         int64_t *out_len, int64_t *first_bad, Shape sh, int cus,
+                         hipStream_t stream);
+hipError_t launch_fill(int64_t *p, int64_t count, int64_t value, hipStream_t stream);
+hipError_t launch_finish(int64_t *out_len, int64_t *first_bad, int64_t count, hipStream_t stream);
+hipError_t launch_encode_batch(const uint8_t *src, const int64_t *in_off, int64_t nbuf,
+                               uint8_t *dst, const int64_t *out_off, int64_t *out_len,
+                               const EncTab &tab, Shape sh, int cus, hipStream_t stream);
+hipError_t launch_decode_batch(const uint8_t *src, const int64_t *in_off, int64_t nbuf,
+                               uint8_t *dst, const int64_t *out_off, int64_t *out_len,
+                               int64_t *first_bad, const DecMap &map, Shape sh, int cus,
+                               hipStream_t stream);
+
+}  // namespace b64hip
+
+#define B64_LAUNCH(KERNEL, U_, NT_, GRID, STREAM, ...) \
+    hipLaunchKernelGGL((KERNEL<U_, NT_>), dim3(GRID), dim3(kThreads), 0, STREAM, __VA_ARGS__)
+#define B64_DISPATCH_NT(KERNEL, U_, SH, GRID, STREAM, ...)                      \
+    do {                                                                       \
+        if ((SH).nt) B64_LAUNCH(KERNEL, U_, true, GRID, STREAM, __VA_ARGS__);  \
+        else B64_LAUNCH(KERNEL, U_, false, GRID, STREAM, __VA_ARGS__);         \
+    } while (0)
+// Instantiates KERNEL for every (unroll, nontemporal) shape and launches the
+// one `SH` selects.
+#define B64_DISPATCH(KERNEL, SH, GRID, STREAM, ...)                                  \
+    do {                                                                            \
+        switch ((SH).unroll) {                                                      \
+        case 1: B64_DISPATCH_NT(KERNEL, 1, SH, GRID, STREAM, __VA_ARGS__); break;   \
+        case 2: B64_DISPATCH_NT(KERNEL, 2, SH, GRID, STREAM, __VA_ARGS__); break;   \
+        case 8: B64_DISPATCH_NT(KERNEL, 8, SH, GRID, STREAM, __VA_ARGS__); break;   \
+        default: B64_DISPATCH_NT(KERNEL, 4, SH, GRID, STREAM, __VA_ARGS__); break;  \
+        }                                                                           \
+    } while (0)

@@ -1,0 +1,183 @@
+// b64_single.hip -- single-buffer encode / decode kernels and their launchers.
+#include "b64_launch.h"
+
+namespace b64hip {
+namespace {
+
+// Single buffer.  `head` whole groups are set aside so that the chunk outputs
+// start on a 128-byte line (when dst is 4-byte aligned); then lane chunk c
+// covers input [3*head + 12c, +12) and output [4*head + 16c, +16), grid-stride
+// with U chunks in flight per lane.  Threads t < head encode one head group
+// each; the last thread encodes the at most three whole groups and the
+// partial group left after the chunks.
+template <int U, bool NT>
+__global__ __launch_bounds__(kThreads) void k_encode(const uint8_t *__restrict__ src, int64_t n,
+                                                     uint8_t *__restrict__ dst, EncTab tab)
+{
+    __shared__ uint32_t s_tab[16];
+    stage_enc_table(s_tab, tab);
+    const uint8_t *a = (const uint8_t *)s_tab;
+
+    const int64_t ng = n / 3;
+    const uint64_t da = (uint64_t)(uintptr_t)dst;
+    int64_t head = (da & 3) ? 0 : (int64_t)((((uint64_t)kLine - (da & (kLine - 1))) & (kLine - 1)) >> 2);
+    if (head > ng) head = ng;
+    const int64_t nch = (ng - head) >> 2;
+    const uint8_t *s0 = src + 3 * head;
+    uint8_t *d0 = dst + 4 * head;
+    const int64_t T = (int64_t)gridDim.x * kThreads;
+    const int64_t t = logical_block() * kThreads + threadIdx.x;
+    for (int64_t c0 = t; c0 < nch; c0 += U * T) {
+        u32x3 in[U];
+#pragma unroll
+        for (int j = 0; j < U; ++j) {
+            const int64_t c = c0 + j * T;
+            if (c < nch) in[j] = load12<NT>(s0 + 12 * c);
+        }
+#pragma unroll
+        for (int j = 0; j < U; ++j) {
+            const int64_t c = c0 + j * T;
+            if (c < nch) store16<NT>(d0 + 16 * c, enc_chunk(in[j], a));
+        }
+    }
+    if (t < head) enc_scalar(src + 3 * t, 3, dst + 4 * t, a);
+    if (t == kThreads - 1) {
+        const int64_t g = head + 4 * nch;
+        enc_scalar(src + 3 * g, n - 3 * g, dst + 4 * g, a);
+    }
+}
+
+// Single buffer.  The body is every quantum but the last (nbq quanta).
+// `head` body quanta are set aside so that the chunk outputs start on a
+// 128-byte line (3*head = -dst mod 128; 43 is the inverse of 3 mod 128); then
+// lane chunk c covers characters [4*head + 16c, +16) and bytes
+// [3*head + 12c, +12).  Threads t < head decode one head quantum each; the
+// last thread runs dec_tail over the (at most three) body quanta left after
+// the chunks and the last quantum.  first_bad must hold kNoError before the
+// launch; out_len is written only when the tail is valid.
+template <int U, bool NT>
+__global__ __launch_bounds__(kThreads) void k_decode(const uint8_t *__restrict__ src, int64_t n,
+                                                     uint8_t *__restrict__ dst, DecMap map,
+                                                     int64_t *__restrict__ out_len,
+                                                     int64_t *__restrict__ first_bad)
+{
+    __shared__ uint32_t s_map[64];
+    stage_dec_map(s_map, map);
+    const uint8_t *m = (const uint8_t *)s_map;
+
+    const int64_t nbq = n >= 1 ? (n - 1) >> 2 : 0;
+    const uint64_t da = (uint64_t)(uintptr_t)dst;
+    int64_t head = (int64_t)(((0 - da) * 43u) & (uint64_t)(kLine - 1));
+    if (head > nbq) head = nbq;
+    const int64_t nch = (nbq - head) >> 2;
+    const uint8_t *s0 = src + 4 * head;
+    uint8_t *d0 = dst + 3 * head;
+    const int64_t T = (int64_t)gridDim.x * kThreads;
+    const int64_t t = logical_block() * kThreads + threadIdx.x;
+    uint32_t err = 0;
+    for (int64_t c0 = t; c0 < nch; c0 += U * T) {
+        u32x4 in[U];
+#pragma unroll
+        for (int j = 0; j < U; ++j) {
+            const int64_t c = c0 + j * T;
+            if (c < nch) in[j] = load16<NT>(s0 + 16 * c);
+        }
+#pragma unroll
+        for (int j = 0; j < U; ++j) {
+            const int64_t c = c0 + j * T;
+            if (c < nch) store12<NT>(d0 + 12 * c, dec_chunk(in[j], m, err));
+        }
+    }
+    // One test per lane for its whole share (bit 7 is set only by kBad).
+    if (__ballot(err & 0x80)) {
+        if (err & 0x80) {
+            for (int64_t c = t; c < nch; c += T) {
+                const int64_t bad = dec_check_inner(s0 + 16 * c, 16, m);
+                if (bad >= 0) {
+                    atomic_min_i64(first_bad, 4 * head + 16 * c + bad);
+                    break;   // later chunks of this lane have larger offsets
+                }
+            }
+        }
+    }
+    if (t < head) {
+        uint32_t qerr = 0;
+        const uint32_t v = dec_quantum(*(const u32a1 *)(src + 4 * t), m, qerr);
+        dst[3 * t] = (uint8_t)(v >> 16);
+        dst[3 * t + 1] = (uint8_t)(v >> 8);
+        dst[3 * t + 2] = (uint8_t)v;
+        if (qerr & 0x80) {
+            const int64_t bad = dec_check_inner(src + 4 * t, 4, m);
+            if (bad >= 0) atomic_min_i64(first_bad, 4 * t + bad);
+        }
+    }
+    if (t == kThreads - 1) {
+        const int64_t q = head + 4 * nch;
+        const int64_t bad = dec_tail(src + 4 * q, n - 4 * q, n, dst + 3 * q, m, out_len);
+        if (bad >= 0) atomic_min_i64(first_bad, 4 * q + bad);
+    }
+}
+
+__global__ void k_fill_i64(int64_t *p, int64_t count, int64_t value)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) p[i] = value;
+}
+
+// After a decode: first_bad == kNoError becomes -1 (valid); otherwise the
+// buffer is invalid and its out_len becomes -1.
+__global__ void k_finish_status(int64_t *out_len, int64_t *first_bad, int64_t count)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) {
+        if (first_bad[i] == kNoError) first_bad[i] = -1;
+        else out_len[i] = -1;
+    }
+}
+
+}  // namespace
+
+int64_t grid_for(int64_t nch, Shape sh, int cus)
+{
+    const int64_t per_block = (int64_t)kThreads * sh.unroll;
+    int64_t need = (nch + per_block - 1) / per_block;
+    const int64_t cap = (int64_t)cus * sh.bpc;
+    if (need > cap) need = cap;
+    if (need >= kXcds) need -= need % kXcds;   // a whole number of blocks per XCD
+    return need < 1 ? 1 : need;
+}
+
+hipError_t launch_encode(const uint8_t *src, int64_t n, uint8_t *dst, const EncTab &tab, Shape sh,
+                         int cus, hipStream_t stream)
+{
+    const int64_t grid = grid_for(n / 12, sh, cus);
+    B64_DISPATCH(k_encode, sh, grid, stream, src, n, dst, tab);
+    return hipGetLastError();
+}
+
+hipError_t launch_decode(const uint8_t *src, int64_t n, uint8_t *dst, const DecMap &map,
+                         int64_t *out_len, int64_t *first_bad, Shape sh, int cus,
+                         hipStream_t stream)
+{
+    const int64_t nbq = n >= 1 ? (n - 1) >> 2 : 0;
+    const int64_t grid = grid_for(nbq >> 2, sh, cus);
+    B64_DISPATCH(k_decode, sh, grid, stream, src, n, dst, map, out_len, first_bad);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill(int64_t *p, int64_t count, int64_t value, hipStream_t stream)
+{
+    const int64_t blocks = (count + kThreads - 1) / kThreads;
+    hipLaunchKernelGGL(k_fill_i64, dim3(blocks), dim3(kThreads), 0, stream, p, count, value);
+    return hipGetLastError();
+}
+
+hipError_t launch_finish(int64_t *out_len, int64_t *first_bad, int64_t count, hipStream_t stream)
+{
+    const int64_t blocks = (count + kThreads - 1) / kThreads;
+    hipLaunchKernelGGL(k_finish_status, dim3(blocks), dim3(kThreads), 0, stream, out_len,
+                       first_bad, count);
+    return hipGetLastError();
+}
+
+}  // namespace b64hip

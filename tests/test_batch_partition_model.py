@@ -1,9 +1,9 @@
 """CPU model of the batched kernels' work partition (no GPU).
 
-The batched kernels split the packed input into one span per wave and let
-each wave walk the buffers its span touches.  This test re-traces that index
-arithmetic on the host for many layouts and grid sizes and checks, before any
-launch, that:
+The batched kernels cut the packed input into equal tiles, deal the tiles to
+waves grid-stride, and let each wave walk the buffers a tile touches.  This
+test re-traces that index arithmetic on the host for many layouts, tile sizes
+and grid sizes and checks, before any launch, that:
   - every group (encode) / quantum (decode) of every buffer is handled exactly
     once, by a lane chunk or by one of the (at most four) leftover lanes;
   - every read stays inside its buffer and every write inside its output
@@ -26,107 +26,107 @@ def logical_block(b, G):
     return (b % XCDS) * (G // XCDS) + b // XCDS
 
 
-def wave_span(in_off, nbuf, quantum, w, nwaves):
-    base, end = int(in_off[0]), int(in_off[nbuf])
-    per = (end - base + nwaves - 1) // nwaves
-    span = (per + quantum - 1) // quantum * quantum
-    last = w == nwaves - 1
-    lo = min(base + w * span, end)
-    hi = end if last else min(lo + span, end)
-    # first b with in_off[b+1] >= lo
+def first_buffer(in_off, nbuf, pos):
     l, r = 0, nbuf
     while l < r:
         mid = (l + r) >> 1
-        if in_off[mid + 1] < lo:
+        if in_off[mid + 1] < pos:
             l = mid + 1
         else:
             r = mid
-    return lo, hi, l, last
+    return l
 
 
-def trace_encode(in_off, out_off, nbuf, grid):
-    nwaves = grid * WAVES_PER_BLOCK
-    seen = [np.zeros((int(in_off[b + 1] - in_off[b]) + 2) // 3, dtype=np.int64) for b in range(nbuf)]
-    owners = np.zeros(nbuf, dtype=np.int64)
+def tiles(in_off, nbuf, tile, grid):
+    """(lo, hi, b0, last) of every tile, in the order the waves take them."""
+    W = grid * WAVES_PER_BLOCK
+    base, end = int(in_off[0]), int(in_off[nbuf])
+    ntiles = (end - base + tile - 1) // tile if end > base else 1
     for blk in range(grid):
         for wv in range(WAVES_PER_BLOCK):
             w = logical_block(blk, grid) * WAVES_PER_BLOCK + wv
-            lo, hi, b0, last = wave_span(in_off, nbuf, 768, w, nwaves)
-            if lo >= hi and not last:
+            k = 0
+            while w + k * W < ntiles:
+                t = w + k * W
+                lo = base + t * tile
+                last = t == ntiles - 1
+                hi = end if last else lo + tile
+                assert hi <= end
+                yield lo, hi, first_buffer(in_off, nbuf, lo), last
+                k += 1
+
+
+def trace_encode(in_off, out_off, nbuf, grid, tile):
+    seen = [np.zeros((int(in_off[b + 1] - in_off[b]) + 2) // 3, dtype=np.int64) for b in range(nbuf)]
+    owners = np.zeros(nbuf, dtype=np.int64)
+    for lo, hi, b0, last in tiles(in_off, nbuf, tile, grid):
+        for b in range(b0, nbuf):
+            s, e = int(in_off[b]), int(in_off[b + 1])
+            if s >= hi and not (last and s == hi):
+                break
+            length = e - s
+            ngroups, nfull = (length + 2) // 3, length // 3
+            if s >= lo:
+                owners[b] += 1
+            g_lo = 0 if s >= lo else (lo - s + 2) // 3
+            g_hi = 0 if hi <= s else (hi - s + 2) // 3
+            g_hi = min(g_hi, ngroups)
+            if g_lo >= g_hi:
                 continue
-            for b in range(b0, nbuf):
-                s, e = int(in_off[b]), int(in_off[b + 1])
-                if s >= hi and not (last and s == hi):
-                    break
-                length = e - s
-                ngroups, nfull = (length + 2) // 3, length // 3
-                if s >= lo:
-                    owners[b] += 1
-                g_lo = 0 if s >= lo else (lo - s + 2) // 3
-                g_hi = 0 if hi <= s else (hi - s + 2) // 3
-                g_hi = min(g_hi, ngroups)
-                if g_lo >= g_hi:
-                    continue
-                g_full = min(g_hi, nfull)
-                nchunk = (g_full - g_lo) >> 2 if g_full > g_lo else 0
-                if nchunk:
-                    seen[b][g_lo: g_lo + 4 * nchunk] += 1
-                    # reads [s + 3 g_lo, s + 3 g_lo + 12 nchunk), writes 16 per chunk
-                    assert s + 3 * g_lo + 12 * nchunk <= e
-                    assert 4 * g_lo + 16 * nchunk <= 4 * ngroups
-                left = g_hi - (g_lo + 4 * nchunk)
-                assert 0 <= left <= 4
-                for lane in range(left):
-                    g = g_lo + 4 * nchunk + lane
-                    rem = length - 3 * g
-                    assert rem > 0 and 3 * g + min(rem, 3) <= length
-                    seen[b][g] += 1
+            g_full = min(g_hi, nfull)
+            nchunk = (g_full - g_lo) >> 2 if g_full > g_lo else 0
+            if nchunk:
+                seen[b][g_lo: g_lo + 4 * nchunk] += 1
+                # reads [s + 3 g_lo, s + 3 g_lo + 12 nchunk), writes 16 per chunk
+                assert s + 3 * g_lo + 12 * nchunk <= e
+                assert 4 * g_lo + 16 * nchunk <= 4 * ngroups
+            left = g_hi - (g_lo + 4 * nchunk)
+            assert 0 <= left <= 4
+            for lane in range(left):
+                g = g_lo + 4 * nchunk + lane
+                rem = length - 3 * g
+                assert rem > 0 and 3 * g + min(rem, 3) <= length
+                seen[b][g] += 1
     for b in range(nbuf):
         assert (seen[b] == 1).all(), (b, seen[b])
     assert (owners == 1).all(), np.nonzero(owners != 1)
 
 
-def trace_decode(in_off, nbuf, grid):
-    nwaves = grid * WAVES_PER_BLOCK
+def trace_decode(in_off, nbuf, grid, tile):
     seen = [np.zeros((int(in_off[b + 1] - in_off[b]) + 3) // 4, dtype=np.int64) for b in range(nbuf)]
     tails = np.zeros(nbuf, dtype=np.int64)
     empty_owner = np.zeros(nbuf, dtype=np.int64)
-    for blk in range(grid):
-        for wv in range(WAVES_PER_BLOCK):
-            w = logical_block(blk, grid) * WAVES_PER_BLOCK + wv
-            lo, hi, b0, last = wave_span(in_off, nbuf, 1024, w, nwaves)
-            if lo >= hi and not last:
+    for lo, hi, b0, last in tiles(in_off, nbuf, tile, grid):
+        for b in range(b0, nbuf):
+            s, e = int(in_off[b]), int(in_off[b + 1])
+            if s >= hi and not (last and s == hi):
+                break
+            length = e - s
+            if length == 0:
+                if s >= lo:
+                    empty_owner[b] += 1
                 continue
-            for b in range(b0, nbuf):
-                s, e = int(in_off[b]), int(in_off[b + 1])
-                if s >= hi and not (last and s == hi):
-                    break
-                length = e - s
-                if length == 0:
-                    if s >= lo:
-                        empty_owner[b] += 1
-                    continue
-                nq, nbody = (length + 3) >> 2, (length - 1) >> 2
-                q_lo = 0 if s >= lo else (lo - s + 3) >> 2
-                q_hi = min(0 if hi <= s else (hi - s + 3) >> 2, nq)
-                if q_lo >= q_hi:
-                    continue
-                q_body = min(q_hi, nbody)
-                nchunk = (q_body - q_lo) >> 2 if q_body > q_lo else 0
-                if nchunk:
-                    seen[b][q_lo: q_lo + 4 * nchunk] += 1
-                    assert 4 * q_lo + 16 * nchunk <= 4 * nbody < length
-                    assert 3 * q_lo + 12 * nchunk <= 3 * (length // 4)
-                left = q_hi - (q_lo + 4 * nchunk)
-                assert 0 <= left <= 4
-                for lane in range(left):
-                    q = q_lo + 4 * nchunk + lane
-                    seen[b][q] += 1
-                    if q < nbody:
-                        assert 4 * q + 4 <= length and 3 * q + 3 <= 3 * (length // 4)
-                    else:
-                        assert q == nq - 1
-                        tails[b] += 1
+            nq, nbody = (length + 3) >> 2, (length - 1) >> 2
+            q_lo = 0 if s >= lo else (lo - s + 3) >> 2
+            q_hi = min(0 if hi <= s else (hi - s + 3) >> 2, nq)
+            if q_lo >= q_hi:
+                continue
+            q_body = min(q_hi, nbody)
+            nchunk = (q_body - q_lo) >> 2 if q_body > q_lo else 0
+            if nchunk:
+                seen[b][q_lo: q_lo + 4 * nchunk] += 1
+                assert 4 * q_lo + 16 * nchunk <= 4 * nbody < length
+                assert 3 * q_lo + 12 * nchunk <= 3 * (length // 4)
+            left = q_hi - (q_lo + 4 * nchunk)
+            assert 0 <= left <= 4
+            for lane in range(left):
+                q = q_lo + 4 * nchunk + lane
+                seen[b][q] += 1
+                if q < nbody:
+                    assert 4 * q + 4 <= length and 3 * q + 3 <= 3 * (length // 4)
+                else:
+                    assert q == nq - 1
+                    tails[b] += 1
     for b in range(nbuf):
         assert (seen[b] == 1).all(), (b, seen[b])
         n = int(in_off[b + 1] - in_off[b])
@@ -149,18 +149,22 @@ def _layouts():
     yield workloads.offsets(lens)
 
 
-@pytest.mark.parametrize("grid", [1, 2, 3, 8, 16, 40])
-def test_encode_partition(grid):
+# the kernels use 32 wave rounds per tile (24576 bytes for encode, 32768
+# characters for decode); smaller tiles exercise more tile boundaries here
+@pytest.mark.parametrize("grid,tile", [(1, 24576), (2, 768), (3, 1536), (8, 24576), (16, 768),
+                                       (40, 3072)])
+def test_encode_partition(grid, tile):
     for in_off in _layouts():
         nbuf = in_off.size - 1
         out_off = workloads.offsets(4 * ((np.diff(in_off) + 2) // 3))
-        trace_encode(in_off, out_off, nbuf, grid)
+        trace_encode(in_off, out_off, nbuf, grid, tile)
 
 
-@pytest.mark.parametrize("grid", [1, 2, 3, 8, 16, 40])
-def test_decode_partition(grid):
+@pytest.mark.parametrize("grid,tile", [(1, 32768), (2, 1024), (3, 2048), (8, 32768), (16, 1024),
+                                       (40, 4096)])
+def test_decode_partition(grid, tile):
     for in_off in _layouts():
-        trace_decode(in_off, in_off.size - 1, grid)
+        trace_decode(in_off, in_off.size - 1, grid, tile)
 
 
 def test_single_buffer_heads_align_outputs():
