@@ -72,7 +72,7 @@ DecMap make_dec(const char *alphabet)
 // Launch shapes per operation (encode, decode, encode_batch, decode_batch);
 // the defaults are the autotuner's choices on MI355X (1 GiB single buffers,
 // 1 GiB log-uniform ragged batches).
-Shape g_shape[4] = {{4, 2, 1}, {4, 2, 1}, {2, 4, 1}, {2, 4, 1}};
+Shape g_shape[4] = {{4, 1, 1}, {8, 1, 1}, {4, 2, 1}, {4, 2, 1}};
 std::mutex g_mu;
 
 Shape shape_of(int op)

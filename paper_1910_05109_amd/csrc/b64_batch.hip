@@ -9,7 +9,7 @@
 // a distant span of its own (which costs DRAM row locality: about a fifth of
 // the bandwidth on MI355X).  A tile covers the groups (encode) or quanta
 // (decode) whose first byte lies in it, buffer after buffer, with consecutive
-// lanes on consecutive chunks.  The 64 lanes of a wave look up the first
+// lanes on consecutive chunks of a per-buffer grid aligned for the stores.  The 64 lanes of a wave look up the first
 // buffer of 64 of its tiles at once (one binary search per lane over in_off),
 // so the lookup costs one search latency per 64 tiles.  No work queue and no
 // atomics beyond the first-invalid minimum.
@@ -72,14 +72,27 @@ struct TileWalk {
 };
 
 // Encode the groups whose first byte lies in [lo, hi), starting at buffer b0.
+// Per buffer the chunk grid starts `h` groups in (h < 4), so that chunk
+// outputs are 16-byte aligned whenever the buffer's output is 4-byte aligned
+// (a 16-byte store that straddles a 16-byte boundary costs two); the groups
+// before the tile's first chunk and after its last one -- at most seven,
+// including the buffer's partial last group -- go to lanes 0..6, one each.
 template <int U, bool NT>
 __device__ void encode_tile(const uint8_t *__restrict__ src, const int64_t *__restrict__ in_off,
                             int64_t nbuf, uint8_t *__restrict__ dst,
                             const int64_t *__restrict__ out_off, int64_t *__restrict__ out_len,
                             const uint8_t *a, int64_t lo, int64_t hi, int64_t b0, bool last, int lane)
 {
+    if (b0 >= nbuf) return;
+    // offsets of the next buffer, loaded one iteration ahead
+    int64_t nx_s = in_off[b0], nx_e = in_off[b0 + 1], nx_o = out_off[b0];
     for (int64_t b = b0; b < nbuf; ++b) {
-        const int64_t s = in_off[b], e = in_off[b + 1];
+        const int64_t s = nx_s, e = nx_e, ob_off = nx_o;
+        if (b + 1 < nbuf) {
+            nx_s = e;
+            nx_e = in_off[b + 2];
+            nx_o = out_off[b + 1];
+        }
         if (s >= hi && !(last && s == hi)) break;
         const int64_t len = e - s;
         const int64_t ngroups = (len + 2) / 3, nfull = len / 3;
@@ -88,28 +101,26 @@ __device__ void encode_tile(const uint8_t *__restrict__ src, const int64_t *__re
         int64_t g_hi = hi <= s ? 0 : (hi - s + 2) / 3;
         if (g_hi > ngroups) g_hi = ngroups;
         if (g_lo >= g_hi) continue;
+        uint8_t *ob = dst + ob_off;
+        const uint64_t oa = (uint64_t)(uintptr_t)ob;
+        const int64_t h = (oa & 3) ? 0 : (int64_t)(((16 - (oa & 15)) & 15) >> 2);
         const int64_t g_full = g_hi < nfull ? g_hi : nfull;
-        const int64_t nchunk = g_full > g_lo ? (g_full - g_lo) >> 2 : 0;
-        const uint8_t *sp = src + s + 3 * g_lo;
-        uint8_t *dp = dst + out_off[b] + 4 * g_lo;
-        for (int64_t k0 = 0; k0 < nchunk; k0 += 64 * U) {
-            u32x3 in[U];
-#pragma unroll
-            for (int j = 0; j < U; ++j) {
-                const int64_t k = k0 + j * 64 + lane;
-                if (k < nchunk) in[j] = load12<NT>(sp + 12 * k);
-            }
-#pragma unroll
-            for (int j = 0; j < U; ++j) {
-                const int64_t k = k0 + j * 64 + lane;
-                if (k < nchunk) store16<NT>(dp + 16 * k, enc_chunk(in[j], a));
-            }
-        }
-        // at most three whole groups and the buffer's partial last group
-        const int64_t g = g_lo + 4 * nchunk + lane;
-        if (lane < 4 && g < g_hi) {
+        const int64_t j_lo = g_lo <= h ? 0 : (g_lo - h + 3) >> 2;
+        const int64_t j_hi = g_full <= h ? 0 : (g_full - h) >> 2;
+        const int64_t nchunk = j_hi > j_lo ? j_hi - j_lo : 0;
+        const int64_t c_first = nchunk ? h + 4 * j_lo : g_lo;   // first chunked group
+        const uint8_t *sp = src + s + 3 * c_first;
+        uint8_t *dp = ob + 4 * c_first;
+        // rounds of 64*U chunks; all but the last are complete
+        const int64_t nround = nchunk / (64 * U);
+        enc_stream<U, NT>(sp, dp, lane, 64, 64 * U, nround, a);
+        enc_round_tail<U, NT>(sp, dp, lane + nround * 64 * U, 64, a, nchunk);
+        // leftover groups: [g_lo, c_first) then [c_first + 4*nchunk, g_hi)
+        const int64_t lead = c_first - g_lo;
+        const int64_t g = lane < lead ? g_lo + lane : c_first + 4 * nchunk + (lane - lead);
+        if (lane < 7 && g < g_hi) {
             const int64_t rem = len - 3 * g;
-            enc_scalar(src + s + 3 * g, rem < 3 ? rem : 3, dst + out_off[b] + 4 * g, a);
+            enc_scalar(src + s + 3 * g, rem < 3 ? rem : 3, ob + 4 * g, a);
         }
     }
 }
@@ -138,9 +149,12 @@ __global__ __launch_bounds__(kThreads) void k_encode_batch(
 }
 
 // Decode the quanta whose first character lies in [lo, hi), starting at
-// buffer b0.  The body of a buffer is its quanta but the last; chunks of four
-// body quanta go to lanes, then lanes 0..3 take up to three leftover body
-// quanta and the last quantum (through dec_tail).
+// buffer b0.  The body of a buffer is its quanta but the last.  Per buffer the
+// chunk grid starts `h` body quanta in (h < 4, 3h = -out mod 4), so that chunk
+// outputs are 4-byte aligned; chunks of four body quanta go to lanes, and the
+// quanta before the tile's first chunk and after its last one -- at most
+// three leading and three trailing body quanta and the last quantum (through
+// dec_tail) -- go to lanes 0..6, one each.
 template <int U, bool NT>
 __device__ void decode_tile(const uint8_t *__restrict__ src, const int64_t *__restrict__ in_off,
                             int64_t nbuf, uint8_t *__restrict__ dst,
@@ -148,8 +162,16 @@ __device__ void decode_tile(const uint8_t *__restrict__ src, const int64_t *__re
                             int64_t *__restrict__ first_bad, const uint8_t *m, int64_t lo,
                             int64_t hi, int64_t b0, bool last, int lane)
 {
+    if (b0 >= nbuf) return;
+    // offsets of the next buffer, loaded one iteration ahead
+    int64_t nx_s = in_off[b0], nx_e = in_off[b0 + 1], nx_o = out_off[b0];
     for (int64_t b = b0; b < nbuf; ++b) {
-        const int64_t s = in_off[b], e = in_off[b + 1];
+        const int64_t s = nx_s, e = nx_e, ob_off = nx_o;
+        if (b + 1 < nbuf) {
+            nx_s = e;
+            nx_e = in_off[b + 2];
+            nx_o = out_off[b + 1];
+        }
         if (s >= hi && !(last && s == hi)) break;
         const int64_t len = e - s;
         if (len == 0) {
@@ -162,39 +184,37 @@ __device__ void decode_tile(const uint8_t *__restrict__ src, const int64_t *__re
         int64_t q_hi = hi <= s ? 0 : (hi - s + 3) >> 2;
         if (q_hi > nq) q_hi = nq;
         if (q_lo >= q_hi) continue;
+        uint8_t *ob = dst + ob_off;
+        const int64_t h = (int64_t)((uint64_t)(uintptr_t)ob & 3);
         const int64_t q_body = q_hi < nbody ? q_hi : nbody;
-        const int64_t nchunk = q_body > q_lo ? (q_body - q_lo) >> 2 : 0;
-        const uint8_t *sp = src + s + 4 * q_lo;
-        uint8_t *dp = dst + out_off[b] + 3 * q_lo;
+        const int64_t j_lo = q_lo <= h ? 0 : (q_lo - h + 3) >> 2;
+        const int64_t j_hi = q_body <= h ? 0 : (q_body - h) >> 2;
+        const int64_t nchunk = j_hi > j_lo ? j_hi - j_lo : 0;
+        const int64_t c_first = nchunk ? h + 4 * j_lo : q_lo;   // first chunked quantum
+        const uint8_t *sp = src + s + 4 * c_first;
+        uint8_t *dp = ob + 3 * c_first;
         uint32_t err = 0;
-        for (int64_t k0 = 0; k0 < nchunk; k0 += 64 * U) {
-            u32x4 in[U];
-#pragma unroll
-            for (int j = 0; j < U; ++j) {
-                const int64_t k = k0 + j * 64 + lane;
-                if (k < nchunk) in[j] = load16<NT>(sp + 16 * k);
-            }
-#pragma unroll
-            for (int j = 0; j < U; ++j) {
-                const int64_t k = k0 + j * 64 + lane;
-                if (k < nchunk) store12<NT>(dp + 12 * k, dec_chunk(in[j], m, err));
-            }
-        }
+        // rounds of 64*U chunks; all but the last are complete
+        const int64_t nround = nchunk / (64 * U);
+        dec_stream<U, NT>(sp, dp, lane, 64, 64 * U, nround, m, err);
+        dec_round_tail<U, NT>(sp, dp, lane + nround * 64 * U, 64, m, err, nchunk);
         if (__ballot(err & 0x80)) {
             if (err & 0x80) {
                 for (int64_t k = lane; k < nchunk; k += 64) {
                     const int64_t bad = dec_check_inner(sp + 16 * k, 16, m);
                     if (bad >= 0) {
-                        atomic_min_i64(first_bad + b, 4 * q_lo + 16 * k + bad);
+                        atomic_min_i64(first_bad + b, 4 * c_first + 16 * k + bad);
                         break;
                     }
                 }
             }
         }
-        const int64_t q = q_lo + 4 * nchunk + lane;
-        if (lane < 4 && q < q_hi) {
+        // leftover quanta: [q_lo, c_first) then [c_first + 4*nchunk, q_hi)
+        const int64_t lead = c_first - q_lo;
+        const int64_t q = lane < lead ? q_lo + lane : c_first + 4 * nchunk + (lane - lead);
+        if (lane < 7 && q < q_hi) {
             const uint8_t *qp = src + s + 4 * q;
-            uint8_t *qo = dst + out_off[b] + 3 * q;
+            uint8_t *qo = ob + 3 * q;
             if (q < nbody) {
                 uint32_t qerr = 0;
                 const uint32_t v = dec_quantum(*(const u32a1 *)qp, m, qerr);

@@ -255,4 +255,130 @@ __device__ __forceinline__ void atomic_min_i64(int64_t *p, int64_t v)
     atomicMin((unsigned long long *)p, (unsigned long long)v);
 }
 
+// `nrounds` complete rounds of lane chunks: round r holds chunks
+// c0 + r*rstep + j*stride, j < U, all in range.  Software-pipelined: the loads
+// of round r+1 are issued before round r is computed and stored.  On gfx9 the
+// vector-memory counter covers loads and stores alike, so waiting for a load
+// also waits for every store issued before it; issuing the next loads first
+// keeps them ahead of the stores, and no load ever waits for a store.  The
+// straight-line rounds (no per-chunk guards) let the compiler wait for each
+// chunk's own load only.
+template <int U, bool NT>
+__device__ __forceinline__ void enc_load(u32x3 (&v)[U], const uint8_t *s0, int64_t c, int64_t stride)
+{
+#pragma unroll
+    for (int j = 0; j < U; ++j) v[j] = load12<NT>(s0 + 12 * (c + j * stride));
+}
+template <int U, bool NT>
+__device__ __forceinline__ void enc_store(const u32x3 (&v)[U], uint8_t *d0, int64_t c, int64_t stride,
+                                          const uint8_t *tab)
+{
+#pragma unroll
+    for (int j = 0; j < U; ++j) store16<NT>(d0 + 16 * (c + j * stride), enc_chunk(v[j], tab));
+}
+
+template <int U, bool NT>
+__device__ __forceinline__ void enc_stream(const uint8_t *s0, uint8_t *d0, int64_t c0, int64_t stride,
+                                           int64_t rstep, int64_t nrounds, const uint8_t *tab)
+{
+    if (nrounds <= 0) return;
+    u32x3 A[U], B[U];                 // rounds alternate between two register sets
+    enc_load<U, NT>(A, s0, c0, stride);
+    int64_t r = 0;
+    for (; r + 2 < nrounds; r += 2) {
+        enc_load<U, NT>(B, s0, c0 + rstep, stride);
+        enc_store<U, NT>(A, d0, c0, stride, tab);
+        enc_load<U, NT>(A, s0, c0 + 2 * rstep, stride);
+        enc_store<U, NT>(B, d0, c0 + rstep, stride, tab);
+        c0 += 2 * rstep;
+    }
+    if (r + 1 < nrounds) {
+        enc_load<U, NT>(B, s0, c0 + rstep, stride);
+        enc_store<U, NT>(A, d0, c0, stride, tab);
+        enc_store<U, NT>(B, d0, c0 + rstep, stride, tab);
+    } else {
+        enc_store<U, NT>(A, d0, c0, stride, tab);
+    }
+}
+
+// The last, partial round: only chunks below nch are stored.  Lanes past the
+// end load the round's last in-range chunk again instead of skipping the load,
+// so the loads stay outside any branch and the compiler waits for each load
+// alone rather than for every earlier store.
+template <int U, bool NT>
+__device__ __forceinline__ void enc_round_tail(const uint8_t *s0, uint8_t *d0, int64_t c0,
+                                               int64_t stride, const uint8_t *tab, int64_t nch)
+{
+    if (nch <= 0) return;
+    u32x3 in[U];
+#pragma unroll
+    for (int j = 0; j < U; ++j) {
+        const int64_t c = c0 + j * stride;
+        in[j] = load12<NT>(s0 + 12 * (c < nch ? c : nch - 1));
+    }
+#pragma unroll
+    for (int j = 0; j < U; ++j) {
+        const int64_t c = c0 + j * stride;
+        if (c < nch) store16<NT>(d0 + 16 * c, enc_chunk(in[j], tab));
+    }
+}
+
+template <int U, bool NT>
+__device__ __forceinline__ void dec_load(u32x4 (&v)[U], const uint8_t *s0, int64_t c, int64_t stride)
+{
+#pragma unroll
+    for (int j = 0; j < U; ++j) v[j] = load16<NT>(s0 + 16 * (c + j * stride));
+}
+template <int U, bool NT>
+__device__ __forceinline__ void dec_store(const u32x4 (&v)[U], uint8_t *d0, int64_t c, int64_t stride,
+                                          const uint8_t *map, uint32_t &err)
+{
+#pragma unroll
+    for (int j = 0; j < U; ++j) store12<NT>(d0 + 12 * (c + j * stride), dec_chunk(v[j], map, err));
+}
+
+template <int U, bool NT>
+__device__ __forceinline__ void dec_stream(const uint8_t *s0, uint8_t *d0, int64_t c0, int64_t stride,
+                                           int64_t rstep, int64_t nrounds, const uint8_t *map,
+                                           uint32_t &err)
+{
+    if (nrounds <= 0) return;
+    u32x4 A[U], B[U];                 // rounds alternate between two register sets
+    dec_load<U, NT>(A, s0, c0, stride);
+    int64_t r = 0;
+    for (; r + 2 < nrounds; r += 2) {
+        dec_load<U, NT>(B, s0, c0 + rstep, stride);
+        dec_store<U, NT>(A, d0, c0, stride, map, err);
+        dec_load<U, NT>(A, s0, c0 + 2 * rstep, stride);
+        dec_store<U, NT>(B, d0, c0 + rstep, stride, map, err);
+        c0 += 2 * rstep;
+    }
+    if (r + 1 < nrounds) {
+        dec_load<U, NT>(B, s0, c0 + rstep, stride);
+        dec_store<U, NT>(A, d0, c0, stride, map, err);
+        dec_store<U, NT>(B, d0, c0 + rstep, stride, map, err);
+    } else {
+        dec_store<U, NT>(A, d0, c0, stride, map, err);
+    }
+}
+
+template <int U, bool NT>
+__device__ __forceinline__ void dec_round_tail(const uint8_t *s0, uint8_t *d0, int64_t c0,
+                                               int64_t stride, const uint8_t *map, uint32_t &err,
+                                               int64_t nch)
+{
+    if (nch <= 0) return;
+    u32x4 in[U];
+#pragma unroll
+    for (int j = 0; j < U; ++j) {
+        const int64_t c = c0 + j * stride;
+        in[j] = load16<NT>(s0 + 16 * (c < nch ? c : nch - 1));
+    }
+#pragma unroll
+    for (int j = 0; j < U; ++j) {
+        const int64_t c = c0 + j * stride;
+        if (c < nch) store12<NT>(d0 + 12 * c, dec_chunk(in[j], map, err));
+    }
+}
+
 }  // namespace b64hip

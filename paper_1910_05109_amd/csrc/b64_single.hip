@@ -27,19 +27,12 @@ __global__ __launch_bounds__(kThreads) void k_encode(const uint8_t *__restrict__
     uint8_t *d0 = dst + 4 * head;
     const int64_t T = (int64_t)gridDim.x * kThreads;
     const int64_t t = logical_block() * kThreads + threadIdx.x;
-    for (int64_t c0 = t; c0 < nch; c0 += U * T) {
-        u32x3 in[U];
-#pragma unroll
-        for (int j = 0; j < U; ++j) {
-            const int64_t c = c0 + j * T;
-            if (c < nch) in[j] = load12<NT>(s0 + 12 * c);
-        }
-#pragma unroll
-        for (int j = 0; j < U; ++j) {
-            const int64_t c = c0 + j * T;
-            if (c < nch) store16<NT>(d0 + 16 * c, enc_chunk(in[j], a));
-        }
-    }
+    // rounds of U*T chunks; all but the last are complete
+    const int64_t nfull = nch / (U * T);
+    int64_t c0 = t;
+    enc_stream<U, NT>(s0, d0, c0, T, U * T, nfull, a);
+    c0 += nfull * U * T;
+    enc_round_tail<U, NT>(s0, d0, c0, T, a, nch);
     if (t < head) enc_scalar(src + 3 * t, 3, dst + 4 * t, a);
     if (t == kThreads - 1) {
         const int64_t g = head + 4 * nch;
@@ -75,19 +68,12 @@ __global__ __launch_bounds__(kThreads) void k_decode(const uint8_t *__restrict__
     const int64_t T = (int64_t)gridDim.x * kThreads;
     const int64_t t = logical_block() * kThreads + threadIdx.x;
     uint32_t err = 0;
-    for (int64_t c0 = t; c0 < nch; c0 += U * T) {
-        u32x4 in[U];
-#pragma unroll
-        for (int j = 0; j < U; ++j) {
-            const int64_t c = c0 + j * T;
-            if (c < nch) in[j] = load16<NT>(s0 + 16 * c);
-        }
-#pragma unroll
-        for (int j = 0; j < U; ++j) {
-            const int64_t c = c0 + j * T;
-            if (c < nch) store12<NT>(d0 + 12 * c, dec_chunk(in[j], m, err));
-        }
-    }
+    // rounds of U*T chunks; all but the last are complete
+    const int64_t nfull = nch / (U * T);
+    int64_t c0 = t;
+    dec_stream<U, NT>(s0, d0, c0, T, U * T, nfull, m, err);
+    c0 += nfull * U * T;
+    dec_round_tail<U, NT>(s0, d0, c0, T, m, err, nch);
     // One test per lane for its whole share (bit 7 is set only by kBad).
     if (__ballot(err & 0x80)) {
         if (err & 0x80) {

@@ -5,7 +5,9 @@ waves grid-stride, and let each wave walk the buffers a tile touches.  This
 test re-traces that index arithmetic on the host for many layouts, tile sizes
 and grid sizes and checks, before any launch, that:
   - every group (encode) / quantum (decode) of every buffer is handled exactly
-    once, by a lane chunk or by one of the (at most four) leftover lanes;
+    once, by a lane chunk or by one of the (at most seven) leftover lanes;
+  - chunk stores start 16-byte aligned (encode, when the output is 4-byte
+    aligned) or 4-byte aligned (decode);
   - every read stays inside its buffer and every write inside its output
     capacity;
   - exactly one wave writes each encode out_len, and exactly one lane runs the
@@ -56,7 +58,7 @@ def tiles(in_off, nbuf, tile, grid):
                 k += 1
 
 
-def trace_encode(in_off, out_off, nbuf, grid, tile):
+def trace_encode(in_off, out_off, nbuf, grid, tile, dst_base=0):
     seen = [np.zeros((int(in_off[b + 1] - in_off[b]) + 2) // 3, dtype=np.int64) for b in range(nbuf)]
     owners = np.zeros(nbuf, dtype=np.int64)
     for lo, hi, b0, last in tiles(in_off, nbuf, tile, grid):
@@ -73,26 +75,36 @@ def trace_encode(in_off, out_off, nbuf, grid, tile):
             g_hi = min(g_hi, ngroups)
             if g_lo >= g_hi:
                 continue
+            oa = dst_base + int(out_off[b])
+            h = 0 if oa & 3 else ((16 - (oa & 15)) & 15) >> 2
             g_full = min(g_hi, nfull)
-            nchunk = (g_full - g_lo) >> 2 if g_full > g_lo else 0
+            j_lo = 0 if g_lo <= h else (g_lo - h + 3) >> 2
+            j_hi = 0 if g_full <= h else (g_full - h) >> 2
+            nchunk = max(j_hi - j_lo, 0)
+            c_first = h + 4 * j_lo if nchunk else g_lo
             if nchunk:
-                seen[b][g_lo: g_lo + 4 * nchunk] += 1
-                # reads [s + 3 g_lo, s + 3 g_lo + 12 nchunk), writes 16 per chunk
-                assert s + 3 * g_lo + 12 * nchunk <= e
-                assert 4 * g_lo + 16 * nchunk <= 4 * ngroups
-            left = g_hi - (g_lo + 4 * nchunk)
-            assert 0 <= left <= 4
-            for lane in range(left):
-                g = g_lo + 4 * nchunk + lane
-                rem = length - 3 * g
-                assert rem > 0 and 3 * g + min(rem, 3) <= length
-                seen[b][g] += 1
+                seen[b][c_first: c_first + 4 * nchunk] += 1
+                # reads [s + 3 c_first, + 12 nchunk), writes 16 per chunk, aligned
+                assert s + 3 * c_first + 12 * nchunk <= e
+                assert 4 * c_first + 16 * nchunk <= 4 * ngroups
+                if oa % 4 == 0:
+                    assert (oa + 4 * c_first) % 16 == 0
+            lead = c_first - g_lo
+            trail = g_hi - (c_first + 4 * nchunk)
+            assert lead >= 0 and trail >= 0 and lead + trail <= 7
+            for lane in range(7):
+                g = g_lo + lane if lane < lead else c_first + 4 * nchunk + (lane - lead)
+                if g < g_hi:
+                    rem = length - 3 * g
+                    assert rem > 0 and 3 * g + min(rem, 3) <= length
+                    seen[b][g] += 1
     for b in range(nbuf):
         assert (seen[b] == 1).all(), (b, seen[b])
     assert (owners == 1).all(), np.nonzero(owners != 1)
 
 
-def trace_decode(in_off, nbuf, grid, tile):
+def trace_decode(in_off, nbuf, grid, tile, dst_base=0):
+    out_off = workloads.offsets(3 * (np.diff(in_off) // 4))
     seen = [np.zeros((int(in_off[b + 1] - in_off[b]) + 3) // 4, dtype=np.int64) for b in range(nbuf)]
     tails = np.zeros(nbuf, dtype=np.int64)
     empty_owner = np.zeros(nbuf, dtype=np.int64)
@@ -111,16 +123,25 @@ def trace_decode(in_off, nbuf, grid, tile):
             q_hi = min(0 if hi <= s else (hi - s + 3) >> 2, nq)
             if q_lo >= q_hi:
                 continue
+            oa = dst_base + int(out_off[b])
+            h = oa & 3
             q_body = min(q_hi, nbody)
-            nchunk = (q_body - q_lo) >> 2 if q_body > q_lo else 0
+            j_lo = 0 if q_lo <= h else (q_lo - h + 3) >> 2
+            j_hi = 0 if q_body <= h else (q_body - h) >> 2
+            nchunk = max(j_hi - j_lo, 0)
+            c_first = h + 4 * j_lo if nchunk else q_lo
             if nchunk:
-                seen[b][q_lo: q_lo + 4 * nchunk] += 1
-                assert 4 * q_lo + 16 * nchunk <= 4 * nbody < length
-                assert 3 * q_lo + 12 * nchunk <= 3 * (length // 4)
-            left = q_hi - (q_lo + 4 * nchunk)
-            assert 0 <= left <= 4
-            for lane in range(left):
-                q = q_lo + 4 * nchunk + lane
+                seen[b][c_first: c_first + 4 * nchunk] += 1
+                assert 4 * c_first + 16 * nchunk <= 4 * nbody < length
+                assert 3 * c_first + 12 * nchunk <= 3 * (length // 4)
+                assert (oa + 3 * c_first) % 4 == 0
+            lead = c_first - q_lo
+            trail = q_hi - (c_first + 4 * nchunk)
+            assert lead >= 0 and trail >= 0 and lead + trail <= 7
+            for lane in range(7):
+                q = q_lo + lane if lane < lead else c_first + 4 * nchunk + (lane - lead)
+                if q >= q_hi:
+                    continue
                 seen[b][q] += 1
                 if q < nbody:
                     assert 4 * q + 4 <= length and 3 * q + 3 <= 3 * (length // 4)
@@ -157,14 +178,16 @@ def test_encode_partition(grid, tile):
     for in_off in _layouts():
         nbuf = in_off.size - 1
         out_off = workloads.offsets(4 * ((np.diff(in_off) + 2) // 3))
-        trace_encode(in_off, out_off, nbuf, grid, tile)
+        for dst_base in (0, 1, 4, 8, 12):
+            trace_encode(in_off, out_off, nbuf, grid, tile, dst_base)
 
 
 @pytest.mark.parametrize("grid,tile", [(1, 32768), (2, 1024), (3, 2048), (8, 32768), (16, 1024),
                                        (40, 4096)])
 def test_decode_partition(grid, tile):
     for in_off in _layouts():
-        trace_decode(in_off, in_off.size - 1, grid, tile)
+        for dst_base in (0, 1, 2, 3):
+            trace_decode(in_off, in_off.size - 1, grid, tile, dst_base)
 
 
 def test_single_buffer_heads_align_outputs():
