@@ -14,12 +14,15 @@ namespace b64hip {
 struct Shape { int unroll, bpc, nt; };
 
 // Blocks for a grid-stride launch over `nch` lane chunks: enough to cover
-// them with `unroll` chunks per lane, at most `bpc` per CU, a whole number
-// per XCD.
+// them with `unroll` chunks per lane if that takes at most 16 per CU, else
+// `bpc` per CU; a whole number per XCD.
 int64_t grid_for(int64_t nch, Shape sh, int cus);
 
 hipError_t launch_encode(const uint8_t *src, int64_t n, uint8_t *dst, const EncTab &tab, Shape sh,
                          int cus, hipStream_t stream);
+// Single-buffer decode (k_decode only): *first_bad must hold kNoError before
+// it; afterwards it holds the first invalid offset or still kNoError, and
+// *out_len the decoded length when the input is valid.
 hipError_t launch_decode(const uint8_t *src, int64_t n, uint8_t *dst, const DecMap &map,
                          int64_t *out_len, int64_t *first_bad, Shape sh, int cus,
                          hipStream_t stream);

@@ -46,8 +46,12 @@ __global__ __launch_bounds__(kThreads) void k_encode(const uint8_t *__restrict__
 // lane chunk c covers characters [4*head + 16c, +16) and bytes
 // [3*head + 12c, +12).  Threads t < head decode one head quantum each; the
 // last thread runs dec_tail over the (at most three) body quanta left after
-// the chunks and the last quantum.  first_bad must hold kNoError before the
-// launch; out_len is written only when the tail is valid.
+// the chunks and the last quantum.
+// first_bad must hold kNoError before the launch; invalid offsets are
+// published with an atomic minimum on it.  out_len is written only when the
+// tail is valid.  (A last-block-finishes protocol would save the status
+// launches, but its device-scope fence at the end of every block writes back
+// L2 on this multi-XCD part, which costs far more than a launch.)
 template <int U, bool NT>
 __global__ __launch_bounds__(kThreads) void k_decode(const uint8_t *__restrict__ src, int64_t n,
                                                      uint8_t *__restrict__ dst, DecMap map,
@@ -126,11 +130,14 @@ __global__ void k_finish_status(int64_t *out_len, int64_t *first_bad, int64_t co
 int64_t grid_for(int64_t nch, Shape sh, int cus)
 {
     const int64_t per_block = (int64_t)kThreads * sh.unroll;
-    int64_t need = (nch + per_block - 1) / per_block;
-    const int64_t cap = (int64_t)cus * sh.bpc;
-    if (need > cap) need = cap;
-    if (need >= kXcds) need -= need % kXcds;   // a whole number of blocks per XCD
-    return need < 1 ? 1 : need;
+    const int64_t need = (nch + per_block - 1) / per_block;
+    // An input small enough to be covered by up to 16 blocks per CU in a
+    // single round is latency-bound: give it every block it needs, so that all
+    // its loads are in flight at once.  Larger inputs stream with the tuned
+    // number of blocks per CU.
+    int64_t grid = need <= (int64_t)cus * 16 ? need : (int64_t)cus * sh.bpc;
+    if (grid >= kXcds) grid -= grid % kXcds;   // a whole number of blocks per XCD
+    return grid < 1 ? 1 : grid;
 }
 
 hipError_t launch_encode(const uint8_t *src, int64_t n, uint8_t *dst, const EncTab &tab, Shape sh,
