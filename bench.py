@@ -15,7 +15,8 @@ on a bounded sample.
 
 Other modes (--mode): sweep (size sweep 2^k + r), batch (100,000 ragged
 buffers, batched launch vs one launch per buffer), serve (continuous batching
-loop), small (the 3 MiB workload).  Each prints its own JSON lines.
+loop), small (the 3 MiB workload), validate (read-only validation of the
+1 GiB encoding).  Each prints its own JSON lines.
 """
 from __future__ import annotations
 
@@ -418,12 +419,35 @@ def run_serve(args, torch, b64):
     print(json.dumps({"workload": "serving", "sigma": workloads.SERVE_SIGMA, "rows": out}), flush=True)
 
 
+def run_validate(args, torch, b64):
+    """Read-only validation of the 1 GiB workload's encoding, against decode."""
+    n = workloads.SINGLE_1GIB[0]
+    N = 4 * ((n + 2) // 3)
+    x = torch.from_numpy(workloads.random_bytes(workloads.SEED_BASE + 2, n)).cuda()
+    text = b64.encode(x)
+    dec = torch.empty(n + 3, dtype=torch.uint8, device="cuda")
+    st = torch.empty(2, dtype=torch.int64, device="cuda")
+    val = lambda: b64.validate_async(text, status=st)
+    dcd = lambda: b64.decode_async(text, out=dec, status=st)
+    for _ in range(3):
+        val(); dcd()
+    tv = _events_time(torch, val, args.steps)
+    td = _events_time(torch, dcd, args.steps)
+    assert st.cpu().tolist() == [n, -1]
+    res = {"workload": "validate 1 GiB encoding", "n_chars": N,
+           "validate_ms": tv["median"], "validate_gbps_b64": N / tv["median"] / 1e6,
+           "validate_hbm_frac": N / tv["median"] / 1e6 / HBM_PEAK_GBS,
+           "decode_ms": td["median"], "decode_gbps_b64": N / td["median"] / 1e6}
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--mode", default="single", choices=["single", "small", "sweep", "batch", "serve"])
+    ap.add_argument("--mode", default="single",
+                    choices=["single", "small", "sweep", "batch", "serve", "validate"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--cpu-sample", type=int, default=512 << 20)
     ap.add_argument("--cpu-reps", type=int, default=5)
@@ -442,7 +466,7 @@ def main():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
     {"single": run_single, "small": run_small, "sweep": run_sweep, "batch": run_batch,
-     "serve": run_serve}[args.mode](args, torch, b64)
+     "serve": run_serve, "validate": run_validate}[args.mode](args, torch, b64)
 
 
 if __name__ == "__main__":

@@ -82,6 +82,18 @@ int64_t b64_decode_async(const uint8_t *src, int64_t n, uint8_t *dst,
                          int64_t *out_len, int64_t *first_bad,
                          const char *alphabet, hipStream_t stream);
 
+/* Validate src[0..n) as a padded base64 encoding without decoding it: the
+ * characters are read and nothing is written.  Blocking.  Returns what
+ * b64_decode would return -- the decoded length r >= 0 for a valid input,
+ * ~off for an invalid one, or B64_EARG / B64_EHIP -- at about 4/7 of the
+ * memory traffic.  (Section "Decoding": the look-up-table validation.) */
+int64_t b64_validate(const uint8_t *src, int64_t n, const char *alphabet, hipStream_t stream);
+
+/* Validate, asynchronous form; results in device memory as for
+ * b64_decode_async.  Returns 0 or B64_EARG / B64_EHIP.  (Section "Decoding".) */
+int64_t b64_validate_async(const uint8_t *src, int64_t n, int64_t *out_len, int64_t *first_bad,
+                           const char *alphabet, hipStream_t stream);
+
 /* Batched encode of nbuf ragged buffers packed back to back.  Asynchronous.
  * Buffer b is src[in_off[b] .. in_off[b+1]); in_off has nbuf+1 non-decreasing
  * entries.  Output b is written at dst + out_off[b] (capacity
@@ -103,7 +115,7 @@ int64_t b64_decode_batch(const uint8_t *src, const int64_t *in_off, int64_t nbuf
                          int64_t *first_bad, const char *alphabet, hipStream_t stream);
 
 /* Launch shape used by the kernels of operation `op` (0 encode, 1 decode,
- * 2 encode_batch, 3 decode_batch): `unroll` lane chunks in flight per lane
+ * 2 encode_batch, 3 decode_batch, 4 validate): `unroll` lane chunks in flight per lane
  * (1, 2, 4 or 8; a lane chunk is 12 bytes -> 16 characters or back),
  * `blocks_per_cu` workgroups of 256 threads per compute unit (1..64), and
  * `nontemporal` (0 or 1) for streaming loads and stores.  Process-wide; meant

@@ -8,6 +8,8 @@ every step of the codec runs in libb64hip.so.
   decode(s)                -> (uint8 tensor, None) or (None, first_invalid_offset)
   decode_async(s)          -> (out, status) with status = int64[2] on the device:
                               [decoded length or -1, -1 or first invalid offset]
+  validate(s)              -> (decoded length, None) or (None, first_invalid_offset),
+                              reading s only (no output is written)
   encode_batch(src, in_off)-> (dst, out_off, out_len)
   decode_batch(src, in_off)-> (dst, out_off, out_len, first_bad)
 
@@ -24,11 +26,11 @@ from ._lib import B64Error, check, load
 STD = b"ABCDEFGHIJKLMNOPQRSTUVWXYZabcdefghijklmnopqrstuvwxyz0123456789+/"
 URL = b"ABCDEFGHIJKLMNOPQRSTUVWXYZabcdefghijklmnopqrstuvwxyz0123456789-_"
 
-OPS = {"encode": 0, "decode": 1, "encode_batch": 2, "decode_batch": 3}
+OPS = {"encode": 0, "decode": 1, "encode_batch": 2, "decode_batch": 3, "validate": 4}
 
 __all__ = ["STD", "URL", "B64Error", "load", "encoded_len", "decoded_max_len", "encode",
-           "decode", "decode_async", "encode_batch", "decode_batch", "tune_set", "tune_get",
-           "stream_ptr"]
+           "decode", "decode_async", "validate", "validate_async", "encode_batch", "decode_batch",
+           "tune_set", "tune_get", "stream_ptr"]
 
 
 def _torch():
@@ -128,6 +130,29 @@ def decode_async(s, alphabet=STD, out=None, status=None, stream=None):
     check(load().b64_decode_async(s.data_ptr(), n, out.data_ptr(), sp, sp + 8, _alpha(alphabet),
                                   stream_ptr(stream)), "b64_decode_async")
     return out, status
+
+
+def validate(s, alphabet=STD, stream=None):
+    """Blocking, read-only: (decoded length, None) if s is a valid padded
+    encoding, (None, first_invalid_offset) if not."""
+    _check_u8(s, "s")
+    r = check(load().b64_validate(s.data_ptr(), s.numel(), _alpha(alphabet), stream_ptr(stream)),
+              "b64_validate")
+    return (r, None) if r >= 0 else (None, ~r)
+
+
+def validate_async(s, alphabet=STD, status=None, stream=None):
+    """Asynchronous validation; status = int64[2] on the device:
+    [decoded length or -1, -1 or first invalid offset]."""
+    torch = _torch()
+    _check_u8(s, "s")
+    if status is None:
+        status = torch.empty(2, dtype=torch.int64, device=s.device)
+    _check_i64(status, "status")
+    sp = status.data_ptr()
+    check(load().b64_validate_async(s.data_ptr(), s.numel(), sp, sp + 8, _alpha(alphabet),
+                                    stream_ptr(stream)), "b64_validate_async")
+    return status
 
 
 def _validate_layout(src, in_off, dst, out_off, cap_of, what):

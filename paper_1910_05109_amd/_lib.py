@@ -24,6 +24,8 @@ SIGNATURES = {
     "b64_encode": ([_P, _I64, _P, _P, _P], _I64),
     "b64_decode": ([_P, _I64, _P, _P, _P], _I64),
     "b64_decode_async": ([_P, _I64, _P, _P, _P, _P, _P], _I64),
+    "b64_validate": ([_P, _I64, _P, _P], _I64),
+    "b64_validate_async": ([_P, _I64, _P, _P, _P, _P], _I64),
     "b64_encode_batch": ([_P, _P, _I64, _P, _P, _P, _P, _P], _I64),
     "b64_decode_batch": ([_P, _P, _I64, _P, _P, _P, _P, _P, _P], _I64),
     "b64_tune_set": ([_INT, _INT, _INT, _INT], _I64),

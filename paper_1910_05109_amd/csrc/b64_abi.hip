@@ -69,10 +69,11 @@ DecMap make_dec(const char *alphabet)
     return d;
 }
 
-// Launch shapes per operation (encode, decode, encode_batch, decode_batch);
-// the defaults are the autotuner's choices on MI355X (1 GiB single buffers,
-// 1 GiB log-uniform ragged batches).
-Shape g_shape[4] = {{4, 1, 1}, {8, 1, 1}, {4, 2, 1}, {4, 2, 1}};
+// Launch shapes per operation (encode, decode, encode_batch, decode_batch,
+// validate); the defaults are the autotuner's choices on MI355X (1 GiB single
+// buffers, 1 GiB log-uniform ragged batches).
+constexpr int kOps = 5;
+Shape g_shape[kOps] = {{4, 1, 1}, {8, 1, 1}, {4, 2, 1}, {4, 2, 1}, {8, 1, 1}};
 std::mutex g_mu;
 
 Shape shape_of(int op)
@@ -147,6 +148,25 @@ int64_t decode_enqueue(const uint8_t *src, int64_t n, uint8_t *dst, int64_t *out
     return 0;
 }
 
+// Enqueue one validation: reset first_bad, run k_validate, and (with
+// `finish`) turn the raw status into the public form.
+int64_t validate_enqueue(const uint8_t *src, int64_t n, int64_t *out_len, int64_t *first_bad,
+                         const char *alphabet, hipStream_t stream, bool finish)
+{
+    int cus = 0;
+    hipError_t e = cu_count(&cus);
+    if (e != hipSuccess) return hip_fail(e, "device query");
+    e = launch_fill(first_bad, 1, kNoError, stream);
+    if (e != hipSuccess) return hip_fail(e, "fill launch");
+    e = launch_validate(src, n, make_dec(alphabet), out_len, first_bad, shape_of(4), cus, stream);
+    if (e != hipSuccess) return hip_fail(e, "validate launch");
+    if (finish) {
+        e = launch_finish(out_len, first_bad, 1, stream);
+        if (e != hipSuccess) return hip_fail(e, "status launch");
+    }
+    return 0;
+}
+
 }  // namespace
 
 extern "C" {
@@ -167,7 +187,7 @@ const char *b64_last_error(void) { return g_err; }
 
 int64_t b64_tune_set(int op, int unroll, int blocks_per_cu, int nontemporal)
 {
-    if (op < 0 || op > 3) return fail(B64_EARG, "bad op");
+    if (op < 0 || op >= kOps) return fail(B64_EARG, "bad op");
     if (!(unroll == 1 || unroll == 2 || unroll == 4 || unroll == 8))
         return fail(B64_EARG, "unroll must be 1, 2, 4 or 8");
     if (blocks_per_cu < 1 || blocks_per_cu > 64) return fail(B64_EARG, "blocks_per_cu out of range");
@@ -179,7 +199,7 @@ int64_t b64_tune_set(int op, int unroll, int blocks_per_cu, int nontemporal)
 
 int64_t b64_tune_get(int op)
 {
-    if (op < 0 || op > 3) return fail(B64_EARG, "bad op");
+    if (op < 0 || op >= kOps) return fail(B64_EARG, "bad op");
     const Shape s = shape_of(op);
     return (int64_t)s.nt * 10000 + (int64_t)s.unroll * 100 + s.bpc;
 }
@@ -227,6 +247,33 @@ int64_t b64_decode(const uint8_t *src, int64_t n, uint8_t *dst, const char *alph
     if (e != hipSuccess) return hip_fail(e, "stream synchronize");
     const int64_t len = slot->h[0], bad = slot->h[1];
     return bad == kNoError ? len : ~bad;
+}
+
+int64_t b64_validate(const uint8_t *src, int64_t n, const char *alphabet, hipStream_t stream)
+{
+    if (n < 0) return fail(B64_EARG, "negative length");
+    if (n > 0 && !src) return fail(B64_EARG, "null buffer");
+    if (!alphabet_ok(alphabet)) return fail(B64_EARG, kBadAlphabet);
+    StatusSlot *slot = nullptr;
+    hipError_t e = status_slot(&slot);
+    if (e != hipSuccess) return hip_fail(e, "status slot");
+    const int64_t r = validate_enqueue(src, n, slot->d, slot->d + 1, alphabet, stream, false);
+    if (r) return r;
+    e = hipMemcpyAsync(slot->h, slot->d, 2 * sizeof(int64_t), hipMemcpyDeviceToHost, stream);
+    if (e != hipSuccess) return hip_fail(e, "status copy");
+    e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return hip_fail(e, "stream synchronize");
+    const int64_t len = slot->h[0], bad = slot->h[1];
+    return bad == kNoError ? len : ~bad;
+}
+
+int64_t b64_validate_async(const uint8_t *src, int64_t n, int64_t *out_len, int64_t *first_bad,
+                           const char *alphabet, hipStream_t stream)
+{
+    if (n < 0) return fail(B64_EARG, "negative length");
+    if ((n > 0 && !src) || !out_len || !first_bad) return fail(B64_EARG, "null pointer");
+    if (!alphabet_ok(alphabet)) return fail(B64_EARG, kBadAlphabet);
+    return validate_enqueue(src, n, out_len, first_bad, alphabet, stream, true);
 }
 
 int64_t b64_encode_batch(const uint8_t *src, const int64_t *in_off, int64_t nbuf, uint8_t *dst,

@@ -26,6 +26,11 @@ hipError_t launch_encode(const uint8_t *src, int64_t n, uint8_t *dst, const EncT
 hipError_t launch_decode(const uint8_t *src, int64_t n, uint8_t *dst, const DecMap &map,
                          int64_t *out_len, int64_t *first_bad, Shape sh, int cus,
                          hipStream_t stream);
+// Read-only validation (k_validate): *first_bad must hold kNoError before it;
+// afterwards it holds the first invalid offset or still kNoError, and
+// *out_len the decoded length when the input is valid.
+hipError_t launch_validate(const uint8_t *src, int64_t n, const DecMap &map, int64_t *out_len,
+                           int64_t *first_bad, Shape sh, int cus, hipStream_t stream);
 hipError_t launch_fill(int64_t *p, int64_t count, int64_t value, hipStream_t stream);
 hipError_t launch_finish(int64_t *out_len, int64_t *first_bad, int64_t count, hipStream_t stream);
 hipError_t launch_encode_batch(const uint8_t *src, const int64_t *in_off, int64_t nbuf,

@@ -20,7 +20,8 @@ import statistics
 
 import numpy as np
 
-from . import OPS, STD, decode_async, decode_batch, encode, encode_batch, tune_get, tune_set
+from . import (OPS, STD, decode_async, decode_batch, encode, encode_batch, tune_get, tune_set,
+               validate_async)
 
 UNROLLS = (1, 2, 4, 8)
 BLOCKS_PER_CU = (1, 2, 4, 8, 16, 32)
@@ -62,6 +63,9 @@ def _workload(torch, op, nbytes, seed=191005109):
         out = torch.empty(3 * (text.numel() // 4), dtype=torch.uint8, device="cuda")
         st = torch.empty(2, dtype=torch.int64, device="cuda")
         return lambda: decode_async(text, STD, out=out, status=st)
+    if op == "validate":
+        st = torch.empty(2, dtype=torch.int64, device="cuda")
+        return lambda: validate_async(text, STD, status=st)
     # ragged batches: log-uniform lengths in [16, 1 MiB) up to nbytes in total
     lens = []
     total = 0

@@ -33,7 +33,8 @@ def test_header_declares_the_boundary():
     funcs, data = _declared()
     assert set(funcs) == {
         "b64_encoded_len", "b64_decoded_max_len", "b64_encode", "b64_decode", "b64_decode_async",
-        "b64_encode_batch", "b64_decode_batch", "b64_tune_set", "b64_tune_get", "b64_last_error"}
+        "b64_validate", "b64_validate_async", "b64_encode_batch", "b64_decode_batch",
+        "b64_tune_set", "b64_tune_get", "b64_last_error"}
     assert set(data) == {"b64_alphabet_std", "b64_alphabet_url"}
 
 
@@ -84,6 +85,9 @@ def test_argument_errors_without_gpu(lib):
     assert lib.b64_decode(fake, 10, fake, with_pad, None) == EARG
     assert lib.b64_decode(fake, -3, fake, std, None) == EARG
     assert lib.b64_decode_async(fake, 10, fake, None, fake, std, None) == EARG
+    assert lib.b64_validate(None, 10, std, None) == EARG
+    assert lib.b64_validate(fake, 10, dup, None) == EARG
+    assert lib.b64_validate_async(fake, 10, fake, None, std, None) == EARG
     assert lib.b64_encode_batch(fake, fake, -1, fake, fake, fake, std, None) == EARG
     assert lib.b64_encode_batch(fake, None, 3, fake, fake, fake, std, None) == EARG
     assert lib.b64_decode_batch(fake, fake, 3, fake, fake, fake, None, std, None) == EARG
@@ -100,6 +104,8 @@ def test_tuning_interface(lib):
     assert lib.b64_tune_set(0, 3, 8, 0) == EARG
     assert lib.b64_tune_set(0, 4, 0, 0) == EARG
     assert lib.b64_tune_set(7, 4, 8, 0) == EARG
+    assert lib.b64_tune_set(5, 4, 8, 0) == EARG
+    assert lib.b64_tune_get(4) > 0
     assert lib.b64_tune_set(0, 4, 8, 2) == EARG
     assert lib.b64_tune_set(0, 8, 16, 1) == 0
     assert lib.b64_tune_get(0) == 10816
