@@ -16,7 +16,8 @@ on a bounded sample.
 Other modes (--mode): sweep (size sweep 2^k + r), batch (100,000 ragged
 buffers, batched launch vs one launch per buffer), serve (continuous batching
 loop), small (the 3 MiB workload), validate (read-only validation of the
-1 GiB encoding).  Each prints its own JSON lines.
+1 GiB encoding), host (the 1 GiB workload in host memory through the chunked
+host-device pipeline, PCIe included).  Each prints its own JSON lines.
 """
 from __future__ import annotations
 
@@ -441,13 +442,56 @@ def run_validate(args, torch, b64):
     print(json.dumps(res), flush=True)
 
 
+def run_host(args, torch, b64):
+    """The 1 GiB workload starting and ending in host memory, through the
+    chunked host -> device -> host pipeline; PCIe included."""
+    from paper_1910_05109_amd.pipeline import HostPipeline
+    n = workloads.SINGLE_1GIB[0]
+    N = 4 * ((n + 2) // 3)
+    x = workloads.random_bytes(workloads.SEED_BASE + 2, n)
+    text = np.empty(N, dtype=np.uint8)
+    dec = np.empty(n + 3, dtype=np.uint8)
+    res = {"workload": "1 GiB in host memory, pipelined through the GPU", "n_bytes": n, "n_chars": N}
+    with HostPipeline(chunk_bytes=args.chunk_mib << 20, depth=3, host_threads=8) as p:
+        p.encode(x[: 64 << 20], out=text)            # warm-up
+        te = []
+        td = []
+        for _ in range(3):
+            t0 = time.perf_counter()
+            p.encode(x, out=text)
+            te.append(time.perf_counter() - t0)
+            t0 = time.perf_counter()
+            out, bad = p.decode(text, out=dec)
+            td.append(time.perf_counter() - t0)
+            assert bad is None and out.size == n
+    # reference: the same bytes over PCIe with pinned torch copies (no codec)
+    h_in = torch.empty(n, dtype=torch.uint8).pin_memory()
+    h_out = torch.empty(N, dtype=torch.uint8).pin_memory()
+    d_in = torch.empty(n, dtype=torch.uint8, device="cuda")
+    d_out = torch.empty(N, dtype=torch.uint8, device="cuda")
+    t0 = time.perf_counter()
+    d_in.copy_(h_in, non_blocking=True)
+    torch.cuda.synchronize()
+    t_h2d = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    h_out.copy_(d_out, non_blocking=True)
+    torch.cuda.synchronize()
+    t_d2h = time.perf_counter() - t0
+    res.update({"encode_s": min(te), "encode_gbps_b64": N / min(te) / 1e9,
+                "decode_s": min(td), "decode_gbps_b64": N / min(td) / 1e9,
+                "pcie_h2d_gbps": n / t_h2d / 1e9, "pcie_d2h_gbps": N / t_d2h / 1e9,
+                "chunk_mib": args.chunk_mib})
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--mode", default="single",
-                    choices=["single", "small", "sweep", "batch", "serve", "validate"])
+                    choices=["single", "small", "sweep", "batch", "serve", "validate", "host"])
+    ap.add_argument("--chunk-mib", type=int, default=64)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--cpu-sample", type=int, default=512 << 20)
     ap.add_argument("--cpu-reps", type=int, default=5)
@@ -466,7 +510,7 @@ def main():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
     {"single": run_single, "small": run_small, "sweep": run_sweep, "batch": run_batch,
-     "serve": run_serve, "validate": run_validate}[args.mode](args, torch, b64)
+     "serve": run_serve, "validate": run_validate, "host": run_host}[args.mode](args, torch, b64)
 
 
 if __name__ == "__main__":

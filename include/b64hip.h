@@ -114,6 +114,32 @@ int64_t b64_decode_batch(const uint8_t *src, const int64_t *in_off, int64_t nbuf
                          uint8_t *dst, const int64_t *out_off, int64_t *out_len,
                          int64_t *first_bad, const char *alphabet, hipStream_t stream);
 
+/* Host-memory pipeline (an opaque handle).  Encodes or decodes data that
+ * lives in ordinary host memory by cutting it into chunks that stream through
+ * pinned staging, host-to-device copies, the kernels and device-to-host
+ * copies on `depth` streams at once.  The handle owns, until
+ * b64_pipeline_destroy, depth x 2 pinned host buffers and depth x 2 device
+ * buffers of 4/3 x chunk_bytes each (chunk_bytes is rounded up to a multiple
+ * of 1536), and is bound to the HIP device current at creation.  One handle
+ * serves one calling thread at a time.  (Section "Experiments": large inputs
+ * are best processed in parts.)
+ * b64_pipeline_create: chunk_bytes >= 48, 1 <= depth <= 16,
+ * 1 <= host_threads <= 64 (threads for the host-side copies); returns NULL on
+ * error (message: b64_pipeline_last_error()). */
+typedef struct b64_pipeline b64_pipeline;
+b64_pipeline *b64_pipeline_create(int64_t chunk_bytes, int depth, int host_threads);
+void b64_pipeline_destroy(b64_pipeline *p);
+/* Blocking.  src / dst are HOST pointers (any memory).  Returns
+ * 4*ceil(n/3), or B64_EARG / B64_EHIP.  dst holds b64_encoded_len(n) bytes. */
+int64_t b64_pipeline_encode(b64_pipeline *p, const uint8_t *src, int64_t n, uint8_t *dst,
+                            const char *alphabet);
+/* Blocking.  src / dst are HOST pointers; dst holds b64_decoded_max_len(n)
+ * bytes.  Returns the decoded length, ~off (the first invalid offset of the
+ * whole input, as b64_decode defines it), or B64_EARG / B64_EHIP. */
+int64_t b64_pipeline_decode(b64_pipeline *p, const uint8_t *src, int64_t n, uint8_t *dst,
+                            const char *alphabet);
+const char *b64_pipeline_last_error(void);
+
 /* Launch shape used by the kernels of operation `op` (0 encode, 1 decode,
  * 2 encode_batch, 3 decode_batch, 4 validate): `unroll` lane chunks in flight per lane
  * (1, 2, 4 or 8; a lane chunk is 12 bytes -> 16 characters or back),

@@ -28,6 +28,11 @@ SIGNATURES = {
     "b64_validate_async": ([_P, _I64, _P, _P, _P, _P], _I64),
     "b64_encode_batch": ([_P, _P, _I64, _P, _P, _P, _P, _P], _I64),
     "b64_decode_batch": ([_P, _P, _I64, _P, _P, _P, _P, _P, _P], _I64),
+    "b64_pipeline_create": ([_I64, _INT, _INT], _P),
+    "b64_pipeline_destroy": ([_P], None),
+    "b64_pipeline_encode": ([_P, _P, _I64, _P, _P], _I64),
+    "b64_pipeline_decode": ([_P, _P, _I64, _P, _P], _I64),
+    "b64_pipeline_last_error": ([], ctypes.c_char_p),
     "b64_tune_set": ([_INT, _INT, _INT, _INT], _I64),
     "b64_tune_get": ([_INT], _I64),
     "b64_last_error": ([], ctypes.c_char_p),

@@ -34,6 +34,8 @@ def test_header_declares_the_boundary():
     assert set(funcs) == {
         "b64_encoded_len", "b64_decoded_max_len", "b64_encode", "b64_decode", "b64_decode_async",
         "b64_validate", "b64_validate_async", "b64_encode_batch", "b64_decode_batch",
+        "b64_pipeline_create", "b64_pipeline_destroy", "b64_pipeline_encode",
+        "b64_pipeline_decode", "b64_pipeline_last_error",
         "b64_tune_set", "b64_tune_get", "b64_last_error"}
     assert set(data) == {"b64_alphabet_std", "b64_alphabet_url"}
 
@@ -93,6 +95,12 @@ def test_argument_errors_without_gpu(lib):
     assert lib.b64_decode_batch(fake, fake, 3, fake, fake, fake, None, std, None) == EARG
     assert lib.b64_decode_batch(fake, fake, 3, fake, fake, fake, fake, dup, None) == EARG
     assert b"alphabet" in lib.b64_last_error()
+    assert lib.b64_pipeline_create(10, 2, 1) is None             # chunk too small
+    assert lib.b64_pipeline_create(1 << 20, 0, 1) is None        # no slots
+    assert b"chunk_bytes" in lib.b64_pipeline_last_error()
+    assert lib.b64_pipeline_encode(None, fake, 10, fake, std) == EARG
+    assert lib.b64_pipeline_decode(None, fake, 10, fake, std) == EARG
+    lib.b64_pipeline_destroy(None)
     # zero-size work needs no device
     assert lib.b64_encode(None, 0, None, std, None) == 0
     assert lib.b64_encode_batch(None, None, 0, None, None, None, std, None) == 0

@@ -1,0 +1,76 @@
+"""GPU parity of the host-memory pipeline (b64_pipeline_*) against the oracle:
+results must equal the single-call results bit for bit, whatever the chunking,
+including the first invalid offset when the fault lies in a middle chunk or
+when a middle chunk ends in padding."""
+import numpy as np
+import pytest
+
+import workloads
+from gpu_util import say
+
+pytestmark = pytest.mark.gpu
+
+STD = b"ABCDEFGHIJKLMNOPQRSTUVWXYZabcdefghijklmnopqrstuvwxyz0123456789+/"
+
+
+@pytest.fixture(scope="module")
+def pipe():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1910_05109_amd.pipeline import HostPipeline
+    p = HostPipeline(chunk_bytes=6144, depth=3, host_threads=2)   # 6144-byte chunks
+    yield p
+    p.close()
+
+
+def _check_dec(pipe, oracle, s, label):
+    say("pipeline decode", label, s.size)
+    dec, bad = pipe.decode(s)
+    ref, ref_bad = oracle.decode(s)
+    assert bad == ref_bad, (label, bad, ref_bad)
+    if ref_bad is None:
+        assert np.array_equal(dec, ref), label
+
+
+def test_encode_decode_many_chunks(pipe, oracle):
+    x = workloads.random_bytes(workloads.SEED_BASE + 160, 400_000)
+    for n in (0, 1, 2, 3, 6143, 6144, 6145, 18_432, 50_000, 300_001, 400_000):
+        say("pipeline encode", n)
+        got = pipe.encode(x[:n])
+        ref = oracle.encode(x[:n])
+        assert np.array_equal(got, ref), n
+        _check_dec(pipe, oracle, ref, f"valid {n}")
+
+
+def test_faults_at_chunk_boundaries(pipe, oracle):
+    x = workloads.random_bytes(workloads.SEED_BASE + 161, 60_000)
+    text = oracle.encode(x)                          # 80,000 chars = 13 chunks of 6144
+    for pos in (0, 5, 6143, 6144, 6145, 12_287, 40_000, 79_990, 79_999):
+        for c in (ord("!"), ord("="), 0xC3):
+            s = text.copy()
+            s[pos] = c
+            _check_dec(pipe, oracle, s, f"byte {c} at {pos}")
+    # a middle chunk ending in a padded quantum: the next character is invalid
+    for q_end in (6144, 12_288, 73_728):
+        for pad in (b"AA==", b"AAA=", b"AB=="):
+            s = text.copy()
+            s[q_end - 4: q_end] = np.frombuffer(pad, dtype=np.uint8)
+            _check_dec(pipe, oracle, s, f"{pad!r} ending at {q_end}")
+    for cut in (1, 2, 3, 6145, 6147):
+        _check_dec(pipe, oracle, text[: text.size - cut], f"truncated by {cut}")
+
+
+def test_large_default_chunks(oracle):
+    from paper_1910_05109_amd.pipeline import HostPipeline
+    x = workloads.random_bytes(workloads.SEED_BASE + 162, (200 << 20) + 1)
+    with HostPipeline() as p:
+        say("pipeline 200 MiB")
+        text = p.encode(x)
+        ref = oracle.encode(x)
+        assert np.array_equal(text, ref)
+        dec, bad = p.decode(ref)
+        assert bad is None and np.array_equal(dec, x)
+        ref[150_000_000] = ord("?")
+        dec, bad = p.decode(ref)
+        assert bad == 150_000_000
