@@ -16,6 +16,10 @@ Python API (numpy uint8 arrays in, numpy arrays out):
   decode_raw(s, alpha) -> the C return value (length, or ~first_bad)
   decode_rows(rows2d, alpha) -> int64 array of C return values, one per row
   encode_list / decode_list -> per-buffer results over packed buffers
+  encode_mode / decode_mode / decode_mode_raw / decode_mode_rows /
+  encoded_len_mode / encode_mode_list / decode_mode_list -> the variants:
+  flags NOPAD (no '=') and SKIP_WS (decode ignores space, tab, CR, LF), and
+  line_len > 0 (encode breaks lines with CR LF)
 """
 from __future__ import annotations
 
@@ -32,6 +36,8 @@ _LIB = os.path.join(_HERE, "libb64oracle.so")
 STD = b"ABCDEFGHIJKLMNOPQRSTUVWXYZabcdefghijklmnopqrstuvwxyz0123456789+/"
 URL = b"ABCDEFGHIJKLMNOPQRSTUVWXYZabcdefghijklmnopqrstuvwxyz0123456789-_"
 EARG = -(2 ** 63)
+NOPAD = 1
+SKIP_WS = 2
 
 
 def build(force: bool = True) -> str:
@@ -66,6 +72,19 @@ def lib() -> ctypes.CDLL:
         for fn in (L.b64o_encode_list, L.b64o_decode_list):
             fn.argtypes = [p, p, i64, p, p, p, p]
             fn.restype = None
+        u32 = ctypes.c_uint
+        L.b64o_encoded_len_mode.argtypes = [i64, u32, i64]
+        L.b64o_encoded_len_mode.restype = i64
+        L.b64o_encode_mode.argtypes = [p, i64, p, p, u32, i64]
+        L.b64o_encode_mode.restype = i64
+        L.b64o_decode_mode.argtypes = [p, i64, p, p, u32]
+        L.b64o_decode_mode.restype = i64
+        L.b64o_decode_mode_rows.argtypes = [p, i64, i64, p, u32, p]
+        L.b64o_decode_mode_rows.restype = None
+        L.b64o_encode_mode_list.argtypes = [p, p, i64, p, p, p, p, u32, i64]
+        L.b64o_encode_mode_list.restype = None
+        L.b64o_decode_mode_list.argtypes = [p, p, i64, p, p, p, p, u32]
+        L.b64o_decode_mode_list.restype = None
         _lib = L
     return _lib
 
@@ -167,4 +186,88 @@ def decode_list(src: np.ndarray, in_off: np.ndarray, alpha=STD):
     a = _alpha(alpha)
     lib().b64o_decode_list(_ptr(src), _ptr(in_off), nbuf, _ptr(dst), _ptr(out_off),
                            _ptr(res), _ptr(a))
+    return dst, out_off, res[:nbuf]
+
+
+# ------------------------------------------------------------- variants --
+
+def encoded_len_mode(n: int, flags: int = 0, line_len: int = 0) -> int:
+    return int(lib().b64o_encoded_len_mode(n, flags, line_len))
+
+
+def encode_mode(x, alpha=STD, flags: int = 0, line_len: int = 0) -> np.ndarray:
+    x = _u8(x)
+    a = _alpha(alpha)
+    m = encoded_len_mode(x.size, flags, line_len)
+    if m < 0:
+        raise ValueError("bad argument")
+    out = np.empty(max(m, 1), dtype=np.uint8)
+    r = lib().b64o_encode_mode(_ptr(x), x.size, _ptr(out), _ptr(a), flags, line_len)
+    if r < 0:
+        raise ValueError("bad argument")
+    assert r == m
+    return out[:r]
+
+
+def decode_mode_raw(s, alpha=STD, flags: int = 0) -> int:
+    s = _u8(s)
+    a = _alpha(alpha)
+    out = np.empty(max(3 * (s.size // 4) + 3, 1), dtype=np.uint8)
+    return int(lib().b64o_decode_mode(_ptr(s), s.size, _ptr(out), _ptr(a), flags))
+
+
+def decode_mode(s, alpha=STD, flags: int = 0):
+    """(bytes, None) for valid input, (None, first_invalid_offset) otherwise."""
+    s = _u8(s)
+    a = _alpha(alpha)
+    out = np.empty(max(3 * (s.size // 4) + 3, 1), dtype=np.uint8)
+    r = int(lib().b64o_decode_mode(_ptr(s), s.size, _ptr(out), _ptr(a), flags))
+    if r == EARG:
+        raise ValueError("bad argument")
+    if r < 0:
+        return None, ~r
+    return out[:r], None
+
+
+def decode_mode_rows(rows: np.ndarray, alpha=STD, flags: int = 0) -> np.ndarray:
+    rows = np.ascontiguousarray(rows, dtype=np.uint8)
+    nrows, length = rows.shape
+    a = _alpha(alpha)
+    res = np.empty(nrows, dtype=np.int64)
+    lib().b64o_decode_mode_rows(_ptr(rows), nrows, length, _ptr(a), flags, _ptr(res))
+    return res
+
+
+def encode_mode_list(src: np.ndarray, in_off: np.ndarray, alpha=STD, flags: int = 0,
+                     line_len: int = 0):
+    """Encode packed buffers with a variant; returns (dst, out_off, out_len)."""
+    src = _u8(src)
+    in_off = np.ascontiguousarray(in_off, dtype=np.int64)
+    nbuf = in_off.size - 1
+    olen = np.array([encoded_len_mode(int(k), flags, line_len) for k in np.diff(in_off)],
+                    dtype=np.int64)
+    out_off = np.zeros(nbuf + 1, dtype=np.int64)
+    np.cumsum(olen, out=out_off[1:])
+    dst = np.empty(max(int(out_off[-1]), 1), dtype=np.uint8)
+    out_len = np.empty(max(nbuf, 1), dtype=np.int64)
+    a = _alpha(alpha)
+    lib().b64o_encode_mode_list(_ptr(src), _ptr(in_off), nbuf, _ptr(dst), _ptr(out_off),
+                                _ptr(out_len), _ptr(a), flags, line_len)
+    return dst[: int(out_off[-1])], out_off, out_len[:nbuf]
+
+
+def decode_mode_list(src: np.ndarray, in_off: np.ndarray, alpha=STD, flags: int = 0):
+    """Decode packed buffers with a variant; as decode_list."""
+    src = _u8(src)
+    in_off = np.ascontiguousarray(in_off, dtype=np.int64)
+    nbuf = in_off.size - 1
+    lens = np.diff(in_off)
+    cap = 3 * (lens // 4) + 3
+    out_off = np.zeros(nbuf + 1, dtype=np.int64)
+    np.cumsum(cap, out=out_off[1:])
+    dst = np.empty(max(int(out_off[-1]), 1), dtype=np.uint8)
+    res = np.empty(max(nbuf, 1), dtype=np.int64)
+    a = _alpha(alpha)
+    lib().b64o_decode_mode_list(_ptr(src), _ptr(in_off), nbuf, _ptr(dst), _ptr(out_off),
+                                _ptr(res), _ptr(a), flags)
     return dst, out_off, res[:nbuf]

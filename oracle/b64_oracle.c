@@ -15,12 +15,15 @@
  *     the 4 values -> 3 bytes closed form used by the look-up-table decoder
  *     (with a special value marking characters outside the alphabet).
  *   - Section "Encoding" (step 2): any 64-byte mapping may serve as alphabet.
- * Readings where the paper is silent (padding is always emitted; the tail
- * zero-fills the missing bytes; '=' is legal only as the last one or two
- * characters of the final quantum; non-canonical trailing bits are rejected;
- * any non-alphabet byte including whitespace is invalid; a length that is not
- * a multiple of four is invalid at offset n) are stated in the design notes
- * and implemented in b64o_decode below.
+ * Readings where the paper is silent (in the base functions padding is always
+ * emitted; the tail zero-fills the missing bytes; '=' is legal only as the
+ * last one or two characters of the final quantum; non-canonical trailing bits
+ * are rejected; any non-alphabet byte including whitespace is invalid; a
+ * length that is not a multiple of four is invalid at offset n) are stated in
+ * the design notes and implemented in b64o_decode below.  The variants
+ * (b64o_*_mode: unpadded output, CR LF line wrapping, whitespace skipping)
+ * follow the paper's remarks that padding is optional and that base64 is
+ * carried in MIME email; their readings are stated where they are defined.
  *
  * Every function is a direct transcription of the definition: ÷, × and mod
  * exactly as the closed forms print them, one group / one character at a time,
@@ -32,6 +35,12 @@
 #define B64O_INVALID 0xFFu          /* "special value" of the decode map       */
 #define B64O_PAD     ((uint8_t)'=') /* padding character, fixed                */
 #define B64O_EARG    INT64_MIN      /* bad argument (NULL, n < 0, bad alphabet) */
+
+/* Variants (Section "Base64": padding "may" be appended; Section
+ * "Introduction": base64 inside MIME email, whose lines are wrapped). */
+#define B64O_NOPAD   1u  /* encode: no '='; decode: '=' is invalid, the final
+                            quantum may be 2 or 3 characters                */
+#define B64O_SKIP_WS 2u  /* decode: space, tab, CR and LF are ignored        */
 
 /* Table tab:base64table: value v -> ASCII.  Written out row by row. */
 const char b64o_alphabet_std[65] =
@@ -217,4 +226,183 @@ void b64o_decode_list(const uint8_t *src, const int64_t *in_off, int64_t nbuf,
     for (b = 0; b < nbuf; b++)
         result[b] = b64o_decode(src + in_off[b], in_off[b + 1] - in_off[b],
                                 dst + out_off[b], alpha);
+}
+
+/* ------------------------------------------------------------ variants -- */
+
+/* The four bytes B64O_SKIP_WS ignores: space, tab, carriage return, line feed. */
+static int b64o_is_ws(uint8_t c)
+{
+    return c == ' ' || c == '\t' || c == '\r' || c == '\n';
+}
+
+/* Characters of the unwrapped encoding: 4 per whole group and, for a last
+ * group of r = 1 or 2 bytes, 4 when padded or r + 1 (the characters that carry
+ * input bits) without padding. */
+static int64_t b64o_chars(int64_t n, unsigned flags)
+{
+    int64_t r = n % 3;
+    if (r == 0 || !(flags & B64O_NOPAD)) return 4 * ((n + 2) / 3);
+    return 4 * (n / 3) + r + 1;
+}
+
+/* Length of the encoding with `flags` (B64O_NOPAD or 0) and, when line_len > 0,
+ * a CR LF pair between consecutive lines of line_len characters. */
+int64_t b64o_encoded_len_mode(int64_t n, unsigned flags, int64_t line_len)
+{
+    int64_t m;
+    if (n < 0 || line_len < 0 || (flags & ~B64O_NOPAD)) return B64O_EARG;
+    m = b64o_chars(n, flags);
+    if (line_len > 0 && m > 0) m += 2 * ((m - 1) / line_len);
+    return m;
+}
+
+/* Encode with padding (flags 0) or without (B64O_NOPAD), then, when
+ * line_len > 0, break the character stream into lines of line_len
+ * characters separated by CR LF; no line break follows the last line.
+ * The characters themselves are b64o_encode's; without padding the trailing
+ * '=' characters are simply not emitted.  Returns the length written or
+ * B64O_EARG. */
+int64_t b64o_encode_mode(const uint8_t *src, int64_t n, uint8_t *dst, const uint8_t *alpha,
+                         unsigned flags, int64_t line_len)
+{
+    uint8_t quantum[4];
+    int64_t g, o = 0, col = 0;
+    int k, m;
+    if (n < 0 || (n > 0 && (!src || !dst)) || !b64o_alphabet_ok(alpha) || line_len < 0 ||
+        (flags & ~B64O_NOPAD))
+        return B64O_EARG;
+    for (g = 0; g < n; g += 3) {
+        int64_t r = n - g < 3 ? n - g : 3;
+        /* one group through the padded encoder: four characters */
+        b64o_encode(src + g, r, quantum, alpha);
+        m = 4;
+        if (flags & B64O_NOPAD) while (m > 0 && quantum[m - 1] == B64O_PAD) m--;
+        for (k = 0; k < m; k++) {
+            if (line_len > 0 && col == line_len) {
+                dst[o++] = '\r';
+                dst[o++] = '\n';
+                col = 0;
+            }
+            dst[o++] = quantum[k];
+            col++;
+        }
+    }
+    return o;
+}
+
+/* Decode with `flags`.  The significant characters are all characters, or,
+ * with B64O_SKIP_WS, those that are not space, tab, CR or LF; the rules below
+ * apply to the sequence of significant characters, and offsets count every
+ * character of the input.  Returns the decoded length, ~off with off the first
+ * invalid offset (n when the input ends too early), or B64O_EARG (also for
+ * B64O_SKIP_WS with an alphabet that contains one of the four ignored bytes).
+ *
+ * Padded (no B64O_NOPAD): the rules of b64o_decode.
+ * Unpadded (B64O_NOPAD): every significant character must be in the alphabet
+ * ('=' is not); the count k of significant characters may not be 1 mod 4; a
+ * final quantum of 2 (3) characters is canonical only when its last value has
+ * its low 4 (2) bits zero, otherwise the input ends too early (it could still
+ * be completed to a valid encoding).  A final quantum of 2 characters yields
+ * one byte, of 3 characters two bytes, by the same closed form. */
+int64_t b64o_decode_mode(const uint8_t *src, int64_t n, uint8_t *dst, const uint8_t *alpha,
+                         unsigned flags)
+{
+    enum { DATA, PAD1, DONE } state = DATA;
+    const int nopad = (flags & B64O_NOPAD) != 0, skip = (flags & B64O_SKIP_WS) != 0;
+    uint8_t map[256], prev = 0;
+    unsigned val[4];
+    int64_t i, k = 0, o = 0;
+    int m = 0;
+    if (n < 0 || (n > 0 && (!src || !dst)) || !b64o_alphabet_ok(alpha) ||
+        (flags & ~(B64O_NOPAD | B64O_SKIP_WS)))
+        return B64O_EARG;
+    if (skip)
+        for (i = 0; i < 64; i++)
+            if (b64o_is_ws(alpha[i])) return B64O_EARG;
+    b64o_build_map(alpha, map);
+
+    /* pass 1: validation over the significant characters */
+    for (i = 0; i < n; i++) {
+        uint8_t c = src[i];
+        int64_t p = k % 4;
+        if (skip && b64o_is_ws(c)) continue;
+        if (state == DONE) return ~i;
+        if (c != B64O_PAD || nopad) {
+            if (map[c] == B64O_INVALID) return ~i;
+            if (state == PAD1) return ~i;
+        } else if (p == 0 || p == 1) {
+            return ~i;
+        } else if (p == 2) {
+            if (map[prev] % 16 != 0) return ~i;
+            state = PAD1;
+        } else if (state == PAD1) {
+            state = DONE;
+        } else {
+            if (map[prev] % 4 != 0) return ~i;
+            state = DONE;
+        }
+        prev = c;
+        k++;
+    }
+    if (nopad) {
+        if (k % 4 == 1) return ~n;
+        if (k % 4 == 2 && map[prev] % 16 != 0) return ~n;
+        if (k % 4 == 3 && map[prev] % 4 != 0) return ~n;
+    } else if (state == PAD1 || (k % 4 != 0 && state != DONE)) {
+        return ~n;
+    }
+
+    /* pass 2: the data values, four at a time, through the closed form
+     * (a*4) + (b div 16), (b*16 mod 256) + (c div 4), (c*64 mod 256) + d;
+     * a last group of 2 or 3 values keeps the bytes they carry. */
+    for (i = 0; i < n; i++) {
+        uint8_t c = src[i];
+        if (skip && b64o_is_ws(c)) continue;
+        if (c == B64O_PAD) break;      /* only reached in padded mode */
+        val[m++] = map[c];
+        if (m == 4) {
+            dst[o++] = (uint8_t)((val[0] * 4) + (val[1] / 16));
+            dst[o++] = (uint8_t)((val[1] * 16) % 256 + (val[2] / 4));
+            dst[o++] = (uint8_t)((val[2] * 64) % 256 + val[3]);
+            m = 0;
+        }
+    }
+    if (m >= 2) dst[o++] = (uint8_t)((val[0] * 4) + (val[1] / 16));
+    if (m == 3) dst[o++] = (uint8_t)((val[1] * 16) % 256 + (val[2] / 4));
+    return o;
+}
+
+/* b64o_decode_mode over `nrows` strings of length `len` (brute-force tests). */
+void b64o_decode_mode_rows(const uint8_t *rows, int64_t nrows, int64_t len, const uint8_t *alpha,
+                           unsigned flags, int64_t *result)
+{
+    uint8_t out[64];
+    int64_t k;
+    for (k = 0; k < nrows; k++) {
+        if (len > 80) { result[k] = B64O_EARG; continue; }
+        result[k] = b64o_decode_mode(rows + k * len, len, out, alpha, flags);
+    }
+}
+
+/* Packed-buffer loops over the variant functions, as b64o_encode_list /
+ * b64o_decode_list. */
+void b64o_encode_mode_list(const uint8_t *src, const int64_t *in_off, int64_t nbuf, uint8_t *dst,
+                           const int64_t *out_off, int64_t *out_len, const uint8_t *alpha,
+                           unsigned flags, int64_t line_len)
+{
+    int64_t b;
+    for (b = 0; b < nbuf; b++)
+        out_len[b] = b64o_encode_mode(src + in_off[b], in_off[b + 1] - in_off[b], dst + out_off[b],
+                                      alpha, flags, line_len);
+}
+
+void b64o_decode_mode_list(const uint8_t *src, const int64_t *in_off, int64_t nbuf, uint8_t *dst,
+                           const int64_t *out_off, int64_t *result, const uint8_t *alpha,
+                           unsigned flags)
+{
+    int64_t b;
+    for (b = 0; b < nbuf; b++)
+        result[b] = b64o_decode_mode(src + in_off[b], in_off[b + 1] - in_off[b], dst + out_off[b],
+                                     alpha, flags);
 }
