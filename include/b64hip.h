@@ -114,6 +114,76 @@ int64_t b64_decode_batch(const uint8_t *src, const int64_t *in_off, int64_t nbuf
                          uint8_t *dst, const int64_t *out_off, int64_t *out_len,
                          int64_t *first_bad, const char *alphabet, hipStream_t stream);
 
+/* ---------------------------------------------------------------- variants --
+ * Section "Base64" makes the '=' padding optional ("may be appended") and
+ * names base64url; Section "Introduction" names MIME email, which carries
+ * base64 in lines.  The _mode entry points take `flags`:
+ *   B64_NOPAD    encode: no '=' -- a last group of 1 or 2 bytes gives 2 or 3
+ *                characters.  decode: '=' is invalid everywhere; the final
+ *                quantum may have 2 or 3 characters (1 or 2 bytes); a final
+ *                quantum of 1 character, or of 2 (3) characters whose last
+ *                value has nonzero low 4 (2) bits, makes the input end too
+ *                early (first invalid offset n).
+ *   B64_SKIP_WS  decode / validate: space, tab, CR and LF are ignored; every
+ *                rule applies to the remaining characters, and offsets count
+ *                every byte of the input.  The alphabet may not contain any
+ *                of those four bytes.
+ * and encode takes `line_len`: 0 for one line, else a multiple of 4; CR LF
+ * then separates consecutive lines of line_len characters (no CR LF after
+ * the last line).  flags = 0 and line_len = 0 give the plain entry points. */
+#define B64_NOPAD   1u
+#define B64_SKIP_WS 2u
+
+/* Characters produced by b64_encode_mode(n, flags, line_len), line breaks
+ * included; B64_EARG for n < 0, a bad line_len or a flag other than B64_NOPAD. */
+int64_t b64_encoded_len_mode(int64_t n, uint32_t flags, int64_t line_len);
+/* Output capacity for decoding n characters with `flags`: 3*(n/4), plus
+ * max(0, n%4 - 1) under B64_NOPAD; B64_EARG for n < 0 or unknown flags. */
+int64_t b64_decoded_max_len_mode(int64_t n, uint32_t flags);
+/* Device workspace, in bytes, that the asynchronous B64_SKIP_WS decode and
+ * validate need for n characters (0 without B64_SKIP_WS): 8 bytes per tile of
+ * 4-64 KiB of input plus 16.  B64_EARG for n < 0 or unknown flags. */
+int64_t b64_decode_workspace_size(int64_t n, uint32_t flags);
+
+/* Encode with variants.  Asynchronous; returns b64_encoded_len_mode(n, flags,
+ * line_len) or B64_EARG / B64_EHIP; dst holds that many bytes. */
+int64_t b64_encode_mode(const uint8_t *src, int64_t n, uint8_t *dst, const char *alphabet,
+                        uint32_t flags, int64_t line_len, hipStream_t stream);
+/* Decode with variants.  Blocking; returns as b64_decode.  dst holds
+ * b64_decoded_max_len_mode(n, flags) bytes.  With B64_SKIP_WS the library
+ * uses a device workspace of its own, per thread and device, grown with
+ * hipMalloc as inputs grow and kept until the process ends. */
+int64_t b64_decode_mode(const uint8_t *src, int64_t n, uint8_t *dst, const char *alphabet,
+                        uint32_t flags, hipStream_t stream);
+/* Decode with variants, asynchronous; status as b64_decode_async.
+ * `workspace` is a device buffer of workspace_bytes >=
+ * b64_decode_workspace_size(n, flags) bytes (may be NULL when that is 0),
+ * owned by the caller and busy until the stream has run the decode.  Safe to
+ * capture in a HIP graph. */
+int64_t b64_decode_mode_async(const uint8_t *src, int64_t n, uint8_t *dst, int64_t *out_len,
+                              int64_t *first_bad, const char *alphabet, uint32_t flags,
+                              void *workspace, int64_t workspace_bytes, hipStream_t stream);
+/* Validate with variants.  Blocking; returns what b64_decode_mode would
+ * return; writes no output. */
+int64_t b64_validate_mode(const uint8_t *src, int64_t n, const char *alphabet, uint32_t flags,
+                          hipStream_t stream);
+/* Validate with variants, asynchronous; status and workspace as
+ * b64_decode_mode_async. */
+int64_t b64_validate_mode_async(const uint8_t *src, int64_t n, int64_t *out_len, int64_t *first_bad,
+                                const char *alphabet, uint32_t flags, void *workspace,
+                                int64_t workspace_bytes, hipStream_t stream);
+/* Batched encode / decode with variants: as b64_encode_batch /
+ * b64_decode_batch, `flags` 0 or B64_NOPAD (out_len[b] of an unpadded encode
+ * is ceil(4*length_b/3); decode capacity per buffer is
+ * b64_decoded_max_len_mode(length_b, flags)). */
+int64_t b64_encode_batch_mode(const uint8_t *src, const int64_t *in_off, int64_t nbuf,
+                              uint8_t *dst, const int64_t *out_off, int64_t *out_len,
+                              const char *alphabet, uint32_t flags, hipStream_t stream);
+int64_t b64_decode_batch_mode(const uint8_t *src, const int64_t *in_off, int64_t nbuf,
+                              uint8_t *dst, const int64_t *out_off, int64_t *out_len,
+                              int64_t *first_bad, const char *alphabet, uint32_t flags,
+                              hipStream_t stream);
+
 /* Host-memory pipeline (an opaque handle).  Encodes or decodes data that
  * lives in ordinary host memory by cutting it into chunks that stream through
  * pinned staging, host-to-device copies, the kernels and device-to-host
@@ -141,7 +211,8 @@ int64_t b64_pipeline_decode(b64_pipeline *p, const uint8_t *src, int64_t n, uint
 const char *b64_pipeline_last_error(void);
 
 /* Launch shape used by the kernels of operation `op` (0 encode, 1 decode,
- * 2 encode_batch, 3 decode_batch, 4 validate): `unroll` lane chunks in flight per lane
+ * 2 encode_batch, 3 decode_batch, 4 validate, 5 line-wrapped encode,
+ * 6 whitespace-skipping decode / validate): `unroll` lane chunks in flight per lane
  * (1, 2, 4 or 8; a lane chunk is 12 bytes -> 16 characters or back),
  * `blocks_per_cu` workgroups of 256 threads per compute unit (1..64), and
  * `nontemporal` (0 or 1) for streaming loads and stores.  Process-wide; meant

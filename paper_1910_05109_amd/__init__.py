@@ -13,6 +13,12 @@ every step of the codec runs in libb64hip.so.
   encode_batch(src, in_off)-> (dst, out_off, out_len)
   decode_batch(src, in_off)-> (dst, out_off, out_len, first_bad)
 
+Variants (keyword arguments; the paper makes '=' optional and names MIME):
+  flags=NOPAD     no '=' (encode), '=' invalid and a final quantum of 2-3
+                  characters allowed (decode / validate; also in batches)
+  flags=SKIP_WS   decode / validate ignore space, tab, CR, LF
+  line_len=L      encode breaks lines of L characters (a multiple of 4) with CR LF
+
 Tensors are torch.uint8 (data) / torch.int64 (offsets) on the current CUDA
 (HIP) device; work is enqueued on torch's current stream.
 """
@@ -26,9 +32,13 @@ from ._lib import B64Error, check, load
 STD = b"ABCDEFGHIJKLMNOPQRSTUVWXYZabcdefghijklmnopqrstuvwxyz0123456789+/"
 URL = b"ABCDEFGHIJKLMNOPQRSTUVWXYZabcdefghijklmnopqrstuvwxyz0123456789-_"
 
-OPS = {"encode": 0, "decode": 1, "encode_batch": 2, "decode_batch": 3, "validate": 4}
+OPS = {"encode": 0, "decode": 1, "encode_batch": 2, "decode_batch": 3, "validate": 4,
+       "encode_wrap": 5, "decode_ws": 6}
+NOPAD = 1
+SKIP_WS = 2
 
-__all__ = ["STD", "URL", "B64Error", "load", "encoded_len", "decoded_max_len", "encode",
+__all__ = ["STD", "URL", "NOPAD", "SKIP_WS", "B64Error", "load", "encoded_len", "decoded_max_len",
+           "workspace_size", "encode",
            "decode", "decode_async", "validate", "validate_async", "encode_batch", "decode_batch",
            "tune_set", "tune_get", "stream_ptr"]
 
@@ -67,57 +77,87 @@ def _check_i64(t, what):
         raise ValueError(f"{what} must be contiguous")
 
 
-def encoded_len(n: int) -> int:
-    return check(load().b64_encoded_len(n), "encoded_len")
+def encoded_len(n: int, flags: int = 0, line_len: int = 0) -> int:
+    if flags == 0 and line_len == 0:
+        return check(load().b64_encoded_len(n), "encoded_len")
+    return check(load().b64_encoded_len_mode(n, flags, line_len), "encoded_len_mode")
 
 
-def decoded_max_len(n: int) -> int:
-    return check(load().b64_decoded_max_len(n), "decoded_max_len")
+def decoded_max_len(n: int, flags: int = 0) -> int:
+    if flags == 0:
+        return check(load().b64_decoded_max_len(n), "decoded_max_len")
+    return check(load().b64_decoded_max_len_mode(n, flags), "decoded_max_len_mode")
 
 
-def encode(x, alphabet=STD, out=None, stream=None):
-    """Encode a uint8 CUDA tensor; returns out[:4*ceil(n/3)] (asynchronous)."""
+def workspace_size(n: int, flags: int = 0) -> int:
+    """Device workspace bytes of an asynchronous decode / validate."""
+    return check(load().b64_decode_workspace_size(n, flags), "decode_workspace_size")
+
+
+def _workspace(n, flags, workspace, device):
+    need = workspace_size(n, flags)
+    if need == 0:
+        return 0, 0
+    if workspace is None:
+        workspace = _torch().empty(need, dtype=_torch().uint8, device=device)
+    _check_u8(workspace, "workspace")
+    return workspace.data_ptr(), workspace.numel()
+
+
+def encode(x, alphabet=STD, out=None, stream=None, flags: int = 0, line_len: int = 0):
+    """Encode a uint8 CUDA tensor; returns out[:encoded length] (asynchronous)."""
     torch = _torch()
     _check_u8(x, "x")
     n = x.numel()
-    m = encoded_len(n)
+    m = encoded_len(n, flags, line_len)
     if out is None:
-        out = torch.empty(m, dtype=torch.uint8, device=x.device)
+        out = torch.empty(max(m, 1), dtype=torch.uint8, device=x.device)
     else:
         _check_u8(out, "out")
         if out.numel() < m:
             raise ValueError("out too small")
-    r = check(load().b64_encode(x.data_ptr(), n, out.data_ptr(), _alpha(alphabet),
-                                stream_ptr(stream)), "b64_encode")
+    if flags == 0 and line_len == 0:
+        r = check(load().b64_encode(x.data_ptr(), n, out.data_ptr(), _alpha(alphabet),
+                                    stream_ptr(stream)), "b64_encode")
+    else:
+        r = check(load().b64_encode_mode(x.data_ptr(), n, out.data_ptr(), _alpha(alphabet), flags,
+                                         line_len, stream_ptr(stream)), "b64_encode_mode")
     return out[:r]
 
 
-def decode(s, alphabet=STD, out=None, stream=None):
+def decode(s, alphabet=STD, out=None, stream=None, flags: int = 0):
     """Blocking decode: (bytes_tensor, None) if valid, (None, first_bad) if not."""
     torch = _torch()
     _check_u8(s, "s")
     n = s.numel()
-    cap = decoded_max_len(n)
+    cap = decoded_max_len(n, flags)
     if out is None:
         out = torch.empty(max(cap, 1), dtype=torch.uint8, device=s.device)
     else:
         _check_u8(out, "out")
         if out.numel() < cap:
             raise ValueError("out too small")
-    r = check(load().b64_decode(s.data_ptr(), n, out.data_ptr(), _alpha(alphabet),
-                                stream_ptr(stream)), "b64_decode")
+    if flags == 0:
+        r = check(load().b64_decode(s.data_ptr(), n, out.data_ptr(), _alpha(alphabet),
+                                    stream_ptr(stream)), "b64_decode")
+    else:
+        r = check(load().b64_decode_mode(s.data_ptr(), n, out.data_ptr(), _alpha(alphabet), flags,
+                                         stream_ptr(stream)), "b64_decode_mode")
     if r < 0:
         return None, ~r
     return out[:r], None
 
 
-def decode_async(s, alphabet=STD, out=None, status=None, stream=None):
+def decode_async(s, alphabet=STD, out=None, status=None, stream=None, flags: int = 0,
+                 workspace=None):
     """Asynchronous decode.  Returns (out, status), status = int64[2] on the
-    device: [decoded length or -1, -1 or first invalid offset]."""
+    device: [decoded length or -1, -1 or first invalid offset].  With SKIP_WS a
+    device workspace of workspace_size(n, flags) bytes is used (allocated here
+    unless given)."""
     torch = _torch()
     _check_u8(s, "s")
     n = s.numel()
-    cap = decoded_max_len(n)
+    cap = decoded_max_len(n, flags)
     if out is None:
         out = torch.empty(max(cap, 1), dtype=torch.uint8, device=s.device)
     if status is None:
@@ -127,21 +167,31 @@ def decode_async(s, alphabet=STD, out=None, status=None, stream=None):
     if out.numel() < cap or status.numel() < 2:
         raise ValueError("out or status too small")
     sp = status.data_ptr()
-    check(load().b64_decode_async(s.data_ptr(), n, out.data_ptr(), sp, sp + 8, _alpha(alphabet),
-                                  stream_ptr(stream)), "b64_decode_async")
+    if flags == 0:
+        check(load().b64_decode_async(s.data_ptr(), n, out.data_ptr(), sp, sp + 8, _alpha(alphabet),
+                                      stream_ptr(stream)), "b64_decode_async")
+    else:
+        wp, wn = _workspace(n, flags, workspace, s.device)
+        check(load().b64_decode_mode_async(s.data_ptr(), n, out.data_ptr(), sp, sp + 8,
+                                           _alpha(alphabet), flags, wp, wn, stream_ptr(stream)),
+              "b64_decode_mode_async")
     return out, status
 
 
-def validate(s, alphabet=STD, stream=None):
-    """Blocking, read-only: (decoded length, None) if s is a valid padded
-    encoding, (None, first_invalid_offset) if not."""
+def validate(s, alphabet=STD, stream=None, flags: int = 0):
+    """Blocking, read-only: (decoded length, None) if s is a valid encoding,
+    (None, first_invalid_offset) if not."""
     _check_u8(s, "s")
-    r = check(load().b64_validate(s.data_ptr(), s.numel(), _alpha(alphabet), stream_ptr(stream)),
-              "b64_validate")
+    if flags == 0:
+        r = check(load().b64_validate(s.data_ptr(), s.numel(), _alpha(alphabet),
+                                      stream_ptr(stream)), "b64_validate")
+    else:
+        r = check(load().b64_validate_mode(s.data_ptr(), s.numel(), _alpha(alphabet), flags,
+                                           stream_ptr(stream)), "b64_validate_mode")
     return (r, None) if r >= 0 else (None, ~r)
 
 
-def validate_async(s, alphabet=STD, status=None, stream=None):
+def validate_async(s, alphabet=STD, status=None, stream=None, flags: int = 0, workspace=None):
     """Asynchronous validation; status = int64[2] on the device:
     [decoded length or -1, -1 or first invalid offset]."""
     torch = _torch()
@@ -150,8 +200,14 @@ def validate_async(s, alphabet=STD, status=None, stream=None):
         status = torch.empty(2, dtype=torch.int64, device=s.device)
     _check_i64(status, "status")
     sp = status.data_ptr()
-    check(load().b64_validate_async(s.data_ptr(), s.numel(), sp, sp + 8, _alpha(alphabet),
-                                    stream_ptr(stream)), "b64_validate_async")
+    if flags == 0:
+        check(load().b64_validate_async(s.data_ptr(), s.numel(), sp, sp + 8, _alpha(alphabet),
+                                        stream_ptr(stream)), "b64_validate_async")
+    else:
+        wp, wn = _workspace(s.numel(), flags, workspace, s.device)
+        check(load().b64_validate_mode_async(s.data_ptr(), s.numel(), sp, sp + 8, _alpha(alphabet),
+                                             flags, wp, wn, stream_ptr(stream)),
+              "b64_validate_mode_async")
     return status
 
 
@@ -186,6 +242,15 @@ def _dec_cap(L):
     return 3 * _torch().div(L, 4, rounding_mode="floor")
 
 
+def _enc_cap_nopad(L):
+    return _torch().div(4 * L + 2, 3, rounding_mode="floor")
+
+
+def _dec_cap_nopad(L):
+    r = L % 4
+    return 3 * _torch().div(L, 4, rounding_mode="floor") + (r - 1).clamp(min=0)
+
+
 def _batch_layout(in_off, per_len):
     torch = _torch()
     lens = in_off[1:] - in_off[:-1]
@@ -195,7 +260,7 @@ def _batch_layout(in_off, per_len):
 
 
 def encode_batch(src, in_off, alphabet=STD, dst=None, out_off=None, out_len=None, stream=None,
-                 validate=True):
+                 validate=True, flags: int = 0):
     """Encode nbuf = len(in_off)-1 packed buffers in one launch (asynchronous
     unless `validate`, which checks the layout on the host first).
     Returns (dst, out_off, out_len); out_off has nbuf+1 entries."""
@@ -203,8 +268,9 @@ def encode_batch(src, in_off, alphabet=STD, dst=None, out_off=None, out_len=None
     _check_u8(src, "src")
     _check_i64(in_off, "in_off")
     nbuf = in_off.numel() - 1
+    cap = _enc_cap_nopad if flags & NOPAD else _enc_cap
     if out_off is None:
-        out_off = _batch_layout(in_off, _enc_cap)
+        out_off = _batch_layout(in_off, cap)
     _check_i64(out_off, "out_off")
     if dst is None:
         dst = torch.empty(max(int(out_off[-1].item()), 1), dtype=torch.uint8, device=src.device)
@@ -215,15 +281,20 @@ def encode_batch(src, in_off, alphabet=STD, dst=None, out_off=None, out_len=None
     if out_len.numel() < nbuf:
         raise ValueError("out_len too small")
     if validate:
-        _validate_layout(src, in_off, dst, out_off, _enc_cap, "encode_batch")
-    check(load().b64_encode_batch(src.data_ptr(), in_off.data_ptr(), nbuf, dst.data_ptr(),
-                                  out_off.data_ptr(), out_len.data_ptr(), _alpha(alphabet),
-                                  stream_ptr(stream)), "b64_encode_batch")
+        _validate_layout(src, in_off, dst, out_off, cap, "encode_batch")
+    if flags == 0:
+        check(load().b64_encode_batch(src.data_ptr(), in_off.data_ptr(), nbuf, dst.data_ptr(),
+                                      out_off.data_ptr(), out_len.data_ptr(), _alpha(alphabet),
+                                      stream_ptr(stream)), "b64_encode_batch")
+    else:
+        check(load().b64_encode_batch_mode(src.data_ptr(), in_off.data_ptr(), nbuf, dst.data_ptr(),
+                                           out_off.data_ptr(), out_len.data_ptr(), _alpha(alphabet),
+                                           flags, stream_ptr(stream)), "b64_encode_batch_mode")
     return dst, out_off, out_len[:nbuf]
 
 
 def decode_batch(src, in_off, alphabet=STD, dst=None, out_off=None, out_len=None,
-                 first_bad=None, stream=None, validate=True):
+                 first_bad=None, stream=None, validate=True, flags: int = 0):
     """Decode nbuf packed buffers in one launch (asynchronous).  Returns
     (dst, out_off, out_len, first_bad): out_len[b] = length or -1,
     first_bad[b] = -1 or the first invalid offset within buffer b."""
@@ -231,8 +302,9 @@ def decode_batch(src, in_off, alphabet=STD, dst=None, out_off=None, out_len=None
     _check_u8(src, "src")
     _check_i64(in_off, "in_off")
     nbuf = in_off.numel() - 1
+    cap = _dec_cap_nopad if flags & NOPAD else _dec_cap
     if out_off is None:
-        out_off = _batch_layout(in_off, _dec_cap)
+        out_off = _batch_layout(in_off, cap)
     _check_i64(out_off, "out_off")
     if dst is None:
         dst = torch.empty(max(int(out_off[-1].item()), 1), dtype=torch.uint8, device=src.device)
@@ -246,10 +318,16 @@ def decode_batch(src, in_off, alphabet=STD, dst=None, out_off=None, out_len=None
     if out_len.numel() < nbuf or first_bad.numel() < nbuf:
         raise ValueError("out_len / first_bad too small")
     if validate:
-        _validate_layout(src, in_off, dst, out_off, _dec_cap, "decode_batch")
-    check(load().b64_decode_batch(src.data_ptr(), in_off.data_ptr(), nbuf, dst.data_ptr(),
-                                  out_off.data_ptr(), out_len.data_ptr(), first_bad.data_ptr(),
-                                  _alpha(alphabet), stream_ptr(stream)), "b64_decode_batch")
+        _validate_layout(src, in_off, dst, out_off, cap, "decode_batch")
+    if flags == 0:
+        check(load().b64_decode_batch(src.data_ptr(), in_off.data_ptr(), nbuf, dst.data_ptr(),
+                                      out_off.data_ptr(), out_len.data_ptr(), first_bad.data_ptr(),
+                                      _alpha(alphabet), stream_ptr(stream)), "b64_decode_batch")
+    else:
+        check(load().b64_decode_batch_mode(src.data_ptr(), in_off.data_ptr(), nbuf, dst.data_ptr(),
+                                           out_off.data_ptr(), out_len.data_ptr(),
+                                           first_bad.data_ptr(), _alpha(alphabet), flags,
+                                           stream_ptr(stream)), "b64_decode_batch_mode")
     return dst, out_off, out_len[:nbuf], first_bad[:nbuf]
 
 

@@ -17,7 +17,7 @@ EARG = -(2 ** 63)
 EHIP = -(2 ** 63) + 1
 
 # entry points and their signatures, in the order of include/b64hip.h
-_P, _I64, _INT = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int
+_P, _I64, _INT, _U32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_uint32
 SIGNATURES = {
     "b64_encoded_len": ([_I64], _I64),
     "b64_decoded_max_len": ([_I64], _I64),
@@ -28,6 +28,16 @@ SIGNATURES = {
     "b64_validate_async": ([_P, _I64, _P, _P, _P, _P], _I64),
     "b64_encode_batch": ([_P, _P, _I64, _P, _P, _P, _P, _P], _I64),
     "b64_decode_batch": ([_P, _P, _I64, _P, _P, _P, _P, _P, _P], _I64),
+    "b64_encoded_len_mode": ([_I64, _U32, _I64], _I64),
+    "b64_decoded_max_len_mode": ([_I64, _U32], _I64),
+    "b64_decode_workspace_size": ([_I64, _U32], _I64),
+    "b64_encode_mode": ([_P, _I64, _P, _P, _U32, _I64, _P], _I64),
+    "b64_decode_mode": ([_P, _I64, _P, _P, _U32, _P], _I64),
+    "b64_decode_mode_async": ([_P, _I64, _P, _P, _P, _P, _U32, _P, _I64, _P], _I64),
+    "b64_validate_mode": ([_P, _I64, _P, _U32, _P], _I64),
+    "b64_validate_mode_async": ([_P, _I64, _P, _P, _P, _U32, _P, _I64, _P], _I64),
+    "b64_encode_batch_mode": ([_P, _P, _I64, _P, _P, _P, _P, _U32, _P], _I64),
+    "b64_decode_batch_mode": ([_P, _P, _I64, _P, _P, _P, _P, _P, _U32, _P], _I64),
     "b64_pipeline_create": ([_I64, _INT, _INT], _P),
     "b64_pipeline_destroy": ([_P], None),
     "b64_pipeline_encode": ([_P, _P, _I64, _P, _P], _I64),

@@ -69,11 +69,27 @@ DecMap make_dec(const char *alphabet)
     return d;
 }
 
+bool is_ws(uint8_t c) { return c == ' ' || c == '\t' || c == '\r' || c == '\n'; }
+
+// Codes of the whitespace-skipping kernels: alphabet values, 0x40 for the four
+// ignored bytes, 0x81 for '=' (padded mode), 0x80 for every other byte.
+DecMap make_dec_ws(const char *alphabet, bool nopad)
+{
+    DecMap d;
+    uint8_t *b = (uint8_t *)d.w;
+    memset(b, 0x80, 256);
+    b[' '] = b['\t'] = b['\r'] = b['\n'] = 0x40;
+    if (!nopad) b[kPad] = 0x81;
+    for (int v = 0; v < 64; ++v) b[(uint8_t)alphabet[v]] = (uint8_t)v;
+    return d;
+}
+
 // Launch shapes per operation (encode, decode, encode_batch, decode_batch,
-// validate); the defaults are the autotuner's choices on MI355X (1 GiB single
-// buffers, 1 GiB log-uniform ragged batches).
-constexpr int kOps = 5;
-Shape g_shape[kOps] = {{4, 1, 1}, {8, 1, 1}, {4, 2, 1}, {4, 2, 1}, {8, 1, 1}};
+// validate, line-wrapped encode, whitespace-skipping decode); the defaults
+// are the autotuner's choices on MI355X (1 GiB single buffers, 1 GiB
+// log-uniform ragged batches).
+constexpr int kOps = 7;
+Shape g_shape[kOps] = {{4, 1, 1}, {8, 1, 1}, {4, 2, 1}, {4, 2, 1}, {8, 1, 1}, {4, 1, 1}, {1, 2, 1}};
 std::mutex g_mu;
 
 Shape shape_of(int op)
@@ -129,18 +145,77 @@ hipError_t status_slot(StatusSlot **out)
 
 const char *const kBadAlphabet = "alphabet must be 64 distinct bytes without '='";
 
-// Enqueue one single-buffer decode: reset first_bad, run k_decode, and (with
-// `finish`) turn the raw status into the public form.
-int64_t decode_enqueue(const uint8_t *src, int64_t n, uint8_t *dst, int64_t *out_len,
-                       int64_t *first_bad, const char *alphabet, hipStream_t stream, bool finish)
+constexpr uint32_t kFlagsAll = kFlagNoPad | kFlagSkipWs;
+
+// Argument checks shared by the decode / validate entry points; returns 0 or
+// an error code with the message set.
+int64_t check_decode_args(int64_t n, const char *alphabet, uint32_t flags)
+{
+    if (n < 0) return fail(B64_EARG, "negative length");
+    if (flags & ~kFlagsAll) return fail(B64_EARG, "unknown flags");
+    if (!alphabet_ok(alphabet)) return fail(B64_EARG, kBadAlphabet);
+    if (flags & kFlagSkipWs)
+        for (int v = 0; v < 64; ++v)
+            if (is_ws((uint8_t)alphabet[v]))
+                return fail(B64_EARG, "B64_SKIP_WS needs an alphabet without space, tab, CR or LF");
+    return 0;
+}
+
+// Per thread and device: the device workspace of the blocking
+// whitespace-skipping decode / validate, grown as needed (held until the
+// process ends).
+struct WsCache { void *d = nullptr; int64_t bytes = 0; };
+thread_local WsCache g_ws[kMaxDevices];
+
+hipError_t ws_cache(int64_t bytes, void **out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    WsCache &c = g_ws[dev];
+    if (c.bytes < bytes) {
+        if (c.d) {
+            e = hipFree(c.d);
+            if (e != hipSuccess) return e;
+            c.d = nullptr;
+            c.bytes = 0;
+        }
+        const int64_t want = bytes < 4096 ? 4096 : bytes;
+        e = hipMalloc(&c.d, (size_t)want);
+        if (e != hipSuccess) return e;
+        c.bytes = want;
+    }
+    *out = c.d;
+    return hipSuccess;
+}
+
+// Enqueue one single-buffer decode (`write`) or validation (!`write`, dst
+// unused).  Without B64_SKIP_WS: reset first_bad, run k_decode / k_validate,
+// and (with `finish`) turn the raw status into the public form.  With
+// B64_SKIP_WS the five-launch whitespace path always ends with the public
+// form.
+int64_t decode_enqueue(const uint8_t *src, int64_t n, uint8_t *dst, bool write, int64_t *out_len,
+                       int64_t *first_bad, const char *alphabet, uint32_t flags, void *workspace,
+                       hipStream_t stream, bool finish)
 {
     int cus = 0;
     hipError_t e = cu_count(&cus);
     if (e != hipSuccess) return hip_fail(e, "device query");
+    if (flags & kFlagSkipWs) {
+        e = launch_decode_ws(src, n, dst, write, make_dec_ws(alphabet, flags & kFlagNoPad), out_len,
+                             first_bad, flags, workspace, shape_of(6), cus, stream);
+        return e == hipSuccess ? 0 : hip_fail(e, "whitespace decode launch");
+    }
     e = launch_fill(first_bad, 1, kNoError, stream);
     if (e != hipSuccess) return hip_fail(e, "fill launch");
-    e = launch_decode(src, n, dst, make_dec(alphabet), out_len, first_bad, shape_of(1), cus, stream);
-    if (e != hipSuccess) return hip_fail(e, "decode launch");
+    if (write)
+        e = launch_decode(src, n, dst, make_dec(alphabet), out_len, first_bad, flags, shape_of(1),
+                          cus, stream);
+    else
+        e = launch_validate(src, n, make_dec(alphabet), out_len, first_bad, flags, shape_of(4), cus,
+                            stream);
+    if (e != hipSuccess) return hip_fail(e, write ? "decode launch" : "validate launch");
     if (finish) {
         e = launch_finish(out_len, first_bad, 1, stream);
         if (e != hipSuccess) return hip_fail(e, "status launch");
@@ -148,23 +223,31 @@ int64_t decode_enqueue(const uint8_t *src, int64_t n, uint8_t *dst, int64_t *out
     return 0;
 }
 
-// Enqueue one validation: reset first_bad, run k_validate, and (with
-// `finish`) turn the raw status into the public form.
-int64_t validate_enqueue(const uint8_t *src, int64_t n, int64_t *out_len, int64_t *first_bad,
-                         const char *alphabet, hipStream_t stream, bool finish)
+// Blocking decode / validation through the per-thread status slot (and
+// workspace): returns the length, ~first_invalid_offset, or an error code.
+int64_t decode_blocking(const uint8_t *src, int64_t n, uint8_t *dst, bool write,
+                        const char *alphabet, uint32_t flags, hipStream_t stream)
 {
-    int cus = 0;
-    hipError_t e = cu_count(&cus);
-    if (e != hipSuccess) return hip_fail(e, "device query");
-    e = launch_fill(first_bad, 1, kNoError, stream);
-    if (e != hipSuccess) return hip_fail(e, "fill launch");
-    e = launch_validate(src, n, make_dec(alphabet), out_len, first_bad, shape_of(4), cus, stream);
-    if (e != hipSuccess) return hip_fail(e, "validate launch");
-    if (finish) {
-        e = launch_finish(out_len, first_bad, 1, stream);
-        if (e != hipSuccess) return hip_fail(e, "status launch");
+    StatusSlot *slot = nullptr;
+    hipError_t e = status_slot(&slot);
+    if (e != hipSuccess) return hip_fail(e, "status slot");
+    void *ws = nullptr;
+    if (flags & kFlagSkipWs) {
+        e = ws_cache(ws_workspace_bytes(n), &ws);
+        if (e != hipSuccess) return hip_fail(e, "workspace");
     }
-    return 0;
+    // raw status (plain path): slot->d[0] = length if the tail is valid,
+    // slot->d[1] = the smallest invalid offset or kNoError.  The whitespace
+    // path leaves the public form (-1 for "valid" in slot->d[1]).
+    const int64_t r = decode_enqueue(src, n, dst, write, slot->d, slot->d + 1, alphabet, flags, ws,
+                                     stream, false);
+    if (r) return r;
+    e = hipMemcpyAsync(slot->h, slot->d, 2 * sizeof(int64_t), hipMemcpyDeviceToHost, stream);
+    if (e != hipSuccess) return hip_fail(e, "status copy");
+    e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return hip_fail(e, "stream synchronize");
+    const int64_t len = slot->h[0], bad = slot->h[1];
+    return (bad == kNoError || bad == -1) ? len : ~bad;
 }
 
 }  // namespace
@@ -181,6 +264,31 @@ int64_t b64_decoded_max_len(int64_t n)
 {
     if (n < 0) return fail(B64_EARG, "negative length");
     return 3 * (n / 4);
+}
+
+int64_t b64_encoded_len_mode(int64_t n, uint32_t flags, int64_t line_len)
+{
+    if (n < 0) return fail(B64_EARG, "negative length");
+    if (flags & ~kFlagNoPad) return fail(B64_EARG, "encode takes no flag but B64_NOPAD");
+    if (line_len < 0 || (line_len & 3)) return fail(B64_EARG, "line_len must be 0 or a positive multiple of 4");
+    int64_t m = (flags & kFlagNoPad) ? (4 * n + 2) / 3 : 4 * ((n + 2) / 3);
+    if (line_len > 0 && m > 0) m += 2 * ((m - 1) / line_len);
+    return m;
+}
+
+int64_t b64_decoded_max_len_mode(int64_t n, uint32_t flags)
+{
+    if (n < 0) return fail(B64_EARG, "negative length");
+    if (flags & ~kFlagsAll) return fail(B64_EARG, "unknown flags");
+    const int64_t r = n & 3;
+    return 3 * (n / 4) + ((flags & kFlagNoPad) && r > 1 ? r - 1 : 0);
+}
+
+int64_t b64_decode_workspace_size(int64_t n, uint32_t flags)
+{
+    if (n < 0) return fail(B64_EARG, "negative length");
+    if (flags & ~kFlagsAll) return fail(B64_EARG, "unknown flags");
+    return (flags & kFlagSkipWs) ? ws_workspace_bytes(n) : 0;
 }
 
 const char *b64_last_error(void) { return g_err; }
@@ -204,99 +312,129 @@ int64_t b64_tune_get(int op)
     return (int64_t)s.nt * 10000 + (int64_t)s.unroll * 100 + s.bpc;
 }
 
-int64_t b64_encode(const uint8_t *src, int64_t n, uint8_t *dst, const char *alphabet,
-                   hipStream_t stream)
+int64_t b64_encode_mode(const uint8_t *src, int64_t n, uint8_t *dst, const char *alphabet,
+                        uint32_t flags, int64_t line_len, hipStream_t stream)
 {
-    if (n < 0) return fail(B64_EARG, "negative length");
+    const int64_t m = b64_encoded_len_mode(n, flags, line_len);
+    if (m < 0) return m;
     if (n > 0 && (!src || !dst)) return fail(B64_EARG, "null buffer");
     if (!alphabet_ok(alphabet)) return fail(B64_EARG, kBadAlphabet);
     if (n == 0) return 0;
     int cus = 0;
     hipError_t e = cu_count(&cus);
     if (e != hipSuccess) return hip_fail(e, "device query");
-    e = launch_encode(src, n, dst, make_enc(alphabet), shape_of(0), cus, stream);
+    if (line_len > 0 && line_len < m)
+        e = launch_encode_wrap(src, n, dst, make_enc(alphabet), flags, line_len, shape_of(5), cus,
+                               stream);
+    else
+        e = launch_encode(src, n, dst, make_enc(alphabet), flags, shape_of(0), cus, stream);
     if (e != hipSuccess) return hip_fail(e, "encode launch");
-    return 4 * ((n + 2) / 3);
+    return m;
+}
+
+int64_t b64_encode(const uint8_t *src, int64_t n, uint8_t *dst, const char *alphabet,
+                   hipStream_t stream)
+{
+    return b64_encode_mode(src, n, dst, alphabet, 0, 0, stream);
+}
+
+int64_t b64_decode_mode_async(const uint8_t *src, int64_t n, uint8_t *dst, int64_t *out_len,
+                              int64_t *first_bad, const char *alphabet, uint32_t flags,
+                              void *workspace, int64_t workspace_bytes, hipStream_t stream)
+{
+    const int64_t c = check_decode_args(n, alphabet, flags);
+    if (c) return c;
+    if ((n > 0 && (!src || !dst)) || !out_len || !first_bad) return fail(B64_EARG, "null pointer");
+    if ((flags & kFlagSkipWs) && (!workspace || workspace_bytes < ws_workspace_bytes(n)))
+        return fail(B64_EARG, "workspace smaller than b64_decode_workspace_size");
+    return decode_enqueue(src, n, dst, true, out_len, first_bad, alphabet, flags, workspace, stream,
+                          true);
 }
 
 int64_t b64_decode_async(const uint8_t *src, int64_t n, uint8_t *dst, int64_t *out_len,
                          int64_t *first_bad, const char *alphabet, hipStream_t stream)
 {
-    if (n < 0) return fail(B64_EARG, "negative length");
-    if ((n > 0 && (!src || !dst)) || !out_len || !first_bad) return fail(B64_EARG, "null pointer");
-    if (!alphabet_ok(alphabet)) return fail(B64_EARG, kBadAlphabet);
-    return decode_enqueue(src, n, dst, out_len, first_bad, alphabet, stream, true);
+    return b64_decode_mode_async(src, n, dst, out_len, first_bad, alphabet, 0, nullptr, 0, stream);
+}
+
+int64_t b64_decode_mode(const uint8_t *src, int64_t n, uint8_t *dst, const char *alphabet,
+                        uint32_t flags, hipStream_t stream)
+{
+    const int64_t c = check_decode_args(n, alphabet, flags);
+    if (c) return c;
+    if (n > 0 && (!src || !dst)) return fail(B64_EARG, "null buffer");
+    return decode_blocking(src, n, dst, true, alphabet, flags, stream);
 }
 
 int64_t b64_decode(const uint8_t *src, int64_t n, uint8_t *dst, const char *alphabet,
                    hipStream_t stream)
 {
-    if (n < 0) return fail(B64_EARG, "negative length");
-    if (n > 0 && (!src || !dst)) return fail(B64_EARG, "null buffer");
-    if (!alphabet_ok(alphabet)) return fail(B64_EARG, kBadAlphabet);
-    StatusSlot *slot = nullptr;
-    hipError_t e = status_slot(&slot);
-    if (e != hipSuccess) return hip_fail(e, "status slot");
-    // raw status: slot->d[0] = length if the tail is valid, slot->d[1] = the
-    // smallest invalid offset or kNoError; read back and combined here.
-    const int64_t r = decode_enqueue(src, n, dst, slot->d, slot->d + 1, alphabet, stream, false);
-    if (r) return r;
-    e = hipMemcpyAsync(slot->h, slot->d, 2 * sizeof(int64_t), hipMemcpyDeviceToHost, stream);
-    if (e != hipSuccess) return hip_fail(e, "status copy");
-    e = hipStreamSynchronize(stream);
-    if (e != hipSuccess) return hip_fail(e, "stream synchronize");
-    const int64_t len = slot->h[0], bad = slot->h[1];
-    return bad == kNoError ? len : ~bad;
+    return b64_decode_mode(src, n, dst, alphabet, 0, stream);
+}
+
+int64_t b64_validate_mode(const uint8_t *src, int64_t n, const char *alphabet, uint32_t flags,
+                          hipStream_t stream)
+{
+    const int64_t c = check_decode_args(n, alphabet, flags);
+    if (c) return c;
+    if (n > 0 && !src) return fail(B64_EARG, "null buffer");
+    return decode_blocking(src, n, nullptr, false, alphabet, flags, stream);
 }
 
 int64_t b64_validate(const uint8_t *src, int64_t n, const char *alphabet, hipStream_t stream)
 {
-    if (n < 0) return fail(B64_EARG, "negative length");
-    if (n > 0 && !src) return fail(B64_EARG, "null buffer");
-    if (!alphabet_ok(alphabet)) return fail(B64_EARG, kBadAlphabet);
-    StatusSlot *slot = nullptr;
-    hipError_t e = status_slot(&slot);
-    if (e != hipSuccess) return hip_fail(e, "status slot");
-    const int64_t r = validate_enqueue(src, n, slot->d, slot->d + 1, alphabet, stream, false);
-    if (r) return r;
-    e = hipMemcpyAsync(slot->h, slot->d, 2 * sizeof(int64_t), hipMemcpyDeviceToHost, stream);
-    if (e != hipSuccess) return hip_fail(e, "status copy");
-    e = hipStreamSynchronize(stream);
-    if (e != hipSuccess) return hip_fail(e, "stream synchronize");
-    const int64_t len = slot->h[0], bad = slot->h[1];
-    return bad == kNoError ? len : ~bad;
+    return b64_validate_mode(src, n, alphabet, 0, stream);
+}
+
+int64_t b64_validate_mode_async(const uint8_t *src, int64_t n, int64_t *out_len, int64_t *first_bad,
+                                const char *alphabet, uint32_t flags, void *workspace,
+                                int64_t workspace_bytes, hipStream_t stream)
+{
+    const int64_t c = check_decode_args(n, alphabet, flags);
+    if (c) return c;
+    if ((n > 0 && !src) || !out_len || !first_bad) return fail(B64_EARG, "null pointer");
+    if ((flags & kFlagSkipWs) && (!workspace || workspace_bytes < ws_workspace_bytes(n)))
+        return fail(B64_EARG, "workspace smaller than b64_decode_workspace_size");
+    return decode_enqueue(src, n, nullptr, false, out_len, first_bad, alphabet, flags, workspace,
+                          stream, true);
 }
 
 int64_t b64_validate_async(const uint8_t *src, int64_t n, int64_t *out_len, int64_t *first_bad,
                            const char *alphabet, hipStream_t stream)
 {
-    if (n < 0) return fail(B64_EARG, "negative length");
-    if ((n > 0 && !src) || !out_len || !first_bad) return fail(B64_EARG, "null pointer");
-    if (!alphabet_ok(alphabet)) return fail(B64_EARG, kBadAlphabet);
-    return validate_enqueue(src, n, out_len, first_bad, alphabet, stream, true);
+    return b64_validate_mode_async(src, n, out_len, first_bad, alphabet, 0, nullptr, 0, stream);
 }
 
-int64_t b64_encode_batch(const uint8_t *src, const int64_t *in_off, int64_t nbuf, uint8_t *dst,
-                         const int64_t *out_off, int64_t *out_len, const char *alphabet,
-                         hipStream_t stream)
+int64_t b64_encode_batch_mode(const uint8_t *src, const int64_t *in_off, int64_t nbuf, uint8_t *dst,
+                              const int64_t *out_off, int64_t *out_len, const char *alphabet,
+                              uint32_t flags, hipStream_t stream)
 {
     if (nbuf < 0) return fail(B64_EARG, "negative buffer count");
+    if (flags & ~kFlagNoPad) return fail(B64_EARG, "batched encode takes no flag but B64_NOPAD");
     if (nbuf == 0) return 0;
     if (!src || !in_off || !dst || !out_off || !out_len) return fail(B64_EARG, "null pointer");
     if (!alphabet_ok(alphabet)) return fail(B64_EARG, kBadAlphabet);
     int cus = 0;
     hipError_t e = cu_count(&cus);
     if (e != hipSuccess) return hip_fail(e, "device query");
-    e = launch_encode_batch(src, in_off, nbuf, dst, out_off, out_len, make_enc(alphabet),
+    e = launch_encode_batch(src, in_off, nbuf, dst, out_off, out_len, make_enc(alphabet), flags,
                             shape_of(2), cus, stream);
     return e == hipSuccess ? 0 : hip_fail(e, "encode_batch launch");
 }
 
-int64_t b64_decode_batch(const uint8_t *src, const int64_t *in_off, int64_t nbuf, uint8_t *dst,
-                         const int64_t *out_off, int64_t *out_len, int64_t *first_bad,
-                         const char *alphabet, hipStream_t stream)
+int64_t b64_encode_batch(const uint8_t *src, const int64_t *in_off, int64_t nbuf, uint8_t *dst,
+                         const int64_t *out_off, int64_t *out_len, const char *alphabet,
+                         hipStream_t stream)
+{
+    return b64_encode_batch_mode(src, in_off, nbuf, dst, out_off, out_len, alphabet, 0, stream);
+}
+
+int64_t b64_decode_batch_mode(const uint8_t *src, const int64_t *in_off, int64_t nbuf, uint8_t *dst,
+                              const int64_t *out_off, int64_t *out_len, int64_t *first_bad,
+                              const char *alphabet, uint32_t flags, hipStream_t stream)
 {
     if (nbuf < 0) return fail(B64_EARG, "negative buffer count");
+    if (flags & ~kFlagNoPad) return fail(B64_EARG, "batched decode takes no flag but B64_NOPAD");
     if (nbuf == 0) return 0;
     if (!src || !in_off || !dst || !out_off || !out_len || !first_bad)
         return fail(B64_EARG, "null pointer");
@@ -307,10 +445,18 @@ int64_t b64_decode_batch(const uint8_t *src, const int64_t *in_off, int64_t nbuf
     e = launch_fill(first_bad, nbuf, kNoError, stream);
     if (e != hipSuccess) return hip_fail(e, "fill launch");
     e = launch_decode_batch(src, in_off, nbuf, dst, out_off, out_len, first_bad,
-                            make_dec(alphabet), shape_of(3), cus, stream);
+                            make_dec(alphabet), flags, shape_of(3), cus, stream);
     if (e != hipSuccess) return hip_fail(e, "decode_batch launch");
     e = launch_finish(out_len, first_bad, nbuf, stream);
     return e == hipSuccess ? 0 : hip_fail(e, "status launch");
+}
+
+int64_t b64_decode_batch(const uint8_t *src, const int64_t *in_off, int64_t nbuf, uint8_t *dst,
+                         const int64_t *out_off, int64_t *out_len, int64_t *first_bad,
+                         const char *alphabet, hipStream_t stream)
+{
+    return b64_decode_batch_mode(src, in_off, nbuf, dst, out_off, out_len, first_bad, alphabet, 0,
+                                 stream);
 }
 
 }  // extern "C"

@@ -81,7 +81,8 @@ template <int U, bool NT>
 __device__ void encode_tile(const uint8_t *__restrict__ src, const int64_t *__restrict__ in_off,
                             int64_t nbuf, uint8_t *__restrict__ dst,
                             const int64_t *__restrict__ out_off, int64_t *__restrict__ out_len,
-                            const uint8_t *a, int64_t lo, int64_t hi, int64_t b0, bool last, int lane)
+                            const uint8_t *a, int64_t lo, int64_t hi, int64_t b0, bool last, int lane,
+                            bool pad)
 {
     if (b0 >= nbuf) return;
     // offsets of the next buffer, loaded one iteration ahead
@@ -96,7 +97,7 @@ __device__ void encode_tile(const uint8_t *__restrict__ src, const int64_t *__re
         if (s >= hi && !(last && s == hi)) break;
         const int64_t len = e - s;
         const int64_t ngroups = (len + 2) / 3, nfull = len / 3;
-        if (s >= lo && lane == 0) out_len[b] = 4 * ngroups;
+        if (s >= lo && lane == 0) out_len[b] = pad ? 4 * ngroups : (4 * len + 2) / 3;
         const int64_t g_lo = s >= lo ? 0 : (lo - s + 2) / 3;
         int64_t g_hi = hi <= s ? 0 : (hi - s + 2) / 3;
         if (g_hi > ngroups) g_hi = ngroups;
@@ -120,7 +121,7 @@ __device__ void encode_tile(const uint8_t *__restrict__ src, const int64_t *__re
         const int64_t g = lane < lead ? g_lo + lane : c_first + 4 * nchunk + (lane - lead);
         if (lane < 7 && g < g_hi) {
             const int64_t rem = len - 3 * g;
-            enc_scalar(src + s + 3 * g, rem < 3 ? rem : 3, ob + 4 * g, a);
+            enc_scalar(src + s + 3 * g, rem < 3 ? rem : 3, ob + 4 * g, a, pad);
         }
     }
 }
@@ -129,8 +130,9 @@ template <int U, bool NT>
 __global__ __launch_bounds__(kThreads) void k_encode_batch(
     const uint8_t *__restrict__ src, const int64_t *__restrict__ in_off, int64_t nbuf,
     uint8_t *__restrict__ dst, const int64_t *__restrict__ out_off, int64_t *__restrict__ out_len,
-    EncTab tab)
+    EncTab tab, uint32_t flags)
 {
+    const bool pad = !(flags & kFlagNoPad);
     __shared__ uint32_t s_tab[16];
     stage_enc_table(s_tab, tab);
     const uint8_t *a = (const uint8_t *)s_tab;
@@ -144,7 +146,7 @@ __global__ __launch_bounds__(kThreads) void k_encode_batch(
         const int64_t lo = tw.base + tile * tw.tile_bytes;
         const bool last = tile == tw.ntiles - 1;
         const int64_t hi = last ? tw.end : lo + tw.tile_bytes;
-        encode_tile<U, NT>(src, in_off, nbuf, dst, out_off, out_len, a, lo, hi, b0, last, lane);
+        encode_tile<U, NT>(src, in_off, nbuf, dst, out_off, out_len, a, lo, hi, b0, last, lane, pad);
     }
 }
 
@@ -160,7 +162,7 @@ __device__ void decode_tile(const uint8_t *__restrict__ src, const int64_t *__re
                             int64_t nbuf, uint8_t *__restrict__ dst,
                             const int64_t *__restrict__ out_off, int64_t *__restrict__ out_len,
                             int64_t *__restrict__ first_bad, const uint8_t *m, int64_t lo,
-                            int64_t hi, int64_t b0, bool last, int lane)
+                            int64_t hi, int64_t b0, bool last, int lane, bool nopad)
 {
     if (b0 >= nbuf) return;
     // offsets of the next buffer, loaded one iteration ahead
@@ -201,7 +203,7 @@ __device__ void decode_tile(const uint8_t *__restrict__ src, const int64_t *__re
         if (__ballot(err & 0x80)) {
             if (err & 0x80) {
                 for (int64_t k = lane; k < nchunk; k += 64) {
-                    const int64_t bad = dec_check_inner(sp + 16 * k, 16, m);
+                    const int64_t bad = dec_check_inner(sp + 16 * k, 16, m, nopad);
                     if (bad >= 0) {
                         atomic_min_i64(first_bad + b, 4 * c_first + 16 * k + bad);
                         break;
@@ -222,12 +224,12 @@ __device__ void decode_tile(const uint8_t *__restrict__ src, const int64_t *__re
                 qo[1] = (uint8_t)(v >> 8);
                 qo[2] = (uint8_t)v;
                 if (qerr & 0x80) {
-                    const int64_t bad = dec_check_inner(qp, 4, m);
+                    const int64_t bad = dec_check_inner(qp, 4, m, nopad);
                     if (bad >= 0) atomic_min_i64(first_bad + b, 4 * q + bad);
                 }
             } else {
                 int64_t ol = 0;
-                const int64_t bad = dec_tail(qp, len - 4 * q, len, qo, m, &ol);
+                const int64_t bad = dec_tail(qp, len - 4 * q, len, qo, m, &ol, nopad);
                 if (bad >= 0) atomic_min_i64(first_bad + b, 4 * q + bad);
                 else out_len[b] = ol;
             }
@@ -239,8 +241,9 @@ template <int U, bool NT>
 __global__ __launch_bounds__(kThreads) void k_decode_batch(
     const uint8_t *__restrict__ src, const int64_t *__restrict__ in_off, int64_t nbuf,
     uint8_t *__restrict__ dst, const int64_t *__restrict__ out_off, int64_t *__restrict__ out_len,
-    int64_t *__restrict__ first_bad, DecMap map)
+    int64_t *__restrict__ first_bad, DecMap map, uint32_t flags)
 {
+    const bool nopad = (flags & kFlagNoPad) != 0;
     __shared__ uint32_t s_map[64];
     stage_dec_map(s_map, map);
     const uint8_t *m = (const uint8_t *)s_map;
@@ -255,7 +258,7 @@ __global__ __launch_bounds__(kThreads) void k_decode_batch(
         const bool last = tile == tw.ntiles - 1;
         const int64_t hi = last ? tw.end : lo + tw.tile_bytes;
         decode_tile<U, NT>(src, in_off, nbuf, dst, out_off, out_len, first_bad, m, lo, hi, b0,
-                           last, lane);
+                           last, lane, nopad);
     }
 }
 
@@ -263,21 +266,22 @@ __global__ __launch_bounds__(kThreads) void k_decode_batch(
 
 hipError_t launch_encode_batch(const uint8_t *src, const int64_t *in_off, int64_t nbuf,
                                uint8_t *dst, const int64_t *out_off, int64_t *out_len,
-                               const EncTab &tab, Shape sh, int cus, hipStream_t stream)
+                               const EncTab &tab, uint32_t flags, Shape sh, int cus, hipStream_t stream)
 {
     const int64_t grid = (int64_t)cus * sh.bpc;
-    B64_DISPATCH(k_encode_batch, sh, grid, stream, src, in_off, nbuf, dst, out_off, out_len, tab);
+    B64_DISPATCH(k_encode_batch, sh, grid, stream, src, in_off, nbuf, dst, out_off, out_len, tab,
+                 flags);
     return hipGetLastError();
 }
 
 hipError_t launch_decode_batch(const uint8_t *src, const int64_t *in_off, int64_t nbuf,
                                uint8_t *dst, const int64_t *out_off, int64_t *out_len,
-                               int64_t *first_bad, const DecMap &map, Shape sh, int cus,
-                               hipStream_t stream)
+                               int64_t *first_bad, const DecMap &map, uint32_t flags, Shape sh,
+                               int cus, hipStream_t stream)
 {
     const int64_t grid = (int64_t)cus * sh.bpc;
     B64_DISPATCH(k_decode_batch, sh, grid, stream, src, in_off, nbuf, dst, out_off, out_len,
-                 first_bad, map);
+                 first_bad, map, flags);
     return hipGetLastError();
 }
 

@@ -41,6 +41,10 @@ constexpr int64_t kNoError = INT64_MAX;
 constexpr int kXcds = 8;               // MI355X: 8 accelerator dies, each with its own L2
 constexpr int kLine = 128;             // L2 cache line, bytes
 
+// Variant flags (the values of B64_NOPAD and B64_SKIP_WS in b64hip.h).
+constexpr uint32_t kFlagNoPad = 1;     // no '=': final quantum of 2 or 3 characters
+constexpr uint32_t kFlagSkipWs = 2;    // decode ignores space, tab, CR and LF
+
 // Runtime alphabet, passed by value as a kernel argument.
 struct EncTab { uint32_t w[16]; };     // byte v = character of value v
 struct DecMap { uint32_t w[64]; };     // byte c = value of character c, or kBad
@@ -108,21 +112,27 @@ __device__ __forceinline__ u32x4 enc_chunk(u32x3 in, const uint8_t *tab)
 }
 
 // Scalar path for 0..r bytes: whole groups, then a last group of one or two
-// bytes zero-filled and padded with '=' (Section "Base64").
-__device__ inline void enc_scalar(const uint8_t *p, int64_t r, uint8_t *o, const uint8_t *tab)
+// bytes zero-filled and either padded with '=' (Section "Base64") or, when
+// `pad` is false, cut to the 2 or 3 characters that carry input bits.
+__device__ inline void enc_scalar(const uint8_t *p, int64_t r, uint8_t *o, const uint8_t *tab,
+                                  bool pad = true)
 {
     int64_t i = 0;
     for (; i + 3 <= r; i += 3, o += 4) {
         uint32_t s1 = p[i], s2 = p[i + 1], s3 = p[i + 2];
         *(u32a1 *)o = enc_group(s2 | (s1 << 8) | (s3 << 16) | (s2 << 24), tab);
     }
-    if (r - i == 1) {
-        uint32_t q = enc_group((uint32_t)p[i] << 8, tab);
-        *(u32a1 *)o = (q & 0xFFFFu) | (kPad << 16) | (kPad << 24);
-    } else if (r - i == 2) {
-        uint32_t s1 = p[i], s2 = p[i + 1];
-        uint32_t q = enc_group(s2 | (s1 << 8) | (s2 << 24), tab);
-        *(u32a1 *)o = (q & 0xFFFFFFu) | (kPad << 24);
+    const int64_t k = r - i;
+    if (k == 0) return;
+    uint32_t q = k == 1 ? enc_group((uint32_t)p[i] << 8, tab)
+                        : enc_group(p[i + 1] | ((uint32_t)p[i] << 8) | ((uint32_t)p[i + 1] << 24), tab);
+    if (pad) {
+        q = k == 1 ? (q & 0xFFFFu) | (kPad << 16) | (kPad << 24) : (q & 0xFFFFFFu) | (kPad << 24);
+        *(u32a1 *)o = q;
+    } else {
+        o[0] = (uint8_t)q;
+        o[1] = (uint8_t)(q >> 8);
+        if (k == 2) o[2] = (uint8_t)(q >> 16);
     }
 }
 
@@ -180,15 +190,17 @@ enum { kData = 0, kPad1 = 1, kDone = 2 };
 // kPad1 after a '=' at quantum position 2, kDone after the final '='.
 // Rules: a non-alphabet character is invalid; '=' may stand only at quantum
 // positions 2 and 3; before "==" the last value needs four zero low bits,
-// before a single '=' two; nothing may follow the padded quantum.
-__device__ inline int64_t dec_validate(const uint8_t *p, int64_t len, const uint8_t *map, int *state)
+// before a single '=' two; nothing may follow the padded quantum.  With
+// `nopad`, '=' is an ordinary non-alphabet character.
+__device__ inline int64_t dec_validate(const uint8_t *p, int64_t len, const uint8_t *map, int *state,
+                                       bool nopad = false)
 {
     int st = kData;
     for (int64_t i = 0; i < len; ++i) {
         const uint32_t c = p[i];
         const int pos = (int)(i & 3);
         if (st == kDone) return i;
-        if (c != kPad) {
+        if (c != kPad || nopad) {
             if (map[c] == kBad || st == kPad1) return i;
             continue;
         }
@@ -209,38 +221,64 @@ __device__ inline int64_t dec_validate(const uint8_t *p, int64_t len, const uint
 // known to be followed by at least one more character, or -1 if the run is
 // clean.  A run ending with its padded quantum makes the next character the
 // first invalid one.
-__device__ __forceinline__ int64_t dec_check_inner(const uint8_t *p, int64_t len, const uint8_t *map)
+__device__ __forceinline__ int64_t dec_check_inner(const uint8_t *p, int64_t len, const uint8_t *map,
+                                                   bool nopad = false)
 {
     int st = kData;
-    int64_t bad = dec_validate(p, len, map, &st);
+    int64_t bad = dec_validate(p, len, map, &st, nopad);
     if (bad >= 0) return bad;
     return st == kDone ? len : -1;
 }
 
-// The last (up to 19) characters of a buffer: validate as the end of the
-// input and, when valid, decode them.  Returns -1 and sets *out_len (the
-// buffer's whole decoded length) when valid, else the first invalid offset
-// relative to p.  `n_total` is the buffer length, p starts at a quantum
-// boundary.
-__device__ inline int64_t dec_tail(const uint8_t *p, int64_t len, int64_t n_total, uint8_t *o,
-                            const uint8_t *map, int64_t *out_len)
+// The last characters of an input, p[0..len) from a quantum boundary to the
+// end (n_total characters in all), checked as the end of the input.  Returns
+// the first invalid offset relative to p, or -1 with *out_len set to the
+// input's decoded length.  Padded: the input must end in the data state with
+// a length that is a multiple of four, or right after the padded quantum.
+// Unpadded: a last quantum of one character is incomplete, and one of 2 (3)
+// characters needs a last value with four (two) zero low bits; otherwise the
+// input could still be completed, so the error is at the end.
+__device__ inline int64_t dec_end(const uint8_t *p, int64_t len, int64_t n_total, const uint8_t *map,
+                                  bool nopad, int64_t *out_len)
 {
     int st = kData;
-    int64_t bad = dec_validate(p, len, map, &st);
+    const int64_t bad = dec_validate(p, len, map, &st, nopad);
     if (bad >= 0) return bad;
-    if (st == kPad1 || ((n_total & 3) != 0 && st != kDone)) return len;
-    int npad = 0;
-    for (int64_t q = 0; q < len; q += 4) {
-        const uint32_t a = map[p[q]], b = map[p[q + 1]];
-        const bool pc = p[q + 2] == kPad, pd = p[q + 3] == kPad;
-        const uint32_t c = pc ? 0u : map[p[q + 2]], d = pd ? 0u : map[p[q + 3]];
-        const uint32_t v = (a << 18) | (b << 12) | (c << 6) | d;
-        *o++ = (uint8_t)(v >> 16);
-        if (!pc) *o++ = (uint8_t)(v >> 8);
-        if (!pd) *o++ = (uint8_t)v;
-        npad = (int)pc + (int)pd;
+    const int r = (int)(n_total & 3);
+    if (nopad) {
+        if (r == 1) return len;
+        if (r >= 2 && (map[p[len - 1]] & (r == 2 ? 15u : 3u))) return len;
+        *out_len = 3 * (n_total >> 2) + (r ? r - 1 : 0);
+    } else {
+        if (st == kPad1 || (r != 0 && st != kDone)) return len;
+        const int64_t pads = n_total >= 4 ? (int64_t)(p[len - 1] == kPad) + (p[len - 2] == kPad) : 0;
+        *out_len = 3 * (n_total >> 2) - pads;
     }
-    *out_len = 3 * (n_total >> 2) - npad;
+    return -1;
+}
+
+// The last (up to 19) characters of a buffer: validate as the end of the
+// input (dec_end) and, when valid, decode them.  Returns -1 and sets *out_len
+// (the buffer's whole decoded length) when valid, else the first invalid
+// offset relative to p.  A quantum of k data characters (4, or 2-3 before
+// '=' or the end) yields k-1 bytes.
+__device__ inline int64_t dec_tail(const uint8_t *p, int64_t len, int64_t n_total, uint8_t *o,
+                                   const uint8_t *map, int64_t *out_len, bool nopad = false)
+{
+    const int64_t bad = dec_end(p, len, n_total, map, nopad, out_len);
+    if (bad >= 0) return bad;
+    for (int64_t q = 0; q < len; q += 4) {
+        uint32_t v = 0;
+        int nd = 0;
+        for (int j = 0; j < 4; ++j) {
+            const bool data = q + j < len && p[q + j] != kPad;
+            v = (v << 6) | (data ? (uint32_t)map[p[q + j]] : 0u);
+            nd += data;
+        }
+        *o++ = (uint8_t)(v >> 16);
+        if (nd >= 3) *o++ = (uint8_t)(v >> 8);
+        if (nd == 4) *o++ = (uint8_t)v;
+    }
     return -1;
 }
 

@@ -18,28 +18,41 @@ struct Shape { int unroll, bpc, nt; };
 // `bpc` per CU; a whole number per XCD.
 int64_t grid_for(int64_t nch, Shape sh, int cus);
 
-hipError_t launch_encode(const uint8_t *src, int64_t n, uint8_t *dst, const EncTab &tab, Shape sh,
-                         int cus, hipStream_t stream);
+// `flags` carries kFlagNoPad (the other variant flags have kernels of their own).
+hipError_t launch_encode(const uint8_t *src, int64_t n, uint8_t *dst, const EncTab &tab, uint32_t flags,
+                         Shape sh, int cus, hipStream_t stream);
 // Single-buffer decode (k_decode only): *first_bad must hold kNoError before
 // it; afterwards it holds the first invalid offset or still kNoError, and
 // *out_len the decoded length when the input is valid.
 hipError_t launch_decode(const uint8_t *src, int64_t n, uint8_t *dst, const DecMap &map,
-                         int64_t *out_len, int64_t *first_bad, Shape sh, int cus,
+                         int64_t *out_len, int64_t *first_bad, uint32_t flags, Shape sh, int cus,
                          hipStream_t stream);
 // Read-only validation (k_validate): *first_bad must hold kNoError before it;
 // afterwards it holds the first invalid offset or still kNoError, and
 // *out_len the decoded length when the input is valid.
 hipError_t launch_validate(const uint8_t *src, int64_t n, const DecMap &map, int64_t *out_len,
-                           int64_t *first_bad, Shape sh, int cus, hipStream_t stream);
+                           int64_t *first_bad, uint32_t flags, Shape sh, int cus, hipStream_t stream);
 hipError_t launch_fill(int64_t *p, int64_t count, int64_t value, hipStream_t stream);
 hipError_t launch_finish(int64_t *out_len, int64_t *first_bad, int64_t count, hipStream_t stream);
 hipError_t launch_encode_batch(const uint8_t *src, const int64_t *in_off, int64_t nbuf,
                                uint8_t *dst, const int64_t *out_off, int64_t *out_len,
-                               const EncTab &tab, Shape sh, int cus, hipStream_t stream);
+                               const EncTab &tab, uint32_t flags, Shape sh, int cus, hipStream_t stream);
 hipError_t launch_decode_batch(const uint8_t *src, const int64_t *in_off, int64_t nbuf,
                                uint8_t *dst, const int64_t *out_off, int64_t *out_len,
-                               int64_t *first_bad, const DecMap &map, Shape sh, int cus,
-                               hipStream_t stream);
+                               int64_t *first_bad, const DecMap &map, uint32_t flags, Shape sh,
+                               int cus, hipStream_t stream);
+// Line-wrapped encode (k_encode_wrap): line_len > 0, a multiple of 4.
+hipError_t launch_encode_wrap(const uint8_t *src, int64_t n, uint8_t *dst, const EncTab &tab,
+                              uint32_t flags, int64_t line_len, Shape sh, int cus, hipStream_t stream);
+// Whitespace-skipping decode (`write`) or validation (!`write`, dst unused):
+// five launches on `stream`, ending with the public status in *out_len and
+// *first_bad.  `map` holds the codes of make_dec_ws (b64_abi.hip);
+// `workspace` holds ws_workspace_bytes(n) bytes.
+int64_t ws_tile_size(int64_t n);
+int64_t ws_workspace_bytes(int64_t n);
+hipError_t launch_decode_ws(const uint8_t *src, int64_t n, uint8_t *dst, bool write, const DecMap &map,
+                            int64_t *out_len, int64_t *first_bad, uint32_t flags, void *workspace,
+                            Shape sh, int cus, hipStream_t stream);
 
 }  // namespace b64hip
 

@@ -9,10 +9,12 @@ namespace {
 // covers input [3*head + 12c, +12) and output [4*head + 16c, +16), grid-stride
 // with U chunks in flight per lane.  Threads t < head encode one head group
 // each; the last thread encodes the at most three whole groups and the
-// partial group left after the chunks.
+// partial group left after the chunks (padded, or cut short under
+// kFlagNoPad).
 template <int U, bool NT>
 __global__ __launch_bounds__(kThreads) void k_encode(const uint8_t *__restrict__ src, int64_t n,
-                                                     uint8_t *__restrict__ dst, EncTab tab)
+                                                     uint8_t *__restrict__ dst, EncTab tab,
+                                                     uint32_t flags)
 {
     __shared__ uint32_t s_tab[16];
     stage_enc_table(s_tab, tab);
@@ -36,7 +38,7 @@ __global__ __launch_bounds__(kThreads) void k_encode(const uint8_t *__restrict__
     if (t < head) enc_scalar(src + 3 * t, 3, dst + 4 * t, a);
     if (t == kThreads - 1) {
         const int64_t g = head + 4 * nch;
-        enc_scalar(src + 3 * g, n - 3 * g, dst + 4 * g, a);
+        enc_scalar(src + 3 * g, n - 3 * g, dst + 4 * g, a, !(flags & kFlagNoPad));
     }
 }
 
@@ -51,13 +53,16 @@ __global__ __launch_bounds__(kThreads) void k_encode(const uint8_t *__restrict__
 // published with an atomic minimum on it.  out_len is written only when the
 // tail is valid.  (A last-block-finishes protocol would save the status
 // launches, but its device-scope fence at the end of every block writes back
-// L2 on this multi-XCD part, which costs far more than a launch.)
+// L2 on this multi-XCD part, which costs far more than a launch.)  Under
+// kFlagNoPad '=' is invalid everywhere and the last quantum may have 2 or 3
+// characters; the body is the same.
 template <int U, bool NT>
 __global__ __launch_bounds__(kThreads) void k_decode(const uint8_t *__restrict__ src, int64_t n,
                                                      uint8_t *__restrict__ dst, DecMap map,
                                                      int64_t *__restrict__ out_len,
-                                                     int64_t *__restrict__ first_bad)
+                                                     int64_t *__restrict__ first_bad, uint32_t flags)
 {
+    const bool nopad = (flags & kFlagNoPad) != 0;
     __shared__ uint32_t s_map[64];
     stage_dec_map(s_map, map);
     const uint8_t *m = (const uint8_t *)s_map;
@@ -82,7 +87,7 @@ __global__ __launch_bounds__(kThreads) void k_decode(const uint8_t *__restrict__
     if (__ballot(err & 0x80)) {
         if (err & 0x80) {
             for (int64_t c = t; c < nch; c += T) {
-                const int64_t bad = dec_check_inner(s0 + 16 * c, 16, m);
+                const int64_t bad = dec_check_inner(s0 + 16 * c, 16, m, nopad);
                 if (bad >= 0) {
                     atomic_min_i64(first_bad, 4 * head + 16 * c + bad);
                     break;   // later chunks of this lane have larger offsets
@@ -97,13 +102,13 @@ __global__ __launch_bounds__(kThreads) void k_decode(const uint8_t *__restrict__
         dst[3 * t + 1] = (uint8_t)(v >> 8);
         dst[3 * t + 2] = (uint8_t)v;
         if (qerr & 0x80) {
-            const int64_t bad = dec_check_inner(src + 4 * t, 4, m);
+            const int64_t bad = dec_check_inner(src + 4 * t, 4, m, nopad);
             if (bad >= 0) atomic_min_i64(first_bad, 4 * t + bad);
         }
     }
     if (t == kThreads - 1) {
         const int64_t q = head + 4 * nch;
-        const int64_t bad = dec_tail(src + 4 * q, n - 4 * q, n, dst + 3 * q, m, out_len);
+        const int64_t bad = dec_tail(src + 4 * q, n - 4 * q, n, dst + 3 * q, m, out_len, nopad);
         if (bad >= 0) atomic_min_i64(first_bad, 4 * q + bad);
     }
 }
@@ -140,21 +145,21 @@ int64_t grid_for(int64_t nch, Shape sh, int cus)
     return grid < 1 ? 1 : grid;
 }
 
-hipError_t launch_encode(const uint8_t *src, int64_t n, uint8_t *dst, const EncTab &tab, Shape sh,
-                         int cus, hipStream_t stream)
+hipError_t launch_encode(const uint8_t *src, int64_t n, uint8_t *dst, const EncTab &tab, uint32_t flags,
+                         Shape sh, int cus, hipStream_t stream)
 {
     const int64_t grid = grid_for(n / 12, sh, cus);
-    B64_DISPATCH(k_encode, sh, grid, stream, src, n, dst, tab);
+    B64_DISPATCH(k_encode, sh, grid, stream, src, n, dst, tab, flags);
     return hipGetLastError();
 }
 
 hipError_t launch_decode(const uint8_t *src, int64_t n, uint8_t *dst, const DecMap &map,
-                         int64_t *out_len, int64_t *first_bad, Shape sh, int cus,
+                         int64_t *out_len, int64_t *first_bad, uint32_t flags, Shape sh, int cus,
                          hipStream_t stream)
 {
     const int64_t nbq = n >= 1 ? (n - 1) >> 2 : 0;
     const int64_t grid = grid_for(nbq >> 2, sh, cus);
-    B64_DISPATCH(k_decode, sh, grid, stream, src, n, dst, map, out_len, first_bad);
+    B64_DISPATCH(k_decode, sh, grid, stream, src, n, dst, map, out_len, first_bad, flags);
     return hipGetLastError();
 }
 

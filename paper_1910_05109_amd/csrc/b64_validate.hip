@@ -63,12 +63,14 @@ __device__ __forceinline__ uint32_t val_stream(const uint8_t *s0, int64_t c0, in
 // [16c, 16c+16).  The last thread validates the characters after the chunks
 // (at most three body quanta and the last quantum) as the end of the input
 // and, when they are valid, writes the decoded length.  first_bad must hold
-// kNoError before the launch.
+// kNoError before the launch.  kFlagNoPad selects the unpadded rules.
 template <int U, bool NT>
 __global__ __launch_bounds__(kThreads) void k_validate(const uint8_t *__restrict__ src, int64_t n,
                                                        DecMap map, int64_t *__restrict__ out_len,
-                                                       int64_t *__restrict__ first_bad)
+                                                       int64_t *__restrict__ first_bad,
+                                                       uint32_t flags)
 {
+    const bool nopad = (flags & kFlagNoPad) != 0;
     __shared__ uint32_t s_map[64];
     stage_dec_map(s_map, map);
     const uint8_t *m = (const uint8_t *)s_map;
@@ -83,7 +85,7 @@ __global__ __launch_bounds__(kThreads) void k_validate(const uint8_t *__restrict
     if (__ballot(err & 0x80)) {
         if (err & 0x80) {
             for (int64_t c = t; c < nch; c += T) {
-                const int64_t bad = dec_check_inner(src + 16 * c, 16, m);
+                const int64_t bad = dec_check_inner(src + 16 * c, 16, m, nopad);
                 if (bad >= 0) {
                     atomic_min_i64(first_bad, 16 * c + bad);
                     break;   // later chunks of this lane have larger offsets
@@ -94,27 +96,21 @@ __global__ __launch_bounds__(kThreads) void k_validate(const uint8_t *__restrict
     if (t == kThreads - 1) {
         const int64_t q0 = 4 * nch;                 // first quantum after the chunks
         const uint8_t *p = src + 4 * q0;
-        const int64_t len = n - 4 * q0;
-        int st = kData;
-        int64_t bad = dec_validate(p, len, m, &st);
-        if (bad < 0 && (st == kPad1 || ((n & 3) != 0 && st != kDone))) bad = len;
-        if (bad >= 0) {
-            atomic_min_i64(first_bad, 4 * q0 + bad);
-        } else {
-            const int64_t pads = n >= 4 ? (int64_t)(src[n - 1] == kPad) + (src[n - 2] == kPad) : 0;
-            *out_len = 3 * (n >> 2) - pads;
-        }
+        int64_t len = 0;
+        const int64_t bad = dec_end(p, n - 4 * q0, n, m, nopad, &len);
+        if (bad >= 0) atomic_min_i64(first_bad, 4 * q0 + bad);
+        else *out_len = len;
     }
 }
 
 }  // namespace
 
 hipError_t launch_validate(const uint8_t *src, int64_t n, const DecMap &map, int64_t *out_len,
-                           int64_t *first_bad, Shape sh, int cus, hipStream_t stream)
+                           int64_t *first_bad, uint32_t flags, Shape sh, int cus, hipStream_t stream)
 {
     const int64_t nbq = n >= 1 ? (n - 1) >> 2 : 0;
     const int64_t grid = grid_for(nbq >> 2, sh, cus);
-    B64_DISPATCH(k_validate, sh, grid, stream, src, n, map, out_len, first_bad);
+    B64_DISPATCH(k_validate, sh, grid, stream, src, n, map, out_len, first_bad, flags);
     return hipGetLastError();
 }
 

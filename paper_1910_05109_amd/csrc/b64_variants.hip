@@ -1,0 +1,687 @@
+// b64_variants.hip -- line-wrapped encode and whitespace-skipping decode.
+//
+// The paper's codec handles base64 as one unbroken string; MIME email, which
+// the paper names as a main carrier of base64 (Section "Introduction"), breaks
+// it into lines separated by CR LF.  These kernels add the two MIME-style
+// variants on top of the same per-lane arithmetic (enc_chunk, the 256-entry
+// LDS map):
+//
+// Wrapped encode (k_encode_wrap).  Character j of the unwrapped encoding goes
+// to position j + 2*floor(j / L) and a CR LF precedes every line after the
+// first.  Lane chunks are the plain kernel's (12 bytes -> 16 characters); a
+// lane tracks the line and column of its chunk incrementally, so no 64-bit
+// division runs per chunk, and stores each group of four characters (L is a
+// multiple of 4, so a line never splits a group) plus a CR LF where a line
+// starts.
+//
+// Whitespace-skipping decode.  The significant characters (all but space,
+// tab, CR, LF) form the encoding; their positions in the input depend on
+// every whitespace byte before them, so decoding is a stream compaction.
+// After a status reset (k_ws_init), four kernels, with no inter-block waiting:
+//   k_ws_count   per tile of TS characters: the number of significant
+//                characters, and (atomic minima) the first invalid character
+//                and the first '='.
+//   k_ws_scan    one block: inclusive prefix sums of the tile counts.
+//   k_ws_decode  per tile: the block compacts its significant values into an
+//                LDS ring (a block-wide exclusive scan per round gives each
+//                thread its write position) and decodes the whole quanta
+//                whose first value lies in the tile; the last one may borrow
+//                up to three values from the following tiles.
+//   k_ws_finish  one block: the '=' and end-of-input rules over the sequence
+//                of significant characters, the final quantum, the status.
+// Tiles are dealt to blocks grid-stride, so the grid streams through one
+// window of memory.
+#include "b64_launch.h"
+
+namespace b64hip {
+namespace {
+
+typedef uint16_t u16a1 __attribute__((aligned(1)));
+
+// ------------------------------------------------------------ wrapped encode --
+
+// Output position of character j of the unwrapped encoding for lines of L.
+__device__ __forceinline__ int64_t wrap_pos(int64_t j, int64_t L) { return j + 2 * (j / L); }
+
+// Characters [j0, j0+4k) of the unwrapped encoding, given as k words of four,
+// stored for lines of L; (line, col) are those of character j0 (col a
+// multiple of 4, col < L).
+__device__ __forceinline__ void store_wrapped(uint8_t *dst, int64_t j0, int64_t line, int64_t col,
+                                              int64_t L, const uint32_t *w, int k)
+{
+    for (int g = 0; g < k; ++g) {
+        const int64_t j = j0 + 4 * g;
+        const int64_t pos = j + 2 * line;
+        if (col == 0 && j > 0) *(u16a1 *)(dst + pos - 2) = (uint16_t)('\r' | ('\n' << 8));
+        *(u32a1 *)(dst + pos) = w[g];
+        col += 4;
+        if (col == L) {
+            col = 0;
+            ++line;
+        }
+    }
+}
+
+// Scalar tail: input bytes p[0..r) whose first character has index j0; the
+// last group is padded or, with !pad, cut to the characters that carry bits.
+__device__ void enc_scalar_wrap(const uint8_t *p, int64_t r, int64_t j0, uint8_t *dst, int64_t L,
+                                const uint8_t *tab, bool pad)
+{
+    uint8_t ch[16];
+    int m = 0;
+    for (int64_t i = 0; i < r; i += 3) {
+        const int64_t k = r - i < 3 ? r - i : 3;
+        const uint32_t s1 = p[i], s2 = k > 1 ? p[i + 1] : 0u, s3 = k > 2 ? p[i + 2] : 0u;
+        const uint32_t q = enc_group(s2 | (s1 << 8) | (s3 << 16) | (s2 << 24), tab);
+        const int keep = k == 3 ? 4 : (int)k + 1;
+        for (int c = 0; c < 4; ++c) {
+            if (c < keep) ch[m++] = (uint8_t)(q >> (8 * c));
+            else if (pad) ch[m++] = (uint8_t)kPad;
+        }
+    }
+    for (int c = 0; c < m; ++c) {
+        const int64_t j = j0 + c;
+        const int64_t pos = wrap_pos(j, L);
+        if (j % L == 0 && j > 0) {
+            dst[pos - 2] = '\r';
+            dst[pos - 1] = '\n';
+        }
+        dst[pos] = ch[c];
+    }
+}
+
+// Lane chunk c (input [12c, 12c+12), characters [16c, 16c+16)) for chunks
+// c = t, t+T, ... < nch, U in flight; the last thread encodes what follows
+// the chunks.
+template <int U, bool NT>
+__global__ __launch_bounds__(kThreads) void k_encode_wrap(const uint8_t *__restrict__ src, int64_t n,
+                                                          uint8_t *__restrict__ dst, EncTab tab,
+                                                          uint32_t flags, int64_t L)
+{
+    __shared__ uint32_t s_tab[16];
+    stage_enc_table(s_tab, tab);
+    const uint8_t *a = (const uint8_t *)s_tab;
+
+    const int64_t nch = n / 12;
+    const int64_t T = (int64_t)gridDim.x * kThreads;
+    const int64_t t = logical_block() * kThreads + threadIdx.x;
+    // line / column of this thread's first character and their steps per T chunks
+    int64_t line = (16 * t) / L, col = (16 * t) % L;
+    const int64_t dline = (16 * T) / L, dcol = (16 * T) % L;
+    for (int64_t c0 = t; c0 < nch; c0 += U * T) {
+        u32x3 in[U];
+#pragma unroll
+        for (int j = 0; j < U; ++j) {
+            const int64_t c = c0 + j * T;
+            in[j] = load12<NT>(src + 12 * (c < nch ? c : nch - 1));
+        }
+#pragma unroll
+        for (int j = 0; j < U; ++j) {
+            const int64_t c = c0 + j * T;
+            if (c < nch) {
+                const u32x4 o = enc_chunk(in[j], a);
+                const uint32_t w[4] = {o.x, o.y, o.z, o.w};
+                store_wrapped(dst, 16 * c, line, col, L, w, 4);
+            }
+            line += dline;
+            col += dcol;
+            if (col >= L) {
+                col -= L;
+                ++line;
+            }
+        }
+    }
+    if (t == kThreads - 1)
+        enc_scalar_wrap(src + 12 * nch, n - 12 * nch, 16 * nch, dst, L, a, !(flags & kFlagNoPad));
+}
+
+// ------------------------------------------------ whitespace-skipping decode --
+
+// Map codes: 0..63 alphabet values, kWsCode for the four ignored bytes,
+// kPadCode for '=' in padded mode, kBadCode for everything else.  Bit 6 marks
+// whitespace, bit 7 an invalid character or '='.
+constexpr uint32_t kWsCode = 0x40, kBadCode = 0x80, kPadCode = 0x81;
+constexpr int kWsBlock = 256;            // threads per block of the tile kernels
+constexpr int64_t kRound = kWsBlock * 16;   // characters per block round
+
+__device__ __forceinline__ bool is_sig(uint32_t code) { return !(code & kWsCode); }
+
+// Four codes of a dword of characters, packed as bytes.
+__device__ __forceinline__ uint32_t codes4(uint32_t q, const uint8_t *map)
+{
+    return (uint32_t)map[q & 0xFF] | ((uint32_t)map[(q >> 8) & 0xFF] << 8) |
+           ((uint32_t)map[(q >> 16) & 0xFF] << 16) | ((uint32_t)map[q >> 24] << 24);
+}
+
+// The 16 characters of thread `tid` in round `r` of a tile as packed codes;
+// characters at or past n read as whitespace.
+template <bool NT>
+__device__ __forceinline__ u32x4 ws_codes(const uint8_t *src, int64_t n, int64_t p,
+                                          const uint8_t *map)
+{
+    u32x4 c;
+    if (p + 16 <= n) {
+        const u32x4 q = load16<NT>(src + p);
+        c.x = codes4(q.x, map);
+        c.y = codes4(q.y, map);
+        c.z = codes4(q.z, map);
+        c.w = codes4(q.w, map);
+    } else {
+        uint32_t w[4] = {0, 0, 0, 0};
+        for (int j = 0; j < 16; ++j) {
+            const uint32_t code = p + j < n ? (uint32_t)map[src[p + j]] : kWsCode;
+            w[j >> 2] |= code << (8 * (j & 3));
+        }
+        c.x = w[0];
+        c.y = w[1];
+        c.z = w[2];
+        c.w = w[3];
+    }
+    return c;
+}
+
+__device__ __forceinline__ int sig_count(u32x4 c)
+{
+    // significant = bit 6 clear
+    return 16 - __builtin_popcount(c.x & 0x40404040u) - __builtin_popcount(c.y & 0x40404040u) -
+           __builtin_popcount(c.z & 0x40404040u) - __builtin_popcount(c.w & 0x40404040u);
+}
+
+__device__ __forceinline__ int64_t ws_tiles(int64_t n, int64_t TS) { return n > 0 ? (n + TS - 1) / TS : 0; }
+
+// Block-wide exclusive scan of v (one value per thread); *total gets the sum.
+// Uses wtot[kWsBlock/64]; contains one __syncthreads.
+__device__ __forceinline__ int block_excl_scan(int v, int *wtot, int *total)
+{
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    int x = v;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const int y = __shfl_up(x, d, 64);
+        if (lane >= d) x += y;
+    }
+    if (lane == 63) wtot[wv] = x;
+    __syncthreads();
+    int before = 0, all = 0;
+#pragma unroll
+    for (int k = 0; k < kWsBlock / 64; ++k) {
+        const int s = wtot[k];
+        before += k < wv ? s : 0;
+        all += s;
+    }
+    *total = all;
+    return before + x - v;
+}
+
+// k_ws_count: tile `tile` covers characters [tile*TS, min(n, (tile+1)*TS));
+// prefix[tile+1] receives its number of significant characters.  Invalid
+// characters go to *first_bad, '=' (padded mode) to *first_pad, both by
+// atomic minimum; both must hold kNoError before the launch.
+template <bool NT>
+__global__ __launch_bounds__(kWsBlock) void k_ws_count(const uint8_t *__restrict__ src, int64_t n,
+                                                       DecMap map, int64_t TS,
+                                                       int64_t *__restrict__ prefix,
+                                                       int64_t *__restrict__ first_pad,
+                                                       int64_t *__restrict__ first_bad)
+{
+    __shared__ uint32_t s_map[64];
+    __shared__ int s_sum;
+    stage_dec_map(s_map, map);
+    const uint8_t *m = (const uint8_t *)s_map;
+    const int64_t ntiles = ws_tiles(n, TS);
+    for (int64_t tile = logical_block(); tile < ntiles; tile += gridDim.x) {
+        const int64_t base = tile * TS, end = base + TS < n ? base + TS : n;
+        int cnt = 0;
+        uint32_t err = 0;
+        for (int64_t p = base + 16 * threadIdx.x; p < end; p += kRound) {
+            const u32x4 c = ws_codes<NT>(src, end, p, m);
+            cnt += sig_count(c);
+            err |= c.x | c.y | c.z | c.w;
+        }
+        // err ORs packed codes: bit 7 of any byte flags an invalid character or '='
+        if (__ballot(err & 0x80808080u)) {
+            if (err & 0x80808080u) {
+                bool bad_found = false, pad_found = false;
+                for (int64_t p = base + 16 * threadIdx.x; p < end && !(bad_found && pad_found); p += kRound) {
+                    for (int64_t i = p; i < p + 16 && i < end; ++i) {
+                        const uint32_t code = m[src[i]];
+                        if (code == kBadCode && !bad_found) {
+                            atomic_min_i64(first_bad, i);
+                            bad_found = true;
+                        } else if (code == kPadCode && !pad_found) {
+                            atomic_min_i64(first_pad, i);
+                            pad_found = true;
+                        }
+                    }
+                }
+            }
+        }
+        if (threadIdx.x == 0) s_sum = 0;
+        __syncthreads();
+        // sum over the block: wave sums, then one LDS atomic per wave
+        int x = cnt;
+#pragma unroll
+        for (int d = 32; d >= 1; d >>= 1) x += __shfl_xor(x, d, 64);
+        if ((threadIdx.x & 63) == 0) atomicAdd(&s_sum, x);
+        __syncthreads();
+        if (threadIdx.x == 0) prefix[tile + 1] = s_sum;
+        __syncthreads();
+    }
+}
+
+// k_ws_scan: prefix[0] = 0 and prefix[1..ntiles] turned into inclusive sums,
+// by one block in passes of kScanThreads*kScanPer values.
+constexpr int kScanThreads = 1024, kScanPer = 8;
+
+__global__ __launch_bounds__(kScanThreads) void k_ws_scan(int64_t *__restrict__ prefix, int64_t ntiles)
+{
+    __shared__ int64_t wsum[kScanThreads / 64];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    int64_t carry = 0;
+    if (threadIdx.x == 0) prefix[0] = 0;
+    for (int64_t base = 1; base <= ntiles; base += (int64_t)kScanThreads * kScanPer) {
+        int64_t v[kScanPer];
+        const int64_t i0 = base + (int64_t)threadIdx.x * kScanPer;
+        int64_t run = 0;
+#pragma unroll
+        for (int k = 0; k < kScanPer; ++k) {
+            v[k] = i0 + k <= ntiles ? prefix[i0 + k] : 0;
+            run += v[k];
+        }
+        // exclusive scan of the per-thread sums over the block
+        int64_t x = run;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const int64_t y = __shfl_up(x, d, 64);
+            if (lane >= d) x += y;
+        }
+        if (lane == 63) wsum[wv] = x;
+        __syncthreads();
+        int64_t before = 0, all = 0;
+#pragma unroll
+        for (int k = 0; k < kScanThreads / 64; ++k) {
+            before += k < wv ? wsum[k] : 0;
+            all += wsum[k];
+        }
+        int64_t acc = carry + before + x - run;
+#pragma unroll
+        for (int k = 0; k < kScanPer; ++k) {
+            acc += v[k];
+            if (i0 + k <= ntiles) prefix[i0 + k] = acc;
+        }
+        carry += all;
+        __syncthreads();
+    }
+}
+
+// Index of the tile that holds significant character g (0 <= g < total):
+// the last u with prefix[u] <= g.
+__device__ int64_t tile_of(const int64_t *prefix, int64_t ntiles, int64_t g)
+{
+    int64_t lo = 0, hi = ntiles;          // prefix[lo] <= g < prefix[hi]
+    while (hi - lo > 1) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (prefix[mid] <= g) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// Position of the first significant character at or after pos, or n.
+__device__ int64_t next_sig(const uint8_t *src, int64_t n, int64_t pos, const uint8_t *m,
+                            const int64_t *prefix, int64_t ntiles, int64_t TS)
+{
+    const int64_t total = prefix[ntiles];
+    while (pos < n) {
+        const int64_t u = pos / TS, end = (u + 1) * TS < n ? (u + 1) * TS : n;
+        for (; pos < end; ++pos)
+            if (is_sig(m[src[pos]])) return pos;
+        const int64_t g = prefix[u + 1];     // index of the next significant character
+        if (g >= total) return n;
+        pos = tile_of(prefix, ntiles, g) * TS;
+    }
+    return n;
+}
+
+// Position of the last significant character before pos, or -1.
+__device__ int64_t prev_sig(const uint8_t *src, int64_t n, int64_t pos, const uint8_t *m,
+                            const int64_t *prefix, int64_t ntiles, int64_t TS)
+{
+    while (pos > 0) {
+        const int64_t u = (pos - 1) / TS, start = u * TS;
+        for (int64_t i = pos - 1; i >= start; --i)
+            if (is_sig(m[src[i]])) return i;
+        const int64_t g = prefix[u] - 1;     // index of the previous significant character
+        if (g < 0) return -1;
+        const int64_t v = tile_of(prefix, ntiles, g);
+        pos = (v + 1) * TS < n ? (v + 1) * TS : n;
+    }
+    return -1;
+}
+
+// Three bytes of the quantum of values w = v0 | v1<<8 | v2<<16 | v3<<24, as
+// b0 | b1<<8 | b2<<16 (the closed form of Section "Base64").
+__device__ __forceinline__ uint32_t ws_quantum(uint32_t w)
+{
+    const uint32_t v = ((w & 0x3F) << 18) | (((w >> 8) & 0x3F) << 12) | (((w >> 16) & 0x3F) << 6) |
+                       ((w >> 24) & 0x3F);
+    return __builtin_amdgcn_perm(0u, v, 0x0C000102u);   // v.b2 v.b1 v.b0 0
+}
+
+__device__ __forceinline__ void store3(uint8_t *o, uint32_t b)
+{
+    o[0] = (uint8_t)b;
+    o[1] = (uint8_t)(b >> 8);
+    o[2] = (uint8_t)(b >> 16);
+}
+
+constexpr int kRing = 16384;             // LDS ring of significant values, bytes
+
+// k_ws_decode: tile `tile` decodes the quanta whose first significant value
+// lies in it, except quanta at index >= qlimit (the final quantum, left to
+// k_ws_finish).  Quantum q covers significant values [4q, 4q+4) and writes
+// dst[3q, 3q+3).
+template <bool NT>
+__global__ __launch_bounds__(kWsBlock) void k_ws_decode(const uint8_t *__restrict__ src, int64_t n,
+                                                        uint8_t *__restrict__ dst, DecMap map,
+                                                        int64_t TS, const int64_t *__restrict__ prefix,
+                                                        uint32_t flags)
+{
+    __shared__ uint32_t s_map[64];
+    __shared__ __align__(16) uint8_t ring[kRing];
+    __shared__ int wtot[kWsBlock / 64];
+    __shared__ uint32_t s_extra;
+    stage_dec_map(s_map, map);
+    const uint8_t *m = (const uint8_t *)s_map;
+    const int64_t ntiles = ws_tiles(n, TS);
+    if (ntiles == 0) return;
+    const int64_t total = prefix[ntiles];
+    const bool nopad = (flags & kFlagNoPad) != 0;
+    const int64_t qlimit = nopad ? total / 4 : (total >= 4 ? total / 4 - 1 : 0);
+    const int tid = threadIdx.x;
+
+    for (int64_t tile = logical_block(); tile < ntiles; tile += gridDim.x) {
+        const int64_t base = tile * TS, end = base + TS < n ? base + TS : n;
+        const int64_t K0 = prefix[tile], C = prefix[tile + 1] - K0;
+        const int64_t skip = (4 - (K0 & 3)) & 3;
+        if (C <= skip) continue;                     // block-uniform
+        const int64_t Q0 = (K0 + skip) >> 2;
+        if (Q0 >= qlimit) continue;
+        int64_t W = -skip, Rd = 0;                   // ring write / read counters
+        for (int64_t p0 = base; p0 < end; p0 += kRound) {
+            const u32x4 c = ws_codes<NT>(src, end, p0 + 16 * tid, m);
+            const uint32_t cw[4] = {c.x, c.y, c.z, c.w};
+            int tot = 0;
+            const int ex = block_excl_scan(sig_count(c), wtot, &tot);
+            int64_t pos = W + ex;
+#pragma unroll
+            for (int j = 0; j < 16; ++j) {
+                const uint32_t code = (cw[j >> 2] >> (8 * (j & 3))) & 0xFF;
+                if (is_sig(code)) {
+                    if (pos >= 0) ring[pos & (kRing - 1)] = (uint8_t)code;
+                    ++pos;
+                }
+            }
+            W += tot;
+            __syncthreads();
+            const int64_t avail = W - Rd;
+            const int64_t nfull = avail > 0 ? avail >> 4 : 0;
+            if (tid < nfull) {
+                const int64_t r = Rd + 16 * tid;
+                const uint4 v = *(const uint4 *)(ring + (r & (kRing - 1)));
+                const int64_t q = Q0 + (r >> 2);
+                const uint32_t b0 = ws_quantum(v.x), b1 = ws_quantum(v.y), b2 = ws_quantum(v.z),
+                               b3 = ws_quantum(v.w);
+                if (q + 4 <= qlimit) {
+                    u32x3 o;
+                    o.x = b0 | (b1 << 24);
+                    o.y = (b1 >> 8) | (b2 << 16);
+                    o.z = (b2 >> 16) | (b3 << 8);
+                    store12<NT>(dst + 3 * q, o);
+                } else {
+                    const uint32_t b[4] = {b0, b1, b2, b3};
+                    for (int k = 0; k < 4; ++k)
+                        if (q + k < qlimit) store3(dst + 3 * (q + k), b[k]);
+                }
+            }
+            Rd += 16 * nfull;
+            // the ring holds 16 KiB: this round's reads and the next round's
+            // writes never meet, and block_excl_scan's barrier orders wtot
+        }
+        // fewer than 16 values left: whole quanta, then one quantum that may
+        // take up to three values from later tiles
+        const int64_t left = W - Rd;
+        if (left > 0) {
+            const int64_t rem = left & 3;
+            if (tid == 0) {
+                uint32_t extra = 0;
+                if (rem) {
+                    // significant values K0+C, K0+C+1, ... (as many as exist)
+                    int64_t g = K0 + C;
+                    int got = 0;
+                    while (got < 4 - rem && g < total) {
+                        const int64_t u = tile_of(prefix, ntiles, g);
+                        int64_t idx = prefix[u];
+                        const int64_t ue = (u + 1) * TS < n ? (u + 1) * TS : n;
+                        for (int64_t i = u * TS; i < ue && got < 4 - rem; ++i) {
+                            const uint32_t code = m[src[i]];
+                            if (!is_sig(code)) continue;
+                            if (idx == g) {
+                                extra |= code << (8 * got);
+                                ++got;
+                                ++g;
+                            }
+                            ++idx;
+                        }
+                    }
+                }
+                s_extra = extra;
+            }
+            __syncthreads();
+            const int64_t nq = (left + 3) >> 2;
+            if (tid < nq) {
+                const int64_t r = Rd + 4 * tid;
+                const int64_t q = Q0 + (r >> 2);
+                uint32_t w = 0;
+                for (int k = 0; k < 4; ++k) {
+                    const int64_t idx = 4 * tid + k;
+                    const uint32_t v = idx < left ? ring[(r + k) & (kRing - 1)]
+                                                  : (s_extra >> (8 * (idx - left))) & 0xFF;
+                    w |= v << (8 * k);
+                }
+                if (q < qlimit) store3(dst + 3 * q, ws_quantum(w));
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// k_ws_finish (one block): the '=' and end rules over the significant
+// characters, the final quantum, and the public status (*out_len = length or
+// -1, *first_bad = -1 or the first invalid offset).  *first_bad holds the raw
+// minimum from k_ws_count, *first_pad the first '=' (padded mode).
+__global__ __launch_bounds__(kWsBlock) void k_ws_finish(const uint8_t *__restrict__ src, int64_t n,
+                                                        uint8_t *__restrict__ dst, DecMap map,
+                                                        int64_t TS, const int64_t *__restrict__ prefix,
+                                                        const int64_t *__restrict__ first_pad,
+                                                        int64_t *__restrict__ out_len,
+                                                        int64_t *__restrict__ first_bad,
+                                                        uint32_t flags, int write_output)
+{
+    __shared__ uint32_t s_map[64];
+    __shared__ int64_t s_a, s_cnt;
+    __shared__ int s_slow;
+    stage_dec_map(s_map, map);
+    const uint8_t *m = (const uint8_t *)s_map;
+    const int64_t ntiles = ws_tiles(n, TS);
+    const int64_t total = ntiles ? prefix[ntiles] : 0;
+    const bool nopad = (flags & kFlagNoPad) != 0;
+    const int tid = threadIdx.x;
+
+    // padded mode with a '=': its index among the significant characters
+    // decides the rules.  Fast case: at most one significant character
+    // follows it (a valid input has that form).
+    int64_t a = -1, after = 0;
+    if (tid == 0) {
+        s_slow = 0;
+        s_cnt = 0;
+        if (!nopad && *first_pad != kNoError) {
+            a = *first_pad;
+            int64_t p = a;
+            while (after < 2) {
+                p = next_sig(src, n, p + 1, m, prefix, ntiles, TS);
+                if (p >= n) break;
+                ++after;
+            }
+            s_slow = after >= 2;
+        }
+        s_a = a;
+    }
+    __syncthreads();
+    if (s_slow) {       // count the significant characters before the '=' in its tile
+        const int64_t aa = s_a, start = aa / TS * TS;
+        int64_t cnt = 0;
+        for (int64_t i = start + tid; i < aa; i += kWsBlock) cnt += is_sig(m[src[i]]);
+        atomicAdd((unsigned long long *)&s_cnt, (unsigned long long)cnt);
+    }
+    __syncthreads();
+    if (tid != 0) return;
+
+    int64_t bad = *first_bad;                 // kNoError when none
+    int64_t len = 0;
+    // the last up to four significant characters (positions, latest last)
+    const int r = (int)(total & 3);
+    const int nlast = nopad ? r : (total >= 4 ? 4 : 0);
+    int64_t lp[4] = {-1, -1, -1, -1};
+    {
+        int64_t p = n;
+        for (int k = nlast - 1; k >= 0; --k) {
+            p = prev_sig(src, n, p, m, prefix, ntiles, TS);
+            lp[k] = p;
+        }
+    }
+    if (nopad) {
+        if (r == 1) bad = bad < n ? bad : n;
+        else if (r >= 2 && (m[src[lp[r - 1]]] & (r == 2 ? 15u : 3u))) bad = bad < n ? bad : n;
+        len = 3 * (total >> 2) + (r ? r - 1 : 0);
+    } else if (a < 0) {
+        if (r != 0) bad = bad < n ? bad : n;
+        len = 3 * (total >> 2);
+    } else {
+        const int64_t i = s_slow ? prefix[a / TS] + s_cnt : total - 1 - after;
+        const int pq = (int)(i & 3);
+        int64_t e = kNoError;
+        if (pq < 2) {
+            e = a;
+        } else {
+            const int64_t pv = prev_sig(src, n, a, m, prefix, ntiles, TS);
+            const uint32_t prev = m[src[pv]];
+            if (pq == 2) {
+                if (prev & 15) {
+                    e = a;
+                } else {
+                    const int64_t nx = next_sig(src, n, a + 1, m, prefix, ntiles, TS);
+                    if (nx >= n) e = n;
+                    else if (src[nx] != kPad) e = nx;
+                    else {
+                        const int64_t nx2 = next_sig(src, n, nx + 1, m, prefix, ntiles, TS);
+                        e = nx2 < n ? nx2 : kNoError;
+                    }
+                }
+            } else {
+                if (prev & 3) {
+                    e = a;
+                } else {
+                    const int64_t nx = next_sig(src, n, a + 1, m, prefix, ntiles, TS);
+                    e = nx < n ? nx : kNoError;
+                }
+            }
+        }
+        bad = bad < e ? bad : e;
+        len = 3 * (total >> 2) - (total - i);
+    }
+    if (bad != kNoError) {
+        *out_len = -1;
+        *first_bad = bad;
+        return;
+    }
+    if (write_output && nlast > 0) {
+        // the final quantum: 4 characters (padded) or r (unpadded); its data
+        // values give (number of data values - 1) bytes
+        uint32_t w = 0;
+        int nd = 0;
+        for (int k = 0; k < nlast; ++k) {
+            const uint8_t ch = src[lp[k]];
+            if (ch == kPad && !nopad) break;
+            w |= (uint32_t)m[ch] << (8 * k);
+            ++nd;
+        }
+        const uint32_t b = ws_quantum(w);
+        uint8_t *o = dst + 3 * (nopad ? (total >> 2) : (total >> 2) - 1);
+        for (int k = 0; k < nd - 1; ++k) o[k] = (uint8_t)(b >> (8 * k));
+    }
+    *out_len = len;
+    *first_bad = -1;
+}
+
+__global__ void k_ws_init(int64_t *first_bad, int64_t *first_pad)
+{
+    if (threadIdx.x == 0) {
+        *first_bad = kNoError;
+        *first_pad = kNoError;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_encode_wrap(const uint8_t *src, int64_t n, uint8_t *dst, const EncTab &tab,
+                              uint32_t flags, int64_t line_len, Shape sh, int cus, hipStream_t stream)
+{
+    const int64_t grid = grid_for(n / 12, sh, cus);
+    B64_DISPATCH(k_encode_wrap, sh, grid, stream, src, n, dst, tab, flags, line_len);
+    return hipGetLastError();
+}
+
+int64_t ws_tile_size(int64_t n)
+{
+    // about 4096 tiles or more; 4 KiB .. 64 KiB, a power of two
+    int64_t ts = kRound;
+    while (ts < 65536 && n / (2 * ts) >= 4096) ts *= 2;
+    return ts;
+}
+
+int64_t ws_workspace_bytes(int64_t n)
+{
+    const int64_t TS = ws_tile_size(n);
+    const int64_t ntiles = n > 0 ? (n + TS - 1) / TS : 0;
+    return 8 * (ntiles + 2);
+}
+
+hipError_t launch_decode_ws(const uint8_t *src, int64_t n, uint8_t *dst, bool write, const DecMap &map,
+                            int64_t *out_len, int64_t *first_bad, uint32_t flags, void *workspace,
+                            Shape sh, int cus, hipStream_t stream)
+{
+    const int64_t TS = ws_tile_size(n);
+    const int64_t ntiles = n > 0 ? (n + TS - 1) / TS : 0;
+    int64_t *prefix = (int64_t *)workspace;      // ntiles + 1 words
+    int64_t *first_pad = prefix + ntiles + 1;
+    hipLaunchKernelGGL(k_ws_init, dim3(1), dim3(64), 0, stream, first_bad, first_pad);
+    int64_t grid = (int64_t)cus * sh.bpc;
+    if (grid > ntiles) grid = ntiles;
+    if (grid >= kXcds) grid -= grid % kXcds;
+    if (grid < 1) grid = 1;
+    if (ntiles > 0) {
+        if (sh.nt) hipLaunchKernelGGL(k_ws_count<true>, dim3(grid), dim3(kWsBlock), 0, stream, src, n, map, TS, prefix, first_pad, first_bad);
+        else hipLaunchKernelGGL(k_ws_count<false>, dim3(grid), dim3(kWsBlock), 0, stream, src, n, map, TS, prefix, first_pad, first_bad);
+    }
+    hipLaunchKernelGGL(k_ws_scan, dim3(1), dim3(kScanThreads), 0, stream, prefix, ntiles);
+    if (write && ntiles > 0) {
+        if (sh.nt) hipLaunchKernelGGL(k_ws_decode<true>, dim3(grid), dim3(kWsBlock), 0, stream, src, n, dst, map, TS, prefix, flags);
+        else hipLaunchKernelGGL(k_ws_decode<false>, dim3(grid), dim3(kWsBlock), 0, stream, src, n, dst, map, TS, prefix, flags);
+    }
+    hipLaunchKernelGGL(k_ws_finish, dim3(1), dim3(kWsBlock), 0, stream, src, n, dst, map, TS, prefix,
+                       first_pad, out_len, first_bad, flags, write ? 1 : 0);
+    return hipGetLastError();
+}
+
+}  // namespace b64hip

@@ -34,6 +34,9 @@ def test_header_declares_the_boundary():
     assert set(funcs) == {
         "b64_encoded_len", "b64_decoded_max_len", "b64_encode", "b64_decode", "b64_decode_async",
         "b64_validate", "b64_validate_async", "b64_encode_batch", "b64_decode_batch",
+        "b64_encoded_len_mode", "b64_decoded_max_len_mode", "b64_decode_workspace_size",
+        "b64_encode_mode", "b64_decode_mode", "b64_decode_mode_async", "b64_validate_mode",
+        "b64_validate_mode_async", "b64_encode_batch_mode", "b64_decode_batch_mode",
         "b64_pipeline_create", "b64_pipeline_destroy", "b64_pipeline_encode",
         "b64_pipeline_decode", "b64_pipeline_last_error",
         "b64_tune_set", "b64_tune_get", "b64_last_error"}
@@ -72,6 +75,37 @@ def test_length_helpers(lib):
     assert lib.b64_encoded_len(big) == 4 * ((big + 2) // 3)
 
 
+def test_variant_length_helpers_match_oracle(lib, oracle):
+    """Output lengths and capacities of the variants, against the oracle's
+    own encoder (lengths) and decoder (largest valid output)."""
+    EARG = -(2 ** 63)
+    for n in range(0, 200):
+        for flags in (0, 1):
+            for L in (0, 4, 8, 76, 1000):
+                assert lib.b64_encoded_len_mode(n, flags, L) == oracle.encoded_len_mode(n, flags, L)
+        r = n % 4
+        assert lib.b64_decoded_max_len_mode(n, 0) == 3 * (n // 4)
+        assert lib.b64_decoded_max_len_mode(n, 2) == 3 * (n // 4)
+        assert lib.b64_decoded_max_len_mode(n, 1) == 3 * (n // 4) + max(0, r - 1)
+        assert lib.b64_decoded_max_len_mode(n, 3) == 3 * (n // 4) + max(0, r - 1)
+        assert lib.b64_decode_workspace_size(n, 0) == 0
+        assert lib.b64_decode_workspace_size(n, 1) == 0
+        assert lib.b64_decode_workspace_size(n, 2) >= 16
+    # the largest unpadded decoded length fits the capacity
+    for n in range(0, 64):
+        m = oracle.encoded_len_mode(n, 1)
+        assert lib.b64_decoded_max_len_mode(m, 1) >= n
+    assert lib.b64_encoded_len_mode(5, 2, 0) == EARG        # SKIP_WS is a decode flag
+    assert lib.b64_encoded_len_mode(5, 0, 6) == EARG        # line length not a multiple of 4
+    assert lib.b64_encoded_len_mode(5, 0, -4) == EARG
+    assert lib.b64_decoded_max_len_mode(5, 4) == EARG
+    assert lib.b64_decode_workspace_size(-1, 2) == EARG
+    # workspace: 8 bytes per tile (4 KiB .. 64 KiB) plus 16
+    big = 1 << 30
+    ws = lib.b64_decode_workspace_size(big, 2)
+    assert 16 + 8 * (big // 65536) <= ws <= 16 + 8 * (big // 4096 + 1)
+
+
 def test_argument_errors_without_gpu(lib):
     """Bad arguments are rejected on the host, before any HIP call."""
     EARG = -(2 ** 63)
@@ -101,9 +135,26 @@ def test_argument_errors_without_gpu(lib):
     assert lib.b64_pipeline_encode(None, fake, 10, fake, std) == EARG
     assert lib.b64_pipeline_decode(None, fake, 10, fake, std) == EARG
     lib.b64_pipeline_destroy(None)
+    # variants
+    with_space = ctypes.create_string_buffer(b" " + std.raw[1:], 64)
+    assert lib.b64_encode_mode(fake, 10, fake, std, 2, 0, None) == EARG          # SKIP_WS
+    assert lib.b64_encode_mode(fake, 10, fake, std, 0, 2, None) == EARG          # line_len 2
+    assert lib.b64_encode_mode(fake, 10, fake, dup, 1, 0, None) == EARG
+    assert lib.b64_decode_mode(fake, 10, fake, std, 8, None) == EARG             # unknown flag
+    assert lib.b64_decode_mode(fake, 10, fake, with_space, 2, None) == EARG
+    assert b"SKIP_WS" in lib.b64_last_error()
+    assert lib.b64_validate_mode(fake, 10, with_space, 3, None) == EARG
+    assert lib.b64_decode_mode_async(fake, 10, fake, fake, fake, std, 2, None, 0, None) == EARG
+    assert lib.b64_decode_mode_async(fake, 1 << 20, fake, fake, fake, std, 2, fake, 8, None) == EARG
+    assert b"workspace" in lib.b64_last_error()
+    assert lib.b64_validate_mode_async(fake, 10, fake, fake, std, 2, None, 0, None) == EARG
+    assert lib.b64_encode_batch_mode(fake, fake, 3, fake, fake, fake, std, 2, None) == EARG
+    assert lib.b64_decode_batch_mode(fake, fake, 3, fake, fake, fake, fake, std, 2, None) == EARG
     # zero-size work needs no device
     assert lib.b64_encode(None, 0, None, std, None) == 0
+    assert lib.b64_encode_mode(None, 0, None, std, 1, 76, None) == 0
     assert lib.b64_encode_batch(None, None, 0, None, None, None, std, None) == 0
+    assert lib.b64_encode_batch_mode(None, None, 0, None, None, None, std, 1, None) == 0
 
 
 def test_tuning_interface(lib):
@@ -112,8 +163,9 @@ def test_tuning_interface(lib):
     assert lib.b64_tune_set(0, 3, 8, 0) == EARG
     assert lib.b64_tune_set(0, 4, 0, 0) == EARG
     assert lib.b64_tune_set(7, 4, 8, 0) == EARG
-    assert lib.b64_tune_set(5, 4, 8, 0) == EARG
+    assert lib.b64_tune_set(5, 3, 8, 0) == EARG
     assert lib.b64_tune_get(4) > 0
+    assert lib.b64_tune_get(6) > 0
     assert lib.b64_tune_set(0, 4, 8, 2) == EARG
     assert lib.b64_tune_set(0, 8, 16, 1) == 0
     assert lib.b64_tune_get(0) == 10816

@@ -1,0 +1,295 @@
+"""GPU parity of the variants (unpadded, CR LF line-wrapped encode,
+whitespace-skipping decode / validate) against the oracle, bit-exact: the
+same characters, the same decoded bytes, the same decoded length or first
+invalid offset.  Inputs come from the seeded generators and the oracle's own
+encoder; every expected value from the oracle."""
+import numpy as np
+import pytest
+
+import workloads
+from gpu_util import first_mismatch, say, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+STD = b"ABCDEFGHIJKLMNOPQRSTUVWXYZabcdefghijklmnopqrstuvwxyz0123456789+/"
+URL = b"ABCDEFGHIJKLMNOPQRSTUVWXYZabcdefghijklmnopqrstuvwxyz0123456789-_"
+NOPAD, SKIP_WS = 1, 2
+
+
+def _alphabets():
+    g = workloads.rng(workloads.SEED_BASE + 171)
+    perm = bytes(g.permutation(np.frombuffer(STD, dtype=np.uint8)).tolist())
+    pool = np.array([c for c in range(256) if c not in b"= \t\r\n"], dtype=np.uint8)
+    hi = bytes(g.choice(pool, 64, replace=False).tolist())
+    return {"std": STD, "url": URL, "perm": perm, "hi": hi}
+
+
+@pytest.fixture(scope="module")
+def b64():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1910_05109_amd as b64
+    b64.load()
+    return b64
+
+
+def _dev(a):
+    import torch
+    return to_dev(a) if a.size else torch.empty(0, dtype=torch.uint8, device="cuda")
+
+
+def _enc(b64, oracle, x, alpha, flags, line_len, label):
+    say("encode", label, "n =", x.size, "flags", flags, "line", line_len)
+    ref = oracle.encode_mode(x, alpha, flags, line_len)
+    got = to_host(b64.encode(_dev(x), alpha, flags=flags, line_len=line_len))
+    assert got.size == ref.size and first_mismatch(got, ref) is None, (label, first_mismatch(got, ref))
+
+
+def _dec(b64, oracle, text, alpha, flags, label, check_validate=True):
+    say("decode", label, "n =", text.size, "flags", flags)
+    ref_raw = oracle.decode_mode_raw(text, alpha, flags)
+    out, bad = b64.decode(_dev(text), alpha, flags=flags)
+    if ref_raw >= 0:
+        ref, _ = oracle.decode_mode(text, alpha, flags)
+        assert bad is None, (label, bad)
+        got = to_host(out)
+        assert first_mismatch(got, ref) is None, (label, first_mismatch(got, ref))
+    else:
+        assert bad == ~ref_raw, (label, bad, ~ref_raw)
+    if check_validate:
+        say("validate", label)
+        length, vbad = b64.validate(_dev(text), alpha, flags=flags)
+        assert (length if vbad is None else ~vbad) == ref_raw, (label, length, vbad, ref_raw)
+    return ref_raw
+
+
+# ---------------------------------------------------------------- unpadded --
+
+@pytest.mark.parametrize("name", ["std", "url", "perm", "hi"])
+def test_nopad_encode_decode_all_lengths(b64, oracle, name):
+    alpha = _alphabets()[name]
+    x = workloads.random_bytes(workloads.SEED_BASE + 172, 2100)
+    step = 1 if name == "url" else 5
+    for n in range(0, 2100, step):
+        _enc(b64, oracle, x[:n], alpha, NOPAD, 0, f"{name} {n}")
+        text = oracle.encode_mode(x[:n], alpha, NOPAD)
+        _dec(b64, oracle, text, alpha, NOPAD, f"{name} {n}", check_validate=(n % 25 == 0))
+
+
+def test_nopad_3mib_misaligned_and_invalid(b64, oracle):
+    import torch
+    x = workloads.random_bytes(workloads.SEED_BASE + 173, workloads.SINGLE_3MIB + 2)
+    for n in (workloads.SINGLE_3MIB, workloads.SINGLE_3MIB + 1, workloads.SINGLE_3MIB + 2):
+        _enc(b64, oracle, x[:n], URL, NOPAD, 0, f"3MiB+{n % 3}")
+        text = oracle.encode_mode(x[:n], URL, NOPAD)
+        assert _dec(b64, oracle, text, URL, NOPAD, f"3MiB+{n % 3}") == n
+    # misaligned source and destination
+    text = oracle.encode_mode(x[:100001], URL, NOPAD)
+    for off in (1, 2, 3, 5):
+        say("nopad misaligned", off)
+        src = torch.zeros(text.size + 8, dtype=torch.uint8, device="cuda")
+        src[off:off + text.size] = to_dev(text)
+        dst = torch.zeros(100001 + 16, dtype=torch.uint8, device="cuda")
+        out, bad = b64.decode(src[off:off + text.size], URL, out=dst[off:], flags=NOPAD)
+        assert bad is None and first_mismatch(to_host(out), x[:100001]) is None
+    # '=' anywhere, a non-alphabet byte, a length of 1 mod 4, a non-canonical end
+    for pos in (0, 1, 2, 3, 4096, text.size - 1):
+        t = text.copy()
+        t[pos] = ord("=")
+        _dec(b64, oracle, t, URL, NOPAD, f"= at {pos}")
+    bad, pos = workloads.plant_invalid(text, workloads.SEED_BASE + 174, URL)
+    _dec(b64, oracle, bad, URL, NOPAD, "invalid byte")
+    _dec(b64, oracle, text[:-2] if text.size % 4 == 3 else text[:-1], URL, NOPAD, "1 mod 4")
+    t = oracle.encode_mode(x[:100000], URL, NOPAD)          # 2 characters in the last quantum
+    t[-1] = URL[1]                                           # nonzero low bits
+    _dec(b64, oracle, t, URL, NOPAD, "non-canonical")
+
+
+def test_nopad_brute_force_as_batch(b64, oracle):
+    """Every string of length <= 6 over a symbol set that exercises '=', the
+    canonical bits and invalid bytes, decoded as buffers of one batch."""
+    import torch
+    symbols = np.frombuffer(b"AQRE=*", dtype=np.uint8)
+    for length in range(0, 7):
+        rows = symbols[np.indices((6,) * length).reshape(length, -1).T] if length else \
+            np.zeros((1, 0), dtype=np.uint8)
+        say("nopad brute force", length, rows.shape[0])
+        ref = oracle.decode_mode_rows(rows, STD, NOPAD)
+        src = rows.reshape(-1)
+        in_off = workloads.offsets(np.full(rows.shape[0], length, dtype=np.int64))
+        dst, out_off, out_len, first_bad = b64.decode_batch(
+            _dev(src) if src.size else torch.zeros(1, dtype=torch.uint8, device="cuda"),
+            to_dev(in_off), STD, flags=NOPAD)
+        got = np.where(to_host(first_bad) >= 0, ~to_host(first_bad), to_host(out_len))
+        assert (got == ref).all(), (length, np.nonzero(got != ref)[0][:5])
+
+
+def test_nopad_ragged_batch(b64, oracle):
+    lens = workloads.batch_lengths(workloads.SEED_BASE + 175, 3000, 1, 5000)
+    lens[::97] = 0                                           # some empty buffers
+    in_off = workloads.offsets(lens)
+    x = workloads.random_bytes(workloads.SEED_BASE + 176, int(in_off[-1]))
+    say("nopad batch encode", lens.size)
+    ref_dst, ref_off, ref_len = oracle.encode_mode_list(x, in_off, URL, NOPAD)
+    dst, out_off, out_len = b64.encode_batch(_dev(x), to_dev(in_off), URL, flags=NOPAD)
+    assert (to_host(out_off) == ref_off).all() and (to_host(out_len) == ref_len).all()
+    assert first_mismatch(to_host(dst)[: ref_dst.size], ref_dst) is None
+    # decode the packed encodings back, with invalid buffers mixed in
+    text = ref_dst.copy()
+    bad_bufs = workloads.pick_buffers(workloads.SEED_BASE + 177, lens.size, 0.05)
+    for b in bad_bufs.tolist():
+        if ref_len[b] > 0:
+            text[ref_off[b] + (b * 7919) % ref_len[b]] = ord("=")
+    say("nopad batch decode", lens.size)
+    _, _, ref_res = oracle.decode_mode_list(text, ref_off, URL, NOPAD)
+    _, _, out_len, first_bad = b64.decode_batch(_dev(text), to_dev(ref_off), URL, flags=NOPAD)
+    got = np.where(to_host(first_bad) >= 0, ~to_host(first_bad), to_host(out_len))
+    assert (got == ref_res).all(), np.nonzero(got != ref_res)[0][:5]
+
+
+# -------------------------------------------------------------- line-wrapped --
+
+@pytest.mark.parametrize("line_len", [4, 8, 12, 16, 64, 76, 1000])
+def test_wrapped_encode_lengths(b64, oracle, line_len):
+    x = workloads.random_bytes(workloads.SEED_BASE + 178, 5000)
+    for n in list(range(0, 200)) + list(range(200, 5000, 97)):
+        for flags in (0, NOPAD):
+            _enc(b64, oracle, x[:n], STD, flags, line_len, f"L{line_len} n{n}")
+
+
+def test_wrapped_encode_large_and_misaligned(b64, oracle):
+    import torch
+    x = workloads.random_bytes(workloads.SEED_BASE + 179, workloads.SINGLE_3MIB + 2)
+    for n in (workloads.SINGLE_3MIB, workloads.SINGLE_3MIB + 1, workloads.SINGLE_3MIB + 2):
+        for flags in (0, NOPAD):
+            _enc(b64, oracle, x[:n], STD, flags, 76, f"3MiB+{n % 3}")
+    ref = oracle.encode_mode(x[:77777], URL, 0, 64)
+    for off in (1, 2, 3):
+        say("wrap misaligned", off)
+        src = torch.zeros(77777 + 8, dtype=torch.uint8, device="cuda")
+        src[off:off + 77777] = to_dev(x[:77777])
+        dst = torch.zeros(ref.size + 8, dtype=torch.uint8, device="cuda")
+        out = b64.encode(src[off:off + 77777], URL, out=dst[off:], line_len=64)
+        assert first_mismatch(to_host(out), ref) is None
+
+
+# ------------------------------------------------------- whitespace skipping --
+
+def _mime(oracle, x, alpha=STD, flags=0):
+    return oracle.encode_mode(x, alpha, flags, workloads.MIME_LINE)
+
+
+@pytest.mark.parametrize("flags", [SKIP_WS, SKIP_WS | NOPAD])
+def test_skip_ws_mime_lengths(b64, oracle, flags):
+    x = workloads.random_bytes(workloads.SEED_BASE + 180, 20000)
+    for n in list(range(0, 150)) + list(range(150, 20000, 331)):
+        text = _mime(oracle, x[:n], STD, flags & NOPAD)
+        assert _dec(b64, oracle, text, STD, flags, f"mime {n}", check_validate=(n % 7 == 0)) == n
+
+
+@pytest.mark.parametrize("name", ["std", "url", "hi"])
+def test_skip_ws_sprinkled_and_long_runs(b64, oracle, name):
+    alpha = _alphabets()[name]
+    x = workloads.random_bytes(workloads.SEED_BASE + 181, 3 << 20)
+    cases = [(1000, 50, 0), (100000, 2000, 0), (300000, 5000, 2), (3 << 20, 20000, 3)]
+    for k, (n, runs, longs) in enumerate(cases):
+        for flags in (SKIP_WS, SKIP_WS | NOPAD):
+            text = workloads.sprinkle_ws(_mime(oracle, x[:n], alpha, flags & NOPAD),
+                                         workloads.SEED_BASE + 182 + k, runs, 5, longs, 1 << 17)
+            assert _dec(b64, oracle, text, alpha, flags, f"{name} sprinkled {n}") == n
+
+
+def test_skip_ws_invalid_cases(b64, oracle):
+    x = workloads.random_bytes(workloads.SEED_BASE + 183, 400000)
+    base = workloads.sprinkle_ws(_mime(oracle, x), workloads.SEED_BASE + 184, 3000, 5, 1, 1 << 17)
+    n = base.size
+    g = workloads.rng(workloads.SEED_BASE + 185)
+    # a non-alphabet byte (not whitespace, not '=') at seeded positions
+    bad_bytes = workloads.non_alphabet_bytes(STD + b" \t\r\n")
+    for k in range(12):
+        t = base.copy()
+        t[int(g.integers(0, n))] = bad_bytes[int(g.integers(0, bad_bytes.size))]
+        _dec(b64, oracle, t, STD, SKIP_WS, f"invalid {k}", check_validate=(k % 3 == 0))
+    # '=' at seeded positions (padded: misplaced pad; unpadded: invalid)
+    for k in range(12):
+        t = base.copy()
+        t[int(g.integers(0, n))] = ord("=")
+        for flags in (SKIP_WS, SKIP_WS | NOPAD):
+            _dec(b64, oracle, t, STD, flags, f"= {k}", check_validate=False)
+    # '=' followed by a long whitespace run and more data (slow path)
+    t = np.concatenate([_mime(oracle, x[:3000]), np.full(1 << 18, ord(" "), dtype=np.uint8),
+                        _mime(oracle, x[3000:6000])])
+    _dec(b64, oracle, t, STD, SKIP_WS, "= then long run then data")
+    # truncations and the end rules
+    text = _mime(oracle, x[:100000])
+    for cut in range(1, 8):
+        _dec(b64, oracle, text[:-cut], STD, SKIP_WS, f"cut {cut}")
+        _dec(b64, oracle, text[:-cut], STD, SKIP_WS | NOPAD, f"nopad cut {cut}")
+    # degenerate inputs
+    for s in (b"", b"\r\n", b"    \t\n", b"====", b"=", b"A", b"AA", b"AA=", b"AA==", b"AA==\r\n",
+              b"AA==\r\nA", b"A\r\nA=\r\n=", b"QQ==", b"QR==", b"QRE=", b"AAAA\n\n\n\nAA"):
+        t = np.frombuffer(s, dtype=np.uint8).copy()
+        for flags in (SKIP_WS, SKIP_WS | NOPAD):
+            _dec(b64, oracle, t, STD, flags, repr(s))
+
+
+def test_skip_ws_async_status_and_graph(b64, oracle):
+    import torch
+    x = workloads.random_bytes(workloads.SEED_BASE + 186, 1 << 20)
+    text = workloads.sprinkle_ws(_mime(oracle, x), workloads.SEED_BASE + 187, 500)
+    bad_text = text.copy()
+    bad_text[text.size // 2] = ord("*")
+    ref_bad = ~oracle.decode_mode_raw(bad_text, STD, SKIP_WS)
+    s_ok, s_bad = _dev(text), _dev(bad_text)
+    say("skip_ws async")
+    out, st = b64.decode_async(s_ok, STD, flags=SKIP_WS)
+    assert to_host(st).tolist() == [x.size, -1]
+    assert first_mismatch(to_host(out)[: x.size], x) is None
+    vst = b64.validate_async(s_bad, STD, flags=SKIP_WS)
+    assert to_host(vst).tolist() == [-1, ref_bad]
+    # capture the five launches in a graph; replay with eager work between
+    say("skip_ws graph capture")
+    cap = b64.decoded_max_len(text.size, SKIP_WS)
+    out = torch.zeros(cap, dtype=torch.uint8, device="cuda")
+    st = torch.zeros(2, dtype=torch.int64, device="cuda")
+    ws = torch.empty(b64.workspace_size(text.size, SKIP_WS), dtype=torch.uint8, device="cuda")
+    src = s_ok.clone()
+    stream = torch.cuda.Stream()
+    stream.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(stream):
+        b64.decode_async(src, STD, out=out, status=st, flags=SKIP_WS, workspace=ws)   # warm up
+    torch.cuda.current_stream().wait_stream(stream)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        b64.decode_async(src, STD, out=out, status=st, flags=SKIP_WS, workspace=ws)
+    for rep in range(4):
+        say("replay", rep)
+        src.copy_(s_bad if rep % 2 else s_ok)
+        out.zero_()
+        st.fill_(7)
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        if rep % 2:
+            assert to_host(st).tolist() == [-1, ref_bad]
+        else:
+            assert to_host(st).tolist() == [x.size, -1]
+            assert first_mismatch(to_host(out)[: x.size], x) is None
+
+
+def test_skip_ws_large(b64, oracle):
+    """A 256 MiB payload as MIME text (about 354 MB): several thousand tiles of
+    16-64 KiB."""
+    x = workloads.random_bytes(workloads.SEED_BASE + 188, 256 << 20)
+    text = _mime(oracle, x)
+    say("skip_ws large", text.size)
+    s = _dev(text)
+    out, bad = b64.decode(s, STD, flags=SKIP_WS)
+    assert bad is None and first_mismatch(to_host(out), x) is None
+    length, vbad = b64.validate(s, STD, flags=SKIP_WS)
+    assert length == x.size and vbad is None
+    say("wrap encode large")
+    enc = to_host(b64.encode(_dev(x), STD, line_len=workloads.MIME_LINE))
+    assert first_mismatch(enc, text) is None

@@ -1,0 +1,138 @@
+"""CPU model of the whitespace-skipping decode's work split (no GPU).
+
+The kernels cut the input into tiles of TS characters.  Tile t holds the
+significant characters with indices prefix[t] .. prefix[t+1]-1 and decodes
+the quanta whose first significant value lies in it: it skips
+(4 - prefix[t] % 4) % 4 values that finish an earlier quantum, reads rounds
+of 4096 characters through a ring, emits every 16 values as 4 quanta, and
+completes its last quantum with up to three values borrowed from later
+tiles.  Quanta at index >= qlimit are left to the finishing block.
+
+This model repeats that index arithmetic in Python, on random inputs with
+whitespace runs of every length (empty tiles, runs longer than a tile), and
+checks that every quantum below qlimit is written exactly once, by one tile,
+from the right significant values.
+"""
+import numpy as np
+import pytest
+
+import workloads
+
+WS = set(b" \t\r\n")
+ROUND = 4096
+
+
+def tile_size(n):
+    ts = ROUND
+    while ts < 65536 and n // (2 * ts) >= 4096:
+        ts *= 2
+    return ts
+
+
+def model(text: bytes, nopad: bool, ts: int):
+    n = len(text)
+    sig = [i for i, c in enumerate(text) if c not in WS]
+    ntiles = (n + ts - 1) // ts if n else 0
+    prefix = [0]
+    for t in range(ntiles):
+        prefix.append(prefix[-1] + sum(1 for c in text[t * ts:(t + 1) * ts] if c not in WS))
+    total = prefix[-1] if ntiles else 0
+    assert total == len(sig)
+    qlimit = total // 4 if nopad else (total // 4 - 1 if total >= 4 else 0)
+    writes = {}                                   # quantum -> (tile, value indices)
+    for t in range(ntiles):
+        K0, C = prefix[t], prefix[t + 1] - prefix[t]
+        skip = (4 - K0 % 4) % 4
+        if C <= skip:
+            continue
+        Q0 = (K0 + skip) // 4
+        if Q0 >= qlimit:
+            continue
+        base, end = t * ts, min(n, (t + 1) * ts)
+        W, Rd = -skip, 0
+        ring = {}
+        g = K0                                     # significant index of the next value
+        for p0 in range(base, end, ROUND):
+            chunk = [c for c in text[p0:min(end, p0 + ROUND)] if c not in WS]
+            for v in chunk:
+                if W >= 0:
+                    ring[W] = g
+                W += 1
+                g += 1
+            nfull = max(0, (W - Rd) // 16)
+            for tid in range(nfull):
+                r = Rd + 16 * tid
+                q = Q0 + r // 4
+                for k in range(4):
+                    if q + k < qlimit:
+                        idx = [ring[r + 4 * k + j] for j in range(4)]
+                        assert (q + k) not in writes
+                        writes[q + k] = (t, idx)
+            Rd += 16 * nfull
+        left = W - Rd
+        if left > 0:
+            rem = left & 3
+            extra = []
+            gg = K0 + C
+            while len(extra) < (4 - rem if rem else 0) and gg < total:
+                extra.append(gg)                   # the kernel finds it via tile_of + scan
+                gg += 1
+            nq = (left + 3) // 4
+            for tid in range(nq):
+                r = Rd + 4 * tid
+                q = Q0 + r // 4
+                idx = []
+                for k in range(4):
+                    i = 4 * tid + k
+                    idx.append(ring[r + k] if i < left else (extra[i - left] if i - left < len(extra) else None))
+                if q < qlimit:
+                    assert None not in idx
+                    assert q not in writes
+                    writes[q] = (t, idx)
+    # every quantum below qlimit written once, from values 4q..4q+3
+    assert sorted(writes) == list(range(max(qlimit, 0)))
+    for q, (t, idx) in writes.items():
+        assert idx == [4 * q + j for j in range(4)], (q, t, idx)
+        first = sig[4 * q]
+        assert t * ts <= first < (t + 1) * ts       # the tile of the quantum's first value
+    return len(writes)
+
+
+def random_text(rng, n_sig, ws_rate, long_runs, tile):
+    out = bytearray()
+    for _ in range(n_sig):
+        while rng.random() < ws_rate:
+            out += bytes([int(rng.choice(list(WS)))])
+        out += b"A"
+    for _ in range(long_runs):
+        pos = int(rng.integers(0, len(out) + 1))
+        out[pos:pos] = b" " * int(rng.integers(tile // 2, 3 * tile))
+    return bytes(out)
+
+
+@pytest.mark.parametrize("nopad", [False, True])
+def test_every_quantum_written_once(nopad):
+    rng = np.random.default_rng(workloads.SEED_BASE + 91)
+    for trial in range(16):
+        n_sig = int(rng.integers(0, 20000))
+        text = random_text(rng, n_sig, float(rng.choice([0.0, 0.02, 0.3, 0.9])),
+                           int(rng.integers(0, 4)), ROUND)
+        model(text, nopad, ROUND)
+        model(text, nopad, 2 * ROUND)
+
+
+def test_mime_lines_and_tile_sizes():
+    # 76-character lines with CR LF, the workload's shape, several tile sizes
+    for n_sig in (0, 1, 3, 4, 5, 76, 4095, 4096, 4097, 30001):
+        lines = [b"A" * 76] * (n_sig // 76) + ([b"A" * (n_sig % 76)] if n_sig % 76 else [])
+        text = b"\r\n".join(lines)
+        for ts in (ROUND, 4 * ROUND):
+            for nopad in (False, True):
+                model(text, nopad, ts)
+
+
+def test_tile_size_rule():
+    assert tile_size(0) == 4096
+    assert tile_size(10 ** 6) == 4096
+    assert tile_size(64 << 20) == 16384
+    assert tile_size(1431655764) == 65536

@@ -23,6 +23,9 @@ Workloads (sizes as named in the design notes):
   serving        : Poisson arrivals, sizes log-normal (median 8 KiB, sigma 1.5)
                    clipped to [1 B, 16 MiB], 50/50 encode/decode, 1% of decode
                    requests carry one invalid byte.
+  MIME text      : the encoding in lines of 76 characters separated by CR LF
+                   (the MIME line length), optionally with extra whitespace
+                   runs inserted at seeded positions (sprinkle_ws).
 """
 from __future__ import annotations
 
@@ -117,3 +120,26 @@ def serve_kinds(seed: int, count: int, invalid_frac: float = 0.01):
     is_dec = g.random(count) < 0.5
     is_bad = is_dec & (g.random(count) < invalid_frac)
     return is_dec, is_bad
+
+
+WHITESPACE = np.frombuffer(b" \t\r\n", dtype=np.uint8)
+MIME_LINE = 76
+
+
+def sprinkle_ws(text: np.ndarray, seed: int, runs: int, max_run: int = 5,
+                long_runs: int = 0, long_len: int = 1 << 17) -> np.ndarray:
+    """Insert `runs` runs of 1..max_run whitespace bytes (space, tab, CR, LF)
+    and `long_runs` runs of long_len spaces at seeded positions."""
+    g = rng(seed)
+    pos = np.sort(g.integers(0, text.size + 1, size=runs + long_runs))
+    lens = np.concatenate([g.integers(1, max_run + 1, size=runs),
+                           np.full(long_runs, long_len, dtype=np.int64)])
+    g.shuffle(lens)
+    parts, prev = [], 0
+    for p, k in zip(pos.tolist(), lens.tolist()):
+        parts.append(text[prev:p])
+        parts.append(WHITESPACE[g.integers(0, 4, size=k)] if k <= max_run
+                     else np.full(k, ord(" "), dtype=np.uint8))
+        prev = p
+    parts.append(text[prev:])
+    return np.concatenate(parts).astype(np.uint8) if parts else text.copy()
