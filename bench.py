@@ -17,7 +17,9 @@ Other modes (--mode): sweep (size sweep 2^k + r), batch (100,000 ragged
 buffers, batched launch vs one launch per buffer), serve (continuous batching
 loop), small (the 3 MiB workload), validate (read-only validation of the
 1 GiB encoding), host (the 1 GiB workload in host memory through the chunked
-host-device pipeline, PCIe included).  Each prints its own JSON lines.
+host-device pipeline, PCIe included), variants (the 1 GiB payload unpadded,
+and as MIME text: 76-character lines with CR LF, wrapped encode and
+whitespace-skipping decode / validate).  Each prints its own JSON lines.
 """
 from __future__ import annotations
 
@@ -484,13 +486,64 @@ def run_host(args, torch, b64):
     print(json.dumps(res), flush=True)
 
 
+def run_variants(args, torch, b64):
+    """The 1 GiB payload through the variants: unpadded encode / decode, and
+    MIME text (lines of 76 characters, CR LF) through the line-wrapped encode
+    and the whitespace-skipping decode and validate.  Algorithmic bytes are
+    what any codec must move (input + output); the whitespace path reads its
+    input twice by design (count pass, then decode pass)."""
+    n = workloads.SINGLE_1GIB[0]
+    L = workloads.MIME_LINE
+    x = torch.from_numpy(workloads.random_bytes(workloads.SEED_BASE + 2, n)).cuda()
+    res = {"workload": "1 GiB payload: unpadded; MIME text (76-char lines, CR LF)", "n_bytes": n}
+    # unpadded
+    Nn = b64.encoded_len(n, b64.NOPAD)
+    tn = torch.empty(Nn, dtype=torch.uint8, device="cuda")
+    dn = torch.empty(n + 3, dtype=torch.uint8, device="cuda")
+    st = torch.empty(2, dtype=torch.int64, device="cuda")
+    enc = lambda: b64.encode(x, out=tn, flags=b64.NOPAD)
+    dec = lambda: b64.decode_async(tn, out=dn, status=st, flags=b64.NOPAD)
+    for _ in range(3):
+        enc(); dec()
+    te, td = _events_time(torch, enc, args.steps), _events_time(torch, dec, args.steps)
+    assert st.cpu().tolist() == [n, -1] and torch.equal(dn[:n], x)
+    res["nopad"] = {"n_chars": Nn, "encode_ms": te["median"], "decode_ms": td["median"],
+                    "encode_hbm_frac": (n + Nn) / te["median"] / 1e6 / HBM_PEAK_GBS,
+                    "decode_hbm_frac": (n + Nn) / td["median"] / 1e6 / HBM_PEAK_GBS}
+    del tn, dn
+    # MIME
+    M = b64.encoded_len(n, 0, L)
+    tm = torch.empty(M, dtype=torch.uint8, device="cuda")
+    dm = torch.empty(b64.decoded_max_len(M, b64.SKIP_WS), dtype=torch.uint8, device="cuda")
+    ws = torch.empty(b64.workspace_size(M, b64.SKIP_WS), dtype=torch.uint8, device="cuda")
+    wenc = lambda: b64.encode(x, out=tm, line_len=L)
+    wdec = lambda: b64.decode_async(tm, out=dm, status=st, flags=b64.SKIP_WS, workspace=ws)
+    wval = lambda: b64.validate_async(tm, status=st, flags=b64.SKIP_WS, workspace=ws)
+    for _ in range(3):
+        wenc(); wdec()
+    tw = _events_time(torch, wenc, args.steps)
+    tdw = _events_time(torch, wdec, args.steps)
+    assert st.cpu().tolist() == [n, -1] and torch.equal(dm[:n], x)
+    tv = _events_time(torch, wval, args.steps)
+    assert st.cpu().tolist() == [n, -1]
+    res["mime"] = {"n_chars": M, "line_len": L,
+                   "wrap_encode_ms": tw["median"], "wrap_encode_gbps_b64": M / tw["median"] / 1e6,
+                   "wrap_encode_hbm_frac": (n + M) / tw["median"] / 1e6 / HBM_PEAK_GBS,
+                   "ws_decode_ms": tdw["median"], "ws_decode_gbps_b64": M / tdw["median"] / 1e6,
+                   "ws_decode_hbm_frac_alg": (M + n) / tdw["median"] / 1e6 / HBM_PEAK_GBS,
+                   "ws_decode_hbm_frac_design": (2 * M + n) / tdw["median"] / 1e6 / HBM_PEAK_GBS,
+                   "ws_validate_ms": tv["median"], "ws_validate_gbps_b64": M / tv["median"] / 1e6}
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--mode", default="single",
-                    choices=["single", "small", "sweep", "batch", "serve", "validate", "host"])
+                    choices=["single", "small", "sweep", "batch", "serve", "validate", "host",
+                             "variants"])
     ap.add_argument("--chunk-mib", type=int, default=64)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--cpu-sample", type=int, default=512 << 20)
@@ -510,7 +563,8 @@ def main():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
     {"single": run_single, "small": run_small, "sweep": run_sweep, "batch": run_batch,
-     "serve": run_serve, "validate": run_validate, "host": run_host}[args.mode](args, torch, b64)
+     "serve": run_serve, "validate": run_validate, "host": run_host,
+     "variants": run_variants}[args.mode](args, torch, b64)
 
 
 if __name__ == "__main__":

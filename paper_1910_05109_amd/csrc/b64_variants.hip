@@ -62,6 +62,38 @@ __device__ __forceinline__ void store_wrapped(uint8_t *dst, int64_t j0, int64_t 
     }
 }
 
+// Characters [j0, j0+16) of the unwrapped encoding (o, four per dword) for
+// lines of L >= 16, so that at most one line starts inside them; (line, col)
+// are those of character j0.  The 16 characters, with a CR LF spliced in
+// where a line starts (before character a, a in {0, 4, 8, 12}), are stored as
+// one 16-byte store plus, after a break, the last two bytes.
+template <bool NT>
+__device__ __forceinline__ void store_chunk_wrapped(uint8_t *dst, int64_t j0, int64_t line,
+                                                    int64_t col, int64_t L, u32x4 o)
+{
+    constexpr uint32_t kCrLf = '\r' | ('\n' << 8);
+    const int64_t pos = j0 + 2 * line;               // position of character j0
+    const int64_t a = col == 0 ? 0 : L - col;        // characters before the next line start
+    const bool brk = col == 0 ? j0 > 0 : a < 16;
+    const int k = brk ? (int)(a >> 2) : 4;           // dword of the break; 4: none
+    const uint32_t w[5] = {o.x, o.y, o.z, o.w, 0u};
+    uint32_t x[5];
+#pragma unroll
+    for (int d = 0; d < 5; ++d) {
+        // the dword shifted by the two inserted bytes: bytes 2,3 of w[d-1], bytes 0,1 of w[d]
+        const uint32_t shifted = d == 0 ? (w[0] << 16) : __builtin_amdgcn_alignbyte(w[d], w[d - 1], 2);
+        x[d] = d < k ? w[d] : (d == k ? (kCrLf | (w[d] << 16)) : shifted);
+    }
+    uint8_t *q = dst + (brk && a == 0 ? pos - 2 : pos);
+    u32x4 v;
+    v.x = x[0];
+    v.y = x[1];
+    v.z = x[2];
+    v.w = x[3];
+    store16<NT>(q, v);
+    if (brk) *(u16a1 *)(q + 16) = (uint16_t)x[4];
+}
+
 // Scalar tail: input bytes p[0..r) whose first character has index j0; the
 // last group is padded or, with !pad, cut to the characters that carry bits.
 __device__ void enc_scalar_wrap(const uint8_t *p, int64_t r, int64_t j0, uint8_t *dst, int64_t L,
@@ -90,9 +122,66 @@ __device__ void enc_scalar_wrap(const uint8_t *p, int64_t r, int64_t j0, uint8_t
     }
 }
 
+// Stores the chunks of one lane, in increasing order c, c+T, c+2T, ...:
+// tracks the line and column of the next chunk's first character and steps
+// them by T chunks (16T characters) per call.
+struct WrapSink {
+    uint8_t *dst;
+    int64_t L, line, col, dline, dcol;
+    template <bool NT>
+    __device__ __forceinline__ void put(int64_t c, u32x4 o)
+    {
+        if (L >= 16) {
+            store_chunk_wrapped<NT>(dst, 16 * c, line, col, L, o);
+        } else {
+            const uint32_t w[4] = {o.x, o.y, o.z, o.w};
+            store_wrapped(dst, 16 * c, line, col, L, w, 4);
+        }
+        line += dline;
+        col += dcol;
+        if (col >= L) {
+            col -= L;
+            ++line;
+        }
+    }
+};
+
+// enc_stream's software-pipelined rounds (the loads of round r+1 issued
+// before round r is stored) with the stores done by a WrapSink.
+template <int U, bool NT>
+__device__ __forceinline__ void enc_stream_wrap(const uint8_t *s0, int64_t c0, int64_t stride,
+                                                int64_t rstep, int64_t nrounds, const uint8_t *tab,
+                                                WrapSink &sink)
+{
+    if (nrounds <= 0) return;
+    u32x3 A[U], B[U];
+    enc_load<U, NT>(A, s0, c0, stride);
+    int64_t r = 0;
+    for (; r + 2 < nrounds; r += 2) {
+        enc_load<U, NT>(B, s0, c0 + rstep, stride);
+#pragma unroll
+        for (int j = 0; j < U; ++j) sink.put<NT>(c0 + j * stride, enc_chunk(A[j], tab));
+        enc_load<U, NT>(A, s0, c0 + 2 * rstep, stride);
+#pragma unroll
+        for (int j = 0; j < U; ++j) sink.put<NT>(c0 + rstep + j * stride, enc_chunk(B[j], tab));
+        c0 += 2 * rstep;
+    }
+    if (r + 1 < nrounds) {
+        enc_load<U, NT>(B, s0, c0 + rstep, stride);
+#pragma unroll
+        for (int j = 0; j < U; ++j) sink.put<NT>(c0 + j * stride, enc_chunk(A[j], tab));
+#pragma unroll
+        for (int j = 0; j < U; ++j) sink.put<NT>(c0 + rstep + j * stride, enc_chunk(B[j], tab));
+    } else {
+#pragma unroll
+        for (int j = 0; j < U; ++j) sink.put<NT>(c0 + j * stride, enc_chunk(A[j], tab));
+    }
+}
+
 // Lane chunk c (input [12c, 12c+12), characters [16c, 16c+16)) for chunks
-// c = t, t+T, ... < nch, U in flight; the last thread encodes what follows
-// the chunks.
+// c = t, t+T, ... < nch: complete rounds of U per lane through
+// enc_stream_wrap, then a partial round with clamped loads; the last thread
+// encodes what follows the chunks.
 template <int U, bool NT>
 __global__ __launch_bounds__(kThreads) void k_encode_wrap(const uint8_t *__restrict__ src, int64_t n,
                                                           uint8_t *__restrict__ dst, EncTab tab,
@@ -106,9 +195,11 @@ __global__ __launch_bounds__(kThreads) void k_encode_wrap(const uint8_t *__restr
     const int64_t T = (int64_t)gridDim.x * kThreads;
     const int64_t t = logical_block() * kThreads + threadIdx.x;
     // line / column of this thread's first character and their steps per T chunks
-    int64_t line = (16 * t) / L, col = (16 * t) % L;
-    const int64_t dline = (16 * T) / L, dcol = (16 * T) % L;
-    for (int64_t c0 = t; c0 < nch; c0 += U * T) {
+    WrapSink sink{dst, L, (16 * t) / L, (16 * t) % L, (16 * T) / L, (16 * T) % L};
+    const int64_t nfull = nch / (U * T);
+    enc_stream_wrap<U, NT>(src, t, T, U * T, nfull, a, sink);
+    const int64_t c0 = t + nfull * U * T;
+    if (c0 < nch) {
         u32x3 in[U];
 #pragma unroll
         for (int j = 0; j < U; ++j) {
@@ -116,20 +207,8 @@ __global__ __launch_bounds__(kThreads) void k_encode_wrap(const uint8_t *__restr
             in[j] = load12<NT>(src + 12 * (c < nch ? c : nch - 1));
         }
 #pragma unroll
-        for (int j = 0; j < U; ++j) {
-            const int64_t c = c0 + j * T;
-            if (c < nch) {
-                const u32x4 o = enc_chunk(in[j], a);
-                const uint32_t w[4] = {o.x, o.y, o.z, o.w};
-                store_wrapped(dst, 16 * c, line, col, L, w, 4);
-            }
-            line += dline;
-            col += dcol;
-            if (col >= L) {
-                col -= L;
-                ++line;
-            }
-        }
+        for (int j = 0; j < U; ++j)
+            if (c0 + j * T < nch) sink.put<NT>(c0 + j * T, enc_chunk(in[j], a));
     }
     if (t == kThreads - 1)
         enc_scalar_wrap(src + 12 * nch, n - 12 * nch, 16 * nch, dst, L, a, !(flags & kFlagNoPad));
@@ -143,6 +222,7 @@ __global__ __launch_bounds__(kThreads) void k_encode_wrap(const uint8_t *__restr
 constexpr uint32_t kWsCode = 0x40, kBadCode = 0x80, kPadCode = 0x81;
 constexpr int kWsBlock = 256;            // threads per block of the tile kernels
 constexpr int64_t kRound = kWsBlock * 16;   // characters per block round
+constexpr int kMaxRounds = 8;            // rounds per tile at most (tiles of 4 .. 32 KiB)
 
 __device__ __forceinline__ bool is_sig(uint32_t code) { return !(code & kWsCode); }
 
@@ -187,19 +267,29 @@ __device__ __forceinline__ int sig_count(u32x4 c)
            __builtin_popcount(c.z & 0x40404040u) - __builtin_popcount(c.w & 0x40404040u);
 }
 
-__device__ __forceinline__ int64_t ws_tiles(int64_t n, int64_t TS) { return n > 0 ? (n + TS - 1) / TS : 0; }
+__host__ __device__ __forceinline__ int64_t ws_tiles(int64_t n, int64_t TS) { return n > 0 ? (n + TS - 1) / TS : 0; }
+
+// Inclusive scan over the 64 lanes of a wave with DPP: shifts by 1, 2, 4, 8
+// within rows of 16 lanes, then the last lane of row 0 / 2 added to rows
+// 1 / 3 and the last lane of row 1 to rows 2 and 3.  Lanes whose source lies
+// outside the row read 0.
+__device__ __forceinline__ int wave_incl_scan(int x)
+{
+    x += __builtin_amdgcn_update_dpp(0, x, 0x111, 0xF, 0xF, false);   // row_shr:1
+    x += __builtin_amdgcn_update_dpp(0, x, 0x112, 0xF, 0xF, false);   // row_shr:2
+    x += __builtin_amdgcn_update_dpp(0, x, 0x114, 0xF, 0xF, false);   // row_shr:4
+    x += __builtin_amdgcn_update_dpp(0, x, 0x118, 0xF, 0xF, false);   // row_shr:8
+    x += __builtin_amdgcn_update_dpp(0, x, 0x142, 0xA, 0xF, false);   // row_bcast:15
+    x += __builtin_amdgcn_update_dpp(0, x, 0x143, 0xC, 0xF, false);   // row_bcast:31
+    return x;
+}
 
 // Block-wide exclusive scan of v (one value per thread); *total gets the sum.
 // Uses wtot[kWsBlock/64]; contains one __syncthreads.
 __device__ __forceinline__ int block_excl_scan(int v, int *wtot, int *total)
 {
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    int x = v;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        const int y = __shfl_up(x, d, 64);
-        if (lane >= d) x += y;
-    }
+    const int x = wave_incl_scan(v);
     if (lane == 63) wtot[wv] = x;
     __syncthreads();
     int before = 0, all = 0;
@@ -213,17 +303,30 @@ __device__ __forceinline__ int block_excl_scan(int v, int *wtot, int *total)
     return before + x - v;
 }
 
-// k_ws_count: tile `tile` covers characters [tile*TS, min(n, (tile+1)*TS));
-// prefix[tile+1] receives its number of significant characters.  Invalid
-// characters go to *first_bad, '=' (padded mode) to *first_pad, both by
-// atomic minimum; both must hold kNoError before the launch.
-template <bool NT>
+// Codes of a full 16-character load.
+__device__ __forceinline__ u32x4 codes16(u32x4 q, const uint8_t *map)
+{
+    u32x4 c;
+    c.x = codes4(q.x, map);
+    c.y = codes4(q.y, map);
+    c.z = codes4(q.z, map);
+    c.w = codes4(q.w, map);
+    return c;
+}
+
+// k_ws_count: tile `tile` covers characters [tile*TS, min(n, (tile+1)*TS)),
+// TS = R rounds of kRound; prefix[tile+1] receives its number of significant
+// characters.  A full tile issues all R loads of a thread before it looks at
+// any.  Invalid characters go to *first_bad, '=' (padded mode) to
+// *first_pad, both by atomic minimum; both must hold kNoError before the
+// launch.
+template <int R, bool NT>
 __global__ __launch_bounds__(kWsBlock) void k_ws_count(const uint8_t *__restrict__ src, int64_t n,
-                                                       DecMap map, int64_t TS,
-                                                       int64_t *__restrict__ prefix,
+                                                       DecMap map, int64_t *__restrict__ prefix,
                                                        int64_t *__restrict__ first_pad,
                                                        int64_t *__restrict__ first_bad)
 {
+    constexpr int64_t TS = R * kRound;
     __shared__ uint32_t s_map[64];
     __shared__ int s_sum;
     stage_dec_map(s_map, map);
@@ -233,10 +336,22 @@ __global__ __launch_bounds__(kWsBlock) void k_ws_count(const uint8_t *__restrict
         const int64_t base = tile * TS, end = base + TS < n ? base + TS : n;
         int cnt = 0;
         uint32_t err = 0;
-        for (int64_t p = base + 16 * threadIdx.x; p < end; p += kRound) {
-            const u32x4 c = ws_codes<NT>(src, end, p, m);
-            cnt += sig_count(c);
-            err |= c.x | c.y | c.z | c.w;
+        if (end - base == TS) {
+            u32x4 q[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) q[r] = load16<NT>(src + base + r * kRound + 16 * threadIdx.x);
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const u32x4 c = codes16(q[r], m);
+                cnt += sig_count(c);
+                err |= c.x | c.y | c.z | c.w;
+            }
+        } else {
+            for (int64_t p = base + 16 * threadIdx.x; p < end; p += kRound) {
+                const u32x4 c = ws_codes<NT>(src, end, p, m);
+                cnt += sig_count(c);
+                err |= c.x | c.y | c.z | c.w;
+            }
         }
         // err ORs packed codes: bit 7 of any byte flags an invalid character or '='
         if (__ballot(err & 0x80808080u)) {
@@ -375,20 +490,71 @@ __device__ __forceinline__ void store3(uint8_t *o, uint32_t b)
     o[2] = (uint8_t)(b >> 16);
 }
 
-constexpr int kRing = 16384;             // LDS ring of significant values, bytes
+// LDS ring of significant values: kRing values, stored with 4 bytes of
+// padding after every 16 so that the byte writes of a wave (lane i near
+// value 16i) fall in distinct banks; ring_at maps a value index to its byte.
+constexpr int kRing = 16384;
+constexpr int kRingBytes = kRing / 16 * 20;
+__device__ __forceinline__ int ring_at(int64_t pos)
+{
+    const int p = (int)(pos & (kRing - 1));
+    return p + 4 * (p >> 4);
+}
+
+// The first `need` (<= 3) significant values after the end of tile `tile`
+// (significant index g0 onwards), packed as bytes; fewer if the input ends
+// first.  Fast path: the next tile is not empty and its first 16 characters
+// (loaded ahead as `head`) hold them; else a search through the prefix sums.
+__device__ uint32_t borrow_values(const uint8_t *src, int64_t n, const uint8_t *m,
+                                  const int64_t *prefix, int64_t ntiles, int64_t TS, int64_t total,
+                                  int64_t g0, int need, bool head_ok, u32x4 head, int64_t next_end)
+{
+    uint32_t extra = 0;
+    int got = 0;
+    if (head_ok && next_end - g0 >= need) {
+        const uint32_t hw[4] = {head.x, head.y, head.z, head.w};
+        for (int j = 0; j < 16 && got < need; ++j) {
+            const uint32_t code = m[(hw[j >> 2] >> (8 * (j & 3))) & 0xFF];
+            if (is_sig(code)) extra |= code << (8 * got++);
+        }
+        if (got == need) return extra;
+        extra = 0;
+        got = 0;
+    }
+    int64_t g = g0;
+    while (got < need && g < total) {
+        const int64_t u = tile_of(prefix, ntiles, g);
+        int64_t idx = prefix[u];
+        const int64_t ue = (u + 1) * TS < n ? (u + 1) * TS : n;
+        for (int64_t i = u * TS; i < ue && got < need; ++i) {
+            const uint32_t code = m[src[i]];
+            if (!is_sig(code)) continue;
+            if (idx == g) {
+                extra |= code << (8 * got++);
+                ++g;
+            }
+            ++idx;
+        }
+    }
+    return extra;
+}
 
 // k_ws_decode: tile `tile` decodes the quanta whose first significant value
 // lies in it, except quanta at index >= qlimit (the final quantum, left to
 // k_ws_finish).  Quantum q covers significant values [4q, 4q+4) and writes
-// dst[3q, 3q+3).
-template <bool NT>
+// dst[3q, 3q+3).  Ring index 0 stands for quantum Qr = Q0 - h, with h < 4
+// chosen so that 3*Qr + dst is a multiple of 4: every group of 16 values read
+// back then stores its 12 bytes at a 4-byte aligned address (the h quanta
+// before Q0 belong to earlier tiles and are not stored).
+template <int R, bool NT>
 __global__ __launch_bounds__(kWsBlock) void k_ws_decode(const uint8_t *__restrict__ src, int64_t n,
                                                         uint8_t *__restrict__ dst, DecMap map,
-                                                        int64_t TS, const int64_t *__restrict__ prefix,
+                                                        const int64_t *__restrict__ prefix,
                                                         uint32_t flags)
 {
+    constexpr int64_t TS = R * kRound;
     __shared__ uint32_t s_map[64];
-    __shared__ __align__(16) uint8_t ring[kRing];
+    __shared__ __align__(16) uint8_t ring[kRingBytes];
     __shared__ int wtot[kWsBlock / 64];
     __shared__ uint32_t s_extra;
     stage_dec_map(s_map, map);
@@ -398,6 +564,7 @@ __global__ __launch_bounds__(kWsBlock) void k_ws_decode(const uint8_t *__restric
     const int64_t total = prefix[ntiles];
     const bool nopad = (flags & kFlagNoPad) != 0;
     const int64_t qlimit = nopad ? total / 4 : (total >= 4 ? total / 4 - 1 : 0);
+    const int64_t dmod = (int64_t)((uint64_t)(uintptr_t)dst & 3);
     const int tid = threadIdx.x;
 
     for (int64_t tile = logical_block(); tile < ntiles; tile += gridDim.x) {
@@ -407,9 +574,28 @@ __global__ __launch_bounds__(kWsBlock) void k_ws_decode(const uint8_t *__restric
         if (C <= skip) continue;                     // block-uniform
         const int64_t Q0 = (K0 + skip) >> 2;
         if (Q0 >= qlimit) continue;
-        int64_t W = -skip, Rd = 0;                   // ring write / read counters
-        for (int64_t p0 = base; p0 < end; p0 += kRound) {
-            const u32x4 c = ws_codes<NT>(src, end, p0 + 16 * tid, m);
+        const int64_t h = (Q0 + 3 * dmod) & 3;
+        const int64_t Qr = Q0 - h;
+        // what the last quantum may borrow from the next tile, fetched early
+        const bool has_next = tile + 1 < ntiles;
+        const int64_t next_end = has_next ? prefix[tile + 2] : total;
+        const bool head_ok = has_next && base + TS + 16 <= n;
+        u32x4 head = u32x4{0u, 0u, 0u, 0u};
+        if (tid == 0 && head_ok) head = load16<false>(src + base + TS);
+        int64_t W = 4 * h - skip, Rd = 0;            // ring write / read counters
+        // a full tile issues all its loads before the first round
+        const bool full = end - base == TS;
+        u32x4 q[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            if (full) q[r] = load16<NT>(src + base + r * kRound + 16 * tid);
+            else q[r] = u32x4{0u, 0u, 0u, 0u};
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int64_t p0 = base + r * kRound;
+            if (p0 >= end) break;                    // block-uniform
+            const u32x4 c = full ? codes16(q[r], m) : ws_codes<NT>(src, end, p0 + 16 * tid, m);
             const uint32_t cw[4] = {c.x, c.y, c.z, c.w};
             int tot = 0;
             const int ex = block_excl_scan(sig_count(c), wtot, &tot);
@@ -418,7 +604,7 @@ __global__ __launch_bounds__(kWsBlock) void k_ws_decode(const uint8_t *__restric
             for (int j = 0; j < 16; ++j) {
                 const uint32_t code = (cw[j >> 2] >> (8 * (j & 3))) & 0xFF;
                 if (is_sig(code)) {
-                    if (pos >= 0) ring[pos & (kRing - 1)] = (uint8_t)code;
+                    if (pos >= 0) ring[ring_at(pos)] = (uint8_t)code;
                     ++pos;
                 }
             }
@@ -428,20 +614,22 @@ __global__ __launch_bounds__(kWsBlock) void k_ws_decode(const uint8_t *__restric
             const int64_t nfull = avail > 0 ? avail >> 4 : 0;
             if (tid < nfull) {
                 const int64_t r = Rd + 16 * tid;
-                const uint4 v = *(const uint4 *)(ring + (r & (kRing - 1)));
-                const int64_t q = Q0 + (r >> 2);
+                // 16 values from a multiple of 16: four dwords, 4-byte aligned
+                const uint32_t *rw = (const uint32_t *)(ring + ring_at(r));
+                const uint4 v = {rw[0], rw[1], rw[2], rw[3]};
+                const int64_t qq = Qr + (r >> 2);
                 const uint32_t b0 = ws_quantum(v.x), b1 = ws_quantum(v.y), b2 = ws_quantum(v.z),
                                b3 = ws_quantum(v.w);
-                if (q + 4 <= qlimit) {
+                if (qq >= Q0 && qq + 4 <= qlimit) {
                     u32x3 o;
                     o.x = b0 | (b1 << 24);
                     o.y = (b1 >> 8) | (b2 << 16);
                     o.z = (b2 >> 16) | (b3 << 8);
-                    store12<NT>(dst + 3 * q, o);
+                    store12<NT>(dst + 3 * qq, o);
                 } else {
                     const uint32_t b[4] = {b0, b1, b2, b3};
                     for (int k = 0; k < 4; ++k)
-                        if (q + k < qlimit) store3(dst + 3 * (q + k), b[k]);
+                        if (qq + k >= Q0 && qq + k < qlimit) store3(dst + 3 * (qq + k), b[k]);
                 }
             }
             Rd += 16 * nfull;
@@ -453,43 +641,23 @@ __global__ __launch_bounds__(kWsBlock) void k_ws_decode(const uint8_t *__restric
         const int64_t left = W - Rd;
         if (left > 0) {
             const int64_t rem = left & 3;
-            if (tid == 0) {
-                uint32_t extra = 0;
-                if (rem) {
-                    // significant values K0+C, K0+C+1, ... (as many as exist)
-                    int64_t g = K0 + C;
-                    int got = 0;
-                    while (got < 4 - rem && g < total) {
-                        const int64_t u = tile_of(prefix, ntiles, g);
-                        int64_t idx = prefix[u];
-                        const int64_t ue = (u + 1) * TS < n ? (u + 1) * TS : n;
-                        for (int64_t i = u * TS; i < ue && got < 4 - rem; ++i) {
-                            const uint32_t code = m[src[i]];
-                            if (!is_sig(code)) continue;
-                            if (idx == g) {
-                                extra |= code << (8 * got);
-                                ++got;
-                                ++g;
-                            }
-                            ++idx;
-                        }
-                    }
-                }
-                s_extra = extra;
-            }
+            if (tid == 0)
+                s_extra = rem ? borrow_values(src, n, m, prefix, ntiles, TS, total, K0 + C,
+                                              (int)(4 - rem), head_ok, head, next_end)
+                              : 0u;
             __syncthreads();
             const int64_t nq = (left + 3) >> 2;
             if (tid < nq) {
                 const int64_t r = Rd + 4 * tid;
-                const int64_t q = Q0 + (r >> 2);
+                const int64_t qq = Qr + (r >> 2);
                 uint32_t w = 0;
                 for (int k = 0; k < 4; ++k) {
                     const int64_t idx = 4 * tid + k;
-                    const uint32_t v = idx < left ? ring[(r + k) & (kRing - 1)]
+                    const uint32_t v = idx < left ? ring[ring_at(r + k)]
                                                   : (s_extra >> (8 * (idx - left))) & 0xFF;
                     w |= v << (8 * k);
                 }
-                if (q < qlimit) store3(dst + 3 * q, ws_quantum(w));
+                if (qq >= Q0 && qq < qlimit) store3(dst + 3 * qq, ws_quantum(w));
             }
         }
         __syncthreads();
@@ -644,9 +812,9 @@ hipError_t launch_encode_wrap(const uint8_t *src, int64_t n, uint8_t *dst, const
 
 int64_t ws_tile_size(int64_t n)
 {
-    // about 4096 tiles or more; 4 KiB .. 64 KiB, a power of two
+    // about 4096 tiles or more; 4 KiB .. 32 KiB (1 .. kMaxRounds rounds), a power of two
     int64_t ts = kRound;
-    while (ts < 65536 && n / (2 * ts) >= 4096) ts *= 2;
+    while (ts < kMaxRounds * kRound && n / (2 * ts) >= 4096) ts *= 2;
     return ts;
 }
 
@@ -656,6 +824,24 @@ int64_t ws_workspace_bytes(int64_t n)
     const int64_t ntiles = n > 0 ? (n + TS - 1) / TS : 0;
     return 8 * (ntiles + 2);
 }
+
+namespace {
+
+template <int R>
+void launch_ws_tiles(const uint8_t *src, int64_t n, uint8_t *dst, bool write, const DecMap &map,
+                     int64_t *prefix, int64_t *first_pad, int64_t *first_bad, uint32_t flags,
+                     int64_t grid, bool nt, hipStream_t stream)
+{
+    if (nt) hipLaunchKernelGGL((k_ws_count<R, true>), dim3(grid), dim3(kWsBlock), 0, stream, src, n, map, prefix, first_pad, first_bad);
+    else hipLaunchKernelGGL((k_ws_count<R, false>), dim3(grid), dim3(kWsBlock), 0, stream, src, n, map, prefix, first_pad, first_bad);
+    const int64_t ntiles = ws_tiles(n, R * kRound);
+    hipLaunchKernelGGL(k_ws_scan, dim3(1), dim3(kScanThreads), 0, stream, prefix, ntiles);
+    if (!write) return;
+    if (nt) hipLaunchKernelGGL((k_ws_decode<R, true>), dim3(grid), dim3(kWsBlock), 0, stream, src, n, dst, map, prefix, flags);
+    else hipLaunchKernelGGL((k_ws_decode<R, false>), dim3(grid), dim3(kWsBlock), 0, stream, src, n, dst, map, prefix, flags);
+}
+
+}  // namespace
 
 hipError_t launch_decode_ws(const uint8_t *src, int64_t n, uint8_t *dst, bool write, const DecMap &map,
                             int64_t *out_len, int64_t *first_bad, uint32_t flags, void *workspace,
@@ -671,13 +857,14 @@ hipError_t launch_decode_ws(const uint8_t *src, int64_t n, uint8_t *dst, bool wr
     if (grid >= kXcds) grid -= grid % kXcds;
     if (grid < 1) grid = 1;
     if (ntiles > 0) {
-        if (sh.nt) hipLaunchKernelGGL(k_ws_count<true>, dim3(grid), dim3(kWsBlock), 0, stream, src, n, map, TS, prefix, first_pad, first_bad);
-        else hipLaunchKernelGGL(k_ws_count<false>, dim3(grid), dim3(kWsBlock), 0, stream, src, n, map, TS, prefix, first_pad, first_bad);
-    }
-    hipLaunchKernelGGL(k_ws_scan, dim3(1), dim3(kScanThreads), 0, stream, prefix, ntiles);
-    if (write && ntiles > 0) {
-        if (sh.nt) hipLaunchKernelGGL(k_ws_decode<true>, dim3(grid), dim3(kWsBlock), 0, stream, src, n, dst, map, TS, prefix, flags);
-        else hipLaunchKernelGGL(k_ws_decode<false>, dim3(grid), dim3(kWsBlock), 0, stream, src, n, dst, map, TS, prefix, flags);
+        switch (TS / kRound) {
+        case 1: launch_ws_tiles<1>(src, n, dst, write, map, prefix, first_pad, first_bad, flags, grid, sh.nt, stream); break;
+        case 2: launch_ws_tiles<2>(src, n, dst, write, map, prefix, first_pad, first_bad, flags, grid, sh.nt, stream); break;
+        case 4: launch_ws_tiles<4>(src, n, dst, write, map, prefix, first_pad, first_bad, flags, grid, sh.nt, stream); break;
+        default: launch_ws_tiles<8>(src, n, dst, write, map, prefix, first_pad, first_bad, flags, grid, sh.nt, stream); break;
+        }
+    } else {
+        hipLaunchKernelGGL(k_ws_scan, dim3(1), dim3(kScanThreads), 0, stream, prefix, ntiles);
     }
     hipLaunchKernelGGL(k_ws_finish, dim3(1), dim3(kWsBlock), 0, stream, src, n, dst, map, TS, prefix,
                        first_pad, out_len, first_bad, flags, write ? 1 : 0);

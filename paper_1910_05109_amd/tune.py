@@ -20,8 +20,8 @@ import statistics
 
 import numpy as np
 
-from . import (OPS, STD, decode_async, decode_batch, encode, encode_batch, tune_get, tune_set,
-               validate_async)
+from . import (OPS, SKIP_WS, STD, decode_async, decode_batch, encode, encode_batch, tune_get,
+               tune_set, validate_async, workspace_size)
 
 UNROLLS = (1, 2, 4, 8)
 BLOCKS_PER_CU = (1, 2, 4, 8, 16, 32)
@@ -66,6 +66,16 @@ def _workload(torch, op, nbytes, seed=191005109):
     if op == "validate":
         st = torch.empty(2, dtype=torch.int64, device="cuda")
         return lambda: validate_async(text, STD, status=st)
+    if op in ("encode_wrap", "decode_ws"):
+        # MIME text: lines of 76 characters separated by CR LF
+        mime = encode(x, STD, line_len=76)
+        if op == "encode_wrap":
+            out = torch.empty_like(mime)
+            return lambda: encode(x, STD, out=out, line_len=76)
+        out = torch.empty(3 * (mime.numel() // 4), dtype=torch.uint8, device="cuda")
+        st = torch.empty(2, dtype=torch.int64, device="cuda")
+        ws = torch.empty(workspace_size(mime.numel(), SKIP_WS), dtype=torch.uint8, device="cuda")
+        return lambda: decode_async(mime, STD, out=out, status=st, flags=SKIP_WS, workspace=ws)
     # ragged batches: log-uniform lengths in [16, 1 MiB) up to nbytes in total
     lens = []
     total = 0
@@ -86,9 +96,16 @@ def _workload(torch, op, nbytes, seed=191005109):
                                 first_bad=dbad)
 
 
+# the whitespace-skipping kernels take no unroll, and their 20 KiB of LDS per
+# workgroup allow at most 7 workgroups per compute unit
+GRIDS = {"decode_ws": {"unrolls": (1,), "bpcs": (1, 2, 3, 4, 5, 6, 7)}}
+
+
 def tune_op(op: str, nbytes: int, reps: int = 10, unrolls=UNROLLS, bpcs=BLOCKS_PER_CU,
             nts=NONTEMPORAL, verbose: bool = True):
     import torch
+    unrolls = GRIDS.get(op, {}).get("unrolls", unrolls)
+    bpcs = GRIDS.get(op, {}).get("bpcs", bpcs)
     fn = _workload(torch, op, nbytes)
     old = tune_get(op)
     results = []

@@ -4,9 +4,11 @@ The kernels cut the input into tiles of TS characters.  Tile t holds the
 significant characters with indices prefix[t] .. prefix[t+1]-1 and decodes
 the quanta whose first significant value lies in it: it skips
 (4 - prefix[t] % 4) % 4 values that finish an earlier quantum, reads rounds
-of 4096 characters through a ring, emits every 16 values as 4 quanta, and
-completes its last quantum with up to three values borrowed from later
-tiles.  Quanta at index >= qlimit are left to the finishing block.
+of 4096 characters through a ring whose index 0 stands for quantum
+Q0 - h (h < 4 chosen so that every 16-value group stores at a 4-byte aligned
+output address), emits every 16 values as 4 quanta, and completes its last
+quantum with up to three values borrowed from later tiles.  Quanta before Q0
+and at index >= qlimit are not stored by the tile.
 
 This model repeats that index arithmetic in Python, on random inputs with
 whitespace runs of every length (empty tiles, runs longer than a tile), and
@@ -24,12 +26,12 @@ ROUND = 4096
 
 def tile_size(n):
     ts = ROUND
-    while ts < 65536 and n // (2 * ts) >= 4096:
+    while ts < 32768 and n // (2 * ts) >= 4096:
         ts *= 2
     return ts
 
 
-def model(text: bytes, nopad: bool, ts: int):
+def model(text: bytes, nopad: bool, ts: int, dmod: int = 0):
     n = len(text)
     sig = [i for i, c in enumerate(text) if c not in WS]
     ntiles = (n + ts - 1) // ts if n else 0
@@ -48,8 +50,11 @@ def model(text: bytes, nopad: bool, ts: int):
         Q0 = (K0 + skip) // 4
         if Q0 >= qlimit:
             continue
+        h = (Q0 + 3 * dmod) & 3
+        Qr = Q0 - h
+        assert (3 * Qr + dmod) % 4 == 0
         base, end = t * ts, min(n, (t + 1) * ts)
-        W, Rd = -skip, 0
+        W, Rd = 4 * h - skip, 0
         ring = {}
         g = K0                                     # significant index of the next value
         for p0 in range(base, end, ROUND):
@@ -62,9 +67,10 @@ def model(text: bytes, nopad: bool, ts: int):
             nfull = max(0, (W - Rd) // 16)
             for tid in range(nfull):
                 r = Rd + 16 * tid
-                q = Q0 + r // 4
+                q = Qr + r // 4
+                assert (3 * q + dmod) % 4 == 0        # aligned 12-byte store
                 for k in range(4):
-                    if q + k < qlimit:
+                    if Q0 <= q + k < qlimit:
                         idx = [ring[r + 4 * k + j] for j in range(4)]
                         assert (q + k) not in writes
                         writes[q + k] = (t, idx)
@@ -80,12 +86,12 @@ def model(text: bytes, nopad: bool, ts: int):
             nq = (left + 3) // 4
             for tid in range(nq):
                 r = Rd + 4 * tid
-                q = Q0 + r // 4
+                q = Qr + r // 4
                 idx = []
                 for k in range(4):
                     i = 4 * tid + k
-                    idx.append(ring[r + k] if i < left else (extra[i - left] if i - left < len(extra) else None))
-                if q < qlimit:
+                    idx.append(ring.get(r + k) if i < left else (extra[i - left] if i - left < len(extra) else None))
+                if Q0 <= q < qlimit:
                     assert None not in idx
                     assert q not in writes
                     writes[q] = (t, idx)
@@ -117,8 +123,8 @@ def test_every_quantum_written_once(nopad):
         n_sig = int(rng.integers(0, 20000))
         text = random_text(rng, n_sig, float(rng.choice([0.0, 0.02, 0.3, 0.9])),
                            int(rng.integers(0, 4)), ROUND)
-        model(text, nopad, ROUND)
-        model(text, nopad, 2 * ROUND)
+        model(text, nopad, ROUND, trial % 4)
+        model(text, nopad, 2 * ROUND, (trial + 1) % 4)
 
 
 def test_mime_lines_and_tile_sizes():
@@ -128,11 +134,12 @@ def test_mime_lines_and_tile_sizes():
         text = b"\r\n".join(lines)
         for ts in (ROUND, 4 * ROUND):
             for nopad in (False, True):
-                model(text, nopad, ts)
+                for dmod in range(4):
+                    model(text, nopad, ts, dmod)
 
 
 def test_tile_size_rule():
     assert tile_size(0) == 4096
     assert tile_size(10 ** 6) == 4096
     assert tile_size(64 << 20) == 16384
-    assert tile_size(1431655764) == 65536
+    assert tile_size(1431655764) == 32768
