@@ -19,7 +19,9 @@ loop), small (the 3 MiB workload), validate (read-only validation of the
 1 GiB encoding), host (the 1 GiB workload in host memory through the chunked
 host-device pipeline, PCIe included), variants (the 1 GiB payload unpadded,
 and as MIME text: 76-character lines with CR LF, wrapped encode and
-whitespace-skipping decode / validate).  Each prints its own JSON lines.
+whitespace-skipping decode / validate), fused (rows of base64 float32 decoded
+straight into bfloat16, against decode + a separate conversion).  Each prints
+its own JSON lines.
 """
 from __future__ import annotations
 
@@ -536,6 +538,49 @@ def run_variants(args, torch, b64):
     print(json.dumps(res), flush=True)
 
 
+def run_fused(args, torch, b64):
+    """Decode fused into its consumer: 65,536 rows of base64 float32 (1,536
+    per row, the size of a common text-embedding vector) straight into a
+    bfloat16 tensor, against decoding the rows to bytes (one batched launch)
+    and converting them with torch in a second pass."""
+    dim, nrows = 1536, 65536
+    raw = torch.from_numpy(workloads.random_bytes(workloads.SEED_BASE + 250, 4 * dim * nrows)).cuda()
+    in_off = torch.from_numpy(workloads.offsets(np.full(nrows, 4 * dim, dtype=np.int64))).cuda()
+    text, t_off, _ = b64.encode_batch(raw, in_off)            # the rows' base64 text
+    t_off = t_off.clone()
+    N = int(t_off[-1].item())
+    text = text[:N]
+    out = torch.empty((nrows, dim), dtype=torch.bfloat16, device="cuda")
+    st = torch.empty(nrows, dtype=torch.int64, device="cuda")
+    fused = lambda: b64.decode_f32_bf16(text, t_off, dim, dst=out, status=st, validate=False)
+    dbytes = torch.empty(nrows * 4 * dim + 16, dtype=torch.uint8, device="cuda")
+    d_off = torch.arange(nrows + 1, dtype=torch.int64, device="cuda") * (4 * dim)
+    dlen = torch.empty(nrows, dtype=torch.int64, device="cuda")
+    dbad = torch.empty(nrows, dtype=torch.int64, device="cuda")
+    out2 = torch.empty((nrows, dim), dtype=torch.bfloat16, device="cuda")
+
+    def unfused():
+        b64.decode_batch(text, t_off, dst=dbytes, out_off=d_off, out_len=dlen, first_bad=dbad,
+                         validate=False)
+        out2.copy_(dbytes[: nrows * 4 * dim].view(torch.float32).view(nrows, dim))
+
+    for _ in range(3):
+        fused(); unfused()
+    tf = _events_time(torch, fused, args.steps)
+    tu = _events_time(torch, unfused, args.steps)
+    assert bool((st == -1).all()) and bool((dbad == -1).all())
+    keep = ~torch.isnan(out2)                                # NaN encodings differ by convention
+    assert torch.equal(out.view(torch.int16)[keep], out2.view(torch.int16)[keep])
+    fb = N + 2 * nrows * dim                                 # algorithmic bytes of the fused kernel
+    ub = N + 2 * 4 * nrows * dim + 2 * nrows * dim           # decode to bytes, then convert
+    res = {"workload": f"{nrows} rows of base64 float32 x {dim} -> bfloat16", "n_chars": N,
+           "fused_ms": tf["median"], "fused_gbps_b64": N / tf["median"] / 1e6,
+           "fused_hbm_frac": fb / tf["median"] / 1e6 / HBM_PEAK_GBS,
+           "unfused_ms": tu["median"], "unfused_gbps_b64": N / tu["median"] / 1e6,
+           "speedup": tu["median"] / tf["median"], "bytes_fused": fb, "bytes_unfused": ub}
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -543,7 +588,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--mode", default="single",
                     choices=["single", "small", "sweep", "batch", "serve", "validate", "host",
-                             "variants"])
+                             "variants", "fused"])
     ap.add_argument("--chunk-mib", type=int, default=64)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--cpu-sample", type=int, default=512 << 20)
@@ -564,7 +609,7 @@ def main():
         sys.exit(1)
     {"single": run_single, "small": run_small, "sweep": run_sweep, "batch": run_batch,
      "serve": run_serve, "validate": run_validate, "host": run_host,
-     "variants": run_variants}[args.mode](args, torch, b64)
+     "variants": run_variants, "fused": run_fused}[args.mode](args, torch, b64)
 
 
 if __name__ == "__main__":

@@ -184,6 +184,24 @@ int64_t b64_decode_batch_mode(const uint8_t *src, const int64_t *in_off, int64_t
                               int64_t *first_bad, const char *alphabet, uint32_t flags,
                               hipStream_t stream);
 
+/* ----------------------------------------------------------- fused decode --
+ * Decode fused into its consumer (Section "Conclusion": run the decoder inside
+ * the code that uses the data).  Each of `nrows` rows packed back to back
+ * (row b is src[in_off[b] .. in_off[b+1]), in_off has nrows+1 non-decreasing
+ * entries) is the base64 encoding (padded, or unpadded with B64_NOPAD) of
+ * `dim` little-endian IEEE-754 float32 values; they are decoded and rounded
+ * to bfloat16 (nearest, ties to even; every NaN becomes 0x7FC0) in registers
+ * and written to dst[b*dim .. (b+1)*dim) (row-major [nrows, dim] bfloat16,
+ * device memory, 2*nrows*dim bytes).  The decoded bytes are never stored.
+ * status[b] (device, nrows entries) = -1 for a good row, the first invalid
+ * offset within the row for an invalid encoding, or -2 for a valid encoding
+ * whose decoded length is not 4*dim bytes; dst rows of bad rows are
+ * unspecified (but nothing outside them is written).  Asynchronous; returns 0
+ * or B64_EARG / B64_EHIP.  Safe to capture in a HIP graph. */
+int64_t b64_decode_f32_bf16(const uint8_t *src, const int64_t *in_off, int64_t nrows, int64_t dim,
+                            uint16_t *dst, int64_t *status, const char *alphabet, uint32_t flags,
+                            hipStream_t stream);
+
 /* Host-memory pipeline (an opaque handle).  Encodes or decodes data that
  * lives in ordinary host memory by cutting it into chunks that stream through
  * pinned staging, host-to-device copies, the kernels and device-to-host
@@ -212,7 +230,8 @@ const char *b64_pipeline_last_error(void);
 
 /* Launch shape used by the kernels of operation `op` (0 encode, 1 decode,
  * 2 encode_batch, 3 decode_batch, 4 validate, 5 line-wrapped encode,
- * 6 whitespace-skipping decode / validate): `unroll` lane chunks in flight per lane
+ * 6 whitespace-skipping decode / validate, 7 fused float32 -> bfloat16
+ * decode): `unroll` lane chunks in flight per lane
  * (1, 2, 4 or 8; a lane chunk is 12 bytes -> 16 characters or back),
  * `blocks_per_cu` workgroups of 256 threads per compute unit (1..64), and
  * `nontemporal` (0 or 1) for streaming loads and stores.  Process-wide; meant

@@ -20,6 +20,8 @@ Python API (numpy uint8 arrays in, numpy arrays out):
   encoded_len_mode / encode_mode_list / decode_mode_list -> the variants:
   flags NOPAD (no '=') and SKIP_WS (decode ignores space, tab, CR, LF), and
   line_len > 0 (encode breaks lines with CR LF)
+  f32_to_bf16 / decode_f32_bf16_rows -> the fused consumer: rows of base64
+  float32 decoded into bfloat16 (round to nearest, ties to even)
 """
 from __future__ import annotations
 
@@ -85,6 +87,10 @@ def lib() -> ctypes.CDLL:
         L.b64o_encode_mode_list.restype = None
         L.b64o_decode_mode_list.argtypes = [p, p, i64, p, p, p, p, u32]
         L.b64o_decode_mode_list.restype = None
+        L.b64o_f32_to_bf16.argtypes = [ctypes.c_uint32]
+        L.b64o_f32_to_bf16.restype = ctypes.c_uint16
+        L.b64o_decode_f32_bf16_rows.argtypes = [p, p, i64, i64, p, p, p, u32]
+        L.b64o_decode_f32_bf16_rows.restype = None
         _lib = L
     return _lib
 
@@ -271,3 +277,25 @@ def decode_mode_list(src: np.ndarray, in_off: np.ndarray, alpha=STD, flags: int 
     lib().b64o_decode_mode_list(_ptr(src), _ptr(in_off), nbuf, _ptr(dst), _ptr(out_off),
                                 _ptr(res), _ptr(a), flags)
     return dst, out_off, res[:nbuf]
+
+
+# --------------------------------------------------------- fused consumer --
+
+def f32_to_bf16(bits) -> np.ndarray:
+    """bfloat16 bits of float32 bit patterns (uint32 array), one C call each."""
+    bits = np.ascontiguousarray(np.asarray(bits, dtype=np.uint32).reshape(-1))
+    L = lib()
+    return np.array([L.b64o_f32_to_bf16(int(u)) for u in bits], dtype=np.uint16)
+
+
+def decode_f32_bf16_rows(src, in_off, dim: int, alpha=STD, flags: int = 0):
+    """(dst uint16 [nrows, dim], status int64 [nrows])."""
+    src = _u8(src)
+    in_off = np.ascontiguousarray(in_off, dtype=np.int64)
+    nrows = in_off.size - 1
+    dst = np.zeros((max(nrows, 1), max(dim, 1)), dtype=np.uint16)
+    status = np.empty(max(nrows, 1), dtype=np.int64)
+    a = _alpha(alpha)
+    lib().b64o_decode_f32_bf16_rows(_ptr(src), _ptr(in_off), nrows, dim, _ptr(dst), _ptr(status),
+                                    _ptr(a), flags)
+    return dst[:nrows, :dim], status[:nrows]

@@ -30,6 +30,7 @@
  * no blocking, no lookahead beyond what the definition needs.
  */
 #include <stdint.h>
+#include <stdlib.h>
 #include <string.h>
 
 #define B64O_INVALID 0xFFu          /* "special value" of the decode map       */
@@ -405,4 +406,51 @@ void b64o_decode_mode_list(const uint8_t *src, const int64_t *in_off, int64_t nb
     for (b = 0; b < nbuf; b++)
         result[b] = b64o_decode_mode(src + in_off[b], in_off[b + 1] - in_off[b], dst + out_off[b],
                                      alpha, flags);
+}
+
+/* ------------------------------------------------------ fused consumer -- */
+
+/* float32 bits -> bfloat16 bits, rounding to nearest with ties to even; every
+ * NaN becomes the quiet NaN 0x7FC0.  Written from the definition: the upper
+ * 16 bits of the float, plus one unit in the last place when the dropped
+ * 16 bits exceed half a unit, or equal it and the kept part is odd. */
+uint16_t b64o_f32_to_bf16(uint32_t u)
+{
+    uint32_t keep = u >> 16, drop = u & 0xFFFFu;
+    if ((u & 0x7F800000u) == 0x7F800000u && (u & 0x007FFFFFu) != 0) return 0x7FC0;
+    if (drop > 0x8000u || (drop == 0x8000u && (keep & 1u))) keep += 1;
+    return (uint16_t)keep;
+}
+
+/* Decode `nrows` rows packed back to back (row b is src[in_off[b] ..
+ * in_off[b+1])), each the base64 encoding (b64o_decode_mode with `flags`) of
+ * `dim` little-endian float32 values, into dst[b*dim .. (b+1)*dim) as
+ * bfloat16.  status[b] = -1 for a good row, the first invalid offset for an
+ * invalid encoding, -2 for a valid encoding whose length is not 4*dim bytes
+ * (its dst row is then unspecified).  A plain loop: decode the row, then
+ * convert each float (the consumer). */
+void b64o_decode_f32_bf16_rows(const uint8_t *src, const int64_t *in_off, int64_t nrows, int64_t dim,
+                               uint16_t *dst, int64_t *status, const uint8_t *alpha, unsigned flags)
+{
+    int64_t b, k, cap = 0;
+    uint8_t *tmp = 0;
+    for (b = 0; b < nrows; b++) {
+        int64_t len = in_off[b + 1] - in_off[b], need = 3 * (len / 4) + 3, r;
+        if (need > cap) {
+            uint8_t *t = (uint8_t *)realloc(tmp, (size_t)need);
+            if (!t) { status[b] = B64O_EARG; continue; }
+            tmp = t;
+            cap = need;
+        }
+        r = b64o_decode_mode(src + in_off[b], len, tmp, alpha, flags);
+        if (r < 0) { status[b] = r == B64O_EARG ? B64O_EARG : ~r; continue; }
+        if (r != 4 * dim) { status[b] = -2; continue; }
+        for (k = 0; k < dim; k++) {
+            uint32_t u = (uint32_t)tmp[4 * k] | ((uint32_t)tmp[4 * k + 1] << 8) |
+                         ((uint32_t)tmp[4 * k + 2] << 16) | ((uint32_t)tmp[4 * k + 3] << 24);
+            dst[b * dim + k] = b64o_f32_to_bf16(u);
+        }
+        status[b] = -1;
+    }
+    free(tmp);
 }

@@ -19,6 +19,10 @@ Variants (keyword arguments; the paper makes '=' optional and names MIME):
   flags=SKIP_WS   decode / validate ignore space, tab, CR, LF
   line_len=L      encode breaks lines of L characters (a multiple of 4) with CR LF
 
+Fused consumer:
+  decode_f32_bf16(src, in_off, dim) -> (bf16 tensor [nrows, dim], status [nrows]):
+                  rows of base64 float32 decoded straight into bfloat16
+
 Tensors are torch.uint8 (data) / torch.int64 (offsets) on the current CUDA
 (HIP) device; work is enqueued on torch's current stream.
 """
@@ -33,14 +37,14 @@ STD = b"ABCDEFGHIJKLMNOPQRSTUVWXYZabcdefghijklmnopqrstuvwxyz0123456789+/"
 URL = b"ABCDEFGHIJKLMNOPQRSTUVWXYZabcdefghijklmnopqrstuvwxyz0123456789-_"
 
 OPS = {"encode": 0, "decode": 1, "encode_batch": 2, "decode_batch": 3, "validate": 4,
-       "encode_wrap": 5, "decode_ws": 6}
+       "encode_wrap": 5, "decode_ws": 6, "decode_f32_bf16": 7}
 NOPAD = 1
 SKIP_WS = 2
 
 __all__ = ["STD", "URL", "NOPAD", "SKIP_WS", "B64Error", "load", "encoded_len", "decoded_max_len",
            "workspace_size", "encode",
            "decode", "decode_async", "validate", "validate_async", "encode_batch", "decode_batch",
-           "tune_set", "tune_get", "stream_ptr"]
+           "decode_f32_bf16", "tune_set", "tune_get", "stream_ptr"]
 
 
 def _torch():
@@ -329,6 +333,38 @@ def decode_batch(src, in_off, alphabet=STD, dst=None, out_off=None, out_len=None
                                            first_bad.data_ptr(), _alpha(alphabet), flags,
                                            stream_ptr(stream)), "b64_decode_batch_mode")
     return dst, out_off, out_len[:nbuf], first_bad[:nbuf]
+
+
+def decode_f32_bf16(src, in_off, dim: int, alphabet=STD, dst=None, status=None, stream=None,
+                    validate=True, flags: int = 0):
+    """Decode nrows = len(in_off)-1 packed rows, each the base64 encoding of
+    `dim` float32 values, straight into a [nrows, dim] bfloat16 tensor
+    (asynchronous).  Returns (dst, status): status[b] = -1 (good), the first
+    invalid offset, or -2 (valid base64 of the wrong length)."""
+    torch = _torch()
+    _check_u8(src, "src")
+    _check_i64(in_off, "in_off")
+    nrows = in_off.numel() - 1
+    if dim < 0 or nrows < 0:
+        raise ValueError("dim and the row count must be >= 0")
+    if dst is None:
+        dst = torch.empty((max(nrows, 1), max(dim, 1)), dtype=torch.bfloat16, device=src.device)
+    if status is None:
+        status = torch.empty(max(nrows, 1), dtype=torch.int64, device=src.device)
+    if dst.dtype != torch.bfloat16 or not dst.is_cuda or not dst.is_contiguous():
+        raise TypeError("dst must be a contiguous torch.bfloat16 CUDA tensor")
+    _check_i64(status, "status")
+    if dst.numel() < nrows * dim or status.numel() < nrows:
+        raise ValueError("dst or status too small")
+    if validate and nrows > 0 and not torch.cuda.is_current_stream_capturing():
+        lens = in_off[1:] - in_off[:-1]
+        first, last, min_len = (int(v) for v in torch.stack([in_off[0], in_off[-1], lens.min()]).cpu())
+        if first < 0 or min_len < 0 or last > src.numel():
+            raise ValueError("decode_f32_bf16: in_off must be non-decreasing within src")
+    check(load().b64_decode_f32_bf16(src.data_ptr(), in_off.data_ptr(), nrows, dim,
+                                     dst.data_ptr(), status.data_ptr(), _alpha(alphabet), flags,
+                                     stream_ptr(stream)), "b64_decode_f32_bf16")
+    return dst.reshape(-1)[: nrows * dim].view(nrows, dim), status[:nrows]
 
 
 def tune_set(op: str, unroll: int, blocks_per_cu: int, nontemporal: int = 1) -> None:

@@ -38,6 +38,7 @@ SIGNATURES = {
     "b64_validate_mode_async": ([_P, _I64, _P, _P, _P, _U32, _P, _I64, _P], _I64),
     "b64_encode_batch_mode": ([_P, _P, _I64, _P, _P, _P, _P, _U32, _P], _I64),
     "b64_decode_batch_mode": ([_P, _P, _I64, _P, _P, _P, _P, _P, _U32, _P], _I64),
+    "b64_decode_f32_bf16": ([_P, _P, _I64, _I64, _P, _P, _P, _U32, _P], _I64),
     "b64_pipeline_create": ([_I64, _INT, _INT], _P),
     "b64_pipeline_destroy": ([_P], None),
     "b64_pipeline_encode": ([_P, _P, _I64, _P, _P], _I64),

@@ -85,11 +85,12 @@ DecMap make_dec_ws(const char *alphabet, bool nopad)
 }
 
 // Launch shapes per operation (encode, decode, encode_batch, decode_batch,
-// validate, line-wrapped encode, whitespace-skipping decode); the defaults
-// are the autotuner's choices on MI355X (1 GiB single buffers, 1 GiB
-// log-uniform ragged batches).
-constexpr int kOps = 7;
-Shape g_shape[kOps] = {{4, 1, 1}, {8, 1, 1}, {4, 2, 1}, {4, 2, 1}, {8, 1, 1}, {8, 1, 1}, {1, 6, 1}};
+// validate, line-wrapped encode, whitespace-skipping decode, fused float32 ->
+// bfloat16 decode); the defaults are the autotuner's choices on MI355X (1 GiB
+// single buffers, 1 GiB log-uniform ragged batches, 1 GiB MIME text).
+constexpr int kOps = 8;
+Shape g_shape[kOps] = {{4, 1, 1}, {8, 1, 1}, {4, 2, 1}, {4, 2, 1}, {8, 1, 1}, {8, 1, 1}, {1, 6, 1},
+                       {4, 8, 1}};
 std::mutex g_mu;
 
 Shape shape_of(int op)
@@ -457,6 +458,23 @@ int64_t b64_decode_batch(const uint8_t *src, const int64_t *in_off, int64_t nbuf
 {
     return b64_decode_batch_mode(src, in_off, nbuf, dst, out_off, out_len, first_bad, alphabet, 0,
                                  stream);
+}
+
+int64_t b64_decode_f32_bf16(const uint8_t *src, const int64_t *in_off, int64_t nrows, int64_t dim,
+                            uint16_t *dst, int64_t *status, const char *alphabet, uint32_t flags,
+                            hipStream_t stream)
+{
+    if (nrows < 0 || dim < 0) return fail(B64_EARG, "negative row count or dim");
+    if (flags & ~kFlagNoPad) return fail(B64_EARG, "fused decode takes no flag but B64_NOPAD");
+    if (nrows == 0) return 0;
+    if (!src || !in_off || (dim > 0 && !dst) || !status) return fail(B64_EARG, "null pointer");
+    if (!alphabet_ok(alphabet)) return fail(B64_EARG, kBadAlphabet);
+    int cus = 0;
+    hipError_t e = cu_count(&cus);
+    if (e != hipSuccess) return hip_fail(e, "device query");
+    e = launch_decode_f32_bf16(src, in_off, nrows, dim, dst, status, make_dec(alphabet), flags,
+                               shape_of(7), cus, stream);
+    return e == hipSuccess ? 0 : hip_fail(e, "fused decode launch");
 }
 
 }  // extern "C"

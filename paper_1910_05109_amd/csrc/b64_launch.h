@@ -48,6 +48,10 @@ hipError_t launch_encode_wrap(const uint8_t *src, int64_t n, uint8_t *dst, const
 // five launches on `stream`, ending with the public status in *out_len and
 // *first_bad.  `map` holds the codes of make_dec_ws (b64_abi.hip);
 // `workspace` holds ws_workspace_bytes(n) bytes.
+// Fused decode + float32 -> bfloat16 of `nrows` rows (k_decode_f32_bf16).
+hipError_t launch_decode_f32_bf16(const uint8_t *src, const int64_t *in_off, int64_t nrows,
+                                  int64_t dim, uint16_t *dst, int64_t *status, const DecMap &map,
+                                  uint32_t flags, Shape sh, int cus, hipStream_t stream);
 int64_t ws_tile_size(int64_t n);
 int64_t ws_workspace_bytes(int64_t n);
 hipError_t launch_decode_ws(const uint8_t *src, int64_t n, uint8_t *dst, bool write, const DecMap &map,

@@ -37,6 +37,7 @@ def test_header_declares_the_boundary():
         "b64_encoded_len_mode", "b64_decoded_max_len_mode", "b64_decode_workspace_size",
         "b64_encode_mode", "b64_decode_mode", "b64_decode_mode_async", "b64_validate_mode",
         "b64_validate_mode_async", "b64_encode_batch_mode", "b64_decode_batch_mode",
+        "b64_decode_f32_bf16",
         "b64_pipeline_create", "b64_pipeline_destroy", "b64_pipeline_encode",
         "b64_pipeline_decode", "b64_pipeline_last_error",
         "b64_tune_set", "b64_tune_get", "b64_last_error"}
@@ -150,6 +151,14 @@ def test_argument_errors_without_gpu(lib):
     assert lib.b64_validate_mode_async(fake, 10, fake, fake, std, 2, None, 0, None) == EARG
     assert lib.b64_encode_batch_mode(fake, fake, 3, fake, fake, fake, std, 2, None) == EARG
     assert lib.b64_decode_batch_mode(fake, fake, 3, fake, fake, fake, fake, std, 2, None) == EARG
+    # fused decode
+    assert lib.b64_decode_f32_bf16(fake, fake, -1, 4, fake, fake, std, 0, None) == EARG
+    assert lib.b64_decode_f32_bf16(fake, fake, 3, -4, fake, fake, std, 0, None) == EARG
+    assert lib.b64_decode_f32_bf16(fake, fake, 3, 4, fake, fake, std, 2, None) == EARG
+    assert lib.b64_decode_f32_bf16(fake, None, 3, 4, fake, fake, std, 0, None) == EARG
+    assert lib.b64_decode_f32_bf16(fake, fake, 3, 4, fake, None, std, 0, None) == EARG
+    assert lib.b64_decode_f32_bf16(fake, fake, 3, 4, fake, fake, dup, 1, None) == EARG
+    assert lib.b64_decode_f32_bf16(None, None, 0, 4, None, None, std, 0, None) == 0
     # zero-size work needs no device
     assert lib.b64_encode(None, 0, None, std, None) == 0
     assert lib.b64_encode_mode(None, 0, None, std, 1, 76, None) == 0
@@ -162,10 +171,12 @@ def test_tuning_interface(lib):
     old = lib.b64_tune_get(0)
     assert lib.b64_tune_set(0, 3, 8, 0) == EARG
     assert lib.b64_tune_set(0, 4, 0, 0) == EARG
-    assert lib.b64_tune_set(7, 4, 8, 0) == EARG
+    assert lib.b64_tune_set(8, 4, 8, 0) == EARG
     assert lib.b64_tune_set(5, 3, 8, 0) == EARG
     assert lib.b64_tune_get(4) > 0
     assert lib.b64_tune_get(6) > 0
+    assert lib.b64_tune_get(7) > 0
+    assert lib.b64_tune_get(8) == EARG
     assert lib.b64_tune_set(0, 4, 8, 2) == EARG
     assert lib.b64_tune_set(0, 8, 16, 1) == 0
     assert lib.b64_tune_get(0) == 10816
