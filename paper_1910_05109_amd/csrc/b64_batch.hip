@@ -156,7 +156,7 @@ __global__ __launch_bounds__(kThreads) void k_encode_batch(
 // outputs are 4-byte aligned; chunks of four body quanta go to lanes, and the
 // quanta before the tile's first chunk and after its last one -- at most
 // three leading and three trailing body quanta and the last quantum (through
-// dec_tail) -- go to lanes 0..6, one each.
+// dec_tail_fast) -- go to lanes 0..6, one each.
 template <int U, bool NT>
 __device__ void decode_tile(const uint8_t *__restrict__ src, const int64_t *__restrict__ in_off,
                             int64_t nbuf, uint8_t *__restrict__ dst,
@@ -229,7 +229,7 @@ __device__ void decode_tile(const uint8_t *__restrict__ src, const int64_t *__re
                 }
             } else {
                 int64_t ol = 0;
-                const int64_t bad = dec_tail(qp, len - 4 * q, len, qo, m, &ol, nopad);
+                const int64_t bad = dec_tail_fast(qp, len - 4 * q, len, qo, m, &ol, nopad);
                 if (bad >= 0) atomic_min_i64(first_bad + b, 4 * q + bad);
                 else out_len[b] = ol;
             }

@@ -24,8 +24,9 @@
 // offset and publishes it with an atomic minimum.  Four 6-bit values are
 // packed as a<<18 | b<<12 | c<<6 | d (the paper's two multiply-adds) and the
 // three bytes of four quanta are packed into three dwords by v_perm_b32 (the
-// paper's final vpermb).  The last quantum, with its '=' rules, goes through
-// a separate single-lane path (the paper's "conventional code path").
+// paper's final vpermb).  The last quanta, with the '=' rules, go through a
+// separate single-lane path (the paper's "conventional code path"),
+// dec_tail_fast, which loads them all at once and checks them on registers.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -230,55 +231,109 @@ __device__ __forceinline__ int64_t dec_check_inner(const uint8_t *p, int64_t len
     return st == kDone ? len : -1;
 }
 
-// The last characters of an input, p[0..len) from a quantum boundary to the
-// end (n_total characters in all), checked as the end of the input.  Returns
-// the first invalid offset relative to p, or -1 with *out_len set to the
-// input's decoded length.  Padded: the input must end in the data state with
-// a length that is a multiple of four, or right after the padded quantum.
-// Unpadded: a last quantum of one character is incomplete, and one of 2 (3)
-// characters needs a last value with four (two) zero low bits; otherwise the
-// input could still be completed, so the error is at the end.
-__device__ inline int64_t dec_end(const uint8_t *p, int64_t len, int64_t n_total, const uint8_t *map,
-                                  bool nopad, int64_t *out_len)
+// The final quantum of an input: its r (1..4) characters in bytes 0..r-1 of
+// c.  The rules of dec_validate, and the end-of-input rules (padded: the
+// input ends in the data state with a length that is a multiple of four, or
+// right after the padded quantum; unpadded: a last quantum of 2 or 3
+// characters with zero trailing bits, or of 4), for one quantum, unrolled on
+// registers.  Returns -1 for a valid end (*nd = its data characters, *val =
+// their values packed as a<<18 | b<<12 | c<<6 | d, absent ones 0), else the
+// offset in the quantum of the first invalid character, r when the input ends
+// too early.
+__device__ __forceinline__ int final_quantum(uint32_t c, int r, const uint8_t *map, bool nopad,
+                                             int *nd, uint32_t *val)
 {
-    int st = kData;
-    const int64_t bad = dec_validate(p, len, map, &st, nopad);
-    if (bad >= 0) return bad;
-    const int r = (int)(n_total & 3);
-    if (nopad) {
-        if (r == 1) return len;
-        if (r >= 2 && (map[p[len - 1]] & (r == 2 ? 15u : 3u))) return len;
-        *out_len = 3 * (n_total >> 2) + (r ? r - 1 : 0);
-    } else {
-        if (st == kPad1 || (r != 0 && st != kDone)) return len;
-        const int64_t pads = n_total >= 4 ? (int64_t)(p[len - 1] == kPad) + (p[len - 2] == kPad) : 0;
-        *out_len = 3 * (n_total >> 2) - pads;
+    int st = kData, ndata = 0;
+    uint32_t v = 0, prev = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        if (i < r) {
+            const uint32_t ch = (c >> (8 * i)) & 0xFF;
+            if (st == kDone) return i;
+            if (ch != kPad || nopad) {
+                const uint32_t x = map[ch];
+                if (x == kBad || st == kPad1) return i;
+                v |= x << (18 - 6 * i);
+                prev = x;
+                ++ndata;
+            } else if (i < 2) {
+                return i;
+            } else if (i == 2) {
+                if (prev & 15) return i;
+                st = kPad1;
+            } else {
+                if (st != kPad1 && (prev & 3)) return i;
+                st = kDone;
+            }
+        }
     }
+    if (nopad) {
+        if (r == 1) return r;
+        if (r < 4 && (prev & (r == 2 ? 15u : 3u))) return r;
+    } else if (r != 4 || st == kPad1) {
+        return r;
+    }
+    *nd = ndata;
+    *val = v;
     return -1;
 }
 
-// The last (up to 19) characters of a buffer: validate as the end of the
-// input (dec_end) and, when valid, decode them.  Returns -1 and sets *out_len
-// (the buffer's whole decoded length) when valid, else the first invalid
-// offset relative to p.  A quantum of k data characters (4, or 2-3 before
-// '=' or the end) yields k-1 bytes.
-__device__ inline int64_t dec_tail(const uint8_t *p, int64_t len, int64_t n_total, uint8_t *o,
-                                   const uint8_t *map, int64_t *out_len, bool nopad = false)
+// The last characters of an input, p[0..len) from a quantum boundary to the
+// end (n_total characters in all, len <= 16: up to three body quanta and the
+// final quantum), validated as the end of the input and, when valid,
+// decoded.  Every load is issued up front and the rules run on registers, so
+// the tail costs one memory round trip instead of one per character.  With o == nullptr it only validates.  Returns -1 and sets
+// *out_len (the whole input's decoded length) when valid, else the first
+// invalid offset relative to p.
+__device__ inline int64_t dec_tail_fast(const uint8_t *p, int64_t len, int64_t n_total, uint8_t *o,
+                                        const uint8_t *map, int64_t *out_len, bool nopad)
 {
-    const int64_t bad = dec_end(p, len, n_total, map, nopad, out_len);
-    if (bad >= 0) return bad;
-    for (int64_t q = 0; q < len; q += 4) {
-        uint32_t v = 0;
-        int nd = 0;
-        for (int j = 0; j < 4; ++j) {
-            const bool data = q + j < len && p[q + j] != kPad;
-            v = (v << 6) | (data ? (uint32_t)map[p[q + j]] : 0u);
-            nd += data;
-        }
-        *o++ = (uint8_t)(v >> 16);
-        if (nd >= 3) *o++ = (uint8_t)(v >> 8);
-        if (nd == 4) *o++ = (uint8_t)v;
+    if (len <= 0) {
+        *out_len = 0;
+        return -1;
     }
+    const int nb = (int)((len - 1) >> 2);                  // body quanta, 0..3
+    const int r = (int)(len - 4 * nb);                     // final quantum, 1..4
+    uint32_t q[3] = {0u, 0u, 0u}, fq = 0;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+        if (i < nb) q[i] = *(const u32a1 *)(p + 4 * i);
+    if (len >= 4) {
+        fq = *(const u32a1 *)(p + len - 4) >> (8 * (4 - r));
+    } else {
+        for (int i = 0; i < r; ++i) fq |= (uint32_t)p[i] << (8 * i);
+    }
+    uint32_t v[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        if (i < nb) {
+            uint32_t qerr = 0;
+            v[i] = dec_quantum(q[i], map, qerr);
+            if (qerr & 0x80) {
+                const int64_t bad = dec_check_inner(p + 4 * i, 4, map, nopad);
+                if (bad >= 0) return 4 * i + bad;
+            }
+        }
+    }
+    int nd = 0;
+    uint32_t fv = 0;
+    const int fbad = final_quantum(fq, r, map, nopad, &nd, &fv);
+    if (fbad >= 0) return 4 * nb + fbad;
+    if (o) {
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            if (i < nb) {
+                o[3 * i] = (uint8_t)(v[i] >> 16);
+                o[3 * i + 1] = (uint8_t)(v[i] >> 8);
+                o[3 * i + 2] = (uint8_t)v[i];
+            }
+        }
+        uint8_t *of = o + 3 * nb;
+        if (nd >= 2) of[0] = (uint8_t)(fv >> 16);
+        if (nd >= 3) of[1] = (uint8_t)(fv >> 8);
+        if (nd >= 4) of[2] = (uint8_t)fv;
+    }
+    *out_len = 3 * ((n_total - r) >> 2) + nd - 1;
     return -1;
 }
 

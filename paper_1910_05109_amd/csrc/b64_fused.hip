@@ -40,50 +40,6 @@ __device__ __forceinline__ int64_t wave_min(int64_t v)
     return v;
 }
 
-// The final quantum of a row: its r (1..4) characters in bytes 0..r-1 of c.
-// The rules of dec_validate and dec_end for one quantum, unrolled on
-// registers.  Returns -1 for a valid end (*nd = its data characters, *val =
-// their values packed as a<<18 | b<<12 | c<<6 | d, absent ones 0), else the
-// offset in the quantum of the first invalid character, r when the row ends
-// too early.
-__device__ __forceinline__ int final_quantum(uint32_t c, int r, const uint8_t *map, bool nopad,
-                                             int *nd, uint32_t *val)
-{
-    int st = kData, ndata = 0;
-    uint32_t v = 0, prev = 0;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        if (i < r) {
-            const uint32_t ch = (c >> (8 * i)) & 0xFF;
-            if (st == kDone) return i;
-            if (ch != kPad || nopad) {
-                const uint32_t x = map[ch];
-                if (x == kBad || st == kPad1) return i;
-                v |= x << (18 - 6 * i);
-                prev = x;
-                ++ndata;
-            } else if (i < 2) {
-                return i;
-            } else if (i == 2) {
-                if (prev & 15) return i;
-                st = kPad1;
-            } else {
-                if (st != kPad1 && (prev & 3)) return i;
-                st = kDone;
-            }
-        }
-    }
-    if (nopad) {
-        if (r == 1) return r;
-        if (r < 4 && (prev & (r == 2 ? 15u : 3u))) return r;
-    } else if (r != 4 || st == kPad1) {
-        return r;
-    }
-    *nd = ndata;
-    *val = v;
-    return -1;
-}
-
 // Three bytes of a quantum value as b0 | b1<<8 | b2<<16 in output order.
 __device__ __forceinline__ uint32_t quantum_bytes(uint32_t v)
 {

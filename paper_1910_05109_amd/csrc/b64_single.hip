@@ -47,7 +47,7 @@ __global__ __launch_bounds__(kThreads) void k_encode(const uint8_t *__restrict__
 // 128-byte line (3*head = -dst mod 128; 43 is the inverse of 3 mod 128); then
 // lane chunk c covers characters [4*head + 16c, +16) and bytes
 // [3*head + 12c, +12).  Threads t < head decode one head quantum each; the
-// last thread runs dec_tail over the (at most three) body quanta left after
+// last thread runs dec_tail_fast over the (at most three) body quanta left after
 // the chunks and the last quantum.
 // first_bad must hold kNoError before the launch; invalid offsets are
 // published with an atomic minimum on it.  out_len is written only when the
@@ -108,7 +108,7 @@ __global__ __launch_bounds__(kThreads) void k_decode(const uint8_t *__restrict__
     }
     if (t == kThreads - 1) {
         const int64_t q = head + 4 * nch;
-        const int64_t bad = dec_tail(src + 4 * q, n - 4 * q, n, dst + 3 * q, m, out_len, nopad);
+        const int64_t bad = dec_tail_fast(src + 4 * q, n - 4 * q, n, dst + 3 * q, m, out_len, nopad);
         if (bad >= 0) atomic_min_i64(first_bad, 4 * q + bad);
     }
 }

@@ -97,7 +97,7 @@ __global__ __launch_bounds__(kThreads) void k_validate(const uint8_t *__restrict
         const int64_t q0 = 4 * nch;                 // first quantum after the chunks
         const uint8_t *p = src + 4 * q0;
         int64_t len = 0;
-        const int64_t bad = dec_end(p, n - 4 * q0, n, m, nopad, &len);
+        const int64_t bad = dec_tail_fast(p, n - 4 * q0, n, nullptr, m, &len, nopad);
         if (bad >= 0) atomic_min_i64(first_bad, 4 * q0 + bad);
         else *out_len = len;
     }
