@@ -495,11 +495,13 @@ __device__ __forceinline__ void store3(uint8_t *o, uint32_t b)
 // value 16i) fall in distinct banks; ring_at maps a value index to its byte.
 constexpr int kRing = 16384;
 constexpr int kRingBytes = kRing / 16 * 20;
-__device__ __forceinline__ int ring_at(int64_t pos)
+__device__ __forceinline__ int ring_at(int pos)
 {
-    const int p = (int)(pos & (kRing - 1));
+    const int p = pos & (kRing - 1);
     return p + 4 * (p >> 4);
 }
+// Ring byte that takes the writes of whitespace codes (never read).
+constexpr int kRingTrash = kRingBytes;
 
 // The first `need` (<= 3) significant values after the end of tile `tile`
 // (significant index g0 onwards), packed as bytes; fewer if the input ends
@@ -554,7 +556,7 @@ __global__ __launch_bounds__(kWsBlock) void k_ws_decode(const uint8_t *__restric
 {
     constexpr int64_t TS = R * kRound;
     __shared__ uint32_t s_map[64];
-    __shared__ __align__(16) uint8_t ring[kRingBytes];
+    __shared__ __align__(16) uint8_t ring[kRingBytes + 4];
     __shared__ int wtot[kWsBlock / 64];
     __shared__ uint32_t s_extra;
     stage_dec_map(s_map, map);
@@ -582,7 +584,9 @@ __global__ __launch_bounds__(kWsBlock) void k_ws_decode(const uint8_t *__restric
         const bool head_ok = has_next && base + TS + 16 <= n;
         u32x4 head = u32x4{0u, 0u, 0u, 0u};
         if (tid == 0 && head_ok) head = load16<false>(src + base + TS);
-        int64_t W = 4 * h - skip, Rd = 0;            // ring write / read counters
+        // ring write / read counters, tile-local.  Ring index 16 stands for
+        // quantum Qr, so that no write position is negative.
+        int W = 16 + 4 * (int)h - (int)skip, Rd = 16;
         // a full tile issues all its loads before the first round
         const bool full = end - base == TS;
         u32x4 q[R];
@@ -595,29 +599,41 @@ __global__ __launch_bounds__(kWsBlock) void k_ws_decode(const uint8_t *__restric
         for (int r = 0; r < R; ++r) {
             const int64_t p0 = base + r * kRound;
             if (p0 >= end) break;                    // block-uniform
-            const u32x4 c = full ? codes16(q[r], m) : ws_codes<NT>(src, end, p0 + 16 * tid, m);
-            const uint32_t cw[4] = {c.x, c.y, c.z, c.w};
+            // the 16 codes of this thread, one per register
+            uint32_t cj[16];
+            if (full) {
+                const uint32_t qw[4] = {q[r].x, q[r].y, q[r].z, q[r].w};
+#pragma unroll
+                for (int j = 0; j < 16; ++j) cj[j] = m[(qw[j >> 2] >> (8 * (j & 3))) & 0xFF];
+            } else {
+                const u32x4 c = ws_codes<NT>(src, end, p0 + 16 * tid, m);
+                const uint32_t cw[4] = {c.x, c.y, c.z, c.w};
+#pragma unroll
+                for (int j = 0; j < 16; ++j) cj[j] = (cw[j >> 2] >> (8 * (j & 3))) & 0xFF;
+            }
+            int cnt = 0;
+#pragma unroll
+            for (int j = 0; j < 16; ++j) cnt += cj[j] != kWsCode;
             int tot = 0;
-            const int ex = block_excl_scan(sig_count(c), wtot, &tot);
-            int64_t pos = W + ex;
+            const int ex = block_excl_scan(cnt, wtot, &tot);
+            int pos = W + ex;
+            // straight-line writes: a whitespace code goes to the trash byte
 #pragma unroll
             for (int j = 0; j < 16; ++j) {
-                const uint32_t code = (cw[j >> 2] >> (8 * (j & 3))) & 0xFF;
-                if (is_sig(code)) {
-                    if (pos >= 0) ring[ring_at(pos)] = (uint8_t)code;
-                    ++pos;
-                }
+                const bool sig = cj[j] != kWsCode;
+                ring[sig ? ring_at(pos) : kRingTrash] = (uint8_t)cj[j];
+                pos += sig;
             }
             W += tot;
             __syncthreads();
-            const int64_t avail = W - Rd;
-            const int64_t nfull = avail > 0 ? avail >> 4 : 0;
+            const int avail = W - Rd;
+            const int nfull = avail > 0 ? avail >> 4 : 0;
             if (tid < nfull) {
-                const int64_t r = Rd + 16 * tid;
+                const int r = Rd + 16 * tid;
                 // 16 values from a multiple of 16: four dwords, 4-byte aligned
                 const uint32_t *rw = (const uint32_t *)(ring + ring_at(r));
                 const uint4 v = {rw[0], rw[1], rw[2], rw[3]};
-                const int64_t qq = Qr + (r >> 2);
+                const int64_t qq = Qr + ((r - 16) >> 2);
                 const uint32_t b0 = ws_quantum(v.x), b1 = ws_quantum(v.y), b2 = ws_quantum(v.z),
                                b3 = ws_quantum(v.w);
                 if (qq >= Q0 && qq + 4 <= qlimit) {
@@ -638,21 +654,21 @@ __global__ __launch_bounds__(kWsBlock) void k_ws_decode(const uint8_t *__restric
         }
         // fewer than 16 values left: whole quanta, then one quantum that may
         // take up to three values from later tiles
-        const int64_t left = W - Rd;
+        const int left = W - Rd;
         if (left > 0) {
-            const int64_t rem = left & 3;
+            const int rem = left & 3;
             if (tid == 0)
                 s_extra = rem ? borrow_values(src, n, m, prefix, ntiles, TS, total, K0 + C,
                                               (int)(4 - rem), head_ok, head, next_end)
                               : 0u;
             __syncthreads();
-            const int64_t nq = (left + 3) >> 2;
+            const int nq = (left + 3) >> 2;
             if (tid < nq) {
-                const int64_t r = Rd + 4 * tid;
-                const int64_t qq = Qr + (r >> 2);
+                const int r = Rd + 4 * tid;
+                const int64_t qq = Qr + ((r - 16) >> 2);
                 uint32_t w = 0;
                 for (int k = 0; k < 4; ++k) {
-                    const int64_t idx = 4 * tid + k;
+                    const int idx = 4 * tid + k;
                     const uint32_t v = idx < left ? ring[ring_at(r + k)]
                                                   : (s_extra >> (8 * (idx - left))) & 0xFF;
                     w |= v << (8 * k);

@@ -54,20 +54,20 @@ def model(text: bytes, nopad: bool, ts: int, dmod: int = 0):
         Qr = Q0 - h
         assert (3 * Qr + dmod) % 4 == 0
         base, end = t * ts, min(n, (t + 1) * ts)
-        W, Rd = 4 * h - skip, 0
+        W, Rd = 16 + 4 * h - skip, 16             # ring index 16 stands for quantum Qr
         ring = {}
         g = K0                                     # significant index of the next value
         for p0 in range(base, end, ROUND):
             chunk = [c for c in text[p0:min(end, p0 + ROUND)] if c not in WS]
             for v in chunk:
-                if W >= 0:
-                    ring[W] = g
+                assert W >= 0
+                ring[W] = g
                 W += 1
                 g += 1
             nfull = max(0, (W - Rd) // 16)
             for tid in range(nfull):
                 r = Rd + 16 * tid
-                q = Qr + r // 4
+                q = Qr + (r - 16) // 4
                 assert (3 * q + dmod) % 4 == 0        # aligned 12-byte store
                 for k in range(4):
                     if Q0 <= q + k < qlimit:
@@ -86,7 +86,7 @@ def model(text: bytes, nopad: bool, ts: int, dmod: int = 0):
             nq = (left + 3) // 4
             for tid in range(nq):
                 r = Rd + 4 * tid
-                q = Qr + r // 4
+                q = Qr + (r - 16) // 4
                 idx = []
                 for k in range(4):
                     i = 4 * tid + k
