@@ -61,7 +61,7 @@ def test_bad_rows(b64, oracle):
     rows = [text[t_off[b]:t_off[b + 1]].copy() for b in range(nrows)]
     bad = workloads.non_alphabet_bytes(STD)
     for b in range(0, nrows, 7):
-        kind = int(g.integers(0, 5))
+        kind = int(g.integers(0, 6))
         r = rows[b]
         if kind == 0:                                        # invalid byte anywhere
             r[int(g.integers(0, r.size))] = bad[int(g.integers(0, bad.size))]
@@ -71,6 +71,8 @@ def test_bad_rows(b64, oracle):
             rows[b] = r[: r.size - int(g.integers(1, 8))]
         elif kind == 3:                                      # valid, 4 bytes short
             rows[b] = oracle.encode(workloads.random_bytes(b, 4 * dim - 4))
+        elif kind == 4:                                      # valid, 4 bytes long
+            rows[b] = oracle.encode(workloads.random_bytes(b, 4 * dim + 4))
         else:                                                # empty row
             rows[b] = r[:0]
     text = np.concatenate(rows)

@@ -65,15 +65,16 @@ def test_rows_match_stdlib_and_torch(oracle):
 
 def test_invalid_and_wrong_length_rows(oracle):
     dim = 10
-    raw, texts = _rows(workloads.SEED_BASE + 210, 6, dim)
+    raw, texts = _rows(workloads.SEED_BASE + 210, 7, dim)
     texts[1] = texts[1][:5] + b"*" + texts[1][6:]          # invalid byte at 5
     texts[2] = base64.b64encode(raw[2].tobytes()[:-4])     # valid, 4 bytes short
     texts[3] = texts[3][:-1]                               # truncated
     texts[4] = b""                                         # empty row
+    texts[6] = base64.b64encode(raw[6].tobytes() + b"1234")  # valid, 4 bytes long
     src = np.frombuffer(b"".join(texts), dtype=np.uint8)
     in_off = workloads.offsets(np.array([len(t) for t in texts], dtype=np.int64))
     dst, status = oracle.decode_f32_bf16_rows(src, in_off, dim)
-    assert status.tolist() == [-1, 5, -2, len(texts[3]), -2, -1]
+    assert status.tolist() == [-1, 5, -2, len(texts[3]), -2, -1, -2]
     assert status[3] == ~oracle.decode_raw(np.frombuffer(texts[3], dtype=np.uint8))
-    ref = torch_bf16(raw.reshape(-1).view(np.uint32)).reshape(6, dim)
+    ref = torch_bf16(raw.reshape(-1).view(np.uint32)).reshape(7, dim)
     assert (dst[0] == ref[0]).all() and (dst[5] == ref[5]).all()
