@@ -142,7 +142,7 @@ int64_t b64_encoded_len_mode(int64_t n, uint32_t flags, int64_t line_len);
 int64_t b64_decoded_max_len_mode(int64_t n, uint32_t flags);
 /* Device workspace, in bytes, that the asynchronous B64_SKIP_WS decode and
  * validate need for n characters (0 without B64_SKIP_WS): 8 bytes per tile of
- * 4-64 KiB of input plus 16.  B64_EARG for n < 0 or unknown flags. */
+ * 4-32 KiB of input plus 16.  B64_EARG for n < 0 or unknown flags. */
 int64_t b64_decode_workspace_size(int64_t n, uint32_t flags);
 
 /* Encode with variants.  Asynchronous; returns b64_encoded_len_mode(n, flags,
@@ -232,7 +232,9 @@ const char *b64_pipeline_last_error(void);
  * 2 encode_batch, 3 decode_batch, 4 validate, 5 line-wrapped encode,
  * 6 whitespace-skipping decode / validate, 7 fused float32 -> bfloat16
  * decode): `unroll` lane chunks in flight per lane
- * (1, 2, 4 or 8; a lane chunk is 12 bytes -> 16 characters or back),
+ * (1, 2, 4 or 8; a lane chunk is 12 bytes -> 16 characters or back; for op 6
+ * the rounds of 1024 characters a decoding wave has in flight: 1, 2 or 4,
+ * and 8 runs as 2),
  * `blocks_per_cu` workgroups of 256 threads per compute unit (1..64), and
  * `nontemporal` (0 or 1) for streaming loads and stores.  Process-wide; meant
  * for the autotuner.  Does not change results.  Returns 0 or B64_EARG. */

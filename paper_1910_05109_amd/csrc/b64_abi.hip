@@ -89,7 +89,7 @@ DecMap make_dec_ws(const char *alphabet, bool nopad)
 // bfloat16 decode); the defaults are the autotuner's choices on MI355X (1 GiB
 // single buffers, 1 GiB log-uniform ragged batches, 1 GiB MIME text).
 constexpr int kOps = 8;
-Shape g_shape[kOps] = {{4, 1, 1}, {8, 1, 1}, {4, 2, 1}, {4, 2, 1}, {8, 1, 1}, {8, 1, 0}, {1, 6, 1},
+Shape g_shape[kOps] = {{4, 1, 1}, {8, 1, 1}, {4, 2, 1}, {4, 2, 1}, {8, 1, 1}, {8, 1, 0}, {4, 4, 1},
                        {4, 8, 1}};
 std::mutex g_mu;
 

@@ -22,15 +22,16 @@
 //                characters, and (atomic minima) the first invalid character
 //                and the first '='.
 //   k_ws_scan    one block: inclusive prefix sums of the tile counts.
-//   k_ws_decode  per tile: the block compacts its significant values into an
-//                LDS ring (a block-wide exclusive scan per round gives each
-//                thread its write position) and decodes the whole quanta
-//                whose first value lies in the tile; the last one may borrow
-//                up to three values from the following tiles.
+//   k_ws_decode  per tile, one wave: rounds of 1024 characters are compacted
+//                into an LDS buffer (characters read back transposed, a
+//                ballot and a masked bit count per row of 64 give each its
+//                position) and the whole quanta whose first value lies in the
+//                tile are decoded; the last one may borrow up to three values
+//                from the following tiles.
 //   k_ws_finish  one block: the '=' and end-of-input rules over the sequence
 //                of significant characters, the final quantum, the status.
-// Tiles are dealt to blocks grid-stride, so the grid streams through one
-// window of memory.
+// Tiles are dealt grid-stride (to blocks in k_ws_count, to waves in
+// k_ws_decode), so the grid streams through one window of memory.
 #include "b64_launch.h"
 
 namespace b64hip {
@@ -269,40 +270,6 @@ __device__ __forceinline__ int sig_count(u32x4 c)
 
 __host__ __device__ __forceinline__ int64_t ws_tiles(int64_t n, int64_t TS) { return n > 0 ? (n + TS - 1) / TS : 0; }
 
-// Inclusive scan over the 64 lanes of a wave with DPP: shifts by 1, 2, 4, 8
-// within rows of 16 lanes, then the last lane of row 0 / 2 added to rows
-// 1 / 3 and the last lane of row 1 to rows 2 and 3.  Lanes whose source lies
-// outside the row read 0.
-__device__ __forceinline__ int wave_incl_scan(int x)
-{
-    x += __builtin_amdgcn_update_dpp(0, x, 0x111, 0xF, 0xF, false);   // row_shr:1
-    x += __builtin_amdgcn_update_dpp(0, x, 0x112, 0xF, 0xF, false);   // row_shr:2
-    x += __builtin_amdgcn_update_dpp(0, x, 0x114, 0xF, 0xF, false);   // row_shr:4
-    x += __builtin_amdgcn_update_dpp(0, x, 0x118, 0xF, 0xF, false);   // row_shr:8
-    x += __builtin_amdgcn_update_dpp(0, x, 0x142, 0xA, 0xF, false);   // row_bcast:15
-    x += __builtin_amdgcn_update_dpp(0, x, 0x143, 0xC, 0xF, false);   // row_bcast:31
-    return x;
-}
-
-// Block-wide exclusive scan of v (one value per thread); *total gets the sum.
-// Uses wtot[kWsBlock/64]; contains one __syncthreads.
-__device__ __forceinline__ int block_excl_scan(int v, int *wtot, int *total)
-{
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int x = wave_incl_scan(v);
-    if (lane == 63) wtot[wv] = x;
-    __syncthreads();
-    int before = 0, all = 0;
-#pragma unroll
-    for (int k = 0; k < kWsBlock / 64; ++k) {
-        const int s = wtot[k];
-        before += k < wv ? s : 0;
-        all += s;
-    }
-    *total = all;
-    return before + x - v;
-}
-
 // Codes of a full 16-character load.
 __device__ __forceinline__ u32x4 codes16(u32x4 q, const uint8_t *map)
 {
@@ -490,18 +457,15 @@ __device__ __forceinline__ void store3(uint8_t *o, uint32_t b)
     o[2] = (uint8_t)(b >> 16);
 }
 
-// LDS ring of significant values: kRing values, stored with 4 bytes of
-// padding after every 16 so that the byte writes of a wave (lane i near
-// value 16i) fall in distinct banks; ring_at maps a value index to its byte.
-constexpr int kRing = 16384;
-constexpr int kRingBytes = kRing / 16 * 20;
-__device__ __forceinline__ int ring_at(int pos)
-{
-    const int p = pos & (kRing - 1);
-    return p + 4 * (p >> 4);
-}
-// Ring byte that takes the writes of whitespace codes (never read).
-constexpr int kRingTrash = kRingBytes;
+// k_ws_decode works per wave: a wave decodes a whole tile in rounds of
+// kWaveRound characters.  Its value buffer takes a round's significant values
+// after those the previous round left over (fewer than 16, moved to position
+// 16), groups of 16 are read back from position 16 on (16-byte aligned
+// loads), and positions 0..15 take at most three values that belong to a
+// quantum of an earlier tile (never read).
+constexpr int kWaveRound = 1024;
+constexpr int kWsTrash = 16 + kWaveRound + 16;   // 64 bytes, one per lane: whitespace writes
+constexpr int kWsBuf = kWsTrash + 64;
 
 // The first `need` (<= 3) significant values after the end of tile `tile`
 // (significant index g0 onwards), packed as bytes; fewer if the input ends
@@ -541,24 +505,163 @@ __device__ uint32_t borrow_values(const uint8_t *src, int64_t n, const uint8_t *
     return extra;
 }
 
+// Per-wave state of k_ws_decode.  W is the next write position in the value
+// buffer and Qb the quantum that buffer position 16 stands for; Q0 and qlimit
+// bound the quanta the tile stores.  held/held_k: a group of four quanta that
+// the hot path leaves for later (the first group of a tile, whose first h
+// quanta are not the tile's), as output bytes and the index of its first
+// quantum relative to Q0 (held_k = 1 when there is none).
+struct WsState {
+    int W;
+    int64_t Qb, Q0, qlimit;
+    uint32_t held[4];
+    int held_k;
+};
+
+// One round of k_ws_decode: the wave's characters [p0, p0 + kWaveRound), of
+// which those at or past `end` count as whitespace (HOT: none are); `raw`
+// holds the lane's 16 characters p0 + 16*lane ...
+//
+// HOT rounds belong to full tiles whose quanta all lie below qlimit.  There
+// every round issues exactly one vector store instruction (lanes without a
+// whole group of the tile's own quanta are masked off), so that the compiler
+// can count the vector memory operations issued after a prefetched load
+// exactly and wait for that load alone, not for the stores as well (loads
+// and stores share one in-order counter).  The group of the tile's first
+// round whose first quanta belong to the tile before is kept in S.held and
+// stored after the rounds.
+//
+// Compaction: the lane puts its 16 characters in the wave's staging area and
+// the wave reads them back transposed, row j being characters 64j .. 64j+63
+// with lane l on character 64j + l.  Characters of a row are in lane order,
+// so a ballot of "significant" over the row and a masked bit count below the
+// lane (mbcnt) give each character its position among the row's significant
+// values, and rows follow each other.  Per character: an LDS read of the
+// staged byte, one of the map, a compare, two mbcnt and an add, and one byte
+// write; a row's writes land on consecutive bytes.  A wave's LDS operations
+// complete in order, so the wave needs no barrier between its phases, only
+// fences that keep the compiler from moving LDS accesses across them.
+// `vb` is the block's array of value buffers and `wo` this wave's offset in
+// it: positions are kept as offsets into the whole array, so the array's
+// address folds into the LDS instructions' constant offsets.
+template <bool HOT, bool NT>
+__device__ __forceinline__ void ws_round(u32x4 raw, int64_t p0, int64_t end, uint8_t *st,
+                                         const uint8_t *m, uint8_t *vb, int wo,
+                                         uint8_t *__restrict__ dst, WsState &S)
+{
+    const int lane = threadIdx.x & 63;
+    *(u32x4 *)(st + 16 * lane) = raw;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // the running write offset lives in a vector register, where the masked
+    // bit count can add it at no cost; whitespace lanes write to their own
+    // trash byte
+    int at0;
+    asm volatile("v_mov_b32 %0, %1" : "=v"(at0) : "s"(wo + S.W));
+    const int start = at0, trash = wo + kWsTrash + lane;
+    // all 32 reads first: the writes below could alias them as far as the
+    // compiler knows
+    uint32_t code[16];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) code[j] = st[64 * j + lane];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        code[j] = m[code[j]];
+        if (!HOT && p0 + 64 * j + lane >= end) code[j] = kWsCode;
+    }
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        const bool sig = code[j] != kWsCode;
+        const uint64_t b = __builtin_amdgcn_ballot_w64(sig);
+        const int at = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(b >> 32),
+                                                      __builtin_amdgcn_mbcnt_lo((uint32_t)b, (uint32_t)at0));
+        vb[sig ? at : trash] = (uint8_t)code[j];
+        at0 += (int)__builtin_popcountll(b);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    uint8_t *const cb = vb + wo;
+    const int rb = S.W + __builtin_amdgcn_readfirstlane(at0 - start);
+    const int avail = rb - 16;
+    const int nfull = avail > 0 ? avail >> 4 : 0;   // at most 64 (rb <= 31 + 1024)
+    const int64_t lo64 = S.Q0 - S.Qb, hi64 = S.qlimit - S.Qb;
+    const int lo = (int)lo64, hi = hi64 < (1 << 20) ? (int)hi64 : (1 << 20);
+    uint8_t *const o = dst + 3 * S.Qb;
+    if (HOT) {
+        // quanta Qb + 4*lane .. +3; every lane computes, whole groups of the
+        // tile's own quanta are stored, with one store instruction
+        const int k0 = 4 * lane;
+        const u32x4 v = *(const u32x4 *)(cb + 16 + 16 * lane);
+        const uint32_t b0 = ws_quantum(v.x), b1 = ws_quantum(v.y), b2 = ws_quantum(v.z),
+                       b3 = ws_quantum(v.w);
+        u32x3 w;
+        w.x = b0 | (b1 << 24);
+        w.y = (b1 >> 8) | (b2 << 16);
+        w.z = (b2 >> 16) | (b3 << 8);
+        // a single masked store, the address and data computed outside it
+        uint8_t *const to = o + 3 * k0;
+        if (lane < nfull && k0 >= lo) store12<NT>(to, w);
+        if (lane < nfull && k0 < lo) {                  // lane 0 of the first round only
+            S.held[0] = b0;
+            S.held[1] = b1;
+            S.held[2] = b2;
+            S.held[3] = b3;
+            S.held_k = k0 - lo;
+        }
+    } else if (lane < nfull) {
+        const int g = lane;
+        const u32x4 v = *(const u32x4 *)(cb + 16 + 16 * g);
+        const uint32_t b0 = ws_quantum(v.x), b1 = ws_quantum(v.y), b2 = ws_quantum(v.z),
+                       b3 = ws_quantum(v.w);
+        // quanta Qb + 4g .. +3; those before Q0 or at qlimit and past are not stored
+        const int k0 = 4 * g;
+        if (k0 >= lo && k0 + 4 <= hi) {
+            u32x3 w;
+            w.x = b0 | (b1 << 24);
+            w.y = (b1 >> 8) | (b2 << 16);
+            w.z = (b2 >> 16) | (b3 << 8);
+            store12<NT>(o + 3 * k0, w);
+        } else {
+            const uint32_t bb[4] = {b0, b1, b2, b3};
+            for (int k = 0; k < 4; ++k)
+                if (k0 + k >= lo && k0 + k < hi) store3(o + 3 * (k0 + k), bb[k]);
+        }
+    }
+    // the values after the last whole group move to position 16 (none while
+    // the write position is still below 16: positions below 16 are never
+    // read); all lanes read before any writes
+    const int keep = avail - 16 * nfull;
+    uint32_t carry = 0;
+    if (lane < keep) carry = cb[16 + 16 * nfull + lane];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    if (lane < keep) cb[16 + lane] = (uint8_t)carry;
+    S.W = keep >= 0 ? 16 + keep : rb;
+    S.Qb += 4 * nfull;
+}
+
 // k_ws_decode: tile `tile` decodes the quanta whose first significant value
 // lies in it, except quanta at index >= qlimit (the final quantum, left to
 // k_ws_finish).  Quantum q covers significant values [4q, 4q+4) and writes
-// dst[3q, 3q+3).  Ring index 0 stands for quantum Qr = Q0 - h, with h < 4
-// chosen so that 3*Qr + dst is a multiple of 4: every group of 16 values read
-// back then stores its 12 bytes at a 4-byte aligned address (the h quanta
-// before Q0 belong to earlier tiles and are not stored).
-template <int R, bool NT>
+// dst[3q, 3q+3).  Buffer position 16 of the first round stands for quantum
+// Qr = Q0 - h, with h < 4 chosen so that 3*Qr + dst is a multiple of 4: every
+// group of 16 values read back then stores its 12 bytes at a 4-byte aligned
+// address (the h quanta before Q0 belong to earlier tiles and are not
+// stored).  Tiles are dealt to waves grid-stride (the launch sizes the grid
+// to the workgroups that are resident at once, so every wave starts at once);
+// a wave keeps the loads of its next D rounds in flight.
+template <int D, bool NT>
 __global__ __launch_bounds__(kWsBlock) void k_ws_decode(const uint8_t *__restrict__ src, int64_t n,
                                                         uint8_t *__restrict__ dst, DecMap map,
                                                         const int64_t *__restrict__ prefix,
-                                                        uint32_t flags)
+                                                        int64_t TS, uint32_t flags)
 {
-    constexpr int64_t TS = R * kRound;
     __shared__ uint32_t s_map[64];
-    __shared__ __align__(16) uint8_t ring[kRingBytes + 4];
-    __shared__ int wtot[kWsBlock / 64];
-    __shared__ uint32_t s_extra;
+    __shared__ __align__(16) uint8_t stage[kWsBlock / 64][kWaveRound];
+    __shared__ __align__(16) uint8_t vbuf[kWsBlock / 64 * kWsBuf];
     stage_dec_map(s_map, map);
     const uint8_t *m = (const uint8_t *)s_map;
     const int64_t ntiles = ws_tiles(n, TS);
@@ -567,116 +670,95 @@ __global__ __launch_bounds__(kWsBlock) void k_ws_decode(const uint8_t *__restric
     const bool nopad = (flags & kFlagNoPad) != 0;
     const int64_t qlimit = nopad ? total / 4 : (total >= 4 ? total / 4 - 1 : 0);
     const int64_t dmod = (int64_t)((uint64_t)(uintptr_t)dst & 3);
-    const int tid = threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    uint8_t *const st = stage[wv];
+    const int wo = wv * kWsBuf;                   // this wave's value buffer
+    uint8_t *const cb = vbuf + wo;
+    const int64_t nwaves = (int64_t)gridDim.x * (kWsBlock / 64);
 
-    for (int64_t tile = logical_block(); tile < ntiles; tile += gridDim.x) {
+    for (int64_t tile = logical_block() * (kWsBlock / 64) + wv; tile < ntiles; tile += nwaves) {
         const int64_t base = tile * TS, end = base + TS < n ? base + TS : n;
         const int64_t K0 = prefix[tile], C = prefix[tile + 1] - K0;
         const int64_t skip = (4 - (K0 & 3)) & 3;
-        if (C <= skip) continue;                     // block-uniform
+        if (C <= skip) continue;                     // wave-uniform
         const int64_t Q0 = (K0 + skip) >> 2;
         if (Q0 >= qlimit) continue;
         const int64_t h = (Q0 + 3 * dmod) & 3;
-        const int64_t Qr = Q0 - h;
         // what the last quantum may borrow from the next tile, fetched early
         const bool has_next = tile + 1 < ntiles;
         const int64_t next_end = has_next ? prefix[tile + 2] : total;
         const bool head_ok = has_next && base + TS + 16 <= n;
         u32x4 head = u32x4{0u, 0u, 0u, 0u};
-        if (tid == 0 && head_ok) head = load16<false>(src + base + TS);
-        // ring write / read counters, tile-local.  Ring index 16 stands for
-        // quantum Qr, so that no write position is negative.
-        int W = 16 + 4 * (int)h - (int)skip, Rd = 16;
-        // a full tile issues all its loads before the first round
-        const bool full = end - base == TS;
-        u32x4 q[R];
+        if (lane == 0 && head_ok) head = load16<false>(src + base + TS);
+        WsState S{16 + 4 * (int)h - (int)skip, Q0 - h, Q0, qlimit, {0u, 0u, 0u, 0u}, 1};
+        const uint8_t *const s0 = src + base + 16 * lane;
+        // a full tile whose quanta (at most Q0 + C/4) all lie below qlimit
+        const bool hot = end - base == TS && Q0 + C / 4 + 1 <= qlimit;
+        if (hot) {
+            // TS/kWaveRound rounds, a multiple of D; the loads of the next D
+            // rounds in flight (the last ones repeat the last round, unused)
+            // (each load is issued after the round that frees its registers)
+            const int nr = (int)(TS / kWaveRound);
+            u32x4 q[D];
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-            if (full) q[r] = load16<NT>(src + base + r * kRound + 16 * tid);
-            else q[r] = u32x4{0u, 0u, 0u, 0u};
-        }
+            for (int d = 0; d < D; ++d) q[d] = load16<NT>(s0 + d * kWaveRound);
+            for (int r = 0; r < nr; r += D) {
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const int64_t p0 = base + r * kRound;
-            if (p0 >= end) break;                    // block-uniform
-            // the 16 codes of this thread, one per register
-            uint32_t cj[16];
-            if (full) {
-                const uint32_t qw[4] = {q[r].x, q[r].y, q[r].z, q[r].w};
-#pragma unroll
-                for (int j = 0; j < 16; ++j) cj[j] = m[(qw[j >> 2] >> (8 * (j & 3))) & 0xFF];
-            } else {
-                const u32x4 c = ws_codes<NT>(src, end, p0 + 16 * tid, m);
-                const uint32_t cw[4] = {c.x, c.y, c.z, c.w};
-#pragma unroll
-                for (int j = 0; j < 16; ++j) cj[j] = (cw[j >> 2] >> (8 * (j & 3))) & 0xFF;
-            }
-            int cnt = 0;
-#pragma unroll
-            for (int j = 0; j < 16; ++j) cnt += cj[j] != kWsCode;
-            int tot = 0;
-            const int ex = block_excl_scan(cnt, wtot, &tot);
-            int pos = W + ex;
-            // straight-line writes: a whitespace code goes to the trash byte
-#pragma unroll
-            for (int j = 0; j < 16; ++j) {
-                const bool sig = cj[j] != kWsCode;
-                ring[sig ? ring_at(pos) : kRingTrash] = (uint8_t)cj[j];
-                pos += sig;
-            }
-            W += tot;
-            __syncthreads();
-            const int avail = W - Rd;
-            const int nfull = avail > 0 ? avail >> 4 : 0;
-            if (tid < nfull) {
-                const int r = Rd + 16 * tid;
-                // 16 values from a multiple of 16: four dwords, 4-byte aligned
-                const uint32_t *rw = (const uint32_t *)(ring + ring_at(r));
-                const uint4 v = {rw[0], rw[1], rw[2], rw[3]};
-                const int64_t qq = Qr + ((r - 16) >> 2);
-                const uint32_t b0 = ws_quantum(v.x), b1 = ws_quantum(v.y), b2 = ws_quantum(v.z),
-                               b3 = ws_quantum(v.w);
-                if (qq >= Q0 && qq + 4 <= qlimit) {
-                    u32x3 o;
-                    o.x = b0 | (b1 << 24);
-                    o.y = (b1 >> 8) | (b2 << 16);
-                    o.z = (b2 >> 16) | (b3 << 8);
-                    store12<NT>(dst + 3 * qq, o);
-                } else {
-                    const uint32_t b[4] = {b0, b1, b2, b3};
-                    for (int k = 0; k < 4; ++k)
-                        if (qq + k >= Q0 && qq + k < qlimit) store3(dst + 3 * (qq + k), b[k]);
+                for (int d = 0; d < D; ++d) {
+                    ws_round<true, NT>(q[d], base + (int64_t)(r + d) * kWaveRound, end, st, m, vbuf, wo,
+                                       dst, S);
+                    const int rn = r + d + D < nr ? r + d + D : nr - 1;
+                    q[d] = load16<NT>(s0 + (int64_t)rn * kWaveRound);
                 }
             }
-            Rd += 16 * nfull;
-            // the ring holds 16 KiB: this round's reads and the next round's
-            // writes never meet, and block_excl_scan's barrier orders wtot
+            // the first group's quanta that are the tile's own
+            if (S.held_k <= 0) {
+#pragma unroll
+                for (int k = 0; k < 4; ++k)
+                    if (k >= -S.held_k) store3(dst + 3 * (Q0 + S.held_k + k), S.held[k]);
+            }
+        } else {
+            for (int64_t p0 = base; p0 < end; p0 += kWaveRound) {
+                u32x4 raw;
+                if (p0 + kWaveRound <= end) {
+                    raw = load16<NT>(s0 + (p0 - base));
+                } else {
+                    uint32_t w[4] = {0, 0, 0, 0};
+                    for (int j = 0; j < 16; ++j) {
+                        const int64_t i = p0 + 16 * lane + j;
+                        if (i < end) w[j >> 2] |= (uint32_t)src[i] << (8 * (j & 3));
+                    }
+                    raw = u32x4{w[0], w[1], w[2], w[3]};
+                }
+                ws_round<false, NT>(raw, p0, end, st, m, vbuf, wo, dst, S);
+            }
         }
         // fewer than 16 values left: whole quanta, then one quantum that may
         // take up to three values from later tiles
-        const int left = W - Rd;
+        const int left = S.W - 16;
         if (left > 0) {
             const int rem = left & 3;
-            if (tid == 0)
-                s_extra = rem ? borrow_values(src, n, m, prefix, ntiles, TS, total, K0 + C,
-                                              (int)(4 - rem), head_ok, head, next_end)
-                              : 0u;
-            __syncthreads();
+            uint32_t extra = 0;
+            if (lane == 0 && rem)
+                extra = borrow_values(src, n, m, prefix, ntiles, TS, total, K0 + C, (int)(4 - rem),
+                                      head_ok, head, next_end);
+            extra = (uint32_t)__shfl((int)extra, 0, 64);
             const int nq = (left + 3) >> 2;
-            if (tid < nq) {
-                const int r = Rd + 4 * tid;
-                const int64_t qq = Qr + ((r - 16) >> 2);
+            if (lane < nq) {
+                const int64_t qq = S.Qb + lane;
                 uint32_t w = 0;
                 for (int k = 0; k < 4; ++k) {
-                    const int idx = 4 * tid + k;
-                    const uint32_t v = idx < left ? ring[ring_at(r + k)]
-                                                  : (s_extra >> (8 * (idx - left))) & 0xFF;
+                    const int idx = 4 * lane + k;
+                    const uint32_t v = idx < left ? cb[16 + idx] : (extra >> (8 * (idx - left))) & 0xFF;
                     w |= v << (8 * k);
                 }
                 if (qq >= Q0 && qq < qlimit) store3(dst + 3 * qq, ws_quantum(w));
             }
         }
-        __syncthreads();
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
 }
 
@@ -844,17 +926,47 @@ int64_t ws_workspace_bytes(int64_t n)
 namespace {
 
 template <int R>
-void launch_ws_tiles(const uint8_t *src, int64_t n, uint8_t *dst, bool write, const DecMap &map,
-                     int64_t *prefix, int64_t *first_pad, int64_t *first_bad, uint32_t flags,
-                     int64_t grid, bool nt, hipStream_t stream)
+void launch_ws_count(const uint8_t *src, int64_t n, const DecMap &map, int64_t *prefix,
+                     int64_t *first_pad, int64_t *first_bad, int64_t grid, bool nt, hipStream_t stream)
 {
     if (nt) hipLaunchKernelGGL((k_ws_count<R, true>), dim3(grid), dim3(kWsBlock), 0, stream, src, n, map, prefix, first_pad, first_bad);
     else hipLaunchKernelGGL((k_ws_count<R, false>), dim3(grid), dim3(kWsBlock), 0, stream, src, n, map, prefix, first_pad, first_bad);
-    const int64_t ntiles = ws_tiles(n, R * kRound);
-    hipLaunchKernelGGL(k_ws_scan, dim3(1), dim3(kScanThreads), 0, stream, prefix, ntiles);
-    if (!write) return;
-    if (nt) hipLaunchKernelGGL((k_ws_decode<R, true>), dim3(grid), dim3(kWsBlock), 0, stream, src, n, dst, map, prefix, flags);
-    else hipLaunchKernelGGL((k_ws_decode<R, false>), dim3(grid), dim3(kWsBlock), 0, stream, src, n, dst, map, prefix, flags);
+}
+
+// Workgroups of `kernel` resident on one compute unit at once (1 if the
+// query fails), asked once per kernel.
+template <typename K>
+int resident_per_cu(K kernel, int *cache)
+{
+    int v = __atomic_load_n(cache, __ATOMIC_RELAXED);
+    if (v > 0) return v;
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, kWsBlock, 0) != hipSuccess || nb < 1) {
+        (void)hipGetLastError();
+        nb = 1;
+    }
+    __atomic_store_n(cache, nb, __ATOMIC_RELAXED);
+    return nb;
+}
+
+// One wave per tile, tiles dealt grid-stride: the grid is at most the
+// workgroups that fit at once (blocks_per_cu caps it), so that no wave starts
+// after others have finished and the tiles are shared evenly.
+template <int D>
+void launch_ws_decode_tiles(const uint8_t *src, int64_t n, uint8_t *dst, const DecMap &map,
+                            const int64_t *prefix, int64_t TS, int64_t ntiles, uint32_t flags,
+                            int bpc, int cus, bool nt, hipStream_t stream)
+{
+    static int fit[2] = {0, 0};
+    const int per_cu = nt ? resident_per_cu(k_ws_decode<D, true>, &fit[1])
+                          : resident_per_cu(k_ws_decode<D, false>, &fit[0]);
+    int64_t grid = (int64_t)cus * (bpc < per_cu ? bpc : per_cu);
+    const int64_t need = (ntiles + kWsBlock / 64 - 1) / (kWsBlock / 64);
+    if (grid > need) grid = need;
+    if (grid >= kXcds) grid -= grid % kXcds;
+    if (grid < 1) grid = 1;
+    if (nt) hipLaunchKernelGGL((k_ws_decode<D, true>), dim3(grid), dim3(kWsBlock), 0, stream, src, n, dst, map, prefix, TS, flags);
+    else hipLaunchKernelGGL((k_ws_decode<D, false>), dim3(grid), dim3(kWsBlock), 0, stream, src, n, dst, map, prefix, TS, flags);
 }
 
 }  // namespace
@@ -874,13 +986,19 @@ hipError_t launch_decode_ws(const uint8_t *src, int64_t n, uint8_t *dst, bool wr
     if (grid < 1) grid = 1;
     if (ntiles > 0) {
         switch (TS / kRound) {
-        case 1: launch_ws_tiles<1>(src, n, dst, write, map, prefix, first_pad, first_bad, flags, grid, sh.nt, stream); break;
-        case 2: launch_ws_tiles<2>(src, n, dst, write, map, prefix, first_pad, first_bad, flags, grid, sh.nt, stream); break;
-        case 4: launch_ws_tiles<4>(src, n, dst, write, map, prefix, first_pad, first_bad, flags, grid, sh.nt, stream); break;
-        default: launch_ws_tiles<8>(src, n, dst, write, map, prefix, first_pad, first_bad, flags, grid, sh.nt, stream); break;
+        case 1: launch_ws_count<1>(src, n, map, prefix, first_pad, first_bad, grid, sh.nt, stream); break;
+        case 2: launch_ws_count<2>(src, n, map, prefix, first_pad, first_bad, grid, sh.nt, stream); break;
+        case 4: launch_ws_count<4>(src, n, map, prefix, first_pad, first_bad, grid, sh.nt, stream); break;
+        default: launch_ws_count<8>(src, n, map, prefix, first_pad, first_bad, grid, sh.nt, stream); break;
         }
-    } else {
-        hipLaunchKernelGGL(k_ws_scan, dim3(1), dim3(kScanThreads), 0, stream, prefix, ntiles);
+    }
+    hipLaunchKernelGGL(k_ws_scan, dim3(1), dim3(kScanThreads), 0, stream, prefix, ntiles);
+    if (write && ntiles > 0) {
+        switch (sh.unroll) {
+        case 1: launch_ws_decode_tiles<1>(src, n, dst, map, prefix, TS, ntiles, flags, sh.bpc, cus, sh.nt, stream); break;
+        case 4: launch_ws_decode_tiles<4>(src, n, dst, map, prefix, TS, ntiles, flags, sh.bpc, cus, sh.nt, stream); break;
+        default: launch_ws_decode_tiles<2>(src, n, dst, map, prefix, TS, ntiles, flags, sh.bpc, cus, sh.nt, stream); break;
+        }
     }
     hipLaunchKernelGGL(k_ws_finish, dim3(1), dim3(kWsBlock), 0, stream, src, n, dst, map, TS, prefix,
                        first_pad, out_len, first_bad, flags, write ? 1 : 0);

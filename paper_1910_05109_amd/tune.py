@@ -96,9 +96,9 @@ def _workload(torch, op, nbytes, seed=191005109):
                                 first_bad=dbad)
 
 
-# the whitespace-skipping kernels take no unroll, and their 20 KiB of LDS per
-# workgroup allow at most 7 workgroups per compute unit
-GRIDS = {"decode_ws": {"unrolls": (1,), "bpcs": (1, 2, 3, 4, 5, 6, 7)}}
+# the whitespace-skipping decode keeps 1, 2 or 4 rounds of loads in flight per
+# wave; 64 VGPRs and 8.5 KiB of LDS per workgroup fit 8 workgroups per CU
+GRIDS = {"decode_ws": {"unrolls": (1, 2, 4), "bpcs": (2, 4, 6, 8, 12, 16)}}
 
 
 def tune_op(op: str, nbytes: int, reps: int = 10, unrolls=UNROLLS, bpcs=BLOCKS_PER_CU,

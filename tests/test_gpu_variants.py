@@ -293,3 +293,32 @@ def test_skip_ws_large(b64, oracle):
     say("wrap encode large")
     enc = to_host(b64.encode(_dev(x), STD, line_len=workloads.MIME_LINE))
     assert first_mismatch(enc, text) is None
+
+
+@pytest.mark.parametrize("shape", [(1, 1, 0), (2, 3, 1), (4, 8, 1), (8, 16, 0)])
+def test_skip_ws_launch_shapes_and_misaligned_output(b64, oracle, shape):
+    """Every launch shape of the whitespace-skipping decode (rounds in flight
+    per wave 1, 2, 4 and 8 -> 2; workgroups per CU; nontemporal on and off)
+    gives the oracle's bytes, also into an output at each offset mod 4."""
+    import torch
+    x = workloads.random_bytes(workloads.SEED_BASE + 189, 6 << 20)
+    texts = [workloads.sprinkle_ws(_mime(oracle, x[:300001]), workloads.SEED_BASE + 190, 3000, 5, 1,
+                                   1 << 15),
+             _mime(oracle, x[:(6 << 20) - 1])]
+    old = b64.tune_get("decode_ws")
+    try:
+        b64.tune_set("decode_ws", *shape)
+        for k, text in enumerate(texts):
+            ref, _ = oracle.decode_mode(text, STD, SKIP_WS)
+            s = _dev(text)
+            for off in range(4):
+                say("ws shape", shape, "text", k, "n", text.size, "offset", off)
+                cap = b64.decoded_max_len(text.size, SKIP_WS)
+                buf = torch.zeros(cap + 8, dtype=torch.uint8, device="cuda")
+                out, st = b64.decode_async(s, STD, out=buf[off:], flags=SKIP_WS)
+                assert to_host(st).tolist() == [ref.size, -1], (shape, k, off)
+                got = to_host(buf)
+                assert first_mismatch(got[off:off + ref.size], ref) is None, (shape, k, off)
+                assert not got[:off].any() and not got[off + ref.size:].any(), (shape, k, off)
+    finally:
+        b64.tune_set("decode_ws", *old)

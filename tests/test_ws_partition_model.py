@@ -3,12 +3,15 @@
 The kernels cut the input into tiles of TS characters.  Tile t holds the
 significant characters with indices prefix[t] .. prefix[t+1]-1 and decodes
 the quanta whose first significant value lies in it: it skips
-(4 - prefix[t] % 4) % 4 values that finish an earlier quantum, reads rounds
-of 4096 characters through a ring whose index 0 stands for quantum
-Q0 - h (h < 4 chosen so that every 16-value group stores at a 4-byte aligned
-output address), emits every 16 values as 4 quanta, and completes its last
-quantum with up to three values borrowed from later tiles.  Quanta before Q0
-and at index >= qlimit are not stored by the tile.
+(4 - prefix[t] % 4) % 4 values that finish an earlier quantum and reads
+rounds of 4096 characters into two value buffers used in turn.  Position 16
+of the first buffer stands for quantum Q0 - h (h < 4 chosen so that every
+16-value group stores at a 4-byte aligned output address); every 16 values
+from position 16 on are emitted as 4 quanta, and the values after the last
+whole group are copied to position 16 of the other buffer, where the next
+round continues.  The last quantum is completed with up to three values
+borrowed from later tiles.  Quanta before Q0 and at index >= qlimit are not
+stored by the tile.
 
 This model repeats that index arithmetic in Python, on random inputs with
 whitespace runs of every length (empty tiles, runs longer than a tile), and
@@ -22,6 +25,7 @@ import workloads
 
 WS = set(b" \t\r\n")
 ROUND = 4096
+BUF = 16 + ROUND + 48                # bytes of one value buffer
 
 
 def tile_size(n):
@@ -54,29 +58,38 @@ def model(text: bytes, nopad: bool, ts: int, dmod: int = 0):
         Qr = Q0 - h
         assert (3 * Qr + dmod) % 4 == 0
         base, end = t * ts, min(n, (t + 1) * ts)
-        W, Rd = 16 + 4 * h - skip, 16             # ring index 16 stands for quantum Qr
-        ring = {}
+        W, Qb = 16 + 4 * h - skip, Qr            # position 16 stands for quantum Qb
+        bufs, cur = [{}, {}], 0                    # stale entries stay, as in LDS
         g = K0                                     # significant index of the next value
         for p0 in range(base, end, ROUND):
+            cb, nb = bufs[cur], bufs[cur ^ 1]
             chunk = [c for c in text[p0:min(end, p0 + ROUND)] if c not in WS]
             for v in chunk:
-                assert W >= 0
-                ring[W] = g
+                assert 0 <= W < BUF
+                cb[W] = g
                 W += 1
                 g += 1
-            nfull = max(0, (W - Rd) // 16)
+            avail = W - 16
+            nfull = max(0, avail >> 4)
             for tid in range(nfull):
-                r = Rd + 16 * tid
-                q = Qr + (r - 16) // 4
+                r = 16 + 16 * tid
+                q = Qb + 4 * tid
                 assert (3 * q + dmod) % 4 == 0        # aligned 12-byte store
                 for k in range(4):
                     if Q0 <= q + k < qlimit:
-                        idx = [ring[r + 4 * k + j] for j in range(4)]
+                        idx = [cb.get(r + 4 * k + j) for j in range(4)]
                         assert (q + k) not in writes
                         writes[q + k] = (t, idx)
-            Rd += 16 * nfull
-        left = W - Rd
+            keep = avail - 16 * nfull
+            assert keep < 16 and (keep >= 0 or nfull == 0)
+            for tid in range(max(keep, 0)):
+                nb[16 + tid] = cb.get(16 + 16 * nfull + tid)   # junk below W0 too
+            W = 16 + keep if keep >= 0 else W
+            Qb += 4 * nfull
+            cur ^= 1
+        left = W - 16
         if left > 0:
+            cb = bufs[cur]
             rem = left & 3
             extra = []
             gg = K0 + C
@@ -85,12 +98,11 @@ def model(text: bytes, nopad: bool, ts: int, dmod: int = 0):
                 gg += 1
             nq = (left + 3) // 4
             for tid in range(nq):
-                r = Rd + 4 * tid
-                q = Qr + (r - 16) // 4
+                q = Qb + tid
                 idx = []
                 for k in range(4):
                     i = 4 * tid + k
-                    idx.append(ring.get(r + k) if i < left else (extra[i - left] if i - left < len(extra) else None))
+                    idx.append(cb.get(16 + i) if i < left else (extra[i - left] if i - left < len(extra) else None))
                 if Q0 <= q < qlimit:
                     assert None not in idx
                     assert q not in writes
