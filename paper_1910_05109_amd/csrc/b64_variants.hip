@@ -441,13 +441,16 @@ __device__ int64_t prev_sig(const uint8_t *src, int64_t n, int64_t pos, const ui
     return -1;
 }
 
-// Three bytes of the quantum of values w = v0 | v1<<8 | v2<<16 | v3<<24, as
-// b0 | b1<<8 | b2<<16 (the closed form of Section "Base64").
+// Three bytes of the quantum of values w = v0 | v1<<8 | v2<<16 | v3<<24
+// (each below 64), as b0 | b1<<8 | b2<<16: the closed form of Section
+// "Base64" as v0<<18 | v1<<12 | v2<<6 | v3, its two 12-bit halves v0*64 + v1
+// and v2*64 + v3 being byte dot products.  (Values of 64 and more, which
+// only invalid input yields, give unspecified bytes.)
 __device__ __forceinline__ uint32_t ws_quantum(uint32_t w)
 {
-    const uint32_t v = ((w & 0x3F) << 18) | (((w >> 8) & 0x3F) << 12) | (((w >> 16) & 0x3F) << 6) |
-                       ((w >> 24) & 0x3F);
-    return __builtin_amdgcn_perm(0u, v, 0x0C000102u);   // v.b2 v.b1 v.b0 0
+    const uint32_t a = __builtin_amdgcn_udot4(w, 0x00000140u, 0u, false);   // v0*64 + v1
+    const uint32_t b = __builtin_amdgcn_udot4(w, 0x01400000u, 0u, false);   // v2*64 + v3
+    return __builtin_amdgcn_perm(0u, (a << 12) | b, 0x0C000102u);           // v.b2 v.b1 v.b0 0
 }
 
 __device__ __forceinline__ void store3(uint8_t *o, uint32_t b)
@@ -600,9 +603,11 @@ __device__ __forceinline__ void ws_round(u32x4 raw, int64_t p0, int64_t end, uin
         w.x = b0 | (b1 << 24);
         w.y = (b1 >> 8) | (b2 << 16);
         w.z = (b2 >> 16) | (b3 << 8);
-        // a single masked store, the address and data computed outside it
+        // a single masked store, the address and data computed outside it;
+        // an ordinary store, so that the two halves of a line shared with the
+        // next round meet in L2 before it is written back
         uint8_t *const to = o + 3 * k0;
-        if (lane < nfull && k0 >= lo) store12<NT>(to, w);
+        if (lane < nfull && k0 >= lo) store12<false>(to, w);
         if (lane < nfull && k0 < lo) {                  // lane 0 of the first round only
             S.held[0] = b0;
             S.held[1] = b1;
@@ -698,20 +703,24 @@ __global__ __launch_bounds__(kWsBlock) void k_ws_decode(const uint8_t *__restric
         if (hot) {
             // TS/kWaveRound rounds, a multiple of D; the loads of the next D
             // rounds in flight (the last ones repeat the last round, unused)
-            // (each load is issued after the round that frees its registers)
+            // (each load is issued after the round that frees its registers;
+            // the last D rounds load nothing)
             const int nr = (int)(TS / kWaveRound);
             u32x4 q[D];
 #pragma unroll
             for (int d = 0; d < D; ++d) q[d] = load16<NT>(s0 + d * kWaveRound);
-            for (int r = 0; r < nr; r += D) {
+            int r = 0;
+            for (; r < nr - D; r += D) {
 #pragma unroll
                 for (int d = 0; d < D; ++d) {
                     ws_round<true, NT>(q[d], base + (int64_t)(r + d) * kWaveRound, end, st, m, vbuf, wo,
                                        dst, S);
-                    const int rn = r + d + D < nr ? r + d + D : nr - 1;
-                    q[d] = load16<NT>(s0 + (int64_t)rn * kWaveRound);
+                    q[d] = load16<NT>(s0 + (int64_t)(r + d + D) * kWaveRound);
                 }
             }
+#pragma unroll
+            for (int d = 0; d < D; ++d)
+                ws_round<true, NT>(q[d], base + (int64_t)(r + d) * kWaveRound, end, st, m, vbuf, wo, dst, S);
             // the first group's quanta that are the tile's own
             if (S.held_k <= 0) {
 #pragma unroll
