@@ -63,38 +63,6 @@ __device__ __forceinline__ void store_wrapped(uint8_t *dst, int64_t j0, int64_t 
     }
 }
 
-// Characters [j0, j0+16) of the unwrapped encoding (o, four per dword) for
-// lines of L >= 16, so that at most one line starts inside them; (line, col)
-// are those of character j0.  The 16 characters, with a CR LF spliced in
-// where a line starts (before character a, a in {0, 4, 8, 12}), are stored as
-// one 16-byte store plus, after a break, the last two bytes.
-template <bool NT>
-__device__ __forceinline__ void store_chunk_wrapped(uint8_t *dst, int64_t j0, int64_t line,
-                                                    int64_t col, int64_t L, u32x4 o)
-{
-    constexpr uint32_t kCrLf = '\r' | ('\n' << 8);
-    const int64_t pos = j0 + 2 * line;               // position of character j0
-    const int64_t a = col == 0 ? 0 : L - col;        // characters before the next line start
-    const bool brk = col == 0 ? j0 > 0 : a < 16;
-    const int k = brk ? (int)(a >> 2) : 4;           // dword of the break; 4: none
-    const uint32_t w[5] = {o.x, o.y, o.z, o.w, 0u};
-    uint32_t x[5];
-#pragma unroll
-    for (int d = 0; d < 5; ++d) {
-        // the dword shifted by the two inserted bytes: bytes 2,3 of w[d-1], bytes 0,1 of w[d]
-        const uint32_t shifted = d == 0 ? (w[0] << 16) : __builtin_amdgcn_alignbyte(w[d], w[d - 1], 2);
-        x[d] = d < k ? w[d] : (d == k ? (kCrLf | (w[d] << 16)) : shifted);
-    }
-    uint8_t *q = dst + (brk && a == 0 ? pos - 2 : pos);
-    u32x4 v;
-    v.x = x[0];
-    v.y = x[1];
-    v.z = x[2];
-    v.w = x[3];
-    store16<NT>(q, v);
-    if (brk) *(u16a1 *)(q + 16) = (uint16_t)x[4];
-}
-
 // Scalar tail: input bytes p[0..r) whose first character has index j0; the
 // last group is padded or, with !pad, cut to the characters that carry bits.
 __device__ void enc_scalar_wrap(const uint8_t *p, int64_t r, int64_t j0, uint8_t *dst, int64_t L,
@@ -126,18 +94,48 @@ __device__ void enc_scalar_wrap(const uint8_t *p, int64_t r, int64_t j0, uint8_t
 // Stores the chunks of one lane, in increasing order c, c+T, c+2T, ...:
 // tracks the line and column of the next chunk's first character and steps
 // them by T chunks (16T characters) per call.
+// Lines of L in [16, 2^31) (at most one line starts inside a chunk): a lane
+// tracks the output position of its chunk's first character (64 bits) and
+// its column (32 bits), stepped by T chunks per call: pos += 16T + 2*(lines
+// crossed).
+struct WideSink {
+    uint8_t *dst;
+    int64_t pos, dpos;              // dpos = 16T + 2*((16T) / L)
+    int32_t col, dcol, L;           // dcol = (16T) % L
+    template <bool NT>
+    __device__ __forceinline__ void put(int64_t c, u32x4 o)
+    {
+        constexpr uint32_t kCrLf = '\r' | ('\n' << 8);
+        const int32_t a = col == 0 ? 0 : L - col;      // characters before the next line start
+        const bool brk = col == 0 ? c > 0 : a < 16;
+        const int k = brk ? a >> 2 : 4;                // dword of the break; 4: none
+        const uint32_t w[5] = {o.x, o.y, o.z, o.w, 0u};
+        uint32_t x[5];
+#pragma unroll
+        for (int d = 0; d < 5; ++d) {
+            // the dword shifted by the two inserted bytes: bytes 2,3 of w[d-1], bytes 0,1 of w[d]
+            const uint32_t shifted = d == 0 ? (w[0] << 16) : __builtin_amdgcn_alignbyte(w[d], w[d - 1], 2);
+            x[d] = d < k ? w[d] : (d == k ? (kCrLf | (w[d] << 16)) : shifted);
+        }
+        uint8_t *q = dst + pos - (brk && a == 0 ? 2 : 0);
+        store16<NT>(q, u32x4{x[0], x[1], x[2], x[3]});
+        if (brk) *(u16a1 *)(q + 16) = (uint16_t)x[4];
+        col += dcol;
+        const bool wrap = col >= L;
+        col -= wrap ? L : 0;
+        pos += dpos + (wrap ? 2 : 0);
+    }
+};
+
+// Shorter lines (or longer than 2^31): lane by lane per group of four.
 struct WrapSink {
     uint8_t *dst;
     int64_t L, line, col, dline, dcol;
     template <bool NT>
     __device__ __forceinline__ void put(int64_t c, u32x4 o)
     {
-        if (L >= 16) {
-            store_chunk_wrapped<NT>(dst, 16 * c, line, col, L, o);
-        } else {
-            const uint32_t w[4] = {o.x, o.y, o.z, o.w};
-            store_wrapped(dst, 16 * c, line, col, L, w, 4);
-        }
+        const uint32_t w[4] = {o.x, o.y, o.z, o.w};
+        store_wrapped(dst, 16 * c, line, col, L, w, 4);
         line += dline;
         col += dcol;
         if (col >= L) {
@@ -149,10 +147,10 @@ struct WrapSink {
 
 // enc_stream's software-pipelined rounds (the loads of round r+1 issued
 // before round r is stored) with the stores done by a WrapSink.
-template <int U, bool NT>
+template <int U, bool NT, typename Sink>
 __device__ __forceinline__ void enc_stream_wrap(const uint8_t *s0, int64_t c0, int64_t stride,
                                                 int64_t rstep, int64_t nrounds, const uint8_t *tab,
-                                                WrapSink &sink)
+                                                Sink &sink)
 {
     if (nrounds <= 0) return;
     u32x3 A[U], B[U];
@@ -161,21 +159,21 @@ __device__ __forceinline__ void enc_stream_wrap(const uint8_t *s0, int64_t c0, i
     for (; r + 2 < nrounds; r += 2) {
         enc_load<U, NT>(B, s0, c0 + rstep, stride);
 #pragma unroll
-        for (int j = 0; j < U; ++j) sink.put<NT>(c0 + j * stride, enc_chunk(A[j], tab));
+        for (int j = 0; j < U; ++j) sink.template put<NT>(c0 + j * stride, enc_chunk(A[j], tab));
         enc_load<U, NT>(A, s0, c0 + 2 * rstep, stride);
 #pragma unroll
-        for (int j = 0; j < U; ++j) sink.put<NT>(c0 + rstep + j * stride, enc_chunk(B[j], tab));
+        for (int j = 0; j < U; ++j) sink.template put<NT>(c0 + rstep + j * stride, enc_chunk(B[j], tab));
         c0 += 2 * rstep;
     }
     if (r + 1 < nrounds) {
         enc_load<U, NT>(B, s0, c0 + rstep, stride);
 #pragma unroll
-        for (int j = 0; j < U; ++j) sink.put<NT>(c0 + j * stride, enc_chunk(A[j], tab));
+        for (int j = 0; j < U; ++j) sink.template put<NT>(c0 + j * stride, enc_chunk(A[j], tab));
 #pragma unroll
-        for (int j = 0; j < U; ++j) sink.put<NT>(c0 + rstep + j * stride, enc_chunk(B[j], tab));
+        for (int j = 0; j < U; ++j) sink.template put<NT>(c0 + rstep + j * stride, enc_chunk(B[j], tab));
     } else {
 #pragma unroll
-        for (int j = 0; j < U; ++j) sink.put<NT>(c0 + j * stride, enc_chunk(A[j], tab));
+        for (int j = 0; j < U; ++j) sink.template put<NT>(c0 + j * stride, enc_chunk(A[j], tab));
     }
 }
 
@@ -195,21 +193,34 @@ __global__ __launch_bounds__(kThreads) void k_encode_wrap(const uint8_t *__restr
     const int64_t nch = n / 12;
     const int64_t T = (int64_t)gridDim.x * kThreads;
     const int64_t t = logical_block() * kThreads + threadIdx.x;
-    // line / column of this thread's first character and their steps per T chunks
-    WrapSink sink{dst, L, (16 * t) / L, (16 * t) % L, (16 * T) / L, (16 * T) % L};
     const int64_t nfull = nch / (U * T);
-    enc_stream_wrap<U, NT>(src, t, T, U * T, nfull, a, sink);
     const int64_t c0 = t + nfull * U * T;
-    if (c0 < nch) {
-        u32x3 in[U];
+    // complete rounds, then the partial round with clamped loads
+    auto run = [&](auto &sink) {
+        enc_stream_wrap<U, NT>(src, t, T, U * T, nfull, a, sink);
+        if (c0 < nch) {
+            u32x3 in[U];
 #pragma unroll
-        for (int j = 0; j < U; ++j) {
-            const int64_t c = c0 + j * T;
-            in[j] = load12<NT>(src + 12 * (c < nch ? c : nch - 1));
+            for (int j = 0; j < U; ++j) {
+                const int64_t c = c0 + j * T;
+                in[j] = load12<NT>(src + 12 * (c < nch ? c : nch - 1));
+            }
+            for (int j = 0; j < U; ++j) {
+                if (c0 + j * T >= nch) break;
+                sink.template put<NT>(c0 + j * T, enc_chunk(in[j], a));
+            }
         }
-#pragma unroll
-        for (int j = 0; j < U; ++j)
-            if (c0 + j * T < nch) sink.put<NT>(c0 + j * T, enc_chunk(in[j], a));
+    };
+    // the output position (or line) and column of this thread's first
+    // character, and their steps per T chunks
+    if (L >= 16 && L < ((int64_t)1 << 31)) {
+        const int64_t line0 = (16 * t) / L, dline = (16 * T) / L;
+        WideSink sink{dst, 16 * t + 2 * line0, 16 * T + 2 * dline, (int32_t)((16 * t) % L),
+                      (int32_t)((16 * T) % L), (int32_t)L};
+        run(sink);
+    } else {
+        WrapSink sink{dst, L, (16 * t) / L, (16 * t) % L, (16 * T) / L, (16 * T) % L};
+        run(sink);
     }
     if (t == kThreads - 1)
         enc_scalar_wrap(src + 12 * nch, n - 12 * nch, 16 * nch, dst, L, a, !(flags & kFlagNoPad));
