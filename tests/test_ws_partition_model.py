@@ -46,6 +46,9 @@ def model(text: bytes, nopad: bool, ts: int, dmod: int = 0):
     assert total == len(sig)
     qlimit = total // 4 if nopad else (total // 4 - 1 if total >= 4 else 0)
     writes = {}                                   # quantum -> (tile, value indices)
+
+    def end_of(t):
+        return min(n, (t + 1) * ts)
     for t in range(ntiles):
         K0, C = prefix[t], prefix[t + 1] - prefix[t]
         skip = (4 - K0 % 4) % 4
@@ -58,6 +61,10 @@ def model(text: bytes, nopad: bool, ts: int, dmod: int = 0):
         Qr = Q0 - h
         assert (3 * Qr + dmod) % 4 == 0
         base, end = t * ts, min(n, (t + 1) * ts)
+        # a full tile whose quanta all lie below qlimit: the kernel's hot path
+        # stores every whole group without checking qlimit, and holds back
+        # only the first group's quanta before Q0
+        hot = end_of(t) - t * ts == ts and Q0 + C // 4 + 1 <= qlimit
         W, Qb = 16 + 4 * h - skip, Qr            # position 16 stands for quantum Qb
         bufs, cur = [{}, {}], 0                    # stale entries stay, as in LDS
         g = K0                                     # significant index of the next value
@@ -75,6 +82,9 @@ def model(text: bytes, nopad: bool, ts: int, dmod: int = 0):
                 r = 16 + 16 * tid
                 q = Qb + 4 * tid
                 assert (3 * q + dmod) % 4 == 0        # aligned 12-byte store
+                if hot:
+                    assert q + 4 <= qlimit
+                    assert q >= Q0 or (q == Q0 - h and q + 4 > Q0)
                 for k in range(4):
                     if Q0 <= q + k < qlimit:
                         idx = [cb.get(r + 4 * k + j) for j in range(4)]
@@ -155,3 +165,22 @@ def test_tile_size_rule():
     assert tile_size(10 ** 6) == 4096
     assert tile_size(64 << 20) == 16384
     assert tile_size(1431655764) == 32768
+
+
+def test_last_tile_full():
+    # inputs that end exactly on a tile boundary, so the tile holding the
+    # final quanta is full: the hot-path condition must turn it away
+    rng = np.random.default_rng(workloads.SEED_BASE + 92)
+    for ts in (ROUND, 2 * ROUND):
+        for k in (1, 2, 3):
+            for trial in range(6):
+                n = k * ts
+                n_ws = int(rng.integers(0, 64))
+                body = bytearray(b"A" * (n - n_ws))
+                for _ in range(n_ws):
+                    pos = int(rng.integers(0, len(body) + 1))
+                    body[pos:pos] = b"\n"
+                text = bytes(body[:n])
+                assert len(text) == n
+                for nopad in (False, True):
+                    model(text, nopad, ts, trial % 4)
