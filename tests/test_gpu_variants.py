@@ -322,3 +322,28 @@ def test_skip_ws_launch_shapes_and_misaligned_output(b64, oracle, shape):
                 assert not got[:off].any() and not got[off + ref.size:].any(), (shape, k, off)
     finally:
         b64.tune_set("decode_ws", *old)
+
+
+def test_skip_ws_input_ends_on_a_tile_boundary(b64, oracle):
+    """Inputs whose length is a whole number of decode tiles (4 KiB at these
+    sizes): the tile holding the final quanta is full, and the decoder must
+    still leave them to its edge path.  Whitespace pads the text to length."""
+    import torch
+    x = workloads.random_bytes(workloads.SEED_BASE + 191, 20000)
+    for k in (1, 2, 3, 5):
+        n = 4096 * k
+        for flags in (SKIP_WS, SKIP_WS | NOPAD):
+            for cut in (0, 1, 2, 40):
+                text = _mime(oracle, x[: (3 * n * 76) // (4 * 78) - 8 - cut], STD, flags & NOPAD)
+                assert text.size <= n
+                text = np.concatenate([text, np.full(n - text.size, ord("\n"), dtype=np.uint8)])
+                ref, _ = oracle.decode_mode(text, STD, flags)
+                s = _dev(text)
+                for off in range(4):
+                    say("ws tile end", n, "flags", flags, "cut", cut, "offset", off)
+                    cap = b64.decoded_max_len(text.size, flags)
+                    buf = torch.zeros(cap + 8, dtype=torch.uint8, device="cuda")
+                    _, st = b64.decode_async(s, STD, out=buf[off:], flags=flags)
+                    assert to_host(st).tolist() == [ref.size, -1], (n, flags, cut, off)
+                    got = to_host(buf)
+                    assert first_mismatch(got[off:off + ref.size], ref) is None, (n, flags, cut, off)
