@@ -363,46 +363,84 @@ __global__ __launch_bounds__(kWsBlock) void k_ws_count(const uint8_t *__restrict
 }
 
 // k_ws_scan: prefix[0] = 0 and prefix[1..ntiles] turned into inclusive sums,
-// by one block in passes of kScanThreads*kScanPer values.
-constexpr int kScanThreads = 1024, kScanPer = 8;
+// by one block, kScanRows rows of kScanThreads counts per pass.  Thread t
+// holds entry t of every row, so every load and store of the block is
+// contiguous.  A row is scanned in 32 bits (a tile count is at most 32 KiB,
+// so a row sums to less than 2^31): an inclusive scan within each wave, the
+// exclusive sums of the waves' totals, then a 64-bit exclusive scan of the row
+// totals carried across passes.
+constexpr int kScanThreads = 1024, kScanRows = 48;
+
+// Inclusive sum over the 64 lanes of a wave with DPP: shifts by 1, 2, 4, 8
+// within rows of 16 lanes, then the last lane of rows 0 and 2 added to rows 1
+// and 3, and the last lane of row 1 to rows 2 and 3.
+__device__ __forceinline__ int wave_incl_scan(int x)
+{
+    x += __builtin_amdgcn_update_dpp(0, x, 0x111, 0xF, 0xF, false);   // row_shr:1
+    x += __builtin_amdgcn_update_dpp(0, x, 0x112, 0xF, 0xF, false);   // row_shr:2
+    x += __builtin_amdgcn_update_dpp(0, x, 0x114, 0xF, 0xF, false);   // row_shr:4
+    x += __builtin_amdgcn_update_dpp(0, x, 0x118, 0xF, 0xF, false);   // row_shr:8
+    x += __builtin_amdgcn_update_dpp(0, x, 0x142, 0xA, 0xF, false);   // row_bcast:15
+    x += __builtin_amdgcn_update_dpp(0, x, 0x143, 0xC, 0xF, false);   // row_bcast:31
+    return x;
+}
 
 __global__ __launch_bounds__(kScanThreads) void k_ws_scan(int64_t *__restrict__ prefix, int64_t ntiles)
 {
-    __shared__ int64_t wsum[kScanThreads / 64];
+    constexpr int kW = kScanThreads / 64;
+    __shared__ int s_wave[kScanRows][kW];        // wave totals, then their exclusive sums
+    __shared__ int64_t s_row[kScanRows];          // rows' exclusive offsets
+    __shared__ int64_t s_carry;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    int64_t carry = 0;
-    if (threadIdx.x == 0) prefix[0] = 0;
-    for (int64_t base = 1; base <= ntiles; base += (int64_t)kScanThreads * kScanPer) {
-        int64_t v[kScanPer];
-        const int64_t i0 = base + (int64_t)threadIdx.x * kScanPer;
-        int64_t run = 0;
+    if (threadIdx.x == 0) {
+        prefix[0] = 0;
+        s_carry = 0;
+    }
+    for (int64_t base = 1; base <= ntiles; base += (int64_t)kScanRows * kScanThreads) {
+        int x[kScanRows];
 #pragma unroll
-        for (int k = 0; k < kScanPer; ++k) {
-            v[k] = i0 + k <= ntiles ? prefix[i0 + k] : 0;
-            run += v[k];
+        for (int i = 0; i < kScanRows; ++i) {
+            const int64_t idx = base + (int64_t)i * kScanThreads + threadIdx.x;
+            x[i] = idx <= ntiles ? (int)prefix[idx] : 0;
         }
-        // exclusive scan of the per-thread sums over the block
-        int64_t x = run;
 #pragma unroll
-        for (int d = 1; d < 64; d <<= 1) {
-            const int64_t y = __shfl_up(x, d, 64);
-            if (lane >= d) x += y;
+        for (int i = 0; i < kScanRows; ++i) {
+            x[i] = wave_incl_scan(x[i]);
+            if (lane == 63) s_wave[i][wv] = x[i];
         }
-        if (lane == 63) wsum[wv] = x;
         __syncthreads();
-        int64_t before = 0, all = 0;
+        if (wv == 0) {
+            // lane i < kScanRows: row i's wave prefixes and total
+            int64_t total = 0;
+            if (lane < kScanRows) {
+                int acc = 0;
 #pragma unroll
-        for (int k = 0; k < kScanThreads / 64; ++k) {
-            before += k < wv ? wsum[k] : 0;
-            all += wsum[k];
-        }
-        int64_t acc = carry + before + x - run;
+                for (int k = 0; k < kW; ++k) {
+                    const int t = s_wave[lane][k];
+                    s_wave[lane][k] = acc;
+                    acc += t;
+                }
+                total = acc;
+            }
+            // exclusive scan of the row totals over the lanes, after the carry
+            int64_t y = total;
 #pragma unroll
-        for (int k = 0; k < kScanPer; ++k) {
-            acc += v[k];
-            if (i0 + k <= ntiles) prefix[i0 + k] = acc;
+            for (int d = 1; d < 64; d <<= 1) {
+                const int64_t z = __shfl_up(y, d, 64);
+                if (lane >= d) y += z;
+            }
+            const int64_t carry = s_carry;
+            if (lane < kScanRows) s_row[lane] = carry + y - total;
+            const int64_t all = __shfl(y, 63, 64);
+            __builtin_amdgcn_wave_barrier();
+            if (lane == 0) s_carry = carry + all;
         }
-        carry += all;
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < kScanRows; ++i) {
+            const int64_t idx = base + (int64_t)i * kScanThreads + threadIdx.x;
+            if (idx <= ntiles) prefix[idx] = s_row[i] + s_wave[i][wv] + x[i];
+        }
         __syncthreads();
     }
 }

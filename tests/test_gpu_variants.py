@@ -347,3 +347,21 @@ def test_skip_ws_input_ends_on_a_tile_boundary(b64, oracle):
                     assert to_host(st).tolist() == [ref.size, -1], (n, flags, cut, off)
                     got = to_host(buf)
                     assert first_mismatch(got[off:off + ref.size], ref) is None, (n, flags, cut, off)
+
+
+def test_skip_ws_round_trip_many_tiles(b64, oracle):
+    """A 1.3 GB payload as MIME text (about 1.78 GB, more than 49,152 tiles of
+    32 KiB, so the tile scan takes two passes): the whitespace-skipping decode
+    of the wrapped encoding gives the payload back (a property that holds at
+    any size; both kernels are checked against the oracle at smaller sizes)."""
+    import torch
+    n = 1_300_000_000
+    x = torch.from_numpy(workloads.random_bytes(workloads.SEED_BASE + 192, n)).cuda()
+    say("ws round trip", n)
+    text = b64.encode(x, STD, line_len=workloads.MIME_LINE)
+    assert text.numel() > 49152 * 32768
+    out, st = b64.decode_async(text, STD, flags=SKIP_WS)
+    assert to_host(st).tolist() == [n, -1]
+    assert torch.equal(out[:n], x)
+    del x, text, out
+    torch.cuda.empty_cache()
