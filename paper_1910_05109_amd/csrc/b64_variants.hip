@@ -458,15 +458,61 @@ __device__ int64_t tile_of(const int64_t *prefix, int64_t ntiles, int64_t g)
     return lo;
 }
 
-// Position of the first significant character at or after pos, or n.
+__device__ __forceinline__ int64_t readlane_i64(int64_t v, int l)
+{
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, l);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)((uint64_t)v >> 32), l);
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+// The scans below are wave-cooperative: every lane of the wave calls them
+// with the same arguments and gets the same result.  A step tests 1,024
+// characters, 16 per lane, so a long whitespace run costs one load latency
+// per KiB instead of one per character.
+//
+// First significant character in [lo, hi), or hi.
+__device__ int64_t wave_first_sig(const uint8_t *src, int64_t lo, int64_t hi, const uint8_t *m)
+{
+    const int lane = threadIdx.x & 63;
+    for (int64_t p = lo; p < hi; p += 64 * 16) {
+        const int64_t q = p + 16 * lane;
+        int best = 16;
+#pragma unroll
+        for (int j = 15; j >= 0; --j)
+            if (q + j < hi && is_sig(m[src[q + j]])) best = j;
+        const uint64_t b = __builtin_amdgcn_ballot_w64(best < 16);
+        if (b) return readlane_i64(q + best, __builtin_ctzll(b));
+    }
+    return hi;
+}
+
+// Last significant character in [lo, hi), or lo - 1.
+__device__ int64_t wave_last_sig(const uint8_t *src, int64_t lo, int64_t hi, const uint8_t *m)
+{
+    const int lane = threadIdx.x & 63;
+    for (int64_t e = hi; e > lo; e -= 64 * 16) {
+        const int64_t s = e - 64 * 16 > lo ? e - 64 * 16 : lo;
+        const int64_t q = s + 16 * lane;
+        int best = -1;
+#pragma unroll
+        for (int j = 0; j < 16; ++j)
+            if (q + j < e && is_sig(m[src[q + j]])) best = j;
+        const uint64_t b = __builtin_amdgcn_ballot_w64(best >= 0);
+        if (b) return readlane_i64(q + best, 63 - __builtin_clzll(b));
+    }
+    return lo - 1;
+}
+
+// Position of the first significant character at or after pos, or n
+// (wave-cooperative); tiles without one are stepped over by the prefix sums.
 __device__ int64_t next_sig(const uint8_t *src, int64_t n, int64_t pos, const uint8_t *m,
                             const int64_t *prefix, int64_t ntiles, int64_t TS)
 {
     const int64_t total = prefix[ntiles];
     while (pos < n) {
         const int64_t u = pos / TS, end = (u + 1) * TS < n ? (u + 1) * TS : n;
-        for (; pos < end; ++pos)
-            if (is_sig(m[src[pos]])) return pos;
+        const int64_t p = wave_first_sig(src, pos, end, m);
+        if (p < end) return p;
         const int64_t g = prefix[u + 1];     // index of the next significant character
         if (g >= total) return n;
         pos = tile_of(prefix, ntiles, g) * TS;
@@ -474,14 +520,15 @@ __device__ int64_t next_sig(const uint8_t *src, int64_t n, int64_t pos, const ui
     return n;
 }
 
-// Position of the last significant character before pos, or -1.
+// Position of the last significant character before pos, or -1
+// (wave-cooperative).
 __device__ int64_t prev_sig(const uint8_t *src, int64_t n, int64_t pos, const uint8_t *m,
                             const int64_t *prefix, int64_t ntiles, int64_t TS)
 {
     while (pos > 0) {
         const int64_t u = (pos - 1) / TS, start = u * TS;
-        for (int64_t i = pos - 1; i >= start; --i)
-            if (is_sig(m[src[i]])) return i;
+        const int64_t p = wave_last_sig(src, start, pos, m);
+        if (p >= start) return p;
         const int64_t g = prefix[u] - 1;     // index of the previous significant character
         if (g < 0) return -1;
         const int64_t v = tile_of(prefix, ntiles, g);
@@ -519,40 +566,35 @@ constexpr int kWaveRound = 1024;
 constexpr int kWsTrash = 16 + kWaveRound + 16;   // 64 bytes, one per lane: whitespace writes
 constexpr int kWsBuf = kWsTrash + 64;
 
-// The first `need` (<= 3) significant values after the end of tile `tile`
-// (significant index g0 onwards), packed as bytes; fewer if the input ends
-// first.  Fast path: the next tile is not empty and its first 16 characters
-// (loaded ahead as `head`) hold them; else a search through the prefix sums.
+// The first `need` (<= 3) significant values at or after position `from`
+// (the end of a tile), packed as bytes; fewer if the input ends first
+// (wave-cooperative).  Fast path (`fast`: the next tile holds at least `need`
+// significant characters): its first 16 characters, loaded ahead by lane 0 as
+// `head`, hold them; else a scan.
 __device__ uint32_t borrow_values(const uint8_t *src, int64_t n, const uint8_t *m,
-                                  const int64_t *prefix, int64_t ntiles, int64_t TS, int64_t total,
-                                  int64_t g0, int need, bool head_ok, u32x4 head, int64_t next_end)
+                                  const int64_t *prefix, int64_t ntiles, int64_t TS, int64_t from,
+                                  int need, bool fast, u32x4 head)
 {
     uint32_t extra = 0;
     int got = 0;
-    if (head_ok && next_end - g0 >= need) {
-        const uint32_t hw[4] = {head.x, head.y, head.z, head.w};
-        for (int j = 0; j < 16 && got < need; ++j) {
-            const uint32_t code = m[(hw[j >> 2] >> (8 * (j & 3))) & 0xFF];
-            if (is_sig(code)) extra |= code << (8 * got++);
+    if (fast) {
+        if ((threadIdx.x & 63) == 0) {
+            const uint32_t hw[4] = {head.x, head.y, head.z, head.w};
+            for (int j = 0; j < 16 && got < need; ++j) {
+                const uint32_t code = m[(hw[j >> 2] >> (8 * (j & 3))) & 0xFF];
+                if (is_sig(code)) extra |= code << (8 * got++);
+            }
         }
+        got = __builtin_amdgcn_readfirstlane(got);
+        extra = (uint32_t)__builtin_amdgcn_readfirstlane((int)extra);
         if (got == need) return extra;
         extra = 0;
         got = 0;
     }
-    int64_t g = g0;
-    while (got < need && g < total) {
-        const int64_t u = tile_of(prefix, ntiles, g);
-        int64_t idx = prefix[u];
-        const int64_t ue = (u + 1) * TS < n ? (u + 1) * TS : n;
-        for (int64_t i = u * TS; i < ue && got < need; ++i) {
-            const uint32_t code = m[src[i]];
-            if (!is_sig(code)) continue;
-            if (idx == g) {
-                extra |= code << (8 * got++);
-                ++g;
-            }
-            ++idx;
-        }
+    for (int64_t p = from; got < need; ++p) {
+        p = next_sig(src, n, p, m, prefix, ntiles, TS);
+        if (p >= n) break;
+        extra |= (uint32_t)m[src[p]] << (8 * got++);
     }
     return extra;
 }
@@ -798,10 +840,9 @@ __global__ __launch_bounds__(kWsBlock) void k_ws_decode(const uint8_t *__restric
         if (left > 0) {
             const int rem = left & 3;
             uint32_t extra = 0;
-            if (lane == 0 && rem)
-                extra = borrow_values(src, n, m, prefix, ntiles, TS, total, K0 + C, (int)(4 - rem),
-                                      head_ok, head, next_end);
-            extra = (uint32_t)__shfl((int)extra, 0, 64);
+            if (rem)
+                extra = borrow_values(src, n, m, prefix, ntiles, TS, end, 4 - rem,
+                                      head_ok && next_end - (K0 + C) >= 4 - rem, head);
             const int nq = (left + 3) >> 2;
             if (lane < nq) {
                 const int64_t qq = S.Qb + lane;
@@ -823,7 +864,9 @@ __global__ __launch_bounds__(kWsBlock) void k_ws_decode(const uint8_t *__restric
 // k_ws_finish (one block): the '=' and end rules over the significant
 // characters, the final quantum, and the public status (*out_len = length or
 // -1, *first_bad = -1 or the first invalid offset).  *first_bad holds the raw
-// minimum from k_ws_count, *first_pad the first '=' (padded mode).
+// minimum from k_ws_count, *first_pad the first '=' (padded mode).  The rules
+// run on wave 0, every lane with the same values, so that its searches for
+// neighbouring significant characters are wave-cooperative; lane 0 writes.
 __global__ __launch_bounds__(kWsBlock) void k_ws_finish(const uint8_t *__restrict__ src, int64_t n,
                                                         uint8_t *__restrict__ dst, DecMap map,
                                                         int64_t TS, const int64_t *__restrict__ prefix,
@@ -846,9 +889,7 @@ __global__ __launch_bounds__(kWsBlock) void k_ws_finish(const uint8_t *__restric
     // decides the rules.  Fast case: at most one significant character
     // follows it (a valid input has that form).
     int64_t a = -1, after = 0;
-    if (tid == 0) {
-        s_slow = 0;
-        s_cnt = 0;
+    if (tid < 64) {
         if (!nopad && *first_pad != kNoError) {
             a = *first_pad;
             int64_t p = a;
@@ -857,9 +898,12 @@ __global__ __launch_bounds__(kWsBlock) void k_ws_finish(const uint8_t *__restric
                 if (p >= n) break;
                 ++after;
             }
-            s_slow = after >= 2;
         }
-        s_a = a;
+        if (tid == 0) {
+            s_slow = after >= 2;
+            s_cnt = 0;
+            s_a = a;
+        }
     }
     __syncthreads();
     if (s_slow) {       // count the significant characters before the '=' in its tile
@@ -869,7 +913,7 @@ __global__ __launch_bounds__(kWsBlock) void k_ws_finish(const uint8_t *__restric
         atomicAdd((unsigned long long *)&s_cnt, (unsigned long long)cnt);
     }
     __syncthreads();
-    if (tid != 0) return;
+    if (tid >= 64) return;
 
     int64_t bad = *first_bad;                 // kNoError when none
     int64_t len = 0;
@@ -925,8 +969,10 @@ __global__ __launch_bounds__(kWsBlock) void k_ws_finish(const uint8_t *__restric
         len = 3 * (total >> 2) - (total - i);
     }
     if (bad != kNoError) {
-        *out_len = -1;
-        *first_bad = bad;
+        if (tid == 0) {
+            *out_len = -1;
+            *first_bad = bad;
+        }
         return;
     }
     if (write_output && nlast > 0) {
@@ -942,10 +988,13 @@ __global__ __launch_bounds__(kWsBlock) void k_ws_finish(const uint8_t *__restric
         }
         const uint32_t b = ws_quantum(w);
         uint8_t *o = dst + 3 * (nopad ? (total >> 2) : (total >> 2) - 1);
-        for (int k = 0; k < nd - 1; ++k) o[k] = (uint8_t)(b >> (8 * k));
+        if (tid == 0)
+            for (int k = 0; k < nd - 1; ++k) o[k] = (uint8_t)(b >> (8 * k));
     }
-    *out_len = len;
-    *first_bad = -1;
+    if (tid == 0) {
+        *out_len = len;
+        *first_bad = -1;
+    }
 }
 
 __global__ void k_ws_init(int64_t *first_bad, int64_t *first_pad)

@@ -234,6 +234,35 @@ def test_skip_ws_invalid_cases(b64, oracle):
             _dec(b64, oracle, t, STD, flags, repr(s))
 
 
+def test_skip_ws_long_runs_at_the_edges(b64, oracle):
+    """Whitespace runs longer than a tile where the decoder searches for
+    neighbouring significant characters: before and after the text, between
+    the two '=' of the final quantum, and just before a tile end, where the
+    tile's last quantum takes its values from after the run."""
+    x = workloads.random_bytes(workloads.SEED_BASE + 193, 20000)
+    sp = lambda k: np.full(k, ord(" "), dtype=np.uint8)
+    for n in (3000, 3001, 3002):
+        for flags in (SKIP_WS, SKIP_WS | NOPAD):
+            text = _mime(oracle, x[:n], STD, flags & NOPAD)
+            _dec(b64, oracle, np.concatenate([text, sp(100000)]), STD, flags, f"{n} then run")
+            _dec(b64, oracle, np.concatenate([sp(100000), text]), STD, flags, f"run then {n}")
+            for cut in (1, 2, 3):
+                _dec(b64, oracle, np.concatenate([text[:-cut], sp(70000)]), STD, flags,
+                     f"{n} cut {cut} then run", check_validate=False)
+    for n in (3001, 3002):                       # "xx==" and "xxx=" split by a run
+        text = _mime(oracle, x[:n])
+        k = text.size - 1                        # the last '='
+        for at in (k, k - 1, k - 2):
+            t = np.concatenate([text[:at], sp(70000), text[at:]])
+            _dec(b64, oracle, t, STD, SKIP_WS, f"{n} run at {at} of {text.size}")
+    for d in (1, 2, 3, 5, 77):
+        for flags in (SKIP_WS, SKIP_WS | NOPAD):
+            t = _mime(oracle, x, STD, flags & NOPAD)
+            t = np.concatenate([t[:2 * 4096 - d], sp(50000), t[2 * 4096 - d:]])
+            _dec(b64, oracle, t, STD, flags, f"run before a tile end, d = {d}",
+                 check_validate=(d == 1))
+
+
 def test_skip_ws_async_status_and_graph(b64, oracle):
     import torch
     x = workloads.random_bytes(workloads.SEED_BASE + 186, 1 << 20)
