@@ -400,6 +400,21 @@ def run_batch(args, torch, b64):
         log("batch", name, json.dumps(res[name]))
     st = stat.view(-1, 2).cpu().numpy()
     assert np.array_equal(st[:, 0], lens) and (st[:, 1] == -1).all()
+    del per_dst, stat
+    # yardstick: the packed input as ONE buffer, the same bytes to move, so
+    # that the batched rates can be told apart from the cost of the footprint
+    text1 = b64.encode(src)
+    out1, st1 = b64.decode_async(text1)
+    torch.cuda.synchronize()
+    assert st1.cpu().tolist() == [total, -1]
+    t1e = _events_time(torch, lambda: b64.encode(src, out=text1), args.steps)
+    t1d = _events_time(torch, lambda: b64.decode_async(text1, out=out1, status=st1), args.steps)
+    n1 = int(text1.numel())
+    res["one_buffer_same_bytes"] = {
+        "chars": n1, "encode_ms": t1e["median"], "decode_ms": t1d["median"],
+        "encode_hbm_gbps": (total + n1) / t1e["median"] / 1e6,
+        "decode_hbm_gbps": (total + n1) / t1d["median"] / 1e6}
+    log("batch one buffer", json.dumps(res["one_buffer_same_bytes"]))
     print(json.dumps(res), flush=True)
 
 

@@ -9,7 +9,9 @@
 // a distant span of its own (which costs DRAM row locality: about a fifth of
 // the bandwidth on MI355X).  A tile covers the groups (encode) or quanta
 // (decode) whose first byte lies in it, buffer after buffer, with consecutive
-// lanes on consecutive chunks of a per-buffer grid aligned for the stores.  The 64 lanes of a wave look up the first
+// lanes on consecutive chunks of a per-buffer grid aligned for the stores;
+// the grid is cut between tiles at output line starts rather than exactly at
+// the tile boundary (grid_cut).  The 64 lanes of a wave look up the first
 // buffer of 64 of its tiles at once (one binary search per lane over in_off),
 // so the lookup costs one search latency per 64 tiles.  No work queue and no
 // atomics beyond the first-invalid minimum.
@@ -71,12 +73,32 @@ struct TileWalk {
     }
 };
 
+// A buffer's chunk grid: chunk j covers units (groups or quanta) h + 4j ..
+// h + 4j + 3, j < nch.  A tile owns the chunks from grid_cut(its first unit)
+// up to grid_cut(the next tile's first unit): the first chunk at or after
+// unit u, rounded up to a multiple of P and capped at nch.  Neighbouring
+// tiles compute the same cut, so every chunk has one owner, and every tile's
+// share starts P chunks apart -- on a 128-byte output line.
+__device__ __forceinline__ int64_t grid_cut(int64_t u, int64_t h, int64_t nch, int64_t P)
+{
+    int64_t j = u <= h ? 0 : (u - h + 3) >> 2;
+    j = (j + P - 1) / P * P;
+    return j < nch ? j : nch;
+}
+
+// Chunks between two line starts: 8 of 16 output bytes (encode), 32 of 12
+// (decode: 384 bytes, three lines).
+constexpr int64_t kEncAlign = kLine / 16, kDecAlign = kLine / 4;
+
 // Encode the groups whose first byte lies in [lo, hi), starting at buffer b0.
-// Per buffer the chunk grid starts `h` groups in (h < 4), so that chunk
-// outputs are 16-byte aligned whenever the buffer's output is 4-byte aligned
-// (a 16-byte store that straddles a 16-byte boundary costs two); the groups
-// before the tile's first chunk and after its last one -- at most seven,
-// including the buffer's partial last group -- go to lanes 0..6, one each.
+// Per buffer the chunk grid starts `h` groups in (h < 32) and tiles cut it at
+// line starts (grid_cut), so that whenever the buffer's output is 4-byte
+// aligned every store instruction of a round (64 chunks, 1 KiB) covers whole
+// 128-byte lines, as in the single-buffer kernel; a span that starts inside a
+// line leaves two partial lines, whose halves reach memory separately under
+// nontemporal stores.  The groups outside the grid -- the h before it and the
+// at most three whole groups and one partial group after it -- go to the
+// lanes in turn, each to the tile holding its first byte.
 template <int U, bool NT>
 __device__ void encode_tile(const uint8_t *__restrict__ src, const int64_t *__restrict__ in_off,
                             int64_t nbuf, uint8_t *__restrict__ dst,
@@ -104,22 +126,25 @@ __device__ void encode_tile(const uint8_t *__restrict__ src, const int64_t *__re
         if (g_lo >= g_hi) continue;
         uint8_t *ob = dst + ob_off;
         const uint64_t oa = (uint64_t)(uintptr_t)ob;
-        const int64_t h = (oa & 3) ? 0 : (int64_t)(((16 - (oa & 15)) & 15) >> 2);
-        const int64_t g_full = g_hi < nfull ? g_hi : nfull;
-        const int64_t j_lo = g_lo <= h ? 0 : (g_lo - h + 3) >> 2;
-        const int64_t j_hi = g_full <= h ? 0 : (g_full - h) >> 2;
-        const int64_t nchunk = j_hi > j_lo ? j_hi - j_lo : 0;
-        const int64_t c_first = nchunk ? h + 4 * j_lo : g_lo;   // first chunked group
+        int64_t h = (oa & 3) ? 0 : (int64_t)((((uint64_t)kLine - (oa & (kLine - 1))) & (kLine - 1)) >> 2);
+        if (h > nfull) h = nfull;
+        const int64_t nch = (nfull - h) >> 2;
+        const int64_t j_lo = grid_cut(g_lo, h, nch, kEncAlign), j_hi = grid_cut(g_hi, h, nch, kEncAlign);
+        const int64_t nchunk = j_hi - j_lo;
+        const int64_t c_first = h + 4 * j_lo;   // first chunked group
         const uint8_t *sp = src + s + 3 * c_first;
         uint8_t *dp = ob + 4 * c_first;
         // rounds of 64*U chunks; all but the last are complete
         const int64_t nround = nchunk / (64 * U);
         enc_stream<U, NT>(sp, dp, lane, 64, 64 * U, nround, a);
         enc_round_tail<U, NT>(sp, dp, lane + nround * 64 * U, 64, a, nchunk);
-        // leftover groups: [g_lo, c_first) then [c_first + 4*nchunk, g_hi)
-        const int64_t lead = c_first - g_lo;
-        const int64_t g = lane < lead ? g_lo + lane : c_first + 4 * nchunk + (lane - lead);
-        if (lane < 7 && g < g_hi) {
+        // groups outside the grid: [g_lo, min(g_hi, h)) and [max(g_lo, h + 4*nch), g_hi)
+        const int64_t pre_hi = g_hi < h ? g_hi : h;
+        const int64_t npre = pre_hi > g_lo ? pre_hi - g_lo : 0;
+        const int64_t post_lo = g_lo > h + 4 * nch ? g_lo : h + 4 * nch;
+        const int64_t nleft = npre + (g_hi > post_lo ? g_hi - post_lo : 0);
+        for (int64_t i = lane; i < nleft; i += 64) {
+            const int64_t g = i < npre ? g_lo + i : post_lo + (i - npre);
             const int64_t rem = len - 3 * g;
             enc_scalar(src + s + 3 * g, rem < 3 ? rem : 3, ob + 4 * g, a, pad);
         }
@@ -152,11 +177,13 @@ __global__ __launch_bounds__(kThreads) void k_encode_batch(
 
 // Decode the quanta whose first character lies in [lo, hi), starting at
 // buffer b0.  The body of a buffer is its quanta but the last.  Per buffer the
-// chunk grid starts `h` body quanta in (h < 4, 3h = -out mod 4), so that chunk
-// outputs are 4-byte aligned; chunks of four body quanta go to lanes, and the
-// quanta before the tile's first chunk and after its last one -- at most
-// three leading and three trailing body quanta and the last quantum (through
-// dec_tail_fast) -- go to lanes 0..6, one each.
+// chunk grid starts `h` body quanta in (h < 128, 3h = -out mod 128) and tiles
+// cut it at line starts (grid_cut), so that every store instruction of a
+// round (64 chunks, 768 bytes) covers whole 128-byte lines; chunks of four
+// body quanta go to lanes, and the quanta outside the grid -- the h before
+// it, the at most three body quanta after it and the last quantum (through
+// dec_tail_fast) -- to the lanes in turn, each to the tile holding its first
+// character.
 template <int U, bool NT>
 __device__ void decode_tile(const uint8_t *__restrict__ src, const int64_t *__restrict__ in_off,
                             int64_t nbuf, uint8_t *__restrict__ dst,
@@ -187,12 +214,12 @@ __device__ void decode_tile(const uint8_t *__restrict__ src, const int64_t *__re
         if (q_hi > nq) q_hi = nq;
         if (q_lo >= q_hi) continue;
         uint8_t *ob = dst + ob_off;
-        const int64_t h = (int64_t)((uint64_t)(uintptr_t)ob & 3);
-        const int64_t q_body = q_hi < nbody ? q_hi : nbody;
-        const int64_t j_lo = q_lo <= h ? 0 : (q_lo - h + 3) >> 2;
-        const int64_t j_hi = q_body <= h ? 0 : (q_body - h) >> 2;
-        const int64_t nchunk = j_hi > j_lo ? j_hi - j_lo : 0;
-        const int64_t c_first = nchunk ? h + 4 * j_lo : q_lo;   // first chunked quantum
+        int64_t h = (int64_t)(((0 - (uint64_t)(uintptr_t)ob) * 43u) & (uint64_t)(kLine - 1));
+        if (h > nbody) h = nbody;
+        const int64_t nch = (nbody - h) >> 2;
+        const int64_t j_lo = grid_cut(q_lo, h, nch, kDecAlign), j_hi = grid_cut(q_hi, h, nch, kDecAlign);
+        const int64_t nchunk = j_hi - j_lo;
+        const int64_t c_first = h + 4 * j_lo;   // first chunked quantum
         const uint8_t *sp = src + s + 4 * c_first;
         uint8_t *dp = ob + 3 * c_first;
         uint32_t err = 0;
@@ -211,10 +238,13 @@ __device__ void decode_tile(const uint8_t *__restrict__ src, const int64_t *__re
                 }
             }
         }
-        // leftover quanta: [q_lo, c_first) then [c_first + 4*nchunk, q_hi)
-        const int64_t lead = c_first - q_lo;
-        const int64_t q = lane < lead ? q_lo + lane : c_first + 4 * nchunk + (lane - lead);
-        if (lane < 7 && q < q_hi) {
+        // quanta outside the grid: [q_lo, min(q_hi, h)) and [max(q_lo, h + 4*nch), q_hi)
+        const int64_t pre_hi = q_hi < h ? q_hi : h;
+        const int64_t npre = pre_hi > q_lo ? pre_hi - q_lo : 0;
+        const int64_t post_lo = q_lo > h + 4 * nch ? q_lo : h + 4 * nch;
+        const int64_t nleft = npre + (q_hi > post_lo ? q_hi - post_lo : 0);
+        for (int64_t i = lane; i < nleft; i += 64) {
+            const int64_t q = i < npre ? q_lo + i : post_lo + (i - npre);
             const uint8_t *qp = src + s + 4 * q;
             uint8_t *qo = ob + 3 * q;
             if (q < nbody) {

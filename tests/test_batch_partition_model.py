@@ -5,9 +5,11 @@ waves grid-stride, and let each wave walk the buffers a tile touches.  This
 test re-traces that index arithmetic on the host for many layouts, tile sizes
 and grid sizes and checks, before any launch, that:
   - every group (encode) / quantum (decode) of every buffer is handled exactly
-    once, by a lane chunk or by one of the (at most seven) leftover lanes;
-  - chunk stores start 16-byte aligned (encode, when the output is 4-byte
-    aligned) or 4-byte aligned (decode);
+    once, by a lane chunk or by a lane that takes one unit outside the chunk
+    grid (the tile holding the unit's first byte);
+  - each tile's share of a buffer's chunk grid starts on a 128-byte output
+    line (encode: when the output is 4-byte aligned; decode: always), so that
+    every store instruction of a round covers whole lines;
   - every read stays inside its buffer and every write inside its output
     capacity;
   - exactly one wave writes each encode out_len, and exactly one lane runs the
@@ -37,6 +39,18 @@ def first_buffer(in_off, nbuf, pos):
         else:
             r = mid
     return l
+
+
+LINE = 128
+ENC_ALIGN, DEC_ALIGN = LINE // 16, LINE // 4
+
+
+def grid_cut(u, h, nch, P):
+    """First chunk of a tile's share: the first chunk at or after unit u,
+    rounded up to a multiple of P, at most nch."""
+    j = 0 if u <= h else (u - h + 3) >> 2
+    j = (j + P - 1) // P * P
+    return min(j, nch)
 
 
 def tiles(in_off, nbuf, tile, grid):
@@ -76,28 +90,31 @@ def trace_encode(in_off, out_off, nbuf, grid, tile, dst_base=0):
             if g_lo >= g_hi:
                 continue
             oa = dst_base + int(out_off[b])
-            h = 0 if oa & 3 else ((16 - (oa & 15)) & 15) >> 2
-            g_full = min(g_hi, nfull)
-            j_lo = 0 if g_lo <= h else (g_lo - h + 3) >> 2
-            j_hi = 0 if g_full <= h else (g_full - h) >> 2
-            nchunk = max(j_hi - j_lo, 0)
-            c_first = h + 4 * j_lo if nchunk else g_lo
+            h = 0 if oa & 3 else ((LINE - (oa & (LINE - 1))) & (LINE - 1)) >> 2
+            h = min(h, nfull)
+            nch = (nfull - h) >> 2
+            j_lo, j_hi = grid_cut(g_lo, h, nch, ENC_ALIGN), grid_cut(g_hi, h, nch, ENC_ALIGN)
+            nchunk = j_hi - j_lo
+            c_first = h + 4 * j_lo
+            assert nchunk >= 0
             if nchunk:
                 seen[b][c_first: c_first + 4 * nchunk] += 1
-                # reads [s + 3 c_first, + 12 nchunk), writes 16 per chunk, aligned
+                # reads [s + 3 c_first, + 12 nchunk), writes 16 per chunk, on lines
                 assert s + 3 * c_first + 12 * nchunk <= e
                 assert 4 * c_first + 16 * nchunk <= 4 * ngroups
                 if oa % 4 == 0:
-                    assert (oa + 4 * c_first) % 16 == 0
-            lead = c_first - g_lo
-            trail = g_hi - (c_first + 4 * nchunk)
-            assert lead >= 0 and trail >= 0 and lead + trail <= 7
-            for lane in range(7):
-                g = g_lo + lane if lane < lead else c_first + 4 * nchunk + (lane - lead)
-                if g < g_hi:
-                    rem = length - 3 * g
-                    assert rem > 0 and 3 * g + min(rem, 3) <= length
-                    seen[b][g] += 1
+                    assert (oa + 4 * c_first) % LINE == 0
+            pre_hi = min(g_hi, h)
+            npre = max(pre_hi - g_lo, 0)
+            post_lo = max(g_lo, h + 4 * nch)
+            nleft = npre + max(g_hi - post_lo, 0)
+            assert nleft <= 35
+            for i in range(nleft):
+                g = g_lo + i if i < npre else post_lo + (i - npre)
+                assert g < g_hi
+                rem = length - 3 * g
+                assert rem > 0 and 3 * g + min(rem, 3) <= length
+                seen[b][g] += 1
     for b in range(nbuf):
         assert (seen[b] == 1).all(), (b, seen[b])
     assert (owners == 1).all(), np.nonzero(owners != 1)
@@ -124,24 +141,25 @@ def trace_decode(in_off, nbuf, grid, tile, dst_base=0):
             if q_lo >= q_hi:
                 continue
             oa = dst_base + int(out_off[b])
-            h = oa & 3
-            q_body = min(q_hi, nbody)
-            j_lo = 0 if q_lo <= h else (q_lo - h + 3) >> 2
-            j_hi = 0 if q_body <= h else (q_body - h) >> 2
-            nchunk = max(j_hi - j_lo, 0)
-            c_first = h + 4 * j_lo if nchunk else q_lo
+            h = min((-oa * 43) & (LINE - 1), nbody)
+            nch = (nbody - h) >> 2
+            j_lo, j_hi = grid_cut(q_lo, h, nch, DEC_ALIGN), grid_cut(q_hi, h, nch, DEC_ALIGN)
+            nchunk = j_hi - j_lo
+            c_first = h + 4 * j_lo
+            assert nchunk >= 0
             if nchunk:
                 seen[b][c_first: c_first + 4 * nchunk] += 1
                 assert 4 * c_first + 16 * nchunk <= 4 * nbody < length
                 assert 3 * c_first + 12 * nchunk <= 3 * (length // 4)
-                assert (oa + 3 * c_first) % 4 == 0
-            lead = c_first - q_lo
-            trail = q_hi - (c_first + 4 * nchunk)
-            assert lead >= 0 and trail >= 0 and lead + trail <= 7
-            for lane in range(7):
-                q = q_lo + lane if lane < lead else c_first + 4 * nchunk + (lane - lead)
-                if q >= q_hi:
-                    continue
+                assert (oa + 3 * c_first) % LINE == 0
+            pre_hi = min(q_hi, h)
+            npre = max(pre_hi - q_lo, 0)
+            post_lo = max(q_lo, h + 4 * nch)
+            nleft = npre + max(q_hi - post_lo, 0)
+            assert nleft <= 131
+            for i in range(nleft):
+                q = q_lo + i if i < npre else post_lo + (i - npre)
+                assert q < q_hi
                 seen[b][q] += 1
                 if q < nbody:
                     assert 4 * q + 4 <= length and 3 * q + 3 <= 3 * (length // 4)
