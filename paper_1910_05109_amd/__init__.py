@@ -47,22 +47,46 @@ __all__ = ["STD", "URL", "NOPAD", "SKIP_WS", "B64Error", "load", "encoded_len", 
            "decode_f32_bf16", "tune_set", "tune_get", "stream_ptr"]
 
 
+# The wrappers below sit on the launch path of every call, so they keep their
+# own host work small: at a few MiB a call costs about as much on the host as
+# on the GPU.
+_torch_mod = None
+
+
 def _torch():
-    import torch
-    return torch
+    global _torch_mod
+    if _torch_mod is None:
+        import torch
+        _torch_mod = torch
+    return _torch_mod
 
 
 def stream_ptr(stream=None) -> int:
-    torch = _torch()
-    s = torch.cuda.current_stream() if stream is None else stream
-    return int(s.cuda_stream)
+    """Raw HIP stream of `stream`, or of torch's current stream."""
+    if stream is not None:
+        return int(stream.cuda_stream)
+    c = _torch()._C
+    if hasattr(c, "_cuda_getCurrentRawStream"):
+        # the raw accessor skips building a torch Stream object (about 3 us)
+        return c._cuda_getCurrentRawStream(c._cuda_getDevice())
+    return int(_torch().cuda.current_stream().cuda_stream)
+
+
+_alpha_cache: dict = {}
 
 
 def _alpha(alphabet) -> ctypes.Array:
-    a = bytes(alphabet)
-    if len(a) != 64:
-        raise ValueError("alphabet must have 64 bytes")
-    return ctypes.create_string_buffer(a, 64)
+    """The 64 alphabet bytes as a C buffer (the library copies them by value
+    at each call); kept per alphabet."""
+    buf = _alpha_cache.get(alphabet) if isinstance(alphabet, bytes) else None
+    if buf is None:
+        a = bytes(alphabet)
+        if len(a) != 64:
+            raise ValueError("alphabet must have 64 bytes")
+        buf = ctypes.create_string_buffer(a, 64)
+        if isinstance(alphabet, bytes) and len(_alpha_cache) < 256:
+            _alpha_cache[alphabet] = buf
+    return buf
 
 
 def _check_u8(t, what):
@@ -113,7 +137,8 @@ def encode(x, alphabet=STD, out=None, stream=None, flags: int = 0, line_len: int
     torch = _torch()
     _check_u8(x, "x")
     n = x.numel()
-    m = encoded_len(n, flags, line_len)
+    # the plain length 4*ceil(n/3) (b64_encoded_len) without a library round trip
+    m = 4 * ((n + 2) // 3) if flags == 0 and line_len == 0 else encoded_len(n, flags, line_len)
     if out is None:
         out = torch.empty(max(m, 1), dtype=torch.uint8, device=x.device)
     else:
@@ -126,7 +151,7 @@ def encode(x, alphabet=STD, out=None, stream=None, flags: int = 0, line_len: int
     else:
         r = check(load().b64_encode_mode(x.data_ptr(), n, out.data_ptr(), _alpha(alphabet), flags,
                                          line_len, stream_ptr(stream)), "b64_encode_mode")
-    return out[:r]
+    return out if out.numel() == r else out[:r]
 
 
 def decode(s, alphabet=STD, out=None, stream=None, flags: int = 0):
@@ -134,7 +159,8 @@ def decode(s, alphabet=STD, out=None, stream=None, flags: int = 0):
     torch = _torch()
     _check_u8(s, "s")
     n = s.numel()
-    cap = decoded_max_len(n, flags)
+    # the plain capacity 3*floor(n/4) (b64_decoded_max_len) without a library round trip
+    cap = 3 * (n // 4) if flags == 0 else decoded_max_len(n, flags)
     if out is None:
         out = torch.empty(max(cap, 1), dtype=torch.uint8, device=s.device)
     else:
@@ -161,7 +187,8 @@ def decode_async(s, alphabet=STD, out=None, status=None, stream=None, flags: int
     torch = _torch()
     _check_u8(s, "s")
     n = s.numel()
-    cap = decoded_max_len(n, flags)
+    # the plain capacity 3*floor(n/4) (b64_decoded_max_len) without a library round trip
+    cap = 3 * (n // 4) if flags == 0 else decoded_max_len(n, flags)
     if out is None:
         out = torch.empty(max(cap, 1), dtype=torch.uint8, device=s.device)
     if status is None:
