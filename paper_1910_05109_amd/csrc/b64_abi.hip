@@ -100,6 +100,8 @@ Shape shape_of(int op)
 }
 
 constexpr int kMaxDevices = 64;
+// Compute units per device, asked once (threads may race to ask; they store
+// the same value).
 int g_cus[kMaxDevices];
 
 hipError_t cu_count(int *cus)
@@ -108,13 +110,15 @@ hipError_t cu_count(int *cus)
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return e;
     if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
-    if (g_cus[dev] == 0) {
+    int c = __atomic_load_n(&g_cus[dev], __ATOMIC_RELAXED);
+    if (c == 0) {
         int v = 0;
         e = hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev);
         if (e != hipSuccess) return e;
-        g_cus[dev] = v > 0 ? v : 1;
+        c = v > 0 ? v : 1;
+        __atomic_store_n(&g_cus[dev], c, __ATOMIC_RELAXED);
     }
-    *cus = g_cus[dev];
+    *cus = c;
     return hipSuccess;
 }
 
