@@ -121,6 +121,29 @@ def test_misaligned_pointers(b64, oracle):
             assert first_mismatch(to_host(dec), x) is None, (so, do)
 
 
+def test_encode_to_unaligned_destinations(b64, oracle):
+    """Destinations 1-3 bytes past a 4-byte boundary (no head groups, every
+    chunk store unaligned): every length up to 300, lengths around rounds,
+    and 64 MiB + 1 (many pipelined rounds), padded and unpadded; the bytes
+    around the output stay untouched."""
+    import torch
+    x = workloads.random_bytes(workloads.SEED_BASE + 126, (64 << 20) + 1)
+    dx = to_dev(x)
+    lengths = list(range(0, 300)) + [1000, 4095, 4096, 4097, 12_345, 100_003, (3 << 20) + 1]
+    for flags in (0, 1):
+        for n in lengths + ([(64 << 20) + 1] if flags == 0 else []):
+            ref = oracle.encode_mode(x[:n], STD, flags)
+            for do in (1, 2, 3):
+                if n > 5000 and do != 2 and n != (64 << 20) + 1:
+                    continue
+                say("unaligned destination", n, "offset", do, "flags", flags)
+                buf = torch.full((ref.size + do + 64,), 0xA5, dtype=torch.uint8, device="cuda")
+                b64.encode(dx[:n], STD, out=buf[do:], flags=flags)
+                got = to_host(buf)
+                assert first_mismatch(got[do: do + ref.size], ref) is None, (n, do, flags)
+                assert (got[:do] == 0xA5).all() and (got[do + ref.size:] == 0xA5).all(), (n, do)
+
+
 @pytest.mark.parametrize("where", ["first", "chunk_edge", "body", "last_body", "final"])
 def test_every_invalid_byte_at_every_position(b64, oracle, where):
     x = workloads.random_bytes(workloads.SEED_BASE + 125, 3 * 1500)
