@@ -127,7 +127,10 @@ int64_t b64_decode_batch(const uint8_t *src, const int64_t *in_off, int64_t nbuf
  *   B64_SKIP_WS  decode / validate: space, tab, CR and LF are ignored; every
  *                rule applies to the remaining characters, and offsets count
  *                every byte of the input.  The alphabet may not contain any
- *                of those four bytes.
+ *                of those four bytes.  The decode may leave any bytes in dst
+ *                past the decoded length (within the output capacity): text
+ *                in regular lines is first decoded with guessed line
+ *                positions, and decoded again if the guess fails.
  * and encode takes `line_len`: 0 for one line, else a multiple of 4; CR LF
  * then separates consecutive lines of line_len characters (no CR LF after
  * the last line).  flags = 0 and line_len = 0 give the plain entry points. */
@@ -142,7 +145,7 @@ int64_t b64_encoded_len_mode(int64_t n, uint32_t flags, int64_t line_len);
 int64_t b64_decoded_max_len_mode(int64_t n, uint32_t flags);
 /* Device workspace, in bytes, that the asynchronous B64_SKIP_WS decode and
  * validate need for n characters (0 without B64_SKIP_WS): 8 bytes per tile of
- * 4-32 KiB of input plus 16.  B64_EARG for n < 0 or unknown flags. */
+ * 4-32 KiB of input plus 24.  B64_EARG for n < 0 or unknown flags. */
 int64_t b64_decode_workspace_size(int64_t n, uint32_t flags);
 
 /* Encode with variants.  Asynchronous; returns b64_encoded_len_mode(n, flags,

@@ -297,16 +297,18 @@ __device__ __forceinline__ u32x4 codes16(u32x4 q, const uint8_t *map)
 // characters.  A full tile issues all R loads of a thread before it looks at
 // any.  Invalid characters go to *first_bad, '=' (padded mode) to
 // *first_pad, both by atomic minimum; both must hold kNoError before the
-// launch.
+// launch.  It does nothing when the checked decode has succeeded (*mode 1).
 template <int R, bool NT>
 __global__ __launch_bounds__(kWsBlock) void k_ws_count(const uint8_t *__restrict__ src, int64_t n,
                                                        DecMap map, int64_t *__restrict__ prefix,
                                                        int64_t *__restrict__ first_pad,
-                                                       int64_t *__restrict__ first_bad)
+                                                       int64_t *__restrict__ first_bad,
+                                                       const int64_t *__restrict__ mode)
 {
     constexpr int64_t TS = R * kRound;
     __shared__ uint32_t s_map[64];
     __shared__ int s_sum;
+    if (*mode == 1) return;
     stage_dec_map(s_map, map);
     const uint8_t *m = (const uint8_t *)s_map;
     const int64_t ntiles = ws_tiles(n, TS);
@@ -385,12 +387,14 @@ __device__ __forceinline__ int wave_incl_scan(int x)
     return x;
 }
 
-__global__ __launch_bounds__(kScanThreads) void k_ws_scan(int64_t *__restrict__ prefix, int64_t ntiles)
+__global__ __launch_bounds__(kScanThreads) void k_ws_scan(int64_t *__restrict__ prefix, int64_t ntiles,
+                                                          const int64_t *__restrict__ mode)
 {
     constexpr int kW = kScanThreads / 64;
     __shared__ int s_wave[kScanRows][kW];        // wave totals, then their exclusive sums
     __shared__ int64_t s_row[kScanRows];          // rows' exclusive offsets
     __shared__ int64_t s_carry;
+    if (*mode == 1) return;                       // the guessed sums were exact
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     if (threadIdx.x == 0) {
         prefix[0] = 0;
@@ -474,6 +478,12 @@ __device__ __forceinline__ int64_t readlane_i64(int64_t v, int l)
 __device__ int64_t wave_first_sig(const uint8_t *src, int64_t lo, int64_t hi, const uint8_t *m)
 {
     const int lane = threadIdx.x & 63;
+    {   // the next 64 characters first, one per lane: the usual distance
+        const bool sig = lo + lane < hi && is_sig(m[src[lo + lane]]);
+        const uint64_t b = __builtin_amdgcn_ballot_w64(sig);
+        if (b) return lo + __builtin_ctzll(b);
+        lo += 64;
+    }
     for (int64_t p = lo; p < hi; p += 64 * 16) {
         const int64_t q = p + 16 * lane;
         int best = 16;
@@ -490,6 +500,13 @@ __device__ int64_t wave_first_sig(const uint8_t *src, int64_t lo, int64_t hi, co
 __device__ int64_t wave_last_sig(const uint8_t *src, int64_t lo, int64_t hi, const uint8_t *m)
 {
     const int lane = threadIdx.x & 63;
+    {   // the previous 64 characters first, one per lane
+        const int64_t i = hi - 64 + lane;
+        const bool sig = i >= lo && is_sig(m[src[i]]);
+        const uint64_t b = __builtin_amdgcn_ballot_w64(sig);
+        if (b) return hi - 64 + (63 - __builtin_clzll(b));
+        hi -= 64;
+    }
     for (int64_t e = hi; e > lo; e -= 64 * 16) {
         const int64_t s = e - 64 * 16 > lo ? e - 64 * 16 : lo;
         const int64_t q = s + 16 * lane;
@@ -610,6 +627,8 @@ struct WsState {
     int64_t Qb, Q0, qlimit;
     uint32_t held[4];
     int held_k;
+    uint32_t err;   // (checked decode) OR of the values read back: bit 7 of a byte flags '=' or an invalid byte
+    int cnt;        // (checked decode) significant characters seen in the tile
 };
 
 // One round of k_ws_decode: the wave's characters [p0, p0 + kWaveRound), of
@@ -638,7 +657,7 @@ struct WsState {
 // `vb` is the block's array of value buffers and `wo` this wave's offset in
 // it: positions are kept as offsets into the whole array, so the array's
 // address folds into the LDS instructions' constant offsets.
-template <bool HOT, bool NT>
+template <bool HOT, bool NT, bool CHECK>
 __device__ __forceinline__ void ws_round(u32x4 raw, int64_t p0, int64_t end, uint8_t *st,
                                          const uint8_t *m, uint8_t *vb, int wo,
                                          uint8_t *__restrict__ dst, WsState &S)
@@ -677,7 +696,9 @@ __device__ __forceinline__ void ws_round(u32x4 raw, int64_t p0, int64_t end, uin
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     uint8_t *const cb = vb + wo;
-    const int rb = S.W + __builtin_amdgcn_readfirstlane(at0 - start);
+    const int got = __builtin_amdgcn_readfirstlane(at0 - start);
+    const int rb = S.W + got;
+    if (CHECK) S.cnt += got;
     const int avail = rb - 16;
     const int nfull = avail > 0 ? avail >> 4 : 0;   // at most 64 (rb <= 31 + 1024)
     const int64_t lo64 = S.Q0 - S.Qb, hi64 = S.qlimit - S.Qb;
@@ -688,6 +709,7 @@ __device__ __forceinline__ void ws_round(u32x4 raw, int64_t p0, int64_t end, uin
         // tile's own quanta are stored, with one store instruction
         const int k0 = 4 * lane;
         const u32x4 v = *(const u32x4 *)(cb + 16 + 16 * lane);
+        if (CHECK) S.err |= v.x | v.y | v.z | v.w;
         const uint32_t b0 = ws_quantum(v.x), b1 = ws_quantum(v.y), b2 = ws_quantum(v.z),
                        b3 = ws_quantum(v.w);
         u32x3 w;
@@ -709,6 +731,7 @@ __device__ __forceinline__ void ws_round(u32x4 raw, int64_t p0, int64_t end, uin
     } else if (lane < nfull) {
         const int g = lane;
         const u32x4 v = *(const u32x4 *)(cb + 16 + 16 * g);
+        if (CHECK) S.err |= v.x | v.y | v.z | v.w;
         const uint32_t b0 = ws_quantum(v.x), b1 = ws_quantum(v.y), b2 = ws_quantum(v.z),
                        b3 = ws_quantum(v.w);
         // quanta Qb + 4g .. +3; those before Q0 or at qlimit and past are not stored
@@ -739,6 +762,55 @@ __device__ __forceinline__ void ws_round(u32x4 raw, int64_t p0, int64_t end, uin
     S.Qb += 4 * nfull;
 }
 
+// The first invalid character and the first '=' (padded mode) of the tile
+// [base, end), by atomic minimum, as k_ws_count records them; each lane scans
+// its own 16 characters of every 1,024 (wave-cooperative).
+__device__ void ws_rescan(const uint8_t *src, int64_t base, int64_t end, const uint8_t *m,
+                          int64_t *first_pad, int64_t *first_bad)
+{
+    const int lane = threadIdx.x & 63;
+    bool bad_found = false, pad_found = false;
+    // a rare path: rolled loops, so that it adds no registers to the decode
+#pragma unroll 1
+    for (int64_t p = base + 16 * lane; p < end && !(bad_found && pad_found); p += kWaveRound) {
+#pragma unroll 1
+        for (int64_t i = p; i < p + 16 && i < end; ++i) {
+            const uint32_t code = m[src[i]];
+            if (code == kBadCode && !bad_found) {
+                atomic_min_i64(first_bad, i);
+                bad_found = true;
+            } else if (code == kPadCode && !pad_found) {
+                atomic_min_i64(first_pad, i);
+                pad_found = true;
+            }
+        }
+    }
+}
+
+// k_ws_check's work on a tile: count its significant characters against the
+// guessed count C (unless it is the last tile) and record its first invalid
+// character and '=' (wave-cooperative).
+__device__ void ws_check_tile(const uint8_t *src, int64_t base, int64_t end, const uint8_t *m,
+                              bool check_count, int64_t C, int64_t *mode, int64_t *first_pad,
+                              int64_t *first_bad)
+{
+    const int lane = threadIdx.x & 63;
+    int cnt = 0;
+    uint32_t err = 0;
+#pragma unroll 4
+    for (int64_t p = base + 16 * lane; p < end; p += kWaveRound) {
+        const u32x4 c = ws_codes<false>(src, end, p, m);
+        cnt += sig_count(c);
+        err |= c.x | c.y | c.z | c.w;
+    }
+    err = (err | (err >> 8) | (err >> 16) | (err >> 24)) & 0xFFu;   // bit 7 of any code
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) cnt += __shfl_xor(cnt, d, 64);
+    if (check_count && cnt != C && lane == 0)
+        __hip_atomic_store(mode, (int64_t)0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (__ballot(err & 0x80u)) ws_rescan(src, base, end, m, first_pad, first_bad);
+}
+
 // k_ws_decode: tile `tile` decodes the quanta whose first significant value
 // lies in it, except quanta at index >= qlimit (the final quantum, left to
 // k_ws_finish).  Quantum q covers significant values [4q, 4q+4) and writes
@@ -749,15 +821,29 @@ __device__ __forceinline__ void ws_round(u32x4 raw, int64_t p0, int64_t end, uin
 // stored).  Tiles are dealt to waves grid-stride (the launch sizes the grid
 // to the workgroups that are resident at once, so every wave starts at once);
 // a wave keeps the loads of its next D rounds in flight.
-template <int D, bool NT>
+//
+// CHECK: the checked decode that runs on k_ws_predict's guessed prefix sums
+// (*mode == 1; it returns at once otherwise).  Every tile it decodes, but the
+// last, compares the significant characters it saw with its guessed count,
+// and clears *mode on a difference or on any '=' or invalid character (the
+// counting path then finds them).  The last tile and the tiles with no
+// quantum of their own are left to k_ws_check.  When every count holds, the
+// guessed sums are the exact ones, so its output is the output of the plain
+// decode on exact sums.  Without CHECK the kernel runs only when *mode is 0
+// (no guess, or a check failed).
+template <int D, bool NT, bool CHECK>
 __global__ __launch_bounds__(kWsBlock) void k_ws_decode(const uint8_t *__restrict__ src, int64_t n,
                                                         uint8_t *__restrict__ dst, DecMap map,
                                                         const int64_t *__restrict__ prefix,
-                                                        int64_t TS, uint32_t flags)
+                                                        int64_t TS, uint32_t flags,
+                                                        int64_t *__restrict__ mode,
+                                                        int64_t *__restrict__ first_pad,
+                                                        int64_t *__restrict__ first_bad)
 {
     __shared__ uint32_t s_map[64];
     __shared__ __align__(16) uint8_t stage[kWsBlock / 64][kWaveRound];
     __shared__ __align__(16) uint8_t vbuf[kWsBlock / 64 * kWsBuf];
+    if (CHECK ? *mode != 1 : *mode == 1) return;    // uniform
     stage_dec_map(s_map, map);
     const uint8_t *m = (const uint8_t *)s_map;
     const int64_t ntiles = ws_tiles(n, TS);
@@ -772,14 +858,18 @@ __global__ __launch_bounds__(kWsBlock) void k_ws_decode(const uint8_t *__restric
     const int wo = wv * kWsBuf;                   // this wave's value buffer
     uint8_t *const cb = vbuf + wo;
     const int64_t nwaves = (int64_t)gridDim.x * (kWsBlock / 64);
+    if (CHECK) {
+        // the checked decode ORs every group it reads back, stale ones too:
+        // start from zeros, so that only this launch's values are seen
+        for (int i = 16 * lane; i < kWsBuf; i += 16 * 64) *(u32x4 *)(cb + i) = u32x4{0u, 0u, 0u, 0u};
+    }
 
     for (int64_t tile = logical_block() * (kWsBlock / 64) + wv; tile < ntiles; tile += nwaves) {
         const int64_t base = tile * TS, end = base + TS < n ? base + TS : n;
         const int64_t K0 = prefix[tile], C = prefix[tile + 1] - K0;
         const int64_t skip = (4 - (K0 & 3)) & 3;
-        if (C <= skip) continue;                     // wave-uniform
         const int64_t Q0 = (K0 + skip) >> 2;
-        if (Q0 >= qlimit) continue;
+        if (C <= skip || Q0 >= qlimit) continue;    // wave-uniform: no quantum of its own
         const int64_t h = (Q0 + 3 * dmod) & 3;
         // what the last quantum may borrow from the next tile, fetched early
         const bool has_next = tile + 1 < ntiles;
@@ -787,7 +877,7 @@ __global__ __launch_bounds__(kWsBlock) void k_ws_decode(const uint8_t *__restric
         const bool head_ok = has_next && base + TS + 16 <= n;
         u32x4 head = u32x4{0u, 0u, 0u, 0u};
         if (lane == 0 && head_ok) head = load16<false>(src + base + TS);
-        WsState S{16 + 4 * (int)h - (int)skip, Q0 - h, Q0, qlimit, {0u, 0u, 0u, 0u}, 1};
+        WsState S{16 + 4 * (int)h - (int)skip, Q0 - h, Q0, qlimit, {0u, 0u, 0u, 0u}, 1, 0u, 0};
         const uint8_t *const s0 = src + base + 16 * lane;
         // a full tile whose quanta (at most Q0 + C/4) all lie below qlimit
         const bool hot = end - base == TS && Q0 + C / 4 + 1 <= qlimit;
@@ -804,14 +894,14 @@ __global__ __launch_bounds__(kWsBlock) void k_ws_decode(const uint8_t *__restric
             for (; r < nr - D; r += D) {
 #pragma unroll
                 for (int d = 0; d < D; ++d) {
-                    ws_round<true, NT>(q[d], base + (int64_t)(r + d) * kWaveRound, end, st, m, vbuf, wo,
+                    ws_round<true, NT, CHECK>(q[d], base + (int64_t)(r + d) * kWaveRound, end, st, m, vbuf, wo,
                                        dst, S);
                     q[d] = load16<NT>(s0 + (int64_t)(r + d + D) * kWaveRound);
                 }
             }
 #pragma unroll
             for (int d = 0; d < D; ++d)
-                ws_round<true, NT>(q[d], base + (int64_t)(r + d) * kWaveRound, end, st, m, vbuf, wo, dst, S);
+                ws_round<true, NT, CHECK>(q[d], base + (int64_t)(r + d) * kWaveRound, end, st, m, vbuf, wo, dst, S);
             // the first group's quanta that are the tile's own
             if (S.held_k <= 0) {
 #pragma unroll
@@ -831,7 +921,7 @@ __global__ __launch_bounds__(kWsBlock) void k_ws_decode(const uint8_t *__restric
                     }
                     raw = u32x4{w[0], w[1], w[2], w[3]};
                 }
-                ws_round<false, NT>(raw, p0, end, st, m, vbuf, wo, dst, S);
+                ws_round<false, NT, CHECK>(raw, p0, end, st, m, vbuf, wo, dst, S);
             }
         }
         // fewer than 16 values left: whole quanta, then one quantum that may
@@ -852,12 +942,61 @@ __global__ __launch_bounds__(kWsBlock) void k_ws_decode(const uint8_t *__restric
                     const uint32_t v = idx < left ? cb[16 + idx] : (extra >> (8 * (idx - left))) & 0xFF;
                     w |= v << (8 * k);
                 }
+                if (CHECK) S.err |= w;
                 if (qq >= Q0 && qq < qlimit) store3(dst + 3 * qq, ws_quantum(w));
             }
+        }
+        if (CHECK && tile + 1 < ntiles) {
+            const bool fail = S.cnt != C || __ballot(S.err & 0x80808080u) != 0;
+            if (fail && lane == 0)
+                __hip_atomic_store(mode, (int64_t)0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+}
+
+// k_ws_check: after the checked decode (only when *mode is still 1), the
+// tiles it left other than the last (k_ws_predict scans that one): those with
+// no quantum of their own are counted against their guessed counts and
+// scanned for the first invalid character and '=', as k_ws_count would.  A wave looks at
+// 64 tiles at once, one per lane, and works through the ones that qualify.
+__global__ __launch_bounds__(kWsBlock) void k_ws_check(const uint8_t *__restrict__ src, int64_t n,
+                                                       DecMap map, const int64_t *__restrict__ prefix,
+                                                       int64_t TS, uint32_t flags,
+                                                       int64_t *__restrict__ mode,
+                                                       int64_t *__restrict__ first_pad,
+                                                       int64_t *__restrict__ first_bad)
+{
+    __shared__ uint32_t s_map[64];
+    if (*mode != 1) return;                       // uniform
+    stage_dec_map(s_map, map);
+    const uint8_t *m = (const uint8_t *)s_map;
+    const int64_t ntiles = ws_tiles(n, TS);
+    if (ntiles == 0) return;
+    const int64_t total = prefix[ntiles];
+    const bool nopad = (flags & kFlagNoPad) != 0;
+    const int64_t qlimit = nopad ? total / 4 : (total >= 4 ? total / 4 - 1 : 0);
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int64_t nwaves = (int64_t)gridDim.x * (kWsBlock / 64);
+    for (int64_t t0 = ((int64_t)blockIdx.x * (kWsBlock / 64) + wv) * 64; t0 < ntiles; t0 += nwaves * 64) {
+        const int64_t t = t0 + lane;
+        int64_t C = 0;
+        bool want = false;
+        if (t < ntiles) {
+            const int64_t K0 = prefix[t];
+            C = prefix[t + 1] - K0;
+            const int64_t skip = (4 - (K0 & 3)) & 3;
+            want = t + 1 < ntiles && (C <= skip || ((K0 + skip) >> 2) >= qlimit);
+        }
+        for (uint64_t b = __builtin_amdgcn_ballot_w64(want); b; b &= b - 1) {
+            const int l = __builtin_ctzll(b);
+            const int64_t tile = t0 + l;
+            const int64_t base = tile * TS, end = base + TS < n ? base + TS : n;
+            ws_check_tile(src, base, end, m, true, readlane_i64(C, l), mode, first_pad, first_bad);
+        }
     }
 }
 
@@ -997,11 +1136,109 @@ __global__ __launch_bounds__(kWsBlock) void k_ws_finish(const uint8_t *__restric
     }
 }
 
-__global__ void k_ws_init(int64_t *first_bad, int64_t *first_pad)
+__global__ void k_ws_init(int64_t *first_bad, int64_t *first_pad, int64_t *mode)
 {
     if (threadIdx.x == 0) {
         *first_bad = kNoError;
         *first_pad = kNoError;
+        *mode = 0;
+    }
+}
+
+// Significant characters before position p of text laid out in lines of L
+// significant characters, each followed by s whitespace bytes (P = L + s).
+// The quotient comes from a double division (exact for p < 2^53) and is then
+// corrected, which is cheaper on the GPU than a 64-bit integer division.
+__device__ __forceinline__ int64_t lined_before(int64_t p, int64_t L, int64_t P)
+{
+    int64_t q = (int64_t)((double)p / (double)P);
+    int64_t r = p - q * P;
+    if (r < 0) {
+        --q;
+        r += P;
+    } else if (r >= P) {
+        ++q;
+        r -= P;
+    }
+    return q * L + (r < L ? r : L);
+}
+
+// k_ws_predict: guessed tile prefix sums for text laid out in lines, as MIME
+// and PEM bodies are: lines of L significant characters, each followed by the
+// same s = 1 or 2 whitespace bytes (LF or CR LF), the last line shorter.
+// Every block takes L and s from the first line and writes the guess for its
+// share of the tiles, prefix[t] = lined_before(t*TS); block 0 checks one line
+// end per thread spread over the input, counts the last tile into
+// prefix[ntiles], records the last tile's first invalid byte and '=' as
+// k_ws_count would (the checked decode leaves that tile to it), and sets
+// *mode = 1 if the checks hold.  Otherwise *mode
+// stays 0 and k_ws_count and k_ws_scan overwrite the guess.  The guess has
+// prefix[t] <= t*TS and at most TS per tile, so the checked decode that uses
+// it stays inside its buffers however wrong it is.
+__global__ __launch_bounds__(kWsBlock) void k_ws_predict(const uint8_t *__restrict__ src, int64_t n,
+                                                         DecMap map, int64_t *__restrict__ prefix,
+                                                         int64_t TS, int64_t *__restrict__ mode,
+                                                         int64_t *__restrict__ first_pad,
+                                                         int64_t *__restrict__ first_bad)
+{
+    __shared__ uint32_t s_map[64];
+    __shared__ int s_first, s_ok, s_cnt, s_err;
+    stage_dec_map(s_map, map);
+    const uint8_t *m = (const uint8_t *)s_map;
+    const int tid = threadIdx.x;
+    const int64_t ntiles = ws_tiles(n, TS);
+    if (tid == 0) {
+        s_first = INT_MAX;
+        s_ok = 1;
+        s_cnt = 0;
+        s_err = 0;
+    }
+    __syncthreads();
+    if (ntiles < 2) return;
+    // block 0: the last tile's significant characters, and whether it holds
+    // a '=' or an invalid byte (loaded first, to overlap the line search)
+    const int64_t lb = (ntiles - 1) * TS;
+    if (blockIdx.x == 0) {
+        int c = 0;
+        uint32_t err = 0;
+        for (int64_t p = lb + 16 * tid; p < n; p += 16 * kWsBlock) {
+            const u32x4 cw = ws_codes<false>(src, n, p, m);
+            c += sig_count(cw);
+            err |= cw.x | cw.y | cw.z | cw.w;
+        }
+        atomicAdd(&s_cnt, c);
+        if (err & 0x80808080u) s_err = 1;
+    }
+    const int64_t look = n < 4096 ? n : 4096;
+    for (int64_t i = tid; i < look; i += kWsBlock)
+        if (!is_sig(m[src[i]])) atomicMin(&s_first, (int)i);
+    __syncthreads();
+    // the last tile's first invalid byte and '=', as k_ws_count records them
+    if (blockIdx.x == 0 && s_err && tid < 64) ws_rescan(src, lb, n, m, first_pad, first_bad);
+    const int64_t L = s_first;                   // the first line's length (uniform)
+    if (L == INT_MAX || L < 4 || L + 3 > look) return;
+    const bool w1 = !is_sig(m[src[L + 1]]), w2 = !is_sig(m[src[L + 2]]);   // src[L] is whitespace
+    const int64_t sep = !w1 ? 1 : (!w2 ? 2 : 3);
+    if (sep > 2) return;
+    const int64_t P = L + sep;
+    for (int64_t t = (int64_t)blockIdx.x * kWsBlock + tid; t < ntiles; t += (int64_t)gridDim.x * kWsBlock)
+        prefix[t] = lined_before(t * TS, L, P);
+    if (blockIdx.x != 0) return;
+    {   // line k's separator, and the characters on either side of it
+        const int64_t k = (n / P) * tid / kWsBlock;
+        const int64_t q = k * P + L;
+        if (q + sep < n) {
+            const uint32_t before = src[q - 1], s0 = src[q], s1 = src[q + 1], after = src[q + sep];
+            const bool ok = is_sig(m[before]) && !is_sig(m[s0]) && (sep == 1 || !is_sig(m[s1])) &&
+                            is_sig(m[after]);
+            if (!ok) s_ok = 0;
+        }
+    }
+    __syncthreads();
+    if (!s_ok) return;
+    if (tid == 0) {
+        prefix[ntiles] = lined_before(lb, L, P) + s_cnt;
+        *mode = 1;
     }
 }
 
@@ -1027,17 +1264,18 @@ int64_t ws_workspace_bytes(int64_t n)
 {
     const int64_t TS = ws_tile_size(n);
     const int64_t ntiles = n > 0 ? (n + TS - 1) / TS : 0;
-    return 8 * (ntiles + 2);
+    return 8 * (ntiles + 3);      // prefix sums, first '=', mode
 }
 
 namespace {
 
 template <int R>
 void launch_ws_count(const uint8_t *src, int64_t n, const DecMap &map, int64_t *prefix,
-                     int64_t *first_pad, int64_t *first_bad, int64_t grid, bool nt, hipStream_t stream)
+                     int64_t *first_pad, int64_t *first_bad, const int64_t *mode, int64_t grid, bool nt,
+                     hipStream_t stream)
 {
-    if (nt) hipLaunchKernelGGL((k_ws_count<R, true>), dim3(grid), dim3(kWsBlock), 0, stream, src, n, map, prefix, first_pad, first_bad);
-    else hipLaunchKernelGGL((k_ws_count<R, false>), dim3(grid), dim3(kWsBlock), 0, stream, src, n, map, prefix, first_pad, first_bad);
+    if (nt) hipLaunchKernelGGL((k_ws_count<R, true>), dim3(grid), dim3(kWsBlock), 0, stream, src, n, map, prefix, first_pad, first_bad, mode);
+    else hipLaunchKernelGGL((k_ws_count<R, false>), dim3(grid), dim3(kWsBlock), 0, stream, src, n, map, prefix, first_pad, first_bad, mode);
 }
 
 // Workgroups of `kernel` resident on one compute unit at once (1 if the
@@ -1059,21 +1297,35 @@ int resident_per_cu(K kernel, int *cache)
 // One wave per tile, tiles dealt grid-stride: the grid is at most the
 // workgroups that fit at once (blocks_per_cu caps it), so that no wave starts
 // after others have finished and the tiles are shared evenly.
-template <int D>
+template <int D, bool CHECK>
 void launch_ws_decode_tiles(const uint8_t *src, int64_t n, uint8_t *dst, const DecMap &map,
                             const int64_t *prefix, int64_t TS, int64_t ntiles, uint32_t flags,
-                            int bpc, int cus, bool nt, hipStream_t stream)
+                            int64_t *mode, int64_t *first_pad, int64_t *first_bad, int bpc, int cus,
+                            bool nt, hipStream_t stream)
 {
     static int fit[2] = {0, 0};
-    const int per_cu = nt ? resident_per_cu(k_ws_decode<D, true>, &fit[1])
-                          : resident_per_cu(k_ws_decode<D, false>, &fit[0]);
+    const int per_cu = nt ? resident_per_cu(k_ws_decode<D, true, CHECK>, &fit[1])
+                          : resident_per_cu(k_ws_decode<D, false, CHECK>, &fit[0]);
     int64_t grid = (int64_t)cus * (bpc < per_cu ? bpc : per_cu);
     const int64_t need = (ntiles + kWsBlock / 64 - 1) / (kWsBlock / 64);
     if (grid > need) grid = need;
     if (grid >= kXcds) grid -= grid % kXcds;
     if (grid < 1) grid = 1;
-    if (nt) hipLaunchKernelGGL((k_ws_decode<D, true>), dim3(grid), dim3(kWsBlock), 0, stream, src, n, dst, map, prefix, TS, flags);
-    else hipLaunchKernelGGL((k_ws_decode<D, false>), dim3(grid), dim3(kWsBlock), 0, stream, src, n, dst, map, prefix, TS, flags);
+    if (nt) hipLaunchKernelGGL((k_ws_decode<D, true, CHECK>), dim3(grid), dim3(kWsBlock), 0, stream, src, n, dst, map, prefix, TS, flags, mode, first_pad, first_bad);
+    else hipLaunchKernelGGL((k_ws_decode<D, false, CHECK>), dim3(grid), dim3(kWsBlock), 0, stream, src, n, dst, map, prefix, TS, flags, mode, first_pad, first_bad);
+}
+
+template <bool CHECK>
+void launch_ws_decode_shape(const uint8_t *src, int64_t n, uint8_t *dst, const DecMap &map,
+                            const int64_t *prefix, int64_t TS, int64_t ntiles, uint32_t flags,
+                            int64_t *mode, int64_t *first_pad, int64_t *first_bad, Shape sh, int cus,
+                            hipStream_t stream)
+{
+    switch (sh.unroll) {
+    case 1: launch_ws_decode_tiles<1, CHECK>(src, n, dst, map, prefix, TS, ntiles, flags, mode, first_pad, first_bad, sh.bpc, cus, sh.nt, stream); break;
+    case 4: launch_ws_decode_tiles<4, CHECK>(src, n, dst, map, prefix, TS, ntiles, flags, mode, first_pad, first_bad, sh.bpc, cus, sh.nt, stream); break;
+    default: launch_ws_decode_tiles<2, CHECK>(src, n, dst, map, prefix, TS, ntiles, flags, mode, first_pad, first_bad, sh.bpc, cus, sh.nt, stream); break;
+    }
 }
 
 }  // namespace
@@ -1086,27 +1338,37 @@ hipError_t launch_decode_ws(const uint8_t *src, int64_t n, uint8_t *dst, bool wr
     const int64_t ntiles = n > 0 ? (n + TS - 1) / TS : 0;
     int64_t *prefix = (int64_t *)workspace;      // ntiles + 1 words
     int64_t *first_pad = prefix + ntiles + 1;
-    hipLaunchKernelGGL(k_ws_init, dim3(1), dim3(64), 0, stream, first_bad, first_pad);
+    int64_t *mode = first_pad + 1;               // 1 while the guessed prefix sums hold
+    hipLaunchKernelGGL(k_ws_init, dim3(1), dim3(64), 0, stream, first_bad, first_pad, mode);
+    // a decode of text in regular lines first tries guessed prefix sums (no
+    // counting pass); every later launch checks *mode and does nothing when
+    // the checked decode succeeded
+    if (write && ntiles > 0) {
+        const int64_t pgrid = std::min<int64_t>((ntiles + kWsBlock - 1) / kWsBlock, 1024);
+        hipLaunchKernelGGL(k_ws_predict, dim3(pgrid), dim3(kWsBlock), 0, stream, src, n, map, prefix, TS, mode,
+                           first_pad, first_bad);
+        launch_ws_decode_shape<true>(src, n, dst, map, prefix, TS, ntiles, flags, mode, first_pad,
+                                     first_bad, sh, cus, stream);
+        const int64_t cgrid = std::min<int64_t>((ntiles + kWsBlock - 1) / kWsBlock, (int64_t)cus);
+        hipLaunchKernelGGL(k_ws_check, dim3(cgrid), dim3(kWsBlock), 0, stream, src, n, map, prefix, TS,
+                           flags, mode, first_pad, first_bad);
+    }
     int64_t grid = (int64_t)cus * sh.bpc;
     if (grid > ntiles) grid = ntiles;
     if (grid >= kXcds) grid -= grid % kXcds;
     if (grid < 1) grid = 1;
     if (ntiles > 0) {
         switch (TS / kRound) {
-        case 1: launch_ws_count<1>(src, n, map, prefix, first_pad, first_bad, grid, sh.nt, stream); break;
-        case 2: launch_ws_count<2>(src, n, map, prefix, first_pad, first_bad, grid, sh.nt, stream); break;
-        case 4: launch_ws_count<4>(src, n, map, prefix, first_pad, first_bad, grid, sh.nt, stream); break;
-        default: launch_ws_count<8>(src, n, map, prefix, first_pad, first_bad, grid, sh.nt, stream); break;
+        case 1: launch_ws_count<1>(src, n, map, prefix, first_pad, first_bad, mode, grid, sh.nt, stream); break;
+        case 2: launch_ws_count<2>(src, n, map, prefix, first_pad, first_bad, mode, grid, sh.nt, stream); break;
+        case 4: launch_ws_count<4>(src, n, map, prefix, first_pad, first_bad, mode, grid, sh.nt, stream); break;
+        default: launch_ws_count<8>(src, n, map, prefix, first_pad, first_bad, mode, grid, sh.nt, stream); break;
         }
     }
-    hipLaunchKernelGGL(k_ws_scan, dim3(1), dim3(kScanThreads), 0, stream, prefix, ntiles);
-    if (write && ntiles > 0) {
-        switch (sh.unroll) {
-        case 1: launch_ws_decode_tiles<1>(src, n, dst, map, prefix, TS, ntiles, flags, sh.bpc, cus, sh.nt, stream); break;
-        case 4: launch_ws_decode_tiles<4>(src, n, dst, map, prefix, TS, ntiles, flags, sh.bpc, cus, sh.nt, stream); break;
-        default: launch_ws_decode_tiles<2>(src, n, dst, map, prefix, TS, ntiles, flags, sh.bpc, cus, sh.nt, stream); break;
-        }
-    }
+    hipLaunchKernelGGL(k_ws_scan, dim3(1), dim3(kScanThreads), 0, stream, prefix, ntiles, mode);
+    if (write && ntiles > 0)
+        launch_ws_decode_shape<false>(src, n, dst, map, prefix, TS, ntiles, flags, mode, first_pad,
+                                      first_bad, sh, cus, stream);
     hipLaunchKernelGGL(k_ws_finish, dim3(1), dim3(kWsBlock), 0, stream, src, n, dst, map, TS, prefix,
                        first_pad, out_len, first_bad, flags, write ? 1 : 0);
     return hipGetLastError();

@@ -101,10 +101,10 @@ def test_variant_length_helpers_match_oracle(lib, oracle):
     assert lib.b64_encoded_len_mode(5, 0, -4) == EARG
     assert lib.b64_decoded_max_len_mode(5, 4) == EARG
     assert lib.b64_decode_workspace_size(-1, 2) == EARG
-    # workspace: 8 bytes per tile (4 KiB .. 32 KiB) plus 16
+    # workspace: 8 bytes per tile (4 KiB .. 32 KiB) plus 24
     big = 1 << 30
     ws = lib.b64_decode_workspace_size(big, 2)
-    assert 16 + 8 * (big // 32768) <= ws <= 16 + 8 * (big // 4096 + 1)
+    assert 24 + 8 * (big // 32768) <= ws <= 24 + 8 * (big // 4096 + 1)
 
 
 def test_argument_errors_without_gpu(lib):

@@ -263,6 +263,60 @@ def test_skip_ws_long_runs_at_the_edges(b64, oracle):
                  check_validate=(d == 1))
 
 
+def _lines(text: np.ndarray, L: int, sep: bytes) -> np.ndarray:
+    """`text` cut into lines of L characters joined by `sep`."""
+    parts = []
+    for i in range(0, text.size, L):
+        if i:
+            parts.append(np.frombuffer(sep, dtype=np.uint8))
+        parts.append(text[i:i + L])
+    return np.concatenate(parts) if parts else text[:0].copy()
+
+
+def test_skip_ws_regular_lines_and_breaks(b64, oracle):
+    """Text in regular lines takes the checked decode on guessed tile counts;
+    any break in the regularity must fall back to the counted path with the
+    same result.  Line layouts: 76 + CR LF, 64 + LF, 64 + CR LF, 10 + LF (not
+    a multiple of 4), lines longer than the first 4 KiB looked at; breaks: one
+    extra space, a missing separator, a doubled separator, in the first tile,
+    the middle and the last tile; invalid bytes, '=' and truncation inside
+    regular text; trailing separators and long trailing runs."""
+    x = workloads.random_bytes(workloads.SEED_BASE + 194, 120_000)
+    g = workloads.rng(workloads.SEED_BASE + 195)
+    for flags in (SKIP_WS, SKIP_WS | NOPAD):
+        plain = oracle.encode_mode(x, STD, flags & NOPAD)
+        for L, sep in ((76, b"\r\n"), (64, b"\n"), (64, b"\r\n"), (10, b"\n"), (5000, b"\r\n")):
+            t = _lines(plain, L, sep)
+            _dec(b64, oracle, t, STD, flags, f"lines {L} {sep!r}", check_validate=False)
+            _dec(b64, oracle, np.concatenate([t, np.frombuffer(sep, dtype=np.uint8)]), STD, flags,
+                 f"lines {L} trailing sep", check_validate=False)
+            for at in (300, t.size // 2, t.size - 700):
+                for kind in ("space", "missing", "double"):
+                    p = at
+                    while p < t.size and t[p] in b" \t\r\n":
+                        p += 1
+                    if kind == "space":
+                        u = np.concatenate([t[:p], np.frombuffer(b" ", np.uint8), t[p:]])
+                    else:
+                        q = int(np.nonzero(t[p:] == sep[-1])[0][0]) + p + 1 if (t[p:] == sep[-1]).any() else t.size
+                        s0 = q - len(sep)
+                        u = (np.concatenate([t[:s0], t[q:]]) if kind == "missing" else
+                             np.concatenate([t[:q], np.frombuffer(sep, np.uint8), t[q:]]))
+                    _dec(b64, oracle, u, STD, flags, f"lines {L} {kind} at {at}", check_validate=False)
+        t = _lines(plain, 76, b"\r\n")
+        for k in range(4):                     # invalid bytes and '=' in regular text
+            u = t.copy()
+            p = int(g.integers(0, u.size))
+            while u[p] in b"\r\n":
+                p += 1
+            u[p] = ord("*") if k % 2 == 0 else ord("=")
+            _dec(b64, oracle, u, STD, flags, f"lines 76 spoiled {k}", check_validate=False)
+        for cut in (1, 2, 3, 5):
+            _dec(b64, oracle, t[:-cut], STD, flags, f"lines 76 cut {cut}", check_validate=False)
+        _dec(b64, oracle, np.concatenate([t, np.full(70_000, ord(" "), np.uint8)]), STD, flags,
+             "lines 76 then a long run", check_validate=False)
+
+
 def test_skip_ws_async_status_and_graph(b64, oracle):
     import torch
     x = workloads.random_bytes(workloads.SEED_BASE + 186, 1 << 20)
