@@ -17,7 +17,7 @@
 // Whitespace-skipping decode.  The significant characters (all but space,
 // tab, CR, LF) form the encoding; their positions in the input depend on
 // every whitespace byte before them, so decoding is a stream compaction.
-// After a status reset (k_ws_init), four kernels, with no inter-block waiting:
+// After a status reset (k_ws_init), kernels with no inter-block waiting:
 //   k_ws_count   per tile of TS characters: the number of significant
 //                characters, and (atomic minima) the first invalid character
 //                and the first '='.
@@ -30,8 +30,14 @@
 //                from the following tiles.
 //   k_ws_finish  one block: the '=' and end-of-input rules over the sequence
 //                of significant characters, the final quantum, the status.
-// Tiles are dealt grid-stride (to blocks in k_ws_count, to waves in
-// k_ws_decode), so the grid streams through one window of memory.
+// Text in regular lines (MIME, PEM) skips the counting pass: k_ws_predict
+// guesses the prefix sums from the first line, k_ws_decode<.., true> decodes
+// with the guess and checks every tile's count, and k_ws_check covers the
+// tiles it leaves.  A failed check leaves *mode at 0, and k_ws_count,
+// k_ws_scan and k_ws_decode then run as above (each returns at once when the
+// checked decode succeeded).  Tiles are dealt grid-stride (to blocks in
+// k_ws_count, to waves in k_ws_decode), so the grid streams through one
+// window of memory.
 #include "b64_launch.h"
 
 namespace b64hip {
