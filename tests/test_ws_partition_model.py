@@ -184,3 +184,50 @@ def test_last_tile_full():
                 assert len(text) == n
                 for nopad in (False, True):
                     model(text, nopad, ts, trial % 4)
+
+
+# ---------------------------------------------------------------------------
+# Guessed prefix sums for text in regular lines (k_ws_predict): lines of L
+# significant characters, each followed by s whitespace bytes, P = L + s.
+
+def lined_before(p: int, L: int, P: int) -> int:
+    """The kernel's closed form, its quotient taken from a double division
+    and corrected, as on the GPU."""
+    q = int(float(p) / float(P))
+    r = p - q * P
+    if r < 0:
+        q, r = q - 1, r + P
+    elif r >= P:
+        q, r = q + 1, r - P
+    return q * L + min(r, L)
+
+
+@pytest.mark.parametrize("L,sep", [(4, 1), (10, 1), (64, 1), (64, 2), (76, 2), (1000, 2)])
+def test_lined_before_counts_significant_characters(L, sep):
+    g = workloads.rng(900 + L + sep)
+    nlines = 3000 // max(1, L // 16) + 5
+    sig = np.ones(nlines * (L + sep), dtype=bool)
+    for k in range(nlines):
+        sig[k * (L + sep) + L: (k + 1) * (L + sep)] = False
+    sig = sig[: sig.size - int(g.integers(0, L + sep))]          # a shorter last line
+    before = np.concatenate([[0], np.cumsum(sig)])
+    for p in list(range(0, min(sig.size + 1, 700))) + g.integers(0, sig.size + 1, 500).tolist():
+        assert lined_before(p, L, L + sep) == before[p], (p, L, sep)
+    # the guess of every tile: never past its position, at most a tile per tile
+    for ts in (4096, 32768):
+        pre = [lined_before(t * ts, L, L + sep) for t in range(sig.size // ts + 2)]
+        assert all(0 <= b - a <= ts for a, b in zip(pre, pre[1:]))
+        assert all(v <= t * ts for t, v in enumerate(pre))
+
+
+def test_lined_before_quotient_at_large_positions():
+    """The double-division quotient, after its correction, is the integer
+    floor for positions far past 2^32 (inputs of hundreds of GB)."""
+    g = workloads.rng(905)
+    for P in (5, 11, 66, 78, 1002, 4097):
+        L = P - 2
+        ps = np.concatenate([g.integers(0, 1 << 40, 2000), (np.arange(1, 200) * P) << 20,
+                             ((np.arange(1, 200) * P) << 20) - 1])
+        for p in ps.tolist():
+            q, r = divmod(p, P)
+            assert lined_before(p, L, P) == q * L + min(r, L), (p, P)
