@@ -1177,8 +1177,9 @@ __device__ __forceinline__ int64_t lined_before(int64_t p, int64_t L, int64_t P)
 // end per thread spread over the input, counts the last tile into
 // prefix[ntiles], records the last tile's first invalid byte and '=' as
 // k_ws_count would (the checked decode leaves that tile to it), and sets
-// *mode = 1 if the checks hold.  Otherwise *mode
-// stays 0 and k_ws_count and k_ws_scan overwrite the guess.  The guess has
+// *mode = 1 if the checks hold; block 0 first resets the status, as
+// k_ws_init does.  Otherwise *mode stays 0 and k_ws_count and k_ws_scan
+// overwrite the guess.  The guess has
 // prefix[t] <= t*TS and at most TS per tile, so the checked decode that uses
 // it stays inside its buffers however wrong it is.
 __global__ __launch_bounds__(kWsBlock) void k_ws_predict(const uint8_t *__restrict__ src, int64_t n,
@@ -1189,9 +1190,14 @@ __global__ __launch_bounds__(kWsBlock) void k_ws_predict(const uint8_t *__restri
 {
     __shared__ uint32_t s_map[64];
     __shared__ int s_first, s_ok, s_cnt, s_err;
+    const int tid = threadIdx.x;
+    if (blockIdx.x == 0 && tid == 0) {          // the status reset of k_ws_init
+        *first_bad = kNoError;
+        *first_pad = kNoError;
+        *mode = 0;
+    }
     stage_dec_map(s_map, map);
     const uint8_t *m = (const uint8_t *)s_map;
-    const int tid = threadIdx.x;
     const int64_t ntiles = ws_tiles(n, TS);
     if (tid == 0) {
         s_first = INT_MAX;
@@ -1345,10 +1351,11 @@ hipError_t launch_decode_ws(const uint8_t *src, int64_t n, uint8_t *dst, bool wr
     int64_t *prefix = (int64_t *)workspace;      // ntiles + 1 words
     int64_t *first_pad = prefix + ntiles + 1;
     int64_t *mode = first_pad + 1;               // 1 while the guessed prefix sums hold
-    hipLaunchKernelGGL(k_ws_init, dim3(1), dim3(64), 0, stream, first_bad, first_pad, mode);
-    // a decode of text in regular lines first tries guessed prefix sums (no
-    // counting pass); every later launch checks *mode and does nothing when
-    // the checked decode succeeded
+    // a decode first tries guessed prefix sums for text in regular lines (no
+    // counting pass; k_ws_predict also resets the status); every later launch
+    // checks *mode and does nothing when the checked decode succeeded
+    if (!(write && ntiles > 0))
+        hipLaunchKernelGGL(k_ws_init, dim3(1), dim3(64), 0, stream, first_bad, first_pad, mode);
     if (write && ntiles > 0) {
         const int64_t pgrid = std::min<int64_t>((ntiles + kWsBlock - 1) / kWsBlock, 1024);
         hipLaunchKernelGGL(k_ws_predict, dim3(pgrid), dim3(kWsBlock), 0, stream, src, n, map, prefix, TS, mode,
