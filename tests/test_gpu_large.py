@@ -172,3 +172,41 @@ def test_mime_past_4g(b64, oracle, big):
     assert b64.validate(text, flags=2) == (n, None)
     del text
     torch.cuda.empty_cache()
+
+
+def test_fused_rows_past_4g(b64, oracle):
+    """The fused consumer with 1,400,000 rows of 1,536 float32: 2.15 G
+    bfloat16 values (4.3 GB of output, element indices past 2^31, byte
+    offsets past 2^32) from 11.5 GB of base64.  Every row is compared on the
+    device with PyTorch's float32 -> bfloat16 conversion (NaN lanes aside,
+    whose rule the oracle pins); rows around the 2^31-element and 2^32-byte
+    marks and the last rows are compared with the oracle."""
+    import torch
+    dim, nrows = 1536, 1_400_000
+    say("large: fused input", nrows, dim)
+    nraw = nrows * dim * 4
+    block = to_dev(workloads.random_bytes(workloads.SEED_BASE + 280, PERIOD))
+    raw = block.repeat(-(-nraw // PERIOD))[:nraw]
+    del block
+    in_off = torch.arange(0, nrows + 1, dtype=torch.int64, device="cuda") * (4 * dim)
+    text, t_off, _ = b64.encode_batch(raw, in_off)
+    del in_off
+    say("large: fused decode")
+    out, st = b64.decode_f32_bf16(text, t_off, dim)
+    assert (st == -1).all().item()
+    f = raw.view(torch.float32).view(nrows, dim)
+    for r0 in range(0, nrows, 100_000):
+        blk = f[r0: r0 + 100_000]
+        ref = blk.to(torch.bfloat16).view(torch.int16)
+        got = out[r0: r0 + 100_000].view(torch.int16)
+        ok = (got == ref) | torch.isnan(blk)
+        assert ok.all().item(), r0
+    tt = to_host(t_off)
+    for b in ((1 << 31) // dim, (1 << 32) // (2 * dim), (1 << 32) // (2 * dim) + 1, nrows - 1):
+        row = to_host(text[int(tt[b]): int(tt[b + 1])])
+        ref, rst = oracle.decode_f32_bf16_rows(row, np.array([0, row.size], dtype=np.int64), dim)
+        assert rst.tolist() == [-1]
+        got = to_host(out[b].view(torch.int16)).view(np.uint16)
+        assert (got == ref.reshape(-1)).all(), b
+    del raw, text, out, f
+    torch.cuda.empty_cache()
