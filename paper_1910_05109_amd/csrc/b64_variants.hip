@@ -1211,12 +1211,23 @@ __global__ __launch_bounds__(kWsBlock) void k_ws_predict(const uint8_t *__restri
     // a '=' or an invalid byte (loaded first, to overlap the line search)
     const int64_t lb = (ntiles - 1) * TS;
     if (blockIdx.x == 0) {
+        // all of a thread's loads first (the tile is at most kMaxRounds rounds)
+        u32x4 q[kMaxRounds];
+#pragma unroll
+        for (int k = 0; k < kMaxRounds; ++k) {
+            const int64_t p = lb + 16 * tid + (int64_t)k * kRound;
+            q[k] = p + 16 <= n ? load16<false>(src + p) : u32x4{0u, 0u, 0u, 0u};
+        }
         int c = 0;
         uint32_t err = 0;
-        for (int64_t p = lb + 16 * tid; p < n; p += 16 * kWsBlock) {
-            const u32x4 cw = ws_codes<false>(src, n, p, m);
-            c += sig_count(cw);
-            err |= cw.x | cw.y | cw.z | cw.w;
+#pragma unroll
+        for (int k = 0; k < kMaxRounds; ++k) {
+            const int64_t p = lb + 16 * tid + (int64_t)k * kRound;
+            if (p < n) {
+                const u32x4 cw = p + 16 <= n ? codes16(q[k], m) : ws_codes<false>(src, n, p, m);
+                c += sig_count(cw);
+                err |= cw.x | cw.y | cw.z | cw.w;
+            }
         }
         atomicAdd(&s_cnt, c);
         if (err & 0x80808080u) s_err = 1;
