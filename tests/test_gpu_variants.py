@@ -311,6 +311,15 @@ def test_skip_ws_regular_lines_and_breaks(b64, oracle):
                 p += 1
             u[p] = ord("*") if k % 2 == 0 else ord("=")
             _dec(b64, oracle, u, STD, flags, f"lines 76 spoiled {k}", check_validate=False)
+        for back in (50, 100, 1000, 3000):    # in the last tile, which k_ws_predict scans
+            for c in (ord("*"), ord("=")):
+                u = t.copy()
+                p = u.size - back
+                while u[p] in b"\r\n":
+                    p += 1
+                u[p] = c
+                _dec(b64, oracle, u, STD, flags, f"lines 76 byte {c} at end-{back}",
+                     check_validate=False)
         for cut in (1, 2, 3, 5):
             _dec(b64, oracle, t[:-cut], STD, flags, f"lines 76 cut {cut}", check_validate=False)
         _dec(b64, oracle, np.concatenate([t, np.full(70_000, ord(" "), np.uint8)]), STD, flags,
