@@ -326,6 +326,31 @@ def test_skip_ws_regular_lines_and_breaks(b64, oracle):
              "lines 76 then a long run", check_validate=False)
 
 
+@pytest.mark.parametrize("n", [32_000_000, 72_000_000], ids=["tiles_8k", "tiles_16k"])
+def test_skip_ws_regular_lines_mid_sizes(b64, oracle, n):
+    """MIME text of 43.8 MB and 98.5 MB, which the decoder cuts into tiles of
+    8 and 16 KiB (the other sizes test 4 and 32 KiB tiles): regular lines on
+    the checked path, and breaks that send it to the counted path: a trailing
+    separator, one extra space, an invalid byte and a '=' inside the text, an
+    invalid byte in the last tile, a cut final quantum."""
+    x = workloads.random_bytes(workloads.SEED_BASE + 196, n)
+    t = _mime(oracle, x)
+    assert (32 << 20) <= t.size < (64 << 20) if n < 50_000_000 else (64 << 20) <= t.size < (128 << 20)
+    cases = [("regular", t), ("trailing sep", np.concatenate([t, np.frombuffer(b"\r\n", np.uint8)]))]
+    mid = t.size // 2 + 1001
+    cases.append(("space", np.concatenate([t[:mid], np.frombuffer(b" ", np.uint8), t[mid:]])))
+    for label, p, c in (("invalid", t.size // 3 + 17, ord("*")), ("pad", 3 * t.size // 4 + 5, ord("=")),
+                        ("invalid last tile", t.size - 100, ord("!"))):
+        u = t.copy()
+        while u[p] in b"\r\n":
+            p += 1
+        u[p] = c
+        cases.append((label, u))
+    cases.append(("cut", t[:-2]))
+    for label, u in cases:
+        _dec(b64, oracle, u, STD, SKIP_WS, f"mid size {n} {label}", check_validate=(label == "space"))
+
+
 def test_skip_ws_async_status_and_graph(b64, oracle):
     import torch
     x = workloads.random_bytes(workloads.SEED_BASE + 186, 1 << 20)
@@ -372,8 +397,8 @@ def test_skip_ws_async_status_and_graph(b64, oracle):
 
 
 def test_skip_ws_large(b64, oracle):
-    """A 256 MiB payload as MIME text (about 354 MB): several thousand tiles of
-    16-64 KiB."""
+    """A 256 MiB payload as MIME text (about 354 MB): about 10,800 tiles of
+    32 KiB."""
     x = workloads.random_bytes(workloads.SEED_BASE + 188, 256 << 20)
     text = _mime(oracle, x)
     say("skip_ws large", text.size)
