@@ -242,6 +242,13 @@ constexpr int kWsBlock = 256;            // threads per block of the tile kernel
 constexpr int64_t kRound = kWsBlock * 16;   // characters per block round
 constexpr int kMaxRounds = 8;            // rounds per tile at most (tiles of 4 .. 32 KiB)
 
+// The mode word in the decode workspace: kModeCounted, the counted path
+// (k_ws_count, k_ws_scan, k_ws_decode) runs; kModeChecked, k_ws_decode<.., true>
+// and k_ws_check run on guessed prefix sums; kModeLines | s << 2 | L << 4,
+// k_ws_lines runs for lines of L significant characters and s separator
+// bytes.  A failed check sets it back to kModeCounted.
+constexpr int64_t kModeCounted = 0, kModeChecked = 1, kModeLines = 2;
+
 __device__ __forceinline__ bool is_sig(uint32_t code) { return !(code & kWsCode); }
 
 // Four codes of a dword of characters, packed as bytes.
@@ -314,7 +321,7 @@ __global__ __launch_bounds__(kWsBlock) void k_ws_count(const uint8_t *__restrict
     constexpr int64_t TS = R * kRound;
     __shared__ uint32_t s_map[64];
     __shared__ int s_sum;
-    if (*mode == 1) return;
+    if (*mode != kModeCounted) return;
     stage_dec_map(s_map, map);
     const uint8_t *m = (const uint8_t *)s_map;
     const int64_t ntiles = ws_tiles(n, TS);
@@ -400,7 +407,7 @@ __global__ __launch_bounds__(kScanThreads) void k_ws_scan(int64_t *__restrict__ 
     __shared__ int s_wave[kScanRows][kW];        // wave totals, then their exclusive sums
     __shared__ int64_t s_row[kScanRows];          // rows' exclusive offsets
     __shared__ int64_t s_carry;
-    if (*mode == 1) return;                       // the guessed sums were exact
+    if (*mode != kModeCounted) return;            // the guessed sums were exact
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     if (threadIdx.x == 0) {
         prefix[0] = 0;
@@ -829,7 +836,7 @@ __device__ void ws_check_tile(const uint8_t *src, int64_t base, int64_t end, con
 // a wave keeps the loads of its next D rounds in flight.
 //
 // CHECK: the checked decode that runs on k_ws_predict's guessed prefix sums
-// (*mode == 1; it returns at once otherwise).  Every tile it decodes, but the
+// (*mode == kModeChecked; it returns at once otherwise).  Every tile it decodes, but the
 // last, compares the significant characters it saw with its guessed count,
 // and clears *mode on a difference or on any '=' or invalid character (the
 // counting path then finds them).  The last tile and the tiles with no
@@ -849,7 +856,7 @@ __global__ __launch_bounds__(kWsBlock) void k_ws_decode(const uint8_t *__restric
     __shared__ uint32_t s_map[64];
     __shared__ __align__(16) uint8_t stage[kWsBlock / 64][kWaveRound];
     __shared__ __align__(16) uint8_t vbuf[kWsBlock / 64 * kWsBuf];
-    if (CHECK ? *mode != 1 : *mode == 1) return;    // uniform
+    if (*mode != (CHECK ? kModeChecked : kModeCounted)) return;    // uniform
     stage_dec_map(s_map, map);
     const uint8_t *m = (const uint8_t *)s_map;
     const int64_t ntiles = ws_tiles(n, TS);
@@ -963,7 +970,7 @@ __global__ __launch_bounds__(kWsBlock) void k_ws_decode(const uint8_t *__restric
     }
 }
 
-// k_ws_check: after the checked decode (only when *mode is still 1), the
+// k_ws_check: after the checked decode (only when *mode is still kModeChecked), the
 // tiles it left other than the last (k_ws_predict scans that one): those with
 // no quantum of their own are counted against their guessed counts and
 // scanned for the first invalid character and '=', as k_ws_count would.  A wave looks at
@@ -976,7 +983,7 @@ __global__ __launch_bounds__(kWsBlock) void k_ws_check(const uint8_t *__restrict
                                                        int64_t *__restrict__ first_bad)
 {
     __shared__ uint32_t s_map[64];
-    if (*mode != 1) return;                       // uniform
+    if (*mode != kModeChecked) return;            // uniform
     stage_dec_map(s_map, map);
     const uint8_t *m = (const uint8_t *)s_map;
     const int64_t ntiles = ws_tiles(n, TS);
@@ -1176,15 +1183,18 @@ __device__ __forceinline__ int64_t lined_before(int64_t p, int64_t L, int64_t P)
 // share of the tiles, prefix[t] = lined_before(t*TS); block 0 checks one line
 // end per thread spread over the input, counts the last tile into
 // prefix[ntiles], records the last tile's first invalid byte and '=' as
-// k_ws_count would (the checked decode leaves that tile to it), and sets
-// *mode = 1 if the checks hold; block 0 first resets the status, as
-// k_ws_init does.  Otherwise *mode stays 0 and k_ws_count and k_ws_scan
-// overwrite the guess.  The guess has
+// k_ws_count would (the checked decode leaves that tile to it), and, if the
+// checks hold, sets *mode to kModeLines (L a multiple of 4, at least 16, and
+// the final quantum at or past the last tile, as far as the guess tells) or
+// else to kModeChecked; block 0 first resets the status, as k_ws_init does.
+// Otherwise *mode stays kModeCounted and k_ws_count and k_ws_scan overwrite
+// the guess.  The guess has
 // prefix[t] <= t*TS and at most TS per tile, so the checked decode that uses
 // it stays inside its buffers however wrong it is.
 __global__ __launch_bounds__(kWsBlock) void k_ws_predict(const uint8_t *__restrict__ src, int64_t n,
                                                          DecMap map, int64_t *__restrict__ prefix,
-                                                         int64_t TS, int64_t *__restrict__ mode,
+                                                         int64_t TS, uint32_t flags,
+                                                         int64_t *__restrict__ mode,
                                                          int64_t *__restrict__ first_pad,
                                                          int64_t *__restrict__ first_bad)
 {
@@ -1260,9 +1270,179 @@ __global__ __launch_bounds__(kWsBlock) void k_ws_predict(const uint8_t *__restri
     __syncthreads();
     if (!s_ok) return;
     if (tid == 0) {
-        prefix[ntiles] = lined_before(lb, L, P) + s_cnt;
-        *mode = 1;
+        const int64_t total = lined_before(lb, L, P) + s_cnt;
+        prefix[ntiles] = total;
+        // the final quantum's first character, where the layout puts it
+        const int64_t ql = (flags & kFlagNoPad) ? total / 4 : (total >= 4 ? total / 4 - 1 : 0);
+        const int64_t jq = 4 * ql;
+        const bool lines = L % 4 == 0 && L >= 16 && (jq / L) * P + jq % L >= lb;
+        *mode = lines ? (kModeLines | sep << 2 | L << 4) : kModeChecked;
     }
+}
+
+// k_ws_lines: the decode of text in regular lines (*mode = kModeLines | s << 2
+// | L << 4, L a multiple of 4 and at least 16) straight from the layout, with
+// no compaction: significant character j lies at (j div L)*P + j mod L, so a
+// quantum is four adjacent bytes of one line.  A lane takes a group of four
+// quanta (16 characters -> 12 bytes): one 16-byte load at the group's
+// position and the dword after it; when a line ends inside the group, the
+// characters past the separator are shifted down over it (v_alignbyte).  The
+// kernel checks what the layout claims, byte by byte: every character of a
+// quantum below qlimit decodes to a value (no whitespace, '=' or invalid
+// byte), and the s bytes after every line end it passes are whitespace.
+// k_ws_predict chose this path only when quantum qlimit lies at or past the
+// last tile, so these bytes are all of the text before the last tile, which
+// k_ws_predict counted exactly: when no check fails, every guessed prefix sum
+// is exact, the output is the plain decode's, and k_ws_finish adds the final
+// quantum.  Any failure sets *mode to kModeCounted, and the counted path
+// decodes everything again.
+//
+// Group g covers quanta 4g - h .. 4g - h + 3 and writes 12 bytes at
+// dst + 12g - 3h; h < 128 makes that 128-byte aligned for g a multiple of 32,
+// so a wave's 64 stores fill six whole cache lines.  Step k of the grid
+// (S lanes) takes groups kS .. kS + S - 1, lane-contiguous.  Steps whose
+// groups all have four quanta below qlimit and 20 readable bytes run
+// pipelined, D steps of loads in flight; a lane tracks its position
+// incrementally (no division per group).  The first and last steps take
+// each group through a guarded path.
+template <int D, bool NT>
+__global__ __launch_bounds__(kWsBlock) void k_ws_lines(const uint8_t *__restrict__ src, int64_t n,
+                                                       uint8_t *__restrict__ dst, DecMap map,
+                                                       const int64_t *__restrict__ prefix, int64_t TS,
+                                                       uint32_t flags, int64_t *__restrict__ mode)
+{
+    __shared__ uint32_t s_map[64];
+    const int64_t md = *mode;
+    if ((md & 3) != kModeLines) return;          // uniform
+    stage_dec_map(s_map, map);
+    const uint8_t *m = (const uint8_t *)s_map;
+    const int64_t L = md >> 4, s = (md >> 2) & 3, P = L + s;
+    const int64_t ntiles = ws_tiles(n, TS);
+    const int64_t total = prefix[ntiles];
+    const bool nopad = (flags & kFlagNoPad) != 0;
+    const int64_t qlimit = nopad ? total / 4 : (total >= 4 ? total / 4 - 1 : 0);
+    const int64_t h = (((int64_t)(uintptr_t)dst & 127) * 43) & 127;   // 3h = dst (mod 128)
+    const int64_t G = (qlimit + h + 3) / 4;       // groups with a quantum below qlimit
+    const int64_t g_lo = (h + 3) / 4;             // first group with no quantum below 0
+    const int64_t g_full = (qlimit + h) / 4;      // groups below it: four quanta below qlimit
+    // groups below g_read: bytes [position, position + 20) lie in the text
+    // (position <= x exactly when lined_before(x + 1) > 16g - 4h)
+    const int64_t g_read = (lined_before(n - 19, L, P) + 4 * h) / 16;
+    const int64_t g_hi = g_full < g_read ? g_full : g_read;
+    const int64_t S = (int64_t)gridDim.x * kWsBlock;
+    const int64_t gid = logical_block() * kWsBlock + threadIdx.x;
+    const int64_t k_lo = (g_lo + S - 1) / S;
+    const int64_t k_hi = g_hi / S > k_lo ? g_hi / S : k_lo;
+    const int64_t nmain = (k_hi - k_lo) - (k_hi - k_lo) % D;
+    bool bad = false;
+    uint32_t err = 0;
+
+    // the group whose 20 bytes from its position are q and t (column c):
+    // its 12 bytes; a separator that is not whitespace sets bit 7 of err
+    const int Li = (int)L;
+    const uint32_t sb = (uint32_t)s;
+    const bool two = s == 2;
+    auto group = [&](u32x4 q, uint32_t t, int c, uint8_t *o) {
+        const int rem = Li - c;                    // characters to the line end: 4, 8, ...
+        u32x4 v;
+        v.x = q.x;
+        v.y = rem <= 4 ? __builtin_amdgcn_alignbyte(q.z, q.y, sb) : q.y;
+        v.z = rem <= 8 ? __builtin_amdgcn_alignbyte(q.w, q.z, sb) : q.z;
+        v.w = rem <= 12 ? __builtin_amdgcn_alignbyte(t, q.w, sb) : q.w;
+        uint32_t sw = t;                           // the dword that starts with the separator
+        sw = rem <= 12 ? q.w : sw;
+        sw = rem <= 8 ? q.z : sw;
+        sw = rem <= 4 ? q.y : sw;
+        const uint32_t c0 = m[sw & 0xFF], c1 = m[(sw >> 8) & 0xFF];
+        const bool sep_bad = (c0 != kWsCode) | (two & (c1 != kWsCode));
+        err |= (uint32_t)((rem <= 16) & sep_bad) << 7;
+        store12<NT>(o, dec_chunk(v, m, err));
+    };
+    // any group, each quantum on its own, every byte read checked against n
+    auto edge = [&](int64_t g) {
+        for (int k = 0; k < 4; ++k) {
+            const int64_t qq = 4 * g - h + k;
+            if (qq < 0 || qq >= qlimit) continue;
+            const int64_t j = 4 * qq, l = j / L, c = j - l * L, p = l * P + c;
+            if (p + 4 > n) {
+                bad = true;
+                continue;
+            }
+            const uint32_t w = (uint32_t)src[p] | ((uint32_t)src[p + 1] << 8) |
+                               ((uint32_t)src[p + 2] << 16) | ((uint32_t)src[p + 3] << 24);
+            const uint32_t v = dec_quantum(w, m, err);
+            uint8_t *const o = dst + 3 * qq;
+            o[0] = (uint8_t)(v >> 16);
+            o[1] = (uint8_t)(v >> 8);
+            o[2] = (uint8_t)v;
+            if (c + 4 == L) {
+                if (p + 4 + s > n) bad = true;
+                else if (m[src[p + 4]] != kWsCode || (s == 2 && m[src[p + 5]] != kWsCode)) bad = true;
+            }
+        }
+    };
+    // a group of an edge step: the vector path if it qualifies
+    auto one = [&](int64_t g) {
+        if (g >= g_lo && g < g_hi) {
+            const int64_t j = 16 * g - 4 * h, l = j / L, c = j - l * L, p = l * P + c;
+            group(load16<NT>(src + p), *(const u32a1 *)(src + p + 16), (int)c, dst + 3 * (j / 4));
+        } else if (g < G) {
+            edge(g);
+        }
+    };
+
+    for (int64_t k = 0; k < k_lo; ++k) one(k * S + gid);
+    if (nmain > 0) {
+        // position (pn, cn) of the next step's group to load; each step moves
+        // it by 16 S characters: dl lines and dc columns, one more line (s
+        // more bytes) when the column passes L
+        const int64_t dj = 16 * S, dl = dj / L, dp = dl * P + (dj - dl * L);
+        const int dc = (int)(dj - dl * L);
+        const int64_t j0 = 16 * (k_lo * S + gid) - 4 * h, l0 = j0 / L;
+        int cn = (int)(j0 - l0 * L);
+        int64_t pn = l0 * P + cn;
+        uint8_t *o = dst + 3 * (j0 / 4);
+        const int64_t dout = 12 * S;
+        u32x4 q[D];
+        uint32_t t[D];
+        int cq[D];
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            q[d] = load16<NT>(src + pn);
+            t[d] = *(const u32a1 *)(src + pn + 16);
+            cq[d] = cn;
+            pn += dp;
+            cn += dc;
+            if (cn >= Li) {
+                cn -= Li;
+                pn += s;
+            }
+        }
+        for (int64_t i = 0; i < nmain - D; i += D) {
+#pragma unroll
+            for (int d = 0; d < D; ++d) {
+                group(q[d], t[d], cq[d], o);
+                o += dout;
+                q[d] = load16<NT>(src + pn);
+                t[d] = *(const u32a1 *)(src + pn + 16);
+                cq[d] = cn;
+                pn += dp;
+                cn += dc;
+                if (cn >= Li) {
+                    cn -= Li;
+                    pn += s;
+                }
+            }
+        }
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            group(q[d], t[d], cq[d], o);
+            o += dout;
+        }
+    }
+    for (int64_t k = k_lo + nmain; k * S < G; ++k) one(k * S + gid);
+    if (__ballot(bad || (err & 0xC0u) != 0) && (threadIdx.x & 63) == 0)
+        __hip_atomic_store(mode, kModeCounted, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 }  // namespace
@@ -1338,6 +1518,21 @@ void launch_ws_decode_tiles(const uint8_t *src, int64_t n, uint8_t *dst, const D
     else hipLaunchKernelGGL((k_ws_decode<D, false, CHECK>), dim3(grid), dim3(kWsBlock), 0, stream, src, n, dst, map, prefix, TS, flags, mode, first_pad, first_bad);
 }
 
+// k_ws_lines on the workgroups resident at once (grid-stride steps).
+void launch_ws_lines(const uint8_t *src, int64_t n, uint8_t *dst, const DecMap &map, const int64_t *prefix,
+                     int64_t TS, uint32_t flags, int64_t *mode, int bpc, int cus, bool nt, hipStream_t stream)
+{
+    constexpr int D = 4;
+    static int fit[2] = {0, 0};
+    const int per_cu = nt ? resident_per_cu(k_ws_lines<D, true>, &fit[1])
+                          : resident_per_cu(k_ws_lines<D, false>, &fit[0]);
+    int64_t grid = (int64_t)cus * (bpc < per_cu ? bpc : per_cu);
+    if (grid >= kXcds) grid -= grid % kXcds;
+    if (grid < 1) grid = 1;
+    if (nt) hipLaunchKernelGGL((k_ws_lines<D, true>), dim3(grid), dim3(kWsBlock), 0, stream, src, n, dst, map, prefix, TS, flags, mode);
+    else hipLaunchKernelGGL((k_ws_lines<D, false>), dim3(grid), dim3(kWsBlock), 0, stream, src, n, dst, map, prefix, TS, flags, mode);
+}
+
 template <bool CHECK>
 void launch_ws_decode_shape(const uint8_t *src, int64_t n, uint8_t *dst, const DecMap &map,
                             const int64_t *prefix, int64_t TS, int64_t ntiles, uint32_t flags,
@@ -1361,16 +1556,17 @@ hipError_t launch_decode_ws(const uint8_t *src, int64_t n, uint8_t *dst, bool wr
     const int64_t ntiles = n > 0 ? (n + TS - 1) / TS : 0;
     int64_t *prefix = (int64_t *)workspace;      // ntiles + 1 words
     int64_t *first_pad = prefix + ntiles + 1;
-    int64_t *mode = first_pad + 1;               // 1 while the guessed prefix sums hold
+    int64_t *mode = first_pad + 1;               // kModeCounted, kModeChecked or kModeLines | ...
     // a decode first tries guessed prefix sums for text in regular lines (no
     // counting pass; k_ws_predict also resets the status); every later launch
-    // checks *mode and does nothing when the checked decode succeeded
+    // checks *mode and does nothing unless it names that launch's path
     if (!(write && ntiles > 0))
         hipLaunchKernelGGL(k_ws_init, dim3(1), dim3(64), 0, stream, first_bad, first_pad, mode);
     if (write && ntiles > 0) {
         const int64_t pgrid = std::min<int64_t>((ntiles + kWsBlock - 1) / kWsBlock, 1024);
-        hipLaunchKernelGGL(k_ws_predict, dim3(pgrid), dim3(kWsBlock), 0, stream, src, n, map, prefix, TS, mode,
-                           first_pad, first_bad);
+        hipLaunchKernelGGL(k_ws_predict, dim3(pgrid), dim3(kWsBlock), 0, stream, src, n, map, prefix, TS, flags,
+                           mode, first_pad, first_bad);
+        launch_ws_lines(src, n, dst, map, prefix, TS, flags, mode, sh.bpc, cus, sh.nt, stream);
         launch_ws_decode_shape<true>(src, n, dst, map, prefix, TS, ntiles, flags, mode, first_pad,
                                      first_bad, sh, cus, stream);
         const int64_t cgrid = std::min<int64_t>((ntiles + kWsBlock - 1) / kWsBlock, (int64_t)cus);

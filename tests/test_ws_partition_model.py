@@ -231,3 +231,97 @@ def test_lined_before_quotient_at_large_positions():
         for p in ps.tolist():
             q, r = divmod(p, P)
             assert lined_before(p, L, P) == q * L + min(r, L), (p, P)
+
+
+def lines_model(text: bytes, L: int, s: int, qlimit: int, h: int, S: int, D: int = 4):
+    """The work split of the line decode (the kernel for text in lines of L
+    significant characters, L a multiple of 4 and at least 16, each followed
+    by s separator bytes): group g covers quanta 4g - h .. 4g - h + 3; step k
+    takes groups kS .. kS + S - 1.  Returns {quantum: 4 characters} as the
+    kernel reads them, after checking every load against the text's end and
+    the incremental positions against the closed form."""
+    n, P = len(text), L + s
+    G = (qlimit + h + 3) // 4
+    g_lo, g_full = (h + 3) // 4, (qlimit + h) // 4
+    g_read = (lined_before(n - 19, L, P) + 4 * h) // 16
+    g_hi = min(g_full, g_read)
+    k_lo = (g_lo + S - 1) // S
+    k_hi = max(g_hi // S, k_lo)
+    nmain = (k_hi - k_lo) - (k_hi - k_lo) % D
+    got = {}
+
+    def pos(j):
+        return (j // L) * P + j % L
+
+    def vector_group(g, p, c):
+        assert g_lo <= g < g_hi and 0 <= p and p + 20 <= n      # the 16 + 4 bytes loaded
+        w = text[p:p + 20]
+        rem = L - c
+        chars = w[:16] if rem > 12 else w[:rem] + w[rem + s:16 + s]
+        if rem <= 16:
+            assert all(b in WS for b in w[rem:rem + s])         # the separator the kernel checks
+        for k in range(4):
+            qq = 4 * g - h + k
+            assert 0 <= qq < qlimit and qq not in got
+            got[qq] = chars[4 * k:4 * k + 4]
+
+    def edge_group(g):
+        for k in range(4):
+            qq = 4 * g - h + k
+            if 0 <= qq < qlimit:
+                p = pos(4 * qq)
+                assert p + 4 <= n and qq not in got
+                got[qq] = text[p:p + 4]
+
+    def one(g):
+        if g_lo <= g < g_hi:
+            j = 16 * g - 4 * h
+            vector_group(g, pos(j), j % L)
+        elif g < G:
+            edge_group(g)
+
+    for lane in range(S):
+        for k in range(k_lo):
+            one(k * S + lane)
+        if nmain > 0:
+            dj = 16 * S
+            dl, dc = divmod(dj, L)
+            dp = dl * P + dc
+            j0 = 16 * (k_lo * S + lane) - 4 * h
+            pn, cn = pos(j0), j0 % L
+            for i in range(nmain):
+                g = (k_lo + i) * S + lane
+                assert (pn, cn) == (pos(16 * g - 4 * h), (16 * g - 4 * h) % L)
+                vector_group(g, pn, cn)
+                pn, cn = pn + dp, cn + dc
+                if cn >= L:
+                    cn, pn = cn - L, pn + s
+        k = k_lo + nmain
+        while k * S < G:
+            one(k * S + lane)
+            k += 1
+    return got
+
+
+@pytest.mark.parametrize("L,s", [(76, 2), (64, 1), (16, 2), (20, 1), (1000, 2)])
+def test_line_decode_split(L, s):
+    """Every quantum below qlimit is read exactly once, from its own four
+    characters, with every load inside the text, for several destination
+    alignments (h), grid sizes and text lengths, the final quantum padded
+    and trailing separators included."""
+    g = workloads.rng(workloads.SEED_BASE + 197)
+    alpha = b"ABCDEFGHIJKLMNOPQRSTUVWXYZabcdefghijklmnopqrstuvwxyz0123456789+/"
+    sep = b"\r\n"[2 - s:]
+    for trial in range(12):
+        n_sig = int(g.integers(300, 6000)) * 4
+        body = bytes(alpha[int(c)] for c in g.integers(0, 64, n_sig))
+        lines = [body[i:i + L] for i in range(0, n_sig, L)]
+        text = sep.join(lines) + (sep if trial % 3 == 0 else b"")
+        total = n_sig
+        qlimit = total // 4 - 1
+        h = int(g.integers(0, 128))
+        S = int(g.choice([64, 128, 256, 512]))
+        got = lines_model(text, L, s, qlimit, h, S)
+        assert sorted(got) == list(range(qlimit))
+        for qq, chars in got.items():
+            assert chars == body[4 * qq:4 * qq + 4], (L, s, trial, qq)
