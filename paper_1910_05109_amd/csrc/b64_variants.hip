@@ -31,11 +31,14 @@
 //   k_ws_finish  one block: the '=' and end-of-input rules over the sequence
 //                of significant characters, the final quantum, the status.
 // Text in regular lines (MIME, PEM) skips the counting pass: k_ws_predict
-// guesses the prefix sums from the first line, k_ws_decode<.., true> decodes
-// with the guess and checks every tile's count, and k_ws_check covers the
-// tiles it leaves.  A failed check leaves *mode at 0, and k_ws_count,
-// k_ws_scan and k_ws_decode then run as above (each returns at once when the
-// checked decode succeeded).  Tiles are dealt grid-stride (to blocks in
+// guesses the prefix sums from the first line and picks a path in the mode
+// word.  For lines whose length is a multiple of 4 (16 or more), k_ws_lines
+// reads every quantum at its closed-form position and checks each byte
+// against the layout; other line lengths take k_ws_decode<.., true>, which
+// decodes on the guessed sums and checks every tile's count, with k_ws_check
+// covering the tiles it leaves.  A failed check sets the mode word back to
+// the counted path, and k_ws_count, k_ws_scan and k_ws_decode then run as
+// above (every launch returns at once unless the mode word names its path).  Tiles are dealt grid-stride (to blocks in
 // k_ws_count, to waves in k_ws_decode), so the grid streams through one
 // window of memory.
 #include "b64_launch.h"
