@@ -1521,14 +1521,15 @@ void launch_ws_decode_tiles(const uint8_t *src, int64_t n, uint8_t *dst, const D
     else hipLaunchKernelGGL((k_ws_decode<D, false, CHECK>), dim3(grid), dim3(kWsBlock), 0, stream, src, n, dst, map, prefix, TS, flags, mode, first_pad, first_bad);
 }
 
-// k_ws_lines with 16 steps of loads in flight per lane (256 VGPRs) on two
-// workgroups per compute unit, a shape of its own: on 1 GiB of MIME text it
-// took 0.49 ms per call against 0.50-0.51 ms for 2 or 4 steps in flight and
-// 0.53-0.54 ms with four workgroups per compute unit (grid-stride steps).
+// k_ws_lines with 12 steps of loads in flight per lane on two workgroups per
+// compute unit, a shape of its own: on 1 GiB of MIME text it took 0.484 ms
+// per call, against 0.488-0.492 ms for 14 or 16 steps, 0.50 ms for 2, 4 or
+// 10, 0.54 ms for 8, and 0.53-0.54 ms for 4 steps on four workgroups per
+// compute unit (grid-stride steps).
 void launch_ws_lines(const uint8_t *src, int64_t n, uint8_t *dst, const DecMap &map, const int64_t *prefix,
                      int64_t TS, uint32_t flags, int64_t *mode, int cus, bool nt, hipStream_t stream)
 {
-    constexpr int D = 16, bpc = 2;
+    constexpr int D = 12, bpc = 2;
     static int fit[2] = {0, 0};
     const int per_cu = nt ? resident_per_cu(k_ws_lines<D, true>, &fit[1])
                           : resident_per_cu(k_ws_lines<D, false>, &fit[0]);
