@@ -351,6 +351,27 @@ def test_skip_ws_regular_lines_mid_sizes(b64, oracle, n):
         _dec(b64, oracle, u, STD, SKIP_WS, f"mid size {n} {label}", check_validate=(label == "space"))
 
 
+def test_skip_ws_regular_lines_output_offsets(b64, oracle):
+    """The line decode aligns its stores by the destination's address mod 128:
+    a 98.5 MB MIME text (enough for several pipelined steps of the whole grid)
+    decoded into outputs at offsets 0..127 (mod 128) gives the payload, and
+    the bytes before and after the output stay untouched."""
+    import torch
+    n = 72_000_000
+    x = workloads.random_bytes(workloads.SEED_BASE + 198, n)
+    dx = to_dev(x)
+    text = b64.encode(dx, STD, line_len=workloads.MIME_LINE)
+    cap = b64.decoded_max_len(text.numel(), SKIP_WS)
+    buf = torch.zeros(cap + 256, dtype=torch.uint8, device="cuda")
+    for off in (1, 5, 17, 42, 64, 100, 127, 128):
+        say("lines output offset", off)
+        buf.zero_()
+        out, st = b64.decode_async(text, STD, out=buf[off:], flags=SKIP_WS)
+        assert to_host(st).tolist() == [n, -1], off
+        assert torch.equal(buf[off:off + n], dx), off
+        assert not buf[:off].any().item() and not buf[off + n:].any().item(), off
+
+
 def test_skip_ws_async_status_and_graph(b64, oracle):
     import torch
     x = workloads.random_bytes(workloads.SEED_BASE + 186, 1 << 20)
