@@ -347,6 +347,19 @@ def test_skip_ws_regular_lines_mid_sizes(b64, oracle, n):
         u[p] = c
         cases.append((label, u))
     cases.append(("cut", t[:-2]))
+    # breaks that the sampled line ends do not see (the layout is restored a
+    # few lines later): only the byte-by-byte check of the line decode can
+    # find them, and the counted path must then give the oracle's result
+    P = workloads.MIME_LINE + 2
+    k = (t.size // P) // 2 + 7                  # a line in the middle, no sample on it
+    cr = k * P + workloads.MIME_LINE            # its CR
+    assert t[cr] == ord("\r") and t[cr + 1] == ord("\n")
+    sp = (k + 3) * P + workloads.MIME_LINE      # three lines later
+    cases.append(("resync", np.concatenate([t[:cr], t[cr + 1:sp], np.frombuffer(b" ", np.uint8), t[sp:]])))
+    u = t.copy()
+    u[cr] = ord("A")                            # a separator byte made significant ...
+    u[cr + P + 5] = ord(" ")                    # ... and a character of the next line whitespace
+    cases.append(("swap", u))
     for label, u in cases:
         _dec(b64, oracle, u, STD, SKIP_WS, f"mid size {n} {label}", check_validate=(label == "space"))
 
