@@ -1245,9 +1245,23 @@ __global__ __launch_bounds__(kWsBlock) void k_ws_predict(const uint8_t *__restri
         atomicAdd(&s_cnt, c);
         if (err & 0x80808080u) s_err = 1;
     }
+    // the first whitespace byte of the first 4 KiB: 16 bytes per thread
     const int64_t look = n < 4096 ? n : 4096;
-    for (int64_t i = tid; i < look; i += kWsBlock)
-        if (!is_sig(m[src[i]])) atomicMin(&s_first, (int)i);
+    {
+        const int64_t p = 16 * (int64_t)tid;
+        int first = INT_MAX;
+        if (p + 16 <= look) {
+            const u32x4 c = codes16(load16<false>(src + p), m);
+            const uint32_t w[4] = {c.x, c.y, c.z, c.w};
+#pragma unroll
+            for (int j = 15; j >= 0; --j)
+                if (!is_sig((w[j >> 2] >> (8 * (j & 3))) & 0xFFu)) first = (int)p + j;
+        } else {
+            for (int64_t i = p + 15; i >= p; --i)
+                if (i < look && !is_sig(m[src[i]])) first = (int)i;
+        }
+        if (first != INT_MAX) atomicMin(&s_first, first);
+    }
     __syncthreads();
     // the last tile's first invalid byte and '=', as k_ws_count records them
     if (blockIdx.x == 0 && s_err && tid < 64) ws_rescan(src, lb, n, m, first_pad, first_bad);
