@@ -325,3 +325,54 @@ def test_line_decode_split(L, s):
         assert sorted(got) == list(range(qlimit))
         for qq, chars in got.items():
             assert chars == body[4 * qq:4 * qq + 4], (L, s, trial, qq)
+
+
+def test_line_decode_eligibility_is_safe():
+    """When the guess picks the line decode (L a multiple of 4, at least 16,
+    and the final quantum at or past the last tile as far as the guessed total
+    goes), the bytes the line decode checks (every character of a quantum
+    below qlimit and the separator after every line end it passes) cover all
+    of the text before the last tile.  So either they all fit the layout and
+    the guessed total is the true one, or one of them does not and the kernel
+    falls back.  Regular texts followed by whitespace runs of every size
+    around a tile, some with an extra space inside, and tiles of 4 KiB."""
+    g = workloads.rng(workloads.SEED_BASE + 199)
+    alpha = b"ABCDEFGHIJKLMNOPQRSTUVWXYZabcdefghijklmnopqrstuvwxyz0123456789+/"
+    picked = fell_back = 0
+    for trial in range(300):
+        L = int(g.choice([16, 20, 64, 76]))
+        s = int(g.integers(1, 3))
+        sep = b"\r\n"[2 - s:]
+        n_sig = int(g.integers(1500, 4000)) * 4
+        body = bytes(alpha[int(c)] for c in g.integers(0, 64, n_sig))
+        text = sep.join(body[i:i + L] for i in range(0, n_sig, L))
+        text += b" " * int(g.choice([0, 1, 2, 100, 4000, 4096, 5000, 9000, 20000]))
+        if trial % 3 == 0:                      # a break in the layout
+            at = int(g.integers(0, len(text) // 2))
+            text = text[:at] + b" " + text[at:]
+        n, P, ts = len(text), L + s, 4096
+        ntiles = (n + ts - 1) // ts
+        if ntiles < 2:
+            continue
+        lb = (ntiles - 1) * ts
+        total = lined_before(lb, L, P) + sum(1 for c in text[lb:] if c not in WS)
+        ql = total // 4 - 1
+        jq = 4 * ql
+        if not ((jq // L) * P + jq % L >= lb):
+            continue
+        picked += 1
+        checked = {}
+        for j in range(4 * ql):
+            p = (j // L) * P + j % L
+            checked[p] = "char"
+            if j % L == L - 1:
+                for k in range(s):
+                    checked[p + 1 + k] = "sep"
+        assert all(p in checked for p in range(lb)), (L, s, trial)
+        fits = all(p < n and ((text[p] in WS) == (kind == "sep")) for p, kind in checked.items())
+        true_total = sum(1 for c in text if c not in WS)
+        if fits:
+            assert total == true_total, (L, s, trial)
+        else:
+            fell_back += 1
+    assert picked > 100 and fell_back > 0
