@@ -364,6 +364,26 @@ def test_skip_ws_regular_lines_mid_sizes(b64, oracle, n):
         _dec(b64, oracle, u, STD, SKIP_WS, f"mid size {n} {label}", check_validate=(label == "space"))
 
 
+@pytest.mark.parametrize("name", ["url", "hi"])
+def test_skip_ws_regular_lines_alphabets(b64, oracle, name):
+    """The line decode's checks go through the alphabet's map: MIME text of a
+    30 MB payload (41 MB, enough for the pipelined steps) in the URL-safe
+    alphabet and in one of 64 arbitrary bytes, padded and unpadded, clean and
+    with a byte outside the alphabet planted past the middle."""
+    alpha = _alphabets()[name]
+    x = workloads.random_bytes(workloads.SEED_BASE + 200, 30_000_000)
+    outside = [c for c in range(256) if c not in alpha and c not in b"= \t\r\n"]
+    for flags in (SKIP_WS, SKIP_WS | NOPAD):
+        t = _mime(oracle, x, alpha, flags & NOPAD)
+        assert _dec(b64, oracle, t, alpha, flags, f"{name} lines", check_validate=False) == x.size
+        u = t.copy()
+        p = 2 * t.size // 3 + 11
+        while u[p] in b"\r\n":
+            p += 1
+        u[p] = outside[len(outside) // 2]
+        _dec(b64, oracle, u, alpha, flags, f"{name} lines invalid at {p}", check_validate=False)
+
+
 def test_skip_ws_regular_lines_output_offsets(b64, oracle):
     """The line decode aligns its stores by the destination's address mod 128:
     a 98.5 MB MIME text (enough for several pipelined steps of the whole grid)
