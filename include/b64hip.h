@@ -245,6 +245,14 @@ int64_t b64_tune_set(int op, int unroll, int blocks_per_cu, int nontemporal);
 /* Current shape of `op` packed as nontemporal*10000 + unroll*100 +
  * blocks_per_cu, or B64_EARG.                                                */
 int64_t b64_tune_get(int op);
+/* Whitespace-skipping decode (B64_SKIP_WS): texts of at least `min_chars`
+ * bytes first try decoding as regular lines (the guess), shorter ones count
+ * their whitespace straight away.  min_chars >= 0 sets the size, a negative
+ * value only reads it; returns the size in force before the call (default
+ * 14 MiB, where the two paths cost the same on MI355X).  Process-wide, for the
+ * autotuner and for tests that want either path on small texts.  Does not
+ * change results.  Not a paper operation: a launch-policy knob.              */
+int64_t b64_tune_ws_guess_min(int64_t min_chars);
 
 /* Message for the last B64_EARG / B64_EHIP returned on this thread.          */
 const char *b64_last_error(void);

@@ -44,7 +44,7 @@ SKIP_WS = 2
 __all__ = ["STD", "URL", "NOPAD", "SKIP_WS", "B64Error", "load", "encoded_len", "decoded_max_len",
            "workspace_size", "encode",
            "decode", "decode_async", "validate", "validate_async", "encode_batch", "decode_batch",
-           "decode_f32_bf16", "tune_set", "tune_get", "stream_ptr"]
+           "decode_f32_bf16", "tune_set", "tune_get", "tune_ws_guess_min", "stream_ptr"]
 
 
 # The wrappers below sit on the launch path of every call, so they keep their
@@ -396,6 +396,13 @@ def decode_f32_bf16(src, in_off, dim: int, alphabet=STD, dst=None, status=None, 
 
 def tune_set(op: str, unroll: int, blocks_per_cu: int, nontemporal: int = 1) -> None:
     check(load().b64_tune_set(OPS[op], unroll, blocks_per_cu, int(nontemporal)), "b64_tune_set")
+
+
+def tune_ws_guess_min(min_chars: int = -1) -> int:
+    """Size in bytes from which the whitespace-skipping decode tries the
+    regular-line guess; sets it when min_chars >= 0.  Returns the previous
+    size."""
+    return int(load().b64_tune_ws_guess_min(int(min_chars)))
 
 
 def tune_get(op: str) -> tuple[int, int, int]:

@@ -45,6 +45,7 @@ SIGNATURES = {
     "b64_pipeline_decode": ([_P, _P, _I64, _P, _P], _I64),
     "b64_pipeline_last_error": ([], ctypes.c_char_p),
     "b64_tune_set": ([_INT, _INT, _INT, _INT], _I64),
+    "b64_tune_ws_guess_min": ([_I64], _I64),
     "b64_tune_get": ([_INT], _I64),
     "b64_last_error": ([], ctypes.c_char_p),
 }

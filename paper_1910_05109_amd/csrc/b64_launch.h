@@ -56,7 +56,7 @@ int64_t ws_tile_size(int64_t n);
 int64_t ws_workspace_bytes(int64_t n);
 hipError_t launch_decode_ws(const uint8_t *src, int64_t n, uint8_t *dst, bool write, const DecMap &map,
                             int64_t *out_len, int64_t *first_bad, uint32_t flags, void *workspace,
-                            Shape sh, int cus, hipStream_t stream);
+                            Shape sh, int cus, int64_t guess_min, hipStream_t stream);
 
 }  // namespace b64hip
 

@@ -1571,7 +1571,7 @@ void launch_ws_decode_shape(const uint8_t *src, int64_t n, uint8_t *dst, const D
 
 hipError_t launch_decode_ws(const uint8_t *src, int64_t n, uint8_t *dst, bool write, const DecMap &map,
                             int64_t *out_len, int64_t *first_bad, uint32_t flags, void *workspace,
-                            Shape sh, int cus, hipStream_t stream)
+                            Shape sh, int cus, int64_t guess_min, hipStream_t stream)
 {
     const int64_t TS = ws_tile_size(n);
     const int64_t ntiles = n > 0 ? (n + TS - 1) / TS : 0;
@@ -1580,10 +1580,13 @@ hipError_t launch_decode_ws(const uint8_t *src, int64_t n, uint8_t *dst, bool wr
     int64_t *mode = first_pad + 1;               // kModeCounted, kModeChecked or kModeLines | ...
     // a decode first tries guessed prefix sums for text in regular lines (no
     // counting pass; k_ws_predict also resets the status); every later launch
-    // checks *mode and does nothing unless it names that launch's path
-    if (!(write && ntiles > 0))
+    // checks *mode and does nothing unless it names that launch's path.
+    // Texts shorter than guess_min take the counted path alone: there the
+    // guess's three extra launches cost more than the counting pass.
+    const bool guess = write && ntiles > 0 && n >= guess_min;
+    if (!guess)
         hipLaunchKernelGGL(k_ws_init, dim3(1), dim3(64), 0, stream, first_bad, first_pad, mode);
-    if (write && ntiles > 0) {
+    if (guess) {
         const int64_t pgrid = std::min<int64_t>((ntiles + kWsBlock - 1) / kWsBlock, 1024);
         hipLaunchKernelGGL(k_ws_predict, dim3(pgrid), dim3(kWsBlock), 0, stream, src, n, map, prefix, TS, flags,
                            mode, first_pad, first_bad);

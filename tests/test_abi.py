@@ -40,7 +40,7 @@ def test_header_declares_the_boundary():
         "b64_decode_f32_bf16",
         "b64_pipeline_create", "b64_pipeline_destroy", "b64_pipeline_encode",
         "b64_pipeline_decode", "b64_pipeline_last_error",
-        "b64_tune_set", "b64_tune_get", "b64_last_error"}
+        "b64_tune_set", "b64_tune_get", "b64_tune_ws_guess_min", "b64_last_error"}
     assert set(data) == {"b64_alphabet_std", "b64_alphabet_url"}
 
 
@@ -182,3 +182,9 @@ def test_tuning_interface(lib):
     assert lib.b64_tune_get(0) == 10816
     assert lib.b64_tune_set(0, (old // 100) % 100, old % 100, old // 10000) == 0
     assert lib.b64_tune_get(0) == old
+    # the whitespace decode's guess threshold: default, set, read, restore
+    assert lib.b64_tune_ws_guess_min(-1) == 14 << 20
+    assert lib.b64_tune_ws_guess_min(0) == 14 << 20
+    assert lib.b64_tune_ws_guess_min(-5) == 0
+    assert lib.b64_tune_ws_guess_min(14 << 20) == 0
+    assert lib.b64_tune_ws_guess_min(-1) == 14 << 20

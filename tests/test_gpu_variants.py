@@ -26,12 +26,17 @@ def _alphabets():
 
 @pytest.fixture(scope="module")
 def b64():
+    """The library, with the regular-line guess of the whitespace-skipping
+    decode tried at every size (by default only texts of 14 MiB and more try
+    it), so that the small texts here reach every path."""
     import torch
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     import paper_1910_05109_amd as b64
     b64.load()
-    return b64
+    old = b64.tune_ws_guess_min(0)
+    yield b64
+    b64.tune_ws_guess_min(old)
 
 
 def _dev(a):
@@ -382,6 +387,26 @@ def test_skip_ws_regular_lines_alphabets(b64, oracle, name):
             p += 1
         u[p] = outside[len(outside) // 2]
         _dec(b64, oracle, u, alpha, flags, f"{name} lines invalid at {p}", check_validate=False)
+
+
+def test_skip_ws_default_guess_threshold(b64, oracle):
+    """With the default threshold, regular lines below 14 MiB take the counted
+    path and those above the guess: both give the oracle's bytes, clean and
+    with an invalid byte, padded and unpadded."""
+    old = b64.tune_ws_guess_min(-1)
+    b64.tune_ws_guess_min(14 << 20)
+    try:
+        x = workloads.random_bytes(workloads.SEED_BASE + 201, 12_000_000)
+        for n in (100_000, 3_000_000, 12_000_000):
+            for flags in (SKIP_WS, SKIP_WS | NOPAD):
+                t = _mime(oracle, x[:n], STD, flags & NOPAD)
+                assert _dec(b64, oracle, t, STD, flags, f"default threshold {n}",
+                            check_validate=False) == n
+                u = t.copy()
+                u[t.size // 2] = ord("*") if u[t.size // 2] not in b"\r\n" else u[t.size // 2]
+                _dec(b64, oracle, u, STD, flags, f"default threshold {n} invalid", check_validate=False)
+    finally:
+        b64.tune_ws_guess_min(old)
 
 
 def test_skip_ws_regular_lines_output_offsets(b64, oracle):
