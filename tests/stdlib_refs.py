@@ -18,6 +18,7 @@ import itertools
 import numpy as np
 
 STD = b"ABCDEFGHIJKLMNOPQRSTUVWXYZabcdefghijklmnopqrstuvwxyz0123456789+/"
+WS = b" \t\r\n"
 
 
 def translator(alpha: bytes) -> bytes:
@@ -140,3 +141,50 @@ def brute_force_results(symbols: list[int], length: int, alpha: bytes = STD):
         pads = (rows[:, -2:] == ord("=")).sum(axis=1) if length else np.zeros(nrows, dtype=np.int64)
         expected[full] = 3 * (length // 4) - pads[full]
     return rows, expected
+
+
+# ------------------------------------------------------------- variants --
+# References for the unpadded, line-wrapped and whitespace-skipping forms,
+# built from the standard-library codec and the prefix rule above.
+
+def ref_nopad(x: bytes, alpha: bytes) -> bytes:
+    return base64.b64encode(x).rstrip(b"=").translate(translator(alpha))
+
+
+def ref_wrap(text: bytes, line_len: int) -> bytes:
+    return b"\r\n".join(text[i:i + line_len] for i in range(0, len(text), line_len))
+
+
+def nopad_reference(s: bytes, alpha: bytes) -> int:
+    """Decoded length, or ~first_invalid_offset, from the standard library."""
+    chars = set(alpha)
+    for i, c in enumerate(s):
+        if c not in chars:
+            return ~i
+    n = len(s)
+    if n % 4 == 1:
+        return ~n
+    std = s.translate(bytes.maketrans(alpha, STD))
+    d = base64.b64decode(std + b"=" * ((4 - n % 4) % 4), validate=True)
+    if base64.b64encode(d).rstrip(b"=") != std:
+        return ~n          # non-canonical trailing bits: could still be completed
+    return len(d)
+
+
+def compacted(s: bytes):
+    keep = [i for i, c in enumerate(s) if c not in WS]
+    return bytes(s[i] for i in keep), keep
+
+
+_RULES = {}
+
+
+def skip_ws_reference(s: bytes, alpha: bytes, nopad: bool) -> int:
+    c, keep = compacted(s)
+    if not nopad and alpha not in _RULES:
+        _RULES[alpha] = PrefixRule(alpha)
+    r = nopad_reference(c, alpha) if nopad else _RULES[alpha].result(c)
+    if r >= 0:
+        return r
+    off = ~r
+    return ~(keep[off] if off < len(c) else len(s))

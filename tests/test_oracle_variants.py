@@ -18,16 +18,15 @@ Each pin reduces the variant to something fixed outside the oracle:
   - flags 0 of the variant decoder == the base decoder (two formulations).
 """
 import base64
-import itertools
 
 import numpy as np
 import pytest
 
 import workloads
-from stdlib_refs import STD, PrefixRule, brute_force_results, translator
+from stdlib_refs import (STD, WS, brute_force_results, nopad_reference, ref_nopad, ref_wrap,
+                         skip_ws_reference)
 
 URL = b"ABCDEFGHIJKLMNOPQRSTUVWXYZabcdefghijklmnopqrstuvwxyz0123456789-_"
-WS = b" \t\r\n"
 
 
 def _alphabets():
@@ -36,14 +35,6 @@ def _alphabets():
     hi = bytes(sorted(rng.choice(np.array([c for c in range(256) if c != ord("=") and c not in WS]),
                                  64, replace=False).tolist()))
     return [STD, URL, perm, hi]
-
-
-def ref_nopad(x: bytes, alpha: bytes) -> bytes:
-    return base64.b64encode(x).rstrip(b"=").translate(translator(alpha))
-
-
-def ref_wrap(text: bytes, line_len: int) -> bytes:
-    return b"\r\n".join(text[i:i + line_len] for i in range(0, len(text), line_len))
 
 
 # ---------------------------------------------------------------- encode --
@@ -97,41 +88,6 @@ def test_encoded_len_mode_closed_form(oracle):
 
 
 # ---------------------------------------------------------------- decode --
-
-def nopad_reference(s: bytes, alpha: bytes) -> int:
-    """Decoded length, or ~first_invalid_offset, from the standard library."""
-    chars = set(alpha)
-    for i, c in enumerate(s):
-        if c not in chars:
-            return ~i
-    n = len(s)
-    if n % 4 == 1:
-        return ~n
-    std = s.translate(bytes.maketrans(alpha, STD))
-    d = base64.b64decode(std + b"=" * ((4 - n % 4) % 4), validate=True)
-    if base64.b64encode(d).rstrip(b"=") != std:
-        return ~n          # non-canonical trailing bits: could still be completed
-    return len(d)
-
-
-def compacted(s: bytes):
-    keep = [i for i, c in enumerate(s) if c not in WS]
-    return bytes(s[i] for i in keep), keep
-
-
-_RULES = {}
-
-
-def skip_ws_reference(s: bytes, alpha: bytes, nopad: bool) -> int:
-    c, keep = compacted(s)
-    if not nopad and alpha not in _RULES:
-        _RULES[alpha] = PrefixRule(alpha)
-    r = nopad_reference(c, alpha) if nopad else _RULES[alpha].result(c)
-    if r >= 0:
-        return r
-    off = ~r
-    return ~(keep[off] if off < len(c) else len(s))
-
 
 @pytest.mark.parametrize("length", range(0, 8))
 def test_nopad_decode_brute_force(oracle, length):
