@@ -70,14 +70,23 @@ int64_t b64_encode(const uint8_t *src, int64_t n, uint8_t *dst,
 /* Decode src[0..n) into dst (capacity b64_decoded_max_len(n)).  Blocking.
  * Returns the decoded length r >= 0 for a valid input, ~off (= -off-1) for an
  * invalid one (off as defined above), or B64_EARG / B64_EHIP (both below
- * -2^62).  (Section "Decoding".) */
+ * -2^62).  One kernel launch, whose last workgroup writes the status into
+ * pinned host memory of the calling thread; then `stream` is synchronized.
+ * (Section "Decoding".) */
 int64_t b64_decode(const uint8_t *src, int64_t n, uint8_t *dst,
                    const char *alphabet, hipStream_t stream);
 
 /* Decode, asynchronous form.  Results land in device memory once `stream`
  * reaches them: *out_len = decoded length (or -1 if invalid), *first_bad = -1
- * if valid (else the first invalid offset).  Returns 0 or B64_EARG /
- * B64_EHIP.  Safe to capture in a HIP graph.  (Section "Decoding".) */
+ * if valid (else the first invalid offset); their previous contents do not
+ * matter.  Returns 0 or B64_EARG / B64_EHIP.  One kernel launch: the
+ * library keeps a 32-byte status slot in device memory per stream handle
+ * (up to 4096 per device; the handle identifies the stream, and
+ * hipStreamPerThread gets a slot per host thread), which is back to zero
+ * after every call.  While `stream` captures a HIP graph, or once every slot
+ * is taken, the call is three launches that keep the status in *out_len /
+ * *first_bad alone (reset, decode, finish), so a captured graph may be
+ * replayed on any stream.  (Section "Decoding".) */
 int64_t b64_decode_async(const uint8_t *src, int64_t n, uint8_t *dst,
                          int64_t *out_len, int64_t *first_bad,
                          const char *alphabet, hipStream_t stream);
@@ -89,8 +98,9 @@ int64_t b64_decode_async(const uint8_t *src, int64_t n, uint8_t *dst,
  * memory traffic.  (Section "Decoding": the look-up-table validation.) */
 int64_t b64_validate(const uint8_t *src, int64_t n, const char *alphabet, hipStream_t stream);
 
-/* Validate, asynchronous form; results in device memory as for
- * b64_decode_async.  Returns 0 or B64_EARG / B64_EHIP.  (Section "Decoding".) */
+/* Validate, asynchronous form; results in device memory, launches and
+ * status slots as for b64_decode_async.  Returns 0 or B64_EARG / B64_EHIP.
+ * (Section "Decoding".) */
 int64_t b64_validate_async(const uint8_t *src, int64_t n, int64_t *out_len, int64_t *first_bad,
                            const char *alphabet, hipStream_t stream);
 

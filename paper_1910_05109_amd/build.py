@@ -7,6 +7,8 @@ from __future__ import annotations
 import os
 import subprocess
 import sys
+import tempfile
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
@@ -19,7 +21,7 @@ INCLUDE = os.path.join(ROOT, "include")
 ARCH = "gfx950"
 
 FLAGS = [
-    f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",
+    f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
     "-Wall", "-Wextra", "-Wno-unused-parameter",
     # no packed-FP32 instructions anywhere
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
@@ -33,11 +35,23 @@ def hipcc() -> str:
     return cand if os.path.exists(cand) else "hipcc"
 
 
-def build(extra: list[str] | None = None, out: str = LIB) -> str:
-    """Compile every HIP source of the package into `out` (always recompiles)."""
-    tmp = out + ".tmp"
-    cmd = [hipcc(), *FLAGS, *(extra or []), *SOURCES, "-o", tmp]
-    subprocess.check_call(cmd)
+def build(extra: list[str] | None = None, out: str = LIB, jobs: int | None = None) -> str:
+    """Compile every HIP source of the package into `out` (always recompiles):
+    one object per source, compiled in parallel, then linked."""
+    extra = list(extra or [])
+    jobs = jobs or min(len(SOURCES), max(1, min(os.cpu_count() or 1, 8)))
+    with tempfile.TemporaryDirectory(prefix="b64hip_build_") as tmpdir:
+        objs = [os.path.join(tmpdir, os.path.basename(src) + ".o") for src in SOURCES]
+
+        def compile_one(pair):
+            src, obj = pair
+            subprocess.check_call([hipcc(), *FLAGS, *extra, "-c", src, "-o", obj])
+
+        with ThreadPoolExecutor(max_workers=jobs) as pool:
+            list(pool.map(compile_one, zip(SOURCES, objs)))
+        tmp = out + ".tmp"
+        subprocess.check_call([hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", *extra,
+                               *objs, "-o", tmp])
     os.replace(tmp, out)
     return out
 

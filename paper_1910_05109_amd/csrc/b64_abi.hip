@@ -6,6 +6,7 @@
 
 #include <atomic>
 #include <mutex>
+#include <unordered_map>
 
 #include "b64_launch.h"
 #include "b64hip.h"
@@ -203,14 +204,64 @@ hipError_t ws_cache(int64_t bytes, void **out)
     return hipSuccess;
 }
 
+// Status slots of the single-launch decode / validation, one per stream and
+// device.  Work on one stream runs in order, so a stream's calls never
+// overlap and can share its slot; the slot is back to zero after each call.
+// Streams are never removed (a slot is 32 bytes of device memory); once all
+// kStatusSlots of a device are taken, further streams use the three-launch
+// form.  hipStreamPerThread names a different stream on every thread, so it
+// gets a slot per thread.
+struct SlotTable {
+    std::mutex mu;
+    std::unordered_map<hipStream_t, int> idx;
+    int next = 0;
+};
+SlotTable g_slot_tables[kMaxDevices];
+thread_local int g_per_thread_slot[kMaxDevices];   // slot index + 1, 0 = none yet
+
+// The status slot of `stream` on the current device, or nullptr when the
+// single-launch form is not used: while `stream` captures a graph (a graph
+// may be replayed on any stream, alongside direct calls, so a captured decode
+// keeps the status in the caller's words), or when every slot is taken.
+int64_t *stream_slot(hipStream_t stream)
+{
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(stream, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone)
+        return nullptr;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+    SlotTable &t = g_slot_tables[dev];
+    int idx = -1;
+    if (stream == hipStreamPerThread) {
+        if (!g_per_thread_slot[dev]) {
+            std::lock_guard<std::mutex> lk(t.mu);
+            if (t.next < kStatusSlots) g_per_thread_slot[dev] = ++t.next;
+        }
+        idx = g_per_thread_slot[dev] - 1;
+    } else {
+        std::lock_guard<std::mutex> lk(t.mu);
+        auto it = t.idx.find(stream);
+        if (it != t.idx.end()) {
+            idx = it->second;
+        } else if (t.next < kStatusSlots) {
+            idx = t.next++;
+            t.idx.emplace(stream, idx);
+        }
+    }
+    if (idx < 0) return nullptr;
+    int64_t *p = nullptr;
+    return status_slot_addr(idx, &p) == hipSuccess ? p : nullptr;
+}
+
 // Enqueue one single-buffer decode (`write`) or validation (!`write`, dst
-// unused).  Without B64_SKIP_WS: reset first_bad, run k_decode / k_validate,
-// and (with `finish`) turn the raw status into the public form.  With
-// B64_SKIP_WS the five-launch whitespace path always ends with the public
-// form.
+// unused), leaving the public status in *out_len / *first_bad.  Without
+// B64_SKIP_WS and with a status slot (`sslot`, from stream_slot) this is one
+// launch; without a slot it is three: reset first_bad, run k_decode /
+// k_validate, turn the raw status into the public form.  With B64_SKIP_WS the
+// whitespace path runs its own launches.
 int64_t decode_enqueue(const uint8_t *src, int64_t n, uint8_t *dst, bool write, int64_t *out_len,
                        int64_t *first_bad, const char *alphabet, uint32_t flags, void *workspace,
-                       hipStream_t stream, bool finish)
+                       int64_t *sslot, hipStream_t stream)
 {
     int cus = 0;
     hipError_t e = cu_count(&cus);
@@ -221,24 +272,28 @@ int64_t decode_enqueue(const uint8_t *src, int64_t n, uint8_t *dst, bool write, 
                              g_ws_guess_min.load(std::memory_order_relaxed), stream);
         return e == hipSuccess ? 0 : hip_fail(e, "whitespace decode launch");
     }
-    e = launch_fill(first_bad, 1, kNoError, stream);
-    if (e != hipSuccess) return hip_fail(e, "fill launch");
+    if (!sslot) {
+        e = launch_fill(first_bad, 1, kNoError, stream);
+        if (e != hipSuccess) return hip_fail(e, "fill launch");
+    }
+    const DecSink sink{out_len, first_bad, sslot};
     if (write)
-        e = launch_decode(src, n, dst, make_dec(alphabet), out_len, first_bad, flags, shape_of(1),
-                          cus, stream);
+        e = launch_decode(src, n, dst, make_dec(alphabet), sink, flags, shape_of(1), cus, stream);
     else
-        e = launch_validate(src, n, make_dec(alphabet), out_len, first_bad, flags, shape_of(4), cus,
-                            stream);
+        e = launch_validate(src, n, make_dec(alphabet), sink, flags, shape_of(4), cus, stream);
     if (e != hipSuccess) return hip_fail(e, write ? "decode launch" : "validate launch");
-    if (finish) {
+    if (!sslot) {
         e = launch_finish(out_len, first_bad, 1, stream);
         if (e != hipSuccess) return hip_fail(e, "status launch");
     }
     return 0;
 }
 
-// Blocking decode / validation through the per-thread status slot (and
-// workspace): returns the length, ~first_invalid_offset, or an error code.
+// Blocking decode / validation: returns the length, ~first_invalid_offset, or
+// an error code.  With a status slot the kernel writes the public status
+// straight into the per-thread pinned host words (one launch, then the
+// stream is synchronized); otherwise the status goes to the per-thread device
+// words and is copied back.
 int64_t decode_blocking(const uint8_t *src, int64_t n, uint8_t *dst, bool write,
                         const char *alphabet, uint32_t flags, hipStream_t stream)
 {
@@ -246,22 +301,25 @@ int64_t decode_blocking(const uint8_t *src, int64_t n, uint8_t *dst, bool write,
     hipError_t e = status_slot(&slot);
     if (e != hipSuccess) return hip_fail(e, "status slot");
     void *ws = nullptr;
+    int64_t *sslot = nullptr;
     if (flags & kFlagSkipWs) {
         e = ws_cache(ws_workspace_bytes(n), &ws);
         if (e != hipSuccess) return hip_fail(e, "workspace");
+    } else {
+        sslot = stream_slot(stream);
     }
-    // raw status (plain path): slot->d[0] = length if the tail is valid,
-    // slot->d[1] = the smallest invalid offset or kNoError.  The whitespace
-    // path leaves the public form (-1 for "valid" in slot->d[1]).
-    const int64_t r = decode_enqueue(src, n, dst, write, slot->d, slot->d + 1, alphabet, flags, ws,
-                                     stream, false);
+    int64_t *words = sslot ? slot->h : slot->d;
+    const int64_t r = decode_enqueue(src, n, dst, write, words, words + 1, alphabet, flags, ws,
+                                     sslot, stream);
     if (r) return r;
-    e = hipMemcpyAsync(slot->h, slot->d, 2 * sizeof(int64_t), hipMemcpyDeviceToHost, stream);
-    if (e != hipSuccess) return hip_fail(e, "status copy");
+    if (!sslot) {
+        e = hipMemcpyAsync(slot->h, slot->d, 2 * sizeof(int64_t), hipMemcpyDeviceToHost, stream);
+        if (e != hipSuccess) return hip_fail(e, "status copy");
+    }
     e = hipStreamSynchronize(stream);
     if (e != hipSuccess) return hip_fail(e, "stream synchronize");
-    const int64_t len = slot->h[0], bad = slot->h[1];
-    return (bad == kNoError || bad == -1) ? len : ~bad;
+    const int64_t len = ((volatile int64_t *)slot->h)[0], bad = ((volatile int64_t *)slot->h)[1];
+    return bad == -1 ? len : ~bad;
 }
 
 }  // namespace
@@ -367,8 +425,8 @@ int64_t b64_decode_mode_async(const uint8_t *src, int64_t n, uint8_t *dst, int64
     if ((n > 0 && (!src || !dst)) || !out_len || !first_bad) return fail(B64_EARG, "null pointer");
     if ((flags & kFlagSkipWs) && (!workspace || workspace_bytes < ws_workspace_bytes(n)))
         return fail(B64_EARG, "workspace smaller than b64_decode_workspace_size");
-    return decode_enqueue(src, n, dst, true, out_len, first_bad, alphabet, flags, workspace, stream,
-                          true);
+    return decode_enqueue(src, n, dst, true, out_len, first_bad, alphabet, flags, workspace,
+                          (flags & kFlagSkipWs) ? nullptr : stream_slot(stream), stream);
 }
 
 int64_t b64_decode_async(const uint8_t *src, int64_t n, uint8_t *dst, int64_t *out_len,
@@ -416,7 +474,7 @@ int64_t b64_validate_mode_async(const uint8_t *src, int64_t n, int64_t *out_len,
     if ((flags & kFlagSkipWs) && (!workspace || workspace_bytes < ws_workspace_bytes(n)))
         return fail(B64_EARG, "workspace smaller than b64_decode_workspace_size");
     return decode_enqueue(src, n, nullptr, false, out_len, first_bad, alphabet, flags, workspace,
-                          stream, true);
+                          (flags & kFlagSkipWs) ? nullptr : stream_slot(stream), stream);
 }
 
 int64_t b64_validate_async(const uint8_t *src, int64_t n, int64_t *out_len, int64_t *first_bad,

@@ -348,6 +348,71 @@ __device__ __forceinline__ void atomic_min_i64(int64_t *p, int64_t v)
     atomicMin((unsigned long long *)p, (unsigned long long)v);
 }
 
+// Keeps `v` alive in a register: the wave waits here until an atomic's
+// returned value has arrived, i.e. until the atomic has been performed.
+__device__ __forceinline__ void consume(int64_t v) { asm volatile("" ::"v"(v)); }
+
+// Where a single-buffer decode or validation leaves its result.
+//
+// Raw form (slot == nullptr): *first_bad holds kNoError before the launch and
+// receives the smallest invalid offset by atomic minimum; *out_len receives
+// the decoded length when the end of the input is valid.  Two more launches
+// (reset before, k_finish_status after) give the public form.
+//
+// Slot form: slot points at three int64 words of library memory that are all
+// zero between calls, and the kernel itself leaves the public form in
+// *out_len / *first_bad (length and -1 for a valid input, -1 and the first
+// invalid offset otherwise).  slot[0] collects kNoError - offset by atomic
+// maximum (so zero means "no invalid offset yet"), slot[2] the length, and
+// slot[1] counts finished workgroups; the last workgroup to finish reads the
+// slot, writes the public form and puts the slot back to zero.  Every report
+// is an atomic read-modify-write whose returned value the reporting lane
+// waits for, so it has been performed before the lane reaches the workgroup's
+// final barrier, and the counter increment that follows the barrier is
+// issued after it; the workgroup that takes the counter to the grid size
+// therefore reads every report.  Only read-modify-write atomics at device
+// scope touch the slot, so no cache writeback is needed for this.  Calls that
+// run at the same time must use different slots.
+struct DecSink {
+    int64_t *out_len, *first_bad, *slot;
+};
+
+__device__ __forceinline__ void sink_bad(const DecSink &s, int64_t off)
+{
+    if (s.slot)
+        consume(__hip_atomic_fetch_max(s.slot, kNoError - off, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT));
+    else
+        atomic_min_i64(s.first_bad, off);
+}
+
+__device__ __forceinline__ void sink_len(const DecSink &s, int64_t len)
+{
+    if (s.slot)
+        consume(__hip_atomic_exchange(s.slot + 2, len, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    else
+        *s.out_len = len;
+}
+
+// Called by every thread of every workgroup after its last report.
+__device__ __forceinline__ void sink_finish(const DecSink &s)
+{
+    if (!s.slot) return;
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    const int64_t done =
+        __hip_atomic_fetch_add(s.slot + 1, (int64_t)1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (done != (int64_t)gridDim.x - 1) return;
+    const int64_t key = __hip_atomic_exchange(s.slot, (int64_t)0, __ATOMIC_RELAXED,
+                                              __HIP_MEMORY_SCOPE_AGENT);
+    const int64_t len = __hip_atomic_exchange(s.slot + 2, (int64_t)0, __ATOMIC_RELAXED,
+                                              __HIP_MEMORY_SCOPE_AGENT);
+    consume(__hip_atomic_exchange(s.slot + 1, (int64_t)0, __ATOMIC_RELAXED,
+                                  __HIP_MEMORY_SCOPE_AGENT));
+    *s.first_bad = key ? kNoError - key : -1;
+    *s.out_len = key ? -1 : len;
+}
+
 // `nrounds` complete rounds of lane chunks: round r holds chunks
 // c0 + r*rstep + j*stride, j < U, all in range.  Software-pipelined: the loads
 // of round r+1 are issued before round r is computed and stored.  On gfx9 the

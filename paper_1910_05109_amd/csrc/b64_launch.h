@@ -21,17 +21,20 @@ int64_t grid_for(int64_t nch, Shape sh, int cus);
 // `flags` carries kFlagNoPad (the other variant flags have kernels of their own).
 hipError_t launch_encode(const uint8_t *src, int64_t n, uint8_t *dst, const EncTab &tab, uint32_t flags,
                          Shape sh, int cus, hipStream_t stream);
-// Single-buffer decode (k_decode only): *first_bad must hold kNoError before
-// it; afterwards it holds the first invalid offset or still kNoError, and
-// *out_len the decoded length when the input is valid.
+// Single-buffer decode (k_decode only), result in `sink`: in the raw form
+// *first_bad must hold kNoError before it, and afterwards holds the first
+// invalid offset or still kNoError, and *out_len the decoded length when the
+// input is valid; in the slot form the launch leaves the public form.
 hipError_t launch_decode(const uint8_t *src, int64_t n, uint8_t *dst, const DecMap &map,
-                         int64_t *out_len, int64_t *first_bad, uint32_t flags, Shape sh, int cus,
-                         hipStream_t stream);
-// Read-only validation (k_validate): *first_bad must hold kNoError before it;
-// afterwards it holds the first invalid offset or still kNoError, and
-// *out_len the decoded length when the input is valid.
-hipError_t launch_validate(const uint8_t *src, int64_t n, const DecMap &map, int64_t *out_len,
-                           int64_t *first_bad, uint32_t flags, Shape sh, int cus, hipStream_t stream);
+                         const DecSink &sink, uint32_t flags, Shape sh, int cus, hipStream_t stream);
+// Read-only validation (k_validate), result in `sink` as for launch_decode.
+hipError_t launch_validate(const uint8_t *src, int64_t n, const DecMap &map, const DecSink &sink,
+                           uint32_t flags, Shape sh, int cus, hipStream_t stream);
+// Device address of status slot `idx` (0 <= idx < kStatusSlots) of the
+// current device: three int64 words, zero between calls (the slot form of
+// DecSink).
+constexpr int kStatusSlots = 4096;
+hipError_t status_slot_addr(int idx, int64_t **out);
 hipError_t launch_fill(int64_t *p, int64_t count, int64_t value, hipStream_t stream);
 hipError_t launch_finish(int64_t *out_len, int64_t *first_bad, int64_t count, hipStream_t stream);
 hipError_t launch_encode_batch(const uint8_t *src, const int64_t *in_off, int64_t nbuf,

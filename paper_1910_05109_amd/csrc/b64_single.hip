@@ -2,7 +2,18 @@
 #include "b64_launch.h"
 
 namespace b64hip {
+
+// Status slots of the single-launch decode and validation (the slot form of
+// DecSink): kStatusSlots x 4 int64 per device, zero when the code object is
+// loaded and put back to zero by every call that uses one.  Kernels reach
+// them through the address passed in DecSink only.
+__device__ __align__(256) int64_t g_status_slots[kStatusSlots * 4];
+
 namespace {
+
+// Device address of g_status_slots per device (each device holds its own
+// copy of the array), looked up once.
+int64_t *g_slots_base[64];
 
 // Single buffer.  `head` whole groups are set aside so that the chunk outputs
 // start on a 128-byte line (when dst is 4-byte aligned); then lane chunk c
@@ -49,18 +60,13 @@ __global__ __launch_bounds__(kThreads) void k_encode(const uint8_t *__restrict__
 // [3*head + 12c, +12).  Threads t < head decode one head quantum each; the
 // last thread runs dec_tail_fast over the (at most three) body quanta left after
 // the chunks and the last quantum.
-// first_bad must hold kNoError before the launch; invalid offsets are
-// published with an atomic minimum on it.  out_len is written only when the
-// tail is valid.  (A last-block-finishes protocol would save the status
-// launches, but its device-scope fence at the end of every block writes back
-// L2 on this multi-XCD part, which costs far more than a launch.)  Under
+// The result goes to `sink` (raw or slot form, see DecSink).  Under
 // kFlagNoPad '=' is invalid everywhere and the last quantum may have 2 or 3
 // characters; the body is the same.
 template <int U, bool NT>
 __global__ __launch_bounds__(kThreads) void k_decode(const uint8_t *__restrict__ src, int64_t n,
                                                      uint8_t *__restrict__ dst, DecMap map,
-                                                     int64_t *__restrict__ out_len,
-                                                     int64_t *__restrict__ first_bad, uint32_t flags)
+                                                     DecSink sink, uint32_t flags)
 {
     const bool nopad = (flags & kFlagNoPad) != 0;
     __shared__ uint32_t s_map[64];
@@ -89,7 +95,7 @@ __global__ __launch_bounds__(kThreads) void k_decode(const uint8_t *__restrict__
             for (int64_t c = t; c < nch; c += T) {
                 const int64_t bad = dec_check_inner(s0 + 16 * c, 16, m, nopad);
                 if (bad >= 0) {
-                    atomic_min_i64(first_bad, 4 * head + 16 * c + bad);
+                    sink_bad(sink, 4 * head + 16 * c + bad);
                     break;   // later chunks of this lane have larger offsets
                 }
             }
@@ -103,14 +109,17 @@ __global__ __launch_bounds__(kThreads) void k_decode(const uint8_t *__restrict__
         dst[3 * t + 2] = (uint8_t)v;
         if (qerr & 0x80) {
             const int64_t bad = dec_check_inner(src + 4 * t, 4, m, nopad);
-            if (bad >= 0) atomic_min_i64(first_bad, 4 * t + bad);
+            if (bad >= 0) sink_bad(sink, 4 * t + bad);
         }
     }
     if (t == kThreads - 1) {
         const int64_t q = head + 4 * nch;
-        const int64_t bad = dec_tail_fast(src + 4 * q, n - 4 * q, n, dst + 3 * q, m, out_len, nopad);
-        if (bad >= 0) atomic_min_i64(first_bad, 4 * q + bad);
+        int64_t len = 0;
+        const int64_t bad = dec_tail_fast(src + 4 * q, n - 4 * q, n, dst + 3 * q, m, &len, nopad);
+        if (bad >= 0) sink_bad(sink, 4 * q + bad);
+        else sink_len(sink, len);
     }
+    sink_finish(sink);
 }
 
 __global__ void k_fill_i64(int64_t *p, int64_t count, int64_t value)
@@ -154,13 +163,31 @@ hipError_t launch_encode(const uint8_t *src, int64_t n, uint8_t *dst, const EncT
 }
 
 hipError_t launch_decode(const uint8_t *src, int64_t n, uint8_t *dst, const DecMap &map,
-                         int64_t *out_len, int64_t *first_bad, uint32_t flags, Shape sh, int cus,
-                         hipStream_t stream)
+                         const DecSink &sink, uint32_t flags, Shape sh, int cus, hipStream_t stream)
 {
     const int64_t nbq = n >= 1 ? (n - 1) >> 2 : 0;
     const int64_t grid = grid_for(nbq >> 2, sh, cus);
-    B64_DISPATCH(k_decode, sh, grid, stream, src, n, dst, map, out_len, first_bad, flags);
+    B64_DISPATCH(k_decode, sh, grid, stream, src, n, dst, map, sink, flags);
     return hipGetLastError();
+}
+
+hipError_t status_slot_addr(int idx, int64_t **out)
+{
+    if (idx < 0 || idx >= kStatusSlots) return hipErrorInvalidValue;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+    int64_t *base = __atomic_load_n(&g_slots_base[dev], __ATOMIC_ACQUIRE);
+    if (!base) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(g_status_slots));
+        if (e != hipSuccess) return e;
+        base = (int64_t *)p;
+        __atomic_store_n(&g_slots_base[dev], base, __ATOMIC_RELEASE);
+    }
+    *out = base + 4 * (int64_t)idx;
+    return hipSuccess;
 }
 
 hipError_t launch_fill(int64_t *p, int64_t count, int64_t value, hipStream_t stream)

@@ -62,13 +62,12 @@ __device__ __forceinline__ uint32_t val_stream(const uint8_t *s0, int64_t c0, in
 // The body is every quantum but the last; lane chunk c covers characters
 // [16c, 16c+16).  The last thread validates the characters after the chunks
 // (at most three body quanta and the last quantum) as the end of the input
-// and, when they are valid, writes the decoded length.  first_bad must hold
-// kNoError before the launch.  kFlagNoPad selects the unpadded rules.
+// and, when they are valid, reports the decoded length.  The result goes to
+// `sink` (raw or slot form, see DecSink).  kFlagNoPad selects the unpadded
+// rules.
 template <int U, bool NT>
 __global__ __launch_bounds__(kThreads) void k_validate(const uint8_t *__restrict__ src, int64_t n,
-                                                       DecMap map, int64_t *__restrict__ out_len,
-                                                       int64_t *__restrict__ first_bad,
-                                                       uint32_t flags)
+                                                       DecMap map, DecSink sink, uint32_t flags)
 {
     const bool nopad = (flags & kFlagNoPad) != 0;
     __shared__ uint32_t s_map[64];
@@ -87,7 +86,7 @@ __global__ __launch_bounds__(kThreads) void k_validate(const uint8_t *__restrict
             for (int64_t c = t; c < nch; c += T) {
                 const int64_t bad = dec_check_inner(src + 16 * c, 16, m, nopad);
                 if (bad >= 0) {
-                    atomic_min_i64(first_bad, 16 * c + bad);
+                    sink_bad(sink, 16 * c + bad);
                     break;   // later chunks of this lane have larger offsets
                 }
             }
@@ -98,19 +97,20 @@ __global__ __launch_bounds__(kThreads) void k_validate(const uint8_t *__restrict
         const uint8_t *p = src + 4 * q0;
         int64_t len = 0;
         const int64_t bad = dec_tail_fast(p, n - 4 * q0, n, nullptr, m, &len, nopad);
-        if (bad >= 0) atomic_min_i64(first_bad, 4 * q0 + bad);
-        else *out_len = len;
+        if (bad >= 0) sink_bad(sink, 4 * q0 + bad);
+        else sink_len(sink, len);
     }
+    sink_finish(sink);
 }
 
 }  // namespace
 
-hipError_t launch_validate(const uint8_t *src, int64_t n, const DecMap &map, int64_t *out_len,
-                           int64_t *first_bad, uint32_t flags, Shape sh, int cus, hipStream_t stream)
+hipError_t launch_validate(const uint8_t *src, int64_t n, const DecMap &map, const DecSink &sink,
+                           uint32_t flags, Shape sh, int cus, hipStream_t stream)
 {
     const int64_t nbq = n >= 1 ? (n - 1) >> 2 : 0;
     const int64_t grid = grid_for(nbq >> 2, sh, cus);
-    B64_DISPATCH(k_validate, sh, grid, stream, src, n, map, out_len, first_bad, flags);
+    B64_DISPATCH(k_validate, sh, grid, stream, src, n, map, sink, flags);
     return hipGetLastError();
 }
 

@@ -26,7 +26,10 @@ SHAPES = [(u, bpc, nt) for u in (1, 2, 4, 8) for bpc in (1, 3, 8, 64) for nt in 
 SHAPE_IDS = [f"u{u}-b{b}-nt{nt}" for u, b, nt in SHAPES]
 SMALL_LENGTHS = list(range(0, 49)) + [95, 96, 97, 767, 768, 769, 3071, 3072, 3073, 12287, 12288,
                                       12289, 49151, 49152, 49153, 100003]
-BIG_N = (48 << 20) + 1            # several grid-stride rounds at 1 and 3 workgroups per CU
+# large enough that every unroll takes the streaming grid (more than 16
+# workgroups per CU would be needed to cover it in one round), with several
+# grid-stride rounds at 1 and 3 workgroups per CU
+BIG_N = (128 << 20) + 1
 MIS_N = (5 << 20) + 2             # misaligned source and destination
 GUARD = 64
 
@@ -305,7 +308,7 @@ def test_decode_batch_shapes(b64, batch, shape):
 
 @pytest.fixture(scope="module")
 def wrap(oracle):
-    x = workloads.random_bytes(workloads.SEED_BASE + 320, (24 << 20) + 2)
+    x = workloads.random_bytes(workloads.SEED_BASE + 320, (128 << 20) + 2)
     cases = []
     for line_len in (4, 64, 76):
         for n in (1, 2, 3, 47, 48, 57, 58, 3073, 100003, x.size):
