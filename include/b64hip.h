@@ -79,14 +79,16 @@ int64_t b64_decode(const uint8_t *src, int64_t n, uint8_t *dst,
 /* Decode, asynchronous form.  Results land in device memory once `stream`
  * reaches them: *out_len = decoded length (or -1 if invalid), *first_bad = -1
  * if valid (else the first invalid offset); their previous contents do not
- * matter.  Returns 0 or B64_EARG / B64_EHIP.  One kernel launch: the
- * library keeps a 32-byte status slot in device memory per stream handle
- * (up to 4096 per device; the handle identifies the stream, and
- * hipStreamPerThread gets a slot per host thread), which is back to zero
- * after every call.  While `stream` captures a HIP graph, or once every slot
- * is taken, the call is three launches that keep the status in *out_len /
- * *first_bad alone (reset, decode, finish), so a captured graph may be
- * replayed on any stream.  (Section "Decoding".) */
+ * matter.  Returns 0 or B64_EARG / B64_EHIP.  One kernel launch, whose last
+ * workgroup writes the status: the library keeps a 2 KiB status slot in
+ * device memory per stream handle (hipStreamPerThread gets one per host
+ * thread), which is back to zero after every call.  Safe to capture in a HIP
+ * graph: the launches captured from one stream in one capture share a slot
+ * of their own (they run in order within a replay, and launches of one graph
+ * run one after another).  Once the 1024 slots of a device are taken, calls
+ * on new streams and in new captures take three launches (reset, decode,
+ * finish) with the status in *out_len / *first_bad alone.
+ * (Section "Decoding".) */
 int64_t b64_decode_async(const uint8_t *src, int64_t n, uint8_t *dst,
                          int64_t *out_len, int64_t *first_bad,
                          const char *alphabet, hipStream_t stream);
@@ -244,17 +246,28 @@ const char *b64_pipeline_last_error(void);
 /* Launch shape used by the kernels of operation `op` (0 encode, 1 decode,
  * 2 encode_batch, 3 decode_batch, 4 validate, 5 line-wrapped encode,
  * 6 whitespace-skipping decode / validate, 7 fused float32 -> bfloat16
- * decode): `unroll` lane chunks in flight per lane
- * (1, 2, 4 or 8; a lane chunk is 12 bytes -> 16 characters or back; for op 6
- * the rounds of 1024 characters a decoding wave has in flight: 1, 2 or 4,
- * and 8 runs as 2),
- * `blocks_per_cu` workgroups of 256 threads per compute unit (1..64), and
- * `nontemporal` (0 or 1) for streaming loads and stores.  Process-wide; meant
- * for the autotuner.  Does not change results.  Returns 0 or B64_EARG. */
+ * decode) for inputs in size bucket `bucket`: `unroll` lane chunks in flight
+ * per lane (1, 2, 4 or 8; a lane chunk is 12 bytes -> 16 characters or back;
+ * for op 6 the rounds of 1024 characters a decoding wave has in flight: 1, 2
+ * or 4, and 8 runs as 2), `blocks_per_cu` workgroups of 256 threads per
+ * compute unit (1..64; an input that fewer workgroups cover in one round gets
+ * just those), and `nontemporal` (0 or 1) for streaming loads and stores.
+ * Size buckets of the input length n in bytes: 0 for n < 1 MiB, 1 for
+ * n < 16 MiB, 2 for n < 128 MiB, 3 from 128 MiB; ops 2, 3 and 7 always use
+ * bucket 3 (their total size lives in device memory); bucket -1 sets every
+ * bucket.  Process-wide; meant for the autotuner.  Does not change results
+ * (every unroll x nontemporal pair is tested against the oracle at 1, 3, 8
+ * and 64 workgroups per CU).  Returns 0 or B64_EARG. */
+int64_t b64_tune_set_bucket(int op, int bucket, int unroll, int blocks_per_cu, int nontemporal);
+/* b64_tune_set_bucket(op, -1, ...): the same shape for every size.           */
 int64_t b64_tune_set(int op, int unroll, int blocks_per_cu, int nontemporal);
-/* Current shape of `op` packed as nontemporal*10000 + unroll*100 +
+/* Shape of `op` in `bucket` packed as nontemporal*10000 + unroll*100 +
  * blocks_per_cu, or B64_EARG.                                                */
+int64_t b64_tune_get_bucket(int op, int bucket);
+/* b64_tune_get_bucket(op, 3).                                                */
 int64_t b64_tune_get(int op);
+/* Size bucket (0..3) of an input of n bytes, or B64_EARG for n < 0.          */
+int64_t b64_tune_bucket(int64_t n);
 /* Whitespace-skipping decode (B64_SKIP_WS): texts of at least `min_chars`
  * bytes first try decoding as regular lines (the guess), shorter ones count
  * their whitespace straight away.  min_chars >= 0 sets the size, a negative

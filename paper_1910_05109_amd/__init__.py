@@ -44,7 +44,8 @@ SKIP_WS = 2
 __all__ = ["STD", "URL", "NOPAD", "SKIP_WS", "B64Error", "load", "encoded_len", "decoded_max_len",
            "workspace_size", "encode",
            "decode", "decode_async", "validate", "validate_async", "encode_batch", "decode_batch",
-           "decode_f32_bf16", "tune_set", "tune_get", "tune_ws_guess_min", "stream_ptr"]
+           "decode_f32_bf16", "tune_set", "tune_get", "tune_shapes", "tune_restore", "tune_bucket",
+           "tune_ws_guess_min", "stream_ptr", "BUCKETS"]
 
 
 # The wrappers below sit on the launch path of every call, so they keep their
@@ -394,8 +395,19 @@ def decode_f32_bf16(src, in_off, dim: int, alphabet=STD, dst=None, status=None, 
     return dst.reshape(-1)[: nrows * dim].view(nrows, dim), status[:nrows]
 
 
-def tune_set(op: str, unroll: int, blocks_per_cu: int, nontemporal: int = 1) -> None:
-    check(load().b64_tune_set(OPS[op], unroll, blocks_per_cu, int(nontemporal)), "b64_tune_set")
+BUCKETS = 4   # size buckets of the launch shapes: < 1 MiB, < 16 MiB, < 128 MiB, larger
+
+
+def tune_set(op: str, unroll: int, blocks_per_cu: int, nontemporal: int = 1,
+             bucket: int = -1) -> None:
+    """Launch shape of `op` for inputs in size `bucket` (-1: every bucket)."""
+    check(load().b64_tune_set_bucket(OPS[op], bucket, unroll, blocks_per_cu, int(nontemporal)),
+          "b64_tune_set_bucket")
+
+
+def tune_bucket(n: int) -> int:
+    """Size bucket of an input of n bytes."""
+    return check(load().b64_tune_bucket(n), "b64_tune_bucket")
 
 
 def tune_ws_guess_min(min_chars: int = -1) -> int:
@@ -405,7 +417,18 @@ def tune_ws_guess_min(min_chars: int = -1) -> int:
     return int(load().b64_tune_ws_guess_min(int(min_chars)))
 
 
-def tune_get(op: str) -> tuple[int, int, int]:
-    """(unroll, blocks_per_cu, nontemporal) of `op`."""
-    v = check(load().b64_tune_get(OPS[op]), "b64_tune_get")
+def tune_get(op: str, bucket: int = BUCKETS - 1) -> tuple[int, int, int]:
+    """(unroll, blocks_per_cu, nontemporal) of `op` in size `bucket`."""
+    v = check(load().b64_tune_get_bucket(OPS[op], bucket), "b64_tune_get_bucket")
     return (v // 100) % 100, v % 100, v // 10000
+
+
+def tune_shapes(op: str) -> list[tuple[int, int, int]]:
+    """The shapes of `op` in every size bucket."""
+    return [tune_get(op, b) for b in range(BUCKETS)]
+
+
+def tune_restore(op: str, shapes) -> None:
+    """Set the shapes of `op` in every bucket (as tune_shapes returns them)."""
+    for b, sh in enumerate(shapes):
+        tune_set(op, *sh, bucket=b)

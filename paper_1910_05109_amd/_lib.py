@@ -44,9 +44,12 @@ SIGNATURES = {
     "b64_pipeline_encode": ([_P, _P, _I64, _P, _P], _I64),
     "b64_pipeline_decode": ([_P, _P, _I64, _P, _P], _I64),
     "b64_pipeline_last_error": ([], ctypes.c_char_p),
+    "b64_tune_set_bucket": ([_INT, _INT, _INT, _INT, _INT], _I64),
     "b64_tune_set": ([_INT, _INT, _INT, _INT], _I64),
-    "b64_tune_ws_guess_min": ([_I64], _I64),
+    "b64_tune_get_bucket": ([_INT, _INT], _I64),
     "b64_tune_get": ([_INT], _I64),
+    "b64_tune_bucket": ([_I64], _I64),
+    "b64_tune_ws_guess_min": ([_I64], _I64),
     "b64_last_error": ([], ctypes.c_char_p),
 }
 DATA_SYMBOLS = ("b64_alphabet_std", "b64_alphabet_url")
@@ -71,7 +74,18 @@ def load() -> ctypes.CDLL:
             fn.argtypes = args
             fn.restype = res
         _lib = L
+        _apply_tune_cache()
     return _lib
+
+
+def _apply_tune_cache() -> None:
+    """Apply the autotuner's cached launch shapes of the current device, when
+    a cache exists ($B64HIP_TUNE_CACHE, else ~/.cache/b64hip/tune.json;
+    B64HIP_TUNE_CACHE=off skips it)."""
+    from . import tune
+    path = tune.cache_path()
+    if path and os.path.exists(path):
+        tune.apply_cached(path)
 
 
 def last_error() -> str:

@@ -88,12 +88,34 @@ DecMap make_dec_ws(const char *alphabet, bool nopad)
 
 // Launch shapes per operation (encode, decode, encode_batch, decode_batch,
 // validate, line-wrapped encode, whitespace-skipping decode, fused float32 ->
-// bfloat16 decode); the defaults are the autotuner's choices on MI355X (1 GiB
-// single buffers, 1 GiB log-uniform ragged batches, 1 GiB MIME text).
+// bfloat16 decode) and size bucket of the operation's input: below 1 MiB
+// (launch-latency bound), below 16 MiB and below 128 MiB (resident in the
+// L2 and last-level caches), and from 128 MiB (HBM streaming).  The batched
+// and fused operations find their total size only on the device and always
+// take the last bucket's shape.  The defaults are the autotuner's choices on
+// MI355X (python -m paper_1910_05109_amd.tune: inputs of 256 KiB, 4 MiB,
+// 48 MiB and 1 GiB).
 constexpr int kOps = 8;
-Shape g_shape[kOps] = {{4, 1, 1}, {8, 1, 1}, {4, 2, 1}, {4, 2, 1}, {8, 1, 1}, {8, 1, 0}, {4, 4, 1},
-                       {4, 8, 1}};
+constexpr int kBuckets = 4;
+constexpr int64_t kBucketLimit[kBuckets - 1] = {1 << 20, 16 << 20, 128 << 20};
+Shape g_shape[kOps][kBuckets] = {
+    {{1, 8, 1}, {2, 32, 0}, {1, 32, 0}, {8, 1, 1}},    // encode
+    {{1, 32, 1}, {2, 8, 1}, {1, 4, 0}, {2, 2, 1}},     // decode
+    {{2, 2, 1}, {2, 2, 1}, {2, 2, 1}, {2, 2, 1}},      // encode_batch
+    {{4, 16, 1}, {4, 16, 1}, {4, 16, 1}, {4, 16, 1}},  // decode_batch
+    {{1, 32, 0}, {2, 4, 0}, {1, 4, 1}, {8, 1, 1}},     // validate
+    {{1, 4, 0}, {1, 8, 0}, {1, 8, 0}, {8, 1, 0}},      // line-wrapped encode
+    {{1, 2, 0}, {1, 16, 0}, {4, 2, 1}, {2, 8, 1}},     // whitespace-skipping decode
+    {{2, 64, 1}, {2, 64, 1}, {2, 64, 1}, {2, 64, 1}},  // fused decode
+};
 std::mutex g_mu;
+
+int bucket_of(int64_t n)
+{
+    int b = 0;
+    while (b < kBuckets - 1 && n >= kBucketLimit[b]) ++b;
+    return b;
+}
 
 // Texts of at least this many bytes try the regular-line guess in the
 // whitespace-skipping decode; shorter ones take the counted path alone.  On
@@ -102,10 +124,11 @@ std::mutex g_mu;
 constexpr int64_t kWsGuessMin = 14 << 20;
 std::atomic<int64_t> g_ws_guess_min{kWsGuessMin};
 
-Shape shape_of(int op)
+// Shape of `op` for an input of n bytes (n < 0: the last bucket).
+Shape shape_of(int op, int64_t n)
 {
     std::lock_guard<std::mutex> lk(g_mu);
-    return g_shape[op];
+    return g_shape[op][n < 0 ? kBuckets - 1 : bucket_of(n)];
 }
 
 constexpr int kMaxDevices = 64;
@@ -204,35 +227,48 @@ hipError_t ws_cache(int64_t bytes, void **out)
     return hipSuccess;
 }
 
-// Status slots of the single-launch decode / validation, one per stream and
-// device.  Work on one stream runs in order, so a stream's calls never
-// overlap and can share its slot; the slot is back to zero after each call.
-// Streams are never removed (a slot is 32 bytes of device memory); once all
-// kStatusSlots of a device are taken, further streams use the three-launch
-// form.  hipStreamPerThread names a different stream on every thread, so it
-// gets a slot per thread.
+// Status slots of the single-launch decode / validation.  Work on one stream
+// runs in order, so a stream's calls never overlap and can share one slot; the
+// slot is back to zero after each call.  hipStreamPerThread names a different
+// stream on every thread, so it gets a slot per thread.  Decodes captured into
+// a graph get a slot per capture and capturing stream: the nodes captured from
+// one stream run in order within a replay, and launches of one graph run one
+// after another, so they never overlap either.  Slots are never given back (a
+// slot is 2,176 bytes of device memory); once all kStatusSlots of a device are
+// taken, further streams and captures use the three-launch form.
 struct SlotTable {
     std::mutex mu;
     std::unordered_map<hipStream_t, int> idx;
+    std::unordered_map<unsigned long long, std::unordered_map<hipStream_t, int>> captured;
     int next = 0;
 };
 SlotTable g_slot_tables[kMaxDevices];
 thread_local int g_per_thread_slot[kMaxDevices];   // slot index + 1, 0 = none yet
 
-// The status slot of `stream` on the current device, or nullptr when the
-// single-launch form is not used: while `stream` captures a graph (a graph
-// may be replayed on any stream, alongside direct calls, so a captured decode
-// keeps the status in the caller's words), or when every slot is taken.
+// The status slot for a call on `stream` on the current device, or nullptr
+// when every slot is taken (or the stream's capture has been invalidated).
 int64_t *stream_slot(hipStream_t stream)
 {
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
-    if (hipStreamIsCapturing(stream, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone)
+    unsigned long long capture_id = 0;
+    if (hipStreamGetCaptureInfo(stream, &cs, &capture_id) != hipSuccess ||
+        cs == hipStreamCaptureStatusInvalidated)
         return nullptr;
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
     SlotTable &t = g_slot_tables[dev];
     int idx = -1;
-    if (stream == hipStreamPerThread) {
+    if (cs == hipStreamCaptureStatusActive) {
+        std::lock_guard<std::mutex> lk(t.mu);
+        auto &per_stream = t.captured[capture_id];
+        auto it = per_stream.find(stream);
+        if (it != per_stream.end()) {
+            idx = it->second;
+        } else if (t.next < kStatusSlots) {
+            idx = t.next++;
+            per_stream.emplace(stream, idx);
+        }
+    } else if (stream == hipStreamPerThread) {
         if (!g_per_thread_slot[dev]) {
             std::lock_guard<std::mutex> lk(t.mu);
             if (t.next < kStatusSlots) g_per_thread_slot[dev] = ++t.next;
@@ -268,7 +304,7 @@ int64_t decode_enqueue(const uint8_t *src, int64_t n, uint8_t *dst, bool write, 
     if (e != hipSuccess) return hip_fail(e, "device query");
     if (flags & kFlagSkipWs) {
         e = launch_decode_ws(src, n, dst, write, make_dec_ws(alphabet, flags & kFlagNoPad), out_len,
-                             first_bad, flags, workspace, shape_of(6), cus,
+                             first_bad, flags, workspace, shape_of(6, n), cus,
                              g_ws_guess_min.load(std::memory_order_relaxed), stream);
         return e == hipSuccess ? 0 : hip_fail(e, "whitespace decode launch");
     }
@@ -278,9 +314,9 @@ int64_t decode_enqueue(const uint8_t *src, int64_t n, uint8_t *dst, bool write, 
     }
     const DecSink sink{out_len, first_bad, sslot};
     if (write)
-        e = launch_decode(src, n, dst, make_dec(alphabet), sink, flags, shape_of(1), cus, stream);
+        e = launch_decode(src, n, dst, make_dec(alphabet), sink, flags, shape_of(1, n), cus, stream);
     else
-        e = launch_validate(src, n, make_dec(alphabet), sink, flags, shape_of(4), cus, stream);
+        e = launch_validate(src, n, make_dec(alphabet), sink, flags, shape_of(4, n), cus, stream);
     if (e != hipSuccess) return hip_fail(e, write ? "decode launch" : "validate launch");
     if (!sslot) {
         e = launch_finish(out_len, first_bad, 1, stream);
@@ -365,16 +401,29 @@ int64_t b64_decode_workspace_size(int64_t n, uint32_t flags)
 
 const char *b64_last_error(void) { return g_err; }
 
-int64_t b64_tune_set(int op, int unroll, int blocks_per_cu, int nontemporal)
+int64_t b64_tune_set_bucket(int op, int bucket, int unroll, int blocks_per_cu, int nontemporal)
 {
     if (op < 0 || op >= kOps) return fail(B64_EARG, "bad op");
+    if (bucket < -1 || bucket >= kBuckets) return fail(B64_EARG, "bad size bucket");
     if (!(unroll == 1 || unroll == 2 || unroll == 4 || unroll == 8))
         return fail(B64_EARG, "unroll must be 1, 2, 4 or 8");
     if (blocks_per_cu < 1 || blocks_per_cu > 64) return fail(B64_EARG, "blocks_per_cu out of range");
     if (nontemporal != 0 && nontemporal != 1) return fail(B64_EARG, "nontemporal must be 0 or 1");
     std::lock_guard<std::mutex> lk(g_mu);
-    g_shape[op] = Shape{unroll, blocks_per_cu, nontemporal};
+    for (int b = 0; b < kBuckets; ++b)
+        if (bucket < 0 || b == bucket) g_shape[op][b] = Shape{unroll, blocks_per_cu, nontemporal};
     return 0;
+}
+
+int64_t b64_tune_set(int op, int unroll, int blocks_per_cu, int nontemporal)
+{
+    return b64_tune_set_bucket(op, -1, unroll, blocks_per_cu, nontemporal);
+}
+
+int64_t b64_tune_bucket(int64_t n)
+{
+    if (n < 0) return fail(B64_EARG, "negative length");
+    return bucket_of(n);
 }
 
 int64_t b64_tune_ws_guess_min(int64_t min_chars)
@@ -383,12 +432,16 @@ int64_t b64_tune_ws_guess_min(int64_t min_chars)
     return g_ws_guess_min.exchange(min_chars, std::memory_order_relaxed);
 }
 
-int64_t b64_tune_get(int op)
+int64_t b64_tune_get_bucket(int op, int bucket)
 {
     if (op < 0 || op >= kOps) return fail(B64_EARG, "bad op");
-    const Shape s = shape_of(op);
+    if (bucket < 0 || bucket >= kBuckets) return fail(B64_EARG, "bad size bucket");
+    std::lock_guard<std::mutex> lk(g_mu);
+    const Shape s = g_shape[op][bucket];
     return (int64_t)s.nt * 10000 + (int64_t)s.unroll * 100 + s.bpc;
 }
+
+int64_t b64_tune_get(int op) { return b64_tune_get_bucket(op, kBuckets - 1); }
 
 int64_t b64_encode_mode(const uint8_t *src, int64_t n, uint8_t *dst, const char *alphabet,
                         uint32_t flags, int64_t line_len, hipStream_t stream)
@@ -402,10 +455,10 @@ int64_t b64_encode_mode(const uint8_t *src, int64_t n, uint8_t *dst, const char 
     hipError_t e = cu_count(&cus);
     if (e != hipSuccess) return hip_fail(e, "device query");
     if (line_len > 0 && line_len < m)
-        e = launch_encode_wrap(src, n, dst, make_enc(alphabet), flags, line_len, shape_of(5), cus,
+        e = launch_encode_wrap(src, n, dst, make_enc(alphabet), flags, line_len, shape_of(5, n), cus,
                                stream);
     else
-        e = launch_encode(src, n, dst, make_enc(alphabet), flags, shape_of(0), cus, stream);
+        e = launch_encode(src, n, dst, make_enc(alphabet), flags, shape_of(0, n), cus, stream);
     if (e != hipSuccess) return hip_fail(e, "encode launch");
     return m;
 }
@@ -496,7 +549,7 @@ int64_t b64_encode_batch_mode(const uint8_t *src, const int64_t *in_off, int64_t
     hipError_t e = cu_count(&cus);
     if (e != hipSuccess) return hip_fail(e, "device query");
     e = launch_encode_batch(src, in_off, nbuf, dst, out_off, out_len, make_enc(alphabet), flags,
-                            shape_of(2), cus, stream);
+                            shape_of(2, -1), cus, stream);
     return e == hipSuccess ? 0 : hip_fail(e, "encode_batch launch");
 }
 
@@ -523,7 +576,7 @@ int64_t b64_decode_batch_mode(const uint8_t *src, const int64_t *in_off, int64_t
     e = launch_fill(first_bad, nbuf, kNoError, stream);
     if (e != hipSuccess) return hip_fail(e, "fill launch");
     e = launch_decode_batch(src, in_off, nbuf, dst, out_off, out_len, first_bad,
-                            make_dec(alphabet), flags, shape_of(3), cus, stream);
+                            make_dec(alphabet), flags, shape_of(3, -1), cus, stream);
     if (e != hipSuccess) return hip_fail(e, "decode_batch launch");
     e = launch_finish(out_len, first_bad, nbuf, stream);
     return e == hipSuccess ? 0 : hip_fail(e, "status launch");
@@ -550,7 +603,7 @@ int64_t b64_decode_f32_bf16(const uint8_t *src, const int64_t *in_off, int64_t n
     hipError_t e = cu_count(&cus);
     if (e != hipSuccess) return hip_fail(e, "device query");
     e = launch_decode_f32_bf16(src, in_off, nrows, dim, dst, status, make_dec(alphabet), flags,
-                               shape_of(7), cus, stream);
+                               shape_of(7, -1), cus, stream);
     return e == hipSuccess ? 0 : hip_fail(e, "fused decode launch");
 }
 

@@ -279,36 +279,54 @@ __device__ __forceinline__ int final_quantum(uint32_t c, int r, const uint8_t *m
 }
 
 // The last characters of an input, p[0..len) from a quantum boundary to the
-// end (n_total characters in all, len <= 16: up to three body quanta and the
-// final quantum), validated as the end of the input and, when valid,
-// decoded.  Every load is issued up front and the rules run on registers, so
-// the tail costs one memory round trip instead of one per character.  With o == nullptr it only validates.  Returns -1 and sets
+// end (len <= 16: up to three body quanta and the final quantum), loaded into
+// registers: the body quanta in q[0..nb) and the final quantum's r
+// characters in bytes 0..r-1 of fq.  Every load is issued at once, so the
+// tail costs one memory round trip; a kernel may issue them early and use
+// them later.
+struct TailIn {
+    uint32_t q[3];
+    uint32_t fq;
+};
+
+__device__ __forceinline__ TailIn tail_load(const uint8_t *p, int64_t len)
+{
+    TailIn ti = {{0u, 0u, 0u}, 0u};
+    if (len <= 0) return ti;
+    const int nb = (int)((len - 1) >> 2);                  // body quanta, 0..3
+    const int r = (int)(len - 4 * nb);                     // final quantum, 1..4
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+        if (i < nb) ti.q[i] = *(const u32a1 *)(p + 4 * i);
+    if (len >= 4) {
+        ti.fq = *(const u32a1 *)(p + len - 4) >> (8 * (4 - r));
+    } else {
+        for (int i = 0; i < r; ++i) ti.fq |= (uint32_t)p[i] << (8 * i);
+    }
+    return ti;
+}
+
+// The tail p[0..len) of an input of n_total characters, loaded by tail_load,
+// validated as the end of the input and, when valid, decoded to o (o ==
+// nullptr: validate only); the rules run on registers.  Returns -1 and sets
 // *out_len (the whole input's decoded length) when valid, else the first
 // invalid offset relative to p.
-__device__ inline int64_t dec_tail_fast(const uint8_t *p, int64_t len, int64_t n_total, uint8_t *o,
-                                        const uint8_t *map, int64_t *out_len, bool nopad)
+__device__ inline int64_t dec_tail_regs(const TailIn &ti, const uint8_t *p, int64_t len,
+                                        int64_t n_total, uint8_t *o, const uint8_t *map,
+                                        int64_t *out_len, bool nopad)
 {
     if (len <= 0) {
         *out_len = 0;
         return -1;
     }
-    const int nb = (int)((len - 1) >> 2);                  // body quanta, 0..3
-    const int r = (int)(len - 4 * nb);                     // final quantum, 1..4
-    uint32_t q[3] = {0u, 0u, 0u}, fq = 0;
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-        if (i < nb) q[i] = *(const u32a1 *)(p + 4 * i);
-    if (len >= 4) {
-        fq = *(const u32a1 *)(p + len - 4) >> (8 * (4 - r));
-    } else {
-        for (int i = 0; i < r; ++i) fq |= (uint32_t)p[i] << (8 * i);
-    }
+    const int nb = (int)((len - 1) >> 2);
+    const int r = (int)(len - 4 * nb);
     uint32_t v[3];
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
         if (i < nb) {
             uint32_t qerr = 0;
-            v[i] = dec_quantum(q[i], map, qerr);
+            v[i] = dec_quantum(ti.q[i], map, qerr);
             if (qerr & 0x80) {
                 const int64_t bad = dec_check_inner(p + 4 * i, 4, map, nopad);
                 if (bad >= 0) return 4 * i + bad;
@@ -317,7 +335,7 @@ __device__ inline int64_t dec_tail_fast(const uint8_t *p, int64_t len, int64_t n
     }
     int nd = 0;
     uint32_t fv = 0;
-    const int fbad = final_quantum(fq, r, map, nopad, &nd, &fv);
+    const int fbad = final_quantum(ti.fq, r, map, nopad, &nd, &fv);
     if (fbad >= 0) return 4 * nb + fbad;
     if (o) {
 #pragma unroll
@@ -335,6 +353,13 @@ __device__ inline int64_t dec_tail_fast(const uint8_t *p, int64_t len, int64_t n
     }
     *out_len = 3 * ((n_total - r) >> 2) + nd - 1;
     return -1;
+}
+
+// tail_load and dec_tail_regs in one step.
+__device__ inline int64_t dec_tail_fast(const uint8_t *p, int64_t len, int64_t n_total, uint8_t *o,
+                                        const uint8_t *map, int64_t *out_len, bool nopad)
+{
+    return dec_tail_regs(tail_load(p, len), p, len, n_total, o, map, out_len, nopad);
 }
 
 __device__ __forceinline__ void stage_dec_map(uint32_t *s_map, const DecMap &map)
@@ -359,58 +384,112 @@ __device__ __forceinline__ void consume(int64_t v) { asm volatile("" ::"v"(v)); 
 // the decoded length when the end of the input is valid.  Two more launches
 // (reset before, k_finish_status after) give the public form.
 //
-// Slot form: slot points at three int64 words of library memory that are all
+// Slot form: slot points at kSlotWords int64 words of library memory that are
 // zero between calls, and the kernel itself leaves the public form in
-// *out_len / *first_bad (length and -1 for a valid input, -1 and the first
-// invalid offset otherwise).  slot[0] collects kNoError - offset by atomic
-// maximum (so zero means "no invalid offset yet"), slot[2] the length, and
-// slot[1] counts finished workgroups; the last workgroup to finish reads the
-// slot, writes the public form and puts the slot back to zero.  Every report
-// is an atomic read-modify-write whose returned value the reporting lane
-// waits for, so it has been performed before the lane reaches the workgroup's
-// final barrier, and the counter increment that follows the barrier is
-// issued after it; the workgroup that takes the counter to the grid size
-// therefore reads every report.  Only read-modify-write atomics at device
-// scope touch the slot, so no cache writeback is needed for this.  Calls that
-// run at the same time must use different slots.
+// *out_len / *first_bad (the length and -1 for a valid input, -1 and the first
+// invalid offset otherwise).  slot[0] collects kNoError - offset of every
+// invalid character found, by atomic maximum (the largest key is the smallest
+// offset).  Every workgroup, when done, makes one atomic add of a count word:
+// finished workgroups in bits 32..63, workgroups that found an invalid
+// character in bits 0..23, and the number of data characters of the valid
+// final quantum in bits 24..31 (from the workgroup of the tail lane; with the
+// input length it gives the decoded length).  Atomics on one word are
+// performed one at a time, about 10 ns each on MI355X, so a grid of more than
+// 8 * kSinkGroups workgroups counts in two levels: workgroup b adds to the
+// word of group b mod kSinkGroups (each on its own 128-byte line), and the
+// last workgroup of each group adds the group's sum to the total at slot[1];
+// smaller grids add to slot[1] directly.  The workgroup whose add completes
+// the total writes the public form; only when some workgroup found an invalid
+// character does it read slot[0] (one more atomic).  Each completing
+// workgroup puts the word it completed back to zero, and the reader of
+// slot[0] clears it.  Every report to slot[0] is an atomic whose returned
+// value the lane waits for, so it has been performed before the lane reaches
+// the workgroup's final barrier, and the workgroup's add is issued after that
+// barrier; each add that completes a count is issued after the adds it
+// counts were performed, so the last one sees every report.  Only atomics at
+// device scope touch the slot, so no cache writeback is needed.  A grid of one
+// workgroup skips the count.  Calls that may run at the same time must use
+// different slots.
+constexpr int kSinkGroups = 16;
+constexpr int kSlotWords = 16 * (kSinkGroups + 1);   // line 0: key, total; then one line per group
 struct DecSink {
     int64_t *out_len, *first_bad, *slot;
 };
 
-__device__ __forceinline__ void sink_bad(const DecSink &s, int64_t off)
+// Per-lane record of what the lane reported in the slot form.
+struct SinkLane {
+    int bad = 0;   // reported an invalid offset
+    int nd = 0;    // tail lane with a valid end: data characters of the final quantum
+};
+
+__device__ __forceinline__ void sink_bad(const DecSink &s, SinkLane &l, int64_t off)
 {
-    if (s.slot)
+    if (s.slot) {
         consume(__hip_atomic_fetch_max(s.slot, kNoError - off, __ATOMIC_RELAXED,
                                        __HIP_MEMORY_SCOPE_AGENT));
-    else
+        l.bad = 1;
+    } else {
         atomic_min_i64(s.first_bad, off);
+    }
 }
 
-__device__ __forceinline__ void sink_len(const DecSink &s, int64_t len)
+// Length of a valid input of n >= 1 characters whose final quantum (the
+// last ((n - 1) mod 4) + 1 characters) holds nd data characters.
+__device__ __forceinline__ int64_t sink_length(int64_t n, int nd)
+{
+    const int64_t r = ((n - 1) & 3) + 1;
+    return 3 * ((n - r) >> 2) + nd - 1;
+}
+
+// The tail lane's valid end: decoded length len of the whole input of n
+// characters.
+__device__ __forceinline__ void sink_len(const DecSink &s, SinkLane &l, int64_t len, int64_t n)
 {
     if (s.slot)
-        consume(__hip_atomic_exchange(s.slot + 2, len, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+        l.nd = n > 0 ? (int)(len - sink_length(n, 1) + 1) : 1;
     else
         *s.out_len = len;
 }
 
-// Called by every thread of every workgroup after its last report.
-__device__ __forceinline__ void sink_finish(const DecSink &s)
+// Called by every thread of every workgroup after its last report; `tail` is
+// whether this workgroup holds the tail lane (thread kThreads - 1).
+__device__ __forceinline__ void sink_finish(const DecSink &s, const SinkLane &l, bool tail,
+                                            int64_t n)
 {
     if (!s.slot) return;
-    __syncthreads();
-    if (threadIdx.x != 0) return;
-    const int64_t done =
-        __hip_atomic_fetch_add(s.slot + 1, (int64_t)1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (done != (int64_t)gridDim.x - 1) return;
-    const int64_t key = __hip_atomic_exchange(s.slot, (int64_t)0, __ATOMIC_RELAXED,
-                                              __HIP_MEMORY_SCOPE_AGENT);
-    const int64_t len = __hip_atomic_exchange(s.slot + 2, (int64_t)0, __ATOMIC_RELAXED,
-                                              __HIP_MEMORY_SCOPE_AGENT);
-    consume(__hip_atomic_exchange(s.slot + 1, (int64_t)0, __ATOMIC_RELAXED,
-                                  __HIP_MEMORY_SCOPE_AGENT));
-    *s.first_bad = key ? kNoError - key : -1;
-    *s.out_len = key ? -1 : len;
+    const int any_bad = __syncthreads_or(l.bad);
+    if ((int)threadIdx.x != (tail ? kThreads - 1 : 0)) return;
+    constexpr int64_t kOne = (int64_t)1 << 32;
+    int64_t v = kOne | ((int64_t)l.nd << 24) | (any_bad ? 1 : 0);
+    const int64_t G = gridDim.x;
+    if (G > 1) {
+        int64_t expect = G;
+        if (G > 8 * kSinkGroups) {
+            const int g = (int)(blockIdx.x % kSinkGroups);
+            int64_t *cnt = s.slot + 16 * (g + 1);
+            const int64_t members = (G - 1 - g) / kSinkGroups + 1;
+            const int64_t old =
+                __hip_atomic_fetch_add(cnt, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if ((old >> 32) + 1 != members) return;
+            __hip_atomic_store(cnt, (int64_t)0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            v = kOne | ((old + v) & 0xFFFFFFFF);        // the group counts as one
+            expect = kSinkGroups;
+        }
+        const int64_t old =
+            __hip_atomic_fetch_add(s.slot + 1, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if ((old >> 32) + 1 != expect) return;
+        v += old;
+        __hip_atomic_store(s.slot + 1, (int64_t)0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    if ((v & 0xFFFFFF) == 0) {
+        *s.first_bad = -1;
+        *s.out_len = n > 0 ? sink_length(n, (int)((v >> 24) & 0xFF)) : 0;
+    } else {
+        const int64_t key =
+            __hip_atomic_exchange(s.slot, (int64_t)0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        *s.first_bad = kNoError - key;
+        *s.out_len = -1;
+    }
 }
 
 // `nrounds` complete rounds of lane chunks: round r holds chunks
@@ -520,23 +599,39 @@ __device__ __forceinline__ void dec_stream(const uint8_t *s0, uint8_t *d0, int64
     }
 }
 
+// The last, partial round in two steps, so that a kernel can issue its loads
+// early: the loads (lanes past the end load the last in-range chunk again),
+// then the decodes and stores of the chunks below nch.
 template <int U, bool NT>
-__device__ __forceinline__ void dec_round_tail(const uint8_t *s0, uint8_t *d0, int64_t c0,
-                                               int64_t stride, const uint8_t *map, uint32_t &err,
-                                               int64_t nch)
+__device__ __forceinline__ void dec_round_load(u32x4 (&in)[U], const uint8_t *s0, int64_t c0,
+                                               int64_t stride, int64_t nch)
 {
     if (nch <= 0) return;
-    u32x4 in[U];
 #pragma unroll
     for (int j = 0; j < U; ++j) {
         const int64_t c = c0 + j * stride;
         in[j] = load16<NT>(s0 + 16 * (c < nch ? c : nch - 1));
     }
+}
+template <int U, bool NT>
+__device__ __forceinline__ void dec_round_store(const u32x4 (&in)[U], uint8_t *d0, int64_t c0,
+                                                int64_t stride, const uint8_t *map, uint32_t &err,
+                                                int64_t nch)
+{
 #pragma unroll
     for (int j = 0; j < U; ++j) {
         const int64_t c = c0 + j * stride;
         if (c < nch) store12<NT>(d0 + 12 * c, dec_chunk(in[j], map, err));
     }
+}
+template <int U, bool NT>
+__device__ __forceinline__ void dec_round_tail(const uint8_t *s0, uint8_t *d0, int64_t c0,
+                                               int64_t stride, const uint8_t *map, uint32_t &err,
+                                               int64_t nch)
+{
+    u32x4 in[U];
+    dec_round_load<U, NT>(in, s0, c0, stride, nch);
+    dec_round_store<U, NT>(in, d0, c0, stride, map, err, nch);
 }
 
 }  // namespace b64hip

@@ -14,7 +14,7 @@ namespace b64hip {
 struct Shape { int unroll, bpc, nt; };
 
 // Blocks for a grid-stride launch over `nch` lane chunks: enough to cover
-// them with `unroll` chunks per lane if that takes at most 16 per CU, else
+// them with `unroll` chunks per lane if that takes at most `bpc` per CU, else
 // `bpc` per CU; a whole number per XCD.
 int64_t grid_for(int64_t nch, Shape sh, int cus);
 
@@ -31,9 +31,9 @@ hipError_t launch_decode(const uint8_t *src, int64_t n, uint8_t *dst, const DecM
 hipError_t launch_validate(const uint8_t *src, int64_t n, const DecMap &map, const DecSink &sink,
                            uint32_t flags, Shape sh, int cus, hipStream_t stream);
 // Device address of status slot `idx` (0 <= idx < kStatusSlots) of the
-// current device: three int64 words, zero between calls (the slot form of
-// DecSink).
-constexpr int kStatusSlots = 4096;
+// current device: kSlotWords int64 words, zero between calls (the slot form
+// of DecSink).
+constexpr int kStatusSlots = 1024;
 hipError_t status_slot_addr(int idx, int64_t **out);
 hipError_t launch_fill(int64_t *p, int64_t count, int64_t value, hipStream_t stream);
 hipError_t launch_finish(int64_t *out_len, int64_t *first_bad, int64_t count, hipStream_t stream);

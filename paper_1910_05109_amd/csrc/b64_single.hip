@@ -4,10 +4,10 @@
 namespace b64hip {
 
 // Status slots of the single-launch decode and validation (the slot form of
-// DecSink): kStatusSlots x 4 int64 per device, zero when the code object is
-// loaded and put back to zero by every call that uses one.  Kernels reach
-// them through the address passed in DecSink only.
-__device__ __align__(256) int64_t g_status_slots[kStatusSlots * 4];
+// DecSink): kStatusSlots x kSlotWords int64 (2.1 MiB) per device, zero when
+// the code object is loaded and put back to zero by every call that uses one.
+// Kernels reach them through the address passed in DecSink only.
+__device__ __align__(256) int64_t g_status_slots[kStatusSlots * kSlotWords];
 
 namespace {
 
@@ -58,7 +58,7 @@ __global__ __launch_bounds__(kThreads) void k_encode(const uint8_t *__restrict__
 // 128-byte line (3*head = -dst mod 128; 43 is the inverse of 3 mod 128); then
 // lane chunk c covers characters [4*head + 16c, +16) and bytes
 // [3*head + 12c, +12).  Threads t < head decode one head quantum each; the
-// last thread runs dec_tail_fast over the (at most three) body quanta left after
+// last thread decodes the tail: the (at most three) body quanta left after
 // the chunks and the last quantum.
 // The result goes to `sink` (raw or slot form, see DecSink).  Under
 // kFlagNoPad '=' is invalid everywhere and the last quantum may have 2 or 3
@@ -69,10 +69,6 @@ __global__ __launch_bounds__(kThreads) void k_decode(const uint8_t *__restrict__
                                                      DecSink sink, uint32_t flags)
 {
     const bool nopad = (flags & kFlagNoPad) != 0;
-    __shared__ uint32_t s_map[64];
-    stage_dec_map(s_map, map);
-    const uint8_t *m = (const uint8_t *)s_map;
-
     const int64_t nbq = n >= 1 ? (n - 1) >> 2 : 0;
     const uint64_t da = (uint64_t)(uintptr_t)dst;
     int64_t head = (int64_t)(((0 - da) * 43u) & (uint64_t)(kLine - 1));
@@ -82,20 +78,37 @@ __global__ __launch_bounds__(kThreads) void k_decode(const uint8_t *__restrict__
     uint8_t *d0 = dst + 3 * head;
     const int64_t T = (int64_t)gridDim.x * kThreads;
     const int64_t t = logical_block() * kThreads + threadIdx.x;
-    uint32_t err = 0;
     // rounds of U*T chunks; all but the last are complete
     const int64_t nfull = nch / (U * T);
-    int64_t c0 = t;
-    dec_stream<U, NT>(s0, d0, c0, T, U * T, nfull, m, err);
-    c0 += nfull * U * T;
-    dec_round_tail<U, NT>(s0, d0, c0, T, m, err, nch);
+    const int64_t q = head + 4 * nch;               // first quantum of the tail
+    // Loads that need no map are issued before the map is staged, so that
+    // their latency overlaps the staging: the head quantum, the tail and, when
+    // the input takes a single round, that round's chunks.
+    uint32_t hq = 0;
+    if (t < head) hq = *(const u32a1 *)(src + 4 * t);
+    TailIn tin = {{0u, 0u, 0u}, 0u};
+    if (t == kThreads - 1) tin = tail_load(src + 4 * q, n - 4 * q);
+    u32x4 first[U];
+    if (nfull == 0) dec_round_load<U, NT>(first, s0, t, T, nch);
+
+    __shared__ uint32_t s_map[64];
+    stage_dec_map(s_map, map);
+    const uint8_t *m = (const uint8_t *)s_map;
+    uint32_t err = 0;
+    SinkLane lane;
+    if (nfull == 0) {
+        if (nch > 0) dec_round_store<U, NT>(first, d0, t, T, m, err, nch);
+    } else {
+        dec_stream<U, NT>(s0, d0, t, T, U * T, nfull, m, err);
+        dec_round_tail<U, NT>(s0, d0, t + nfull * U * T, T, m, err, nch);
+    }
     // One test per lane for its whole share (bit 7 is set only by kBad).
     if (__ballot(err & 0x80)) {
         if (err & 0x80) {
             for (int64_t c = t; c < nch; c += T) {
                 const int64_t bad = dec_check_inner(s0 + 16 * c, 16, m, nopad);
                 if (bad >= 0) {
-                    sink_bad(sink, 4 * head + 16 * c + bad);
+                    sink_bad(sink, lane, 4 * head + 16 * c + bad);
                     break;   // later chunks of this lane have larger offsets
                 }
             }
@@ -103,23 +116,23 @@ __global__ __launch_bounds__(kThreads) void k_decode(const uint8_t *__restrict__
     }
     if (t < head) {
         uint32_t qerr = 0;
-        const uint32_t v = dec_quantum(*(const u32a1 *)(src + 4 * t), m, qerr);
+        const uint32_t v = dec_quantum(hq, m, qerr);
         dst[3 * t] = (uint8_t)(v >> 16);
         dst[3 * t + 1] = (uint8_t)(v >> 8);
         dst[3 * t + 2] = (uint8_t)v;
         if (qerr & 0x80) {
             const int64_t bad = dec_check_inner(src + 4 * t, 4, m, nopad);
-            if (bad >= 0) sink_bad(sink, 4 * t + bad);
+            if (bad >= 0) sink_bad(sink, lane, 4 * t + bad);
         }
     }
     if (t == kThreads - 1) {
-        const int64_t q = head + 4 * nch;
         int64_t len = 0;
-        const int64_t bad = dec_tail_fast(src + 4 * q, n - 4 * q, n, dst + 3 * q, m, &len, nopad);
-        if (bad >= 0) sink_bad(sink, 4 * q + bad);
-        else sink_len(sink, len);
+        const int64_t bad =
+            dec_tail_regs(tin, src + 4 * q, n - 4 * q, n, dst + 3 * q, m, &len, nopad);
+        if (bad >= 0) sink_bad(sink, lane, 4 * q + bad);
+        else sink_len(sink, lane, len, n);
     }
-    sink_finish(sink);
+    sink_finish(sink, lane, logical_block() == 0, n);
 }
 
 __global__ void k_fill_i64(int64_t *p, int64_t count, int64_t value)
@@ -145,11 +158,11 @@ int64_t grid_for(int64_t nch, Shape sh, int cus)
 {
     const int64_t per_block = (int64_t)kThreads * sh.unroll;
     const int64_t need = (nch + per_block - 1) / per_block;
-    // An input small enough to be covered by up to 16 blocks per CU in a
-    // single round is latency-bound: give it every block it needs, so that all
-    // its loads are in flight at once.  Larger inputs stream with the tuned
-    // number of blocks per CU.
-    int64_t grid = need <= (int64_t)cus * 16 ? need : (int64_t)cus * sh.bpc;
+    // An input that `bpc` blocks per CU cover in one round gets exactly the
+    // blocks it needs, so that all its loads are in flight at once; larger
+    // inputs stream through `bpc` blocks per CU.  (Small inputs are tuned to
+    // many blocks per CU, large ones to few.)
+    int64_t grid = need <= (int64_t)cus * sh.bpc ? need : (int64_t)cus * sh.bpc;
     if (grid >= kXcds) grid -= grid % kXcds;   // a whole number of blocks per XCD
     return grid < 1 ? 1 : grid;
 }
@@ -186,7 +199,7 @@ hipError_t status_slot_addr(int idx, int64_t **out)
         base = (int64_t *)p;
         __atomic_store_n(&g_slots_base[dev], base, __ATOMIC_RELEASE);
     }
-    *out = base + 4 * (int64_t)idx;
+    *out = base + (int64_t)kSlotWords * idx;
     return hipSuccess;
 }
 

@@ -70,37 +70,59 @@ __global__ __launch_bounds__(kThreads) void k_validate(const uint8_t *__restrict
                                                        DecMap map, DecSink sink, uint32_t flags)
 {
     const bool nopad = (flags & kFlagNoPad) != 0;
-    __shared__ uint32_t s_map[64];
-    stage_dec_map(s_map, map);
-    const uint8_t *m = (const uint8_t *)s_map;
-
     const int64_t nbq = n >= 1 ? (n - 1) >> 2 : 0;
     const int64_t nch = nbq >> 2;
     const int64_t T = (int64_t)gridDim.x * kThreads;
     const int64_t t = logical_block() * kThreads + threadIdx.x;
     const int64_t nfull = nch / (U * T);
-    uint32_t err = val_stream<U, NT>(src, t, T, U * T, nfull, m);
-    for (int64_t c = t + nfull * U * T; c < nch; c += T) err |= val_chunk(load16<NT>(src + 16 * c), m);
+    const int64_t q0 = 4 * nch;                     // first quantum after the chunks
+    // Loads that need no map go first, overlapping the staging of the map:
+    // the tail and, when the input takes a single round, that round's chunks.
+    TailIn tin = {{0u, 0u, 0u}, 0u};
+    if (t == kThreads - 1) tin = tail_load(src + 4 * q0, n - 4 * q0);
+    u32x4 first[U];
+    if (nfull == 0 && nch > 0) {
+#pragma unroll
+        for (int j = 0; j < U; ++j) {
+            const int64_t c = t + j * T;
+            first[j] = load16<NT>(src + 16 * (c < nch ? c : nch - 1));
+        }
+    }
+
+    __shared__ uint32_t s_map[64];
+    stage_dec_map(s_map, map);
+    const uint8_t *m = (const uint8_t *)s_map;
+    SinkLane lane;
+    uint32_t err = 0;
+    if (nfull == 0) {
+        if (nch > 0) {
+#pragma unroll
+            for (int j = 0; j < U; ++j)
+                if (t + j * T < nch) err |= val_chunk(first[j], m);
+        }
+    } else {
+        err = val_stream<U, NT>(src, t, T, U * T, nfull, m);
+        for (int64_t c = t + nfull * U * T; c < nch; c += T)
+            err |= val_chunk(load16<NT>(src + 16 * c), m);
+    }
     if (__ballot(err & 0x80)) {
         if (err & 0x80) {
             for (int64_t c = t; c < nch; c += T) {
                 const int64_t bad = dec_check_inner(src + 16 * c, 16, m, nopad);
                 if (bad >= 0) {
-                    sink_bad(sink, 16 * c + bad);
+                    sink_bad(sink, lane, 16 * c + bad);
                     break;   // later chunks of this lane have larger offsets
                 }
             }
         }
     }
     if (t == kThreads - 1) {
-        const int64_t q0 = 4 * nch;                 // first quantum after the chunks
-        const uint8_t *p = src + 4 * q0;
         int64_t len = 0;
-        const int64_t bad = dec_tail_fast(p, n - 4 * q0, n, nullptr, m, &len, nopad);
-        if (bad >= 0) sink_bad(sink, 4 * q0 + bad);
-        else sink_len(sink, len);
+        const int64_t bad = dec_tail_regs(tin, src + 4 * q0, n - 4 * q0, n, nullptr, m, &len, nopad);
+        if (bad >= 0) sink_bad(sink, lane, 4 * q0 + bad);
+        else sink_len(sink, lane, len, n);
     }
-    sink_finish(sink);
+    sink_finish(sink, lane, logical_block() == 0, n);
 }
 
 }  // namespace

@@ -2,8 +2,9 @@
 one graph holds b64_encode, b64_decode_async, b64_validate_async and
 b64_decode_f32_bf16; it is replayed several times with new input contents
 (valid and invalid, in turn) and eager work between the replays, and every
-replay is checked against the oracle.  The status words are reset by fill
-kernels inside the graph (no memset nodes)."""
+replay is checked against the oracle.  The status words hold garbage before
+each replay (the captured decode and validation keep their running status in
+a status slot of their own, and no memset nodes are recorded)."""
 import numpy as np
 import pytest
 

@@ -51,11 +51,11 @@ class _Shape:
         self.b64, self.op, self.shape = b64, op, shape
 
     def __enter__(self):
-        self.old = self.b64.tune_get(self.op)
-        self.b64.tune_set(self.op, *self.shape)
+        self.old = self.b64.tune_shapes(self.op)
+        self.b64.tune_set(self.op, *self.shape)          # every size bucket
 
     def __exit__(self, *exc):
-        self.b64.tune_set(self.op, *self.old)
+        self.b64.tune_restore(self.op, self.old)
 
 
 def _place(parts, misalign=True):

@@ -159,3 +159,55 @@ def test_per_thread_stream_from_four_threads(b64, cases):
                 _, want, ref = cases[i]
                 if want[1] == -1:
                     assert torch.equal(outs[tid][i][: ref.numel()], ref), (tid, i)
+
+
+def test_graph_replays_back_to_back(b64, cases):
+    """A captured decode and validation own a status slot: replays queued
+    back to back, each after new input contents are copied in and followed by
+    a copy of its status words, all give the oracle's statuses."""
+    import torch
+    picks = [i for i, (t, _, _) in enumerate(cases) if 0 < t.numel() <= 4 << 20]
+    stream = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    for i in picks:
+        t, want, ref = cases[i]
+        n = t.numel()
+        src = torch.empty(n, dtype=torch.uint8, device="cuda")
+        out = torch.empty(max(3 * (n // 4), 1), dtype=torch.uint8, device="cuda")
+        st = torch.empty(2, dtype=torch.int64, device="cuda")
+        vt = torch.empty(2, dtype=torch.int64, device="cuda")
+        with torch.cuda.stream(stream):
+            src.copy_(t)
+            b64.decode_async(src, out=out, status=st)          # warm-up outside the capture
+            b64.validate_async(src, status=vt)
+        stream.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=stream):
+            b64.decode_async(src, out=out, status=st)
+            b64.validate_async(src, status=vt)
+        # replays alternate this input with a spoiled copy, all queued at once
+        bad = t.clone()
+        bad[n // 2] = ord("*")
+        bad_first = min(want[1], n // 2) if want[1] >= 0 else n // 2
+        hist = torch.empty((12, 4), dtype=torch.int64, device="cuda")
+        with torch.cuda.stream(stream):
+            for rep in range(12):
+                src.copy_(bad if rep % 2 else t)
+                st.fill_(-7)
+                vt.fill_(-7)
+                g.replay()
+                hist[rep, :2].copy_(st)
+                hist[rep, 2:].copy_(vt)
+        stream.synchronize()
+        say("status graph replays", i, "n", n)
+        h = to_host(hist)
+        for rep in range(12):
+            exp = [-1, bad_first] if rep % 2 else want
+            assert h[rep, :2].tolist() == exp and h[rep, 2:].tolist() == exp, (i, rep, h[rep], exp)
+        if ref is not None:
+            # the last replay decoded the spoiled copy; one more of the input itself
+            with torch.cuda.stream(stream):
+                src.copy_(t)
+                g.replay()
+            stream.synchronize()
+            assert to_host(st).tolist() == want and torch.equal(out[: ref.numel()], ref), i

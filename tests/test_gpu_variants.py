@@ -501,7 +501,7 @@ def test_skip_ws_launch_shapes_and_misaligned_output(b64, oracle, shape):
     texts = [workloads.sprinkle_ws(_mime(oracle, x[:300001]), workloads.SEED_BASE + 190, 3000, 5, 1,
                                    1 << 15),
              _mime(oracle, x[:(6 << 20) - 1])]
-    old = b64.tune_get("decode_ws")
+    old = b64.tune_shapes("decode_ws")
     try:
         b64.tune_set("decode_ws", *shape)
         for k, text in enumerate(texts):
@@ -517,7 +517,7 @@ def test_skip_ws_launch_shapes_and_misaligned_output(b64, oracle, shape):
                 assert first_mismatch(got[off:off + ref.size], ref) is None, (shape, k, off)
                 assert not got[:off].any() and not got[off + ref.size:].any(), (shape, k, off)
     finally:
-        b64.tune_set("decode_ws", *old)
+        b64.tune_restore("decode_ws", old)
 
 
 def test_skip_ws_input_ends_on_a_tile_boundary(b64, oracle):
