@@ -178,6 +178,23 @@ int64_t b64_decode_mode(const uint8_t *src, int64_t n, uint8_t *dst, const char 
 int64_t b64_decode_mode_async(const uint8_t *src, int64_t n, uint8_t *dst, int64_t *out_len,
                               int64_t *first_bad, const char *alphabet, uint32_t flags,
                               void *workspace, int64_t workspace_bytes, hipStream_t stream);
+/* For callers that cannot allocate device memory -- code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc: the
+ * whitespace-skipping decode of b64_decode_mode_async (flags = B64_SKIP_WS,
+ * optionally | B64_NOPAD; results in *out_len / *first_bad as there) whose
+ * workspace is a fixed 1 MiB array of device memory inside the library
+ * instead of a caller's buffer.  The library holds one such array per
+ * device until the process ends; the call allocates nothing.  Every call on
+ * one device uses that device's array, so calls that overlap on one device
+ * (on different streams, or from different threads) race and must not be
+ * made; calls one after another on one stream are fine (each starts by
+ * resetting what must start at zero).  Inputs longer than
+ * B64_NOALLOC_MAX_CHARS bytes, or flags without B64_SKIP_WS, return
+ * B64_EARG.  Asynchronous; returns 0 or B64_EARG / B64_EHIP. */
+#define B64_NOALLOC_MAX_CHARS INT64_C(4294868992)   /* 131,069 tiles of 32 KiB */
+int64_t b64_decode_ws_async_noalloc(const uint8_t *src, int64_t n, uint8_t *dst, int64_t *out_len,
+                                    int64_t *first_bad, const char *alphabet, uint32_t flags,
+                                    hipStream_t stream);
 /* Validate with variants.  Blocking; returns what b64_decode_mode would
  * return; writes no output. */
 int64_t b64_validate_mode(const uint8_t *src, int64_t n, const char *alphabet, uint32_t flags,

@@ -34,6 +34,7 @@ SIGNATURES = {
     "b64_encode_mode": ([_P, _I64, _P, _P, _U32, _I64, _P], _I64),
     "b64_decode_mode": ([_P, _I64, _P, _P, _U32, _P], _I64),
     "b64_decode_mode_async": ([_P, _I64, _P, _P, _P, _P, _U32, _P, _I64, _P], _I64),
+    "b64_decode_ws_async_noalloc": ([_P, _I64, _P, _P, _P, _P, _U32, _P], _I64),
     "b64_validate_mode": ([_P, _I64, _P, _U32, _P], _I64),
     "b64_validate_mode_async": ([_P, _I64, _P, _P, _P, _U32, _P, _I64, _P], _I64),
     "b64_encode_batch_mode": ([_P, _P, _I64, _P, _P, _P, _P, _U32, _P], _I64),

@@ -26,6 +26,15 @@ const char b64_alphabet_url[64] = {
 
 using namespace b64hip;
 
+// Device scratch of b64_decode_ws_async_noalloc: the workspace of the
+// whitespace-skipping decode as a fixed array of device memory, one copy per
+// device, held until the process ends.  In host code `scratch` names a
+// host-side stand-in, not device memory: its address on each device comes
+// from hipGetSymbolAddress (scratch_ptr below), and only that address is
+// passed to kernels.
+constexpr int64_t kScratchBytes = 1 << 20;
+static __device__ __align__(256) uint8_t scratch[kScratchBytes];
+
 namespace {
 
 thread_local char g_err[256];
@@ -177,6 +186,29 @@ hipError_t status_slot(StatusSlot **out)
         }
     }
     *out = &s;
+    return hipSuccess;
+}
+
+// Device address of `scratch` on the current device, looked up once per
+// device with that device current.
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices];
+
+hipError_t scratch_ptr(void **out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
     return hipSuccess;
 }
 
@@ -480,6 +512,23 @@ int64_t b64_decode_mode_async(const uint8_t *src, int64_t n, uint8_t *dst, int64
         return fail(B64_EARG, "workspace smaller than b64_decode_workspace_size");
     return decode_enqueue(src, n, dst, true, out_len, first_bad, alphabet, flags, workspace,
                           (flags & kFlagSkipWs) ? nullptr : stream_slot(stream), stream);
+}
+
+int64_t b64_decode_ws_async_noalloc(const uint8_t *src, int64_t n, uint8_t *dst, int64_t *out_len,
+                                    int64_t *first_bad, const char *alphabet, uint32_t flags,
+                                    hipStream_t stream)
+{
+    if (!(flags & kFlagSkipWs)) return fail(B64_EARG, "b64_decode_ws_async_noalloc needs B64_SKIP_WS");
+    const int64_t c = check_decode_args(n, alphabet, flags);
+    if (c) return c;
+    if (ws_workspace_bytes(n) > kScratchBytes)
+        return fail(B64_EARG, "input longer than B64_NOALLOC_MAX_CHARS (the 1 MiB scratch array)");
+    if ((n > 0 && (!src || !dst)) || !out_len || !first_bad) return fail(B64_EARG, "null pointer");
+    void *ws = nullptr;
+    const hipError_t e = scratch_ptr(&ws);
+    if (e != hipSuccess) return hip_fail(e, "scratch address");
+    return decode_enqueue(src, n, dst, true, out_len, first_bad, alphabet, flags, ws, nullptr,
+                          stream);
 }
 
 int64_t b64_decode_async(const uint8_t *src, int64_t n, uint8_t *dst, int64_t *out_len,

@@ -37,7 +37,7 @@ def test_header_declares_the_boundary():
         "b64_encoded_len_mode", "b64_decoded_max_len_mode", "b64_decode_workspace_size",
         "b64_encode_mode", "b64_decode_mode", "b64_decode_mode_async", "b64_validate_mode",
         "b64_validate_mode_async", "b64_encode_batch_mode", "b64_decode_batch_mode",
-        "b64_decode_f32_bf16",
+        "b64_decode_ws_async_noalloc", "b64_decode_f32_bf16",
         "b64_pipeline_create", "b64_pipeline_destroy", "b64_pipeline_encode",
         "b64_pipeline_decode", "b64_pipeline_last_error",
         "b64_tune_set_bucket", "b64_tune_set", "b64_tune_get_bucket", "b64_tune_get",
@@ -126,6 +126,17 @@ def test_argument_errors_without_gpu(lib):
     assert lib.b64_validate(None, 10, std, None) == EARG
     assert lib.b64_validate(fake, 10, dup, None) == EARG
     assert lib.b64_validate_async(fake, 10, fake, None, std, None) == EARG
+    # the allocation-free whitespace decode: B64_SKIP_WS required, length capped
+    assert lib.b64_decode_ws_async_noalloc(fake, 10, fake, fake, fake, std, 0, None) == EARG
+    assert lib.b64_decode_ws_async_noalloc(fake, 10, fake, fake, fake, std, 1, None) == EARG
+    assert lib.b64_decode_ws_async_noalloc(fake, 4294868993, fake, fake, fake, std, 2, None) == EARG
+    assert b"B64_NOALLOC_MAX_CHARS" in lib.b64_last_error()
+    assert lib.b64_decode_ws_async_noalloc(fake, -1, fake, fake, fake, std, 2, None) == EARG
+    assert lib.b64_decode_ws_async_noalloc(fake, 10, fake, None, fake, std, 2, None) == EARG
+    assert lib.b64_decode_ws_async_noalloc(fake, 10, fake, fake, fake, dup, 2, None) == EARG
+    # the cap matches the workspace the whitespace decode needs
+    assert lib.b64_decode_workspace_size(4294868992, 2) == 1 << 20
+    assert lib.b64_decode_workspace_size(4294868993, 2) > 1 << 20
     assert lib.b64_encode_batch(fake, fake, -1, fake, fake, fake, std, None) == EARG
     assert lib.b64_encode_batch(fake, None, 3, fake, fake, fake, std, None) == EARG
     assert lib.b64_decode_batch(fake, fake, 3, fake, fake, fake, None, std, None) == EARG
