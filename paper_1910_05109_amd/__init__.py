@@ -106,6 +106,17 @@ def _check_i64(t, what):
         raise ValueError(f"{what} must be contiguous")
 
 
+# The plain sizes 4*ceil(n/3) and 3*floor(n/4) (b64_encoded_len and
+# b64_decoded_max_len) computed here, without a library round trip on every
+# call; tests/test_abi.py pins these copies to the library's helpers.
+def _plain_enc_len(n: int) -> int:
+    return 4 * ((n + 2) // 3)
+
+
+def _plain_dec_cap(n: int) -> int:
+    return 3 * (n // 4)
+
+
 def encoded_len(n: int, flags: int = 0, line_len: int = 0) -> int:
     if flags == 0 and line_len == 0:
         return check(load().b64_encoded_len(n), "encoded_len")
@@ -138,8 +149,7 @@ def encode(x, alphabet=STD, out=None, stream=None, flags: int = 0, line_len: int
     torch = _torch()
     _check_u8(x, "x")
     n = x.numel()
-    # the plain length 4*ceil(n/3) (b64_encoded_len) without a library round trip
-    m = 4 * ((n + 2) // 3) if flags == 0 and line_len == 0 else encoded_len(n, flags, line_len)
+    m = _plain_enc_len(n) if flags == 0 and line_len == 0 else encoded_len(n, flags, line_len)
     if out is None:
         out = torch.empty(max(m, 1), dtype=torch.uint8, device=x.device)
     else:
@@ -160,8 +170,7 @@ def decode(s, alphabet=STD, out=None, stream=None, flags: int = 0):
     torch = _torch()
     _check_u8(s, "s")
     n = s.numel()
-    # the plain capacity 3*floor(n/4) (b64_decoded_max_len) without a library round trip
-    cap = 3 * (n // 4) if flags == 0 else decoded_max_len(n, flags)
+    cap = _plain_dec_cap(n) if flags == 0 else decoded_max_len(n, flags)
     if out is None:
         out = torch.empty(max(cap, 1), dtype=torch.uint8, device=s.device)
     else:
@@ -188,8 +197,7 @@ def decode_async(s, alphabet=STD, out=None, status=None, stream=None, flags: int
     torch = _torch()
     _check_u8(s, "s")
     n = s.numel()
-    # the plain capacity 3*floor(n/4) (b64_decoded_max_len) without a library round trip
-    cap = 3 * (n // 4) if flags == 0 else decoded_max_len(n, flags)
+    cap = _plain_dec_cap(n) if flags == 0 else decoded_max_len(n, flags)
     if out is None:
         out = torch.empty(max(cap, 1), dtype=torch.uint8, device=s.device)
     if status is None:

@@ -12,6 +12,21 @@ from . import STD, _lib
 from ._lib import B64Error, check, load
 
 
+def check_out(out, need: int, what: str) -> np.ndarray:
+    """A host output buffer of at least `need` bytes for the C pipeline, which
+    writes `need` bytes through a raw pointer: a new one when `out` is None,
+    else `out` itself if it is a writable, contiguous, one-dimensional uint8
+    numpy array that large (anything else raises ValueError)."""
+    if out is None:
+        return np.empty(max(need, 1), dtype=np.uint8)
+    if (not isinstance(out, np.ndarray) or out.dtype != np.uint8 or out.ndim != 1
+            or not out.flags.c_contiguous or not out.flags.writeable):
+        raise ValueError(f"{what}: out must be a writable, contiguous 1-D uint8 numpy array")
+    if out.size < need:
+        raise ValueError(f"{what}: out holds {out.size} bytes, {need} are needed")
+    return out
+
+
 class HostPipeline:
     """Owns the pipeline's streams and staging buffers until close()."""
 
@@ -52,9 +67,8 @@ class HostPipeline:
 
     def encode(self, x, alphabet=STD, out: np.ndarray | None = None) -> np.ndarray:
         x = self._u8(x)
-        m = 4 * ((x.size + 2) // 3)
-        if out is None:
-            out = np.empty(max(m, 1), dtype=np.uint8)
+        out = check_out(out, check(load().b64_encoded_len(x.size), "b64_encoded_len"),
+                        "HostPipeline.encode")
         a = ctypes.create_string_buffer(bytes(alphabet), 64)
         r = self._check(load().b64_pipeline_encode(self._h, x.ctypes.data, x.size,
                                                    out.ctypes.data, a), "b64_pipeline_encode")
@@ -63,9 +77,8 @@ class HostPipeline:
     def decode(self, s, alphabet=STD, out: np.ndarray | None = None):
         """(bytes, None) if valid, (None, first_invalid_offset) if not."""
         s = self._u8(s)
-        cap = 3 * (s.size // 4)
-        if out is None:
-            out = np.empty(max(cap, 1), dtype=np.uint8)
+        out = check_out(out, check(load().b64_decoded_max_len(s.size), "b64_decoded_max_len"),
+                        "HostPipeline.decode")
         a = ctypes.create_string_buffer(bytes(alphabet), 64)
         r = self._check(load().b64_pipeline_decode(self._h, s.ctypes.data, s.size,
                                                    out.ctypes.data, a), "b64_pipeline_decode")

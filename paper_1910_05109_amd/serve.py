@@ -30,6 +30,7 @@ from dataclasses import dataclass, field
 import numpy as np
 
 from . import STD, _lib
+from .batch import decoded_capacity, encoded_lengths
 
 ENC, DEC = 0, 1
 
@@ -67,7 +68,7 @@ class Pool:
 
 def make_pool(kind: int, data, lens: np.ndarray) -> Pool:
     lens = np.asarray(lens, dtype=np.int64)
-    cap = 4 * ((lens + 2) // 3) if kind == ENC else 3 * (lens // 4)
+    cap = encoded_lengths(lens) if kind == ENC else decoded_capacity(lens)
     return Pool(kind, data, _prefix(lens), _prefix(cap))
 
 

@@ -6,6 +6,7 @@ import os
 import re
 import subprocess
 
+import numpy as np
 import pytest
 
 from conftest import ROOT
@@ -214,3 +215,27 @@ def test_tuning_interface(lib):
     assert lib.b64_tune_ws_guess_min(-5) == 0
     assert lib.b64_tune_ws_guess_min(14 << 20) == 0
     assert lib.b64_tune_ws_guess_min(-1) == 14 << 20
+
+
+def test_binding_size_copies_match_the_library(lib):
+    """The Python side computes output sizes itself on hot paths (no library
+    round trip per call); every such copy must equal the library's helpers."""
+    import torch
+
+    import paper_1910_05109_amd as b64
+    from paper_1910_05109_amd import batch
+    ns = list(range(0, 3000)) + [2 ** k + r for k in range(12, 41) for r in (-2, -1, 0, 1, 2)]
+    arr = np.array(ns, dtype=np.int64)
+    t = torch.from_numpy(arr)
+    enc = np.array([lib.b64_encoded_len(n) for n in ns])
+    dec = np.array([lib.b64_decoded_max_len(n) for n in ns])
+    enc_np = np.array([lib.b64_encoded_len_mode(n, 1, 0) for n in ns])
+    dec_np = np.array([lib.b64_decoded_max_len_mode(n, 1) for n in ns])
+    assert [b64._plain_enc_len(n) for n in ns] == enc.tolist()
+    assert [b64._plain_dec_cap(n) for n in ns] == dec.tolist()
+    assert np.array_equal(batch.encoded_lengths(arr), enc)
+    assert np.array_equal(batch.decoded_capacity(arr), dec)
+    assert np.array_equal(b64._enc_cap(t).numpy(), enc)
+    assert np.array_equal(b64._dec_cap(t).numpy(), dec)
+    assert np.array_equal(b64._enc_cap_nopad(t).numpy(), enc_np)
+    assert np.array_equal(b64._dec_cap_nopad(t).numpy(), dec_np)

@@ -71,3 +71,26 @@ def test_workload_recipes():
     assert workloads.non_alphabet_bytes(
         b"ABCDEFGHIJKLMNOPQRSTUVWXYZabcdefghijklmnopqrstuvwxyz0123456789+/").size == 191
     assert len(workloads.sweep_lengths()) == 51
+
+
+def test_pipeline_output_buffer_checks():
+    """The host pipeline writes through a raw pointer, so a short or unusable
+    caller buffer must be refused before the call."""
+    from paper_1910_05109_amd.pipeline import check_out
+    assert check_out(None, 10, "t").size == 10
+    ok = np.zeros(16, dtype=np.uint8)
+    assert check_out(ok, 16, "t") is ok
+    with pytest.raises(ValueError):
+        check_out(np.zeros(15, dtype=np.uint8), 16, "t")
+    with pytest.raises(ValueError):
+        check_out(np.zeros(16, dtype=np.int32), 16, "t")
+    with pytest.raises(ValueError):
+        check_out(np.zeros((4, 4), dtype=np.uint8), 16, "t")
+    with pytest.raises(ValueError):
+        check_out(np.zeros(32, dtype=np.uint8)[::2], 16, "t")
+    ro = np.zeros(16, dtype=np.uint8)
+    ro.setflags(write=False)
+    with pytest.raises(ValueError):
+        check_out(ro, 16, "t")
+    with pytest.raises(ValueError):
+        check_out(bytearray(16), 16, "t")
