@@ -418,48 +418,80 @@ def run_batch(args, torch, b64):
     print(json.dumps(res), flush=True)
 
 
+def serve_requests(torch, b64, count: int):
+    """The serving workload's requests (without arrival times): sizes
+    log-normal (median 8 KiB, sigma 1.5) clipped to [1 B, 16 MiB], 50/50
+    encode / decode, 1% of decodes spoiled by one byte outside the alphabet.
+    Decode payloads are encodings of random bytes (made on the GPU with the
+    batched encode).  Returns kinds, packed host payloads, their offsets, the
+    raw lengths and the indices of the spoiled requests."""
+    seed = workloads.SEED_BASE + 5
+    sizes = workloads.serve_sizes(seed, count)
+    is_dec, is_bad = workloads.serve_kinds(seed + 1, count)
+    raw = workloads.random_bytes(seed + 3, int(sizes.sum()))
+    roff = workloads.offsets(sizes)
+    dec_idx = np.nonzero(is_dec)[0]
+    # encodings of the decode requests' bytes, one batched launch
+    draw = np.concatenate([raw[roff[i]:roff[i + 1]] for i in dec_idx]) if dec_idx.size else raw[:0]
+    d_in = torch.from_numpy(draw if draw.size else np.zeros(1, np.uint8)).cuda()
+    dtext, doff, _ = b64.encode_batch(d_in, torch.from_numpy(workloads.offsets(sizes[dec_idx])).cuda())
+    dtext = dtext.cpu().numpy()
+    doff = doff.cpu().numpy()
+    lens = sizes.copy()
+    lens[dec_idx] = np.diff(doff)
+    off = workloads.offsets(lens)
+    payload = np.empty(int(off[-1]), dtype=np.uint8)
+    enc_idx = np.nonzero(~is_dec)[0]
+    for i in enc_idx:
+        payload[off[i]:off[i + 1]] = raw[roff[i]:roff[i + 1]]
+    for k, i in enumerate(dec_idx):
+        payload[off[i]:off[i + 1]] = dtext[doff[k]:doff[k + 1]]
+    g = workloads.rng(seed + 4)
+    bad_bytes = workloads.non_alphabet_bytes(b64.STD)
+    spoil = np.nonzero(is_bad)[0]
+    for i in spoil:
+        if off[i + 1] > off[i]:
+            payload[off[i] + int(g.integers(0, off[i + 1] - off[i]))] = bad_bytes[g.integers(0, bad_bytes.size)]
+    return is_dec.astype(np.int32), payload, off, sizes, spoil
+
+
+def serve_rate(srv, torch, b64, kinds, payload, off, sizes, spoil, rate, count):
+    """Serve the first `count` requests at Poisson rate `rate`; check every
+    status; return the run's summary."""
+    seed = workloads.SEED_BASE + 5
+    arrival = workloads.serve_arrivals(seed + 2, count, rate)
+    arrival -= arrival[0]
+    res = srv.run(kinds[:count], arrival, payload, off[:count + 1])
+    enc = kinds[:count] == 0
+    sp = spoil[spoil < count]
+    ok = np.ones(count, dtype=bool)
+    ok[sp] = False
+    want_len = np.where(enc, 4 * ((sizes[:count] + 2) // 3), sizes[:count])
+    assert np.array_equal(res.out_len[ok], want_len[ok]) and (res.first_bad[ok] == -1).all()
+    assert (res.first_bad[sp] >= 0).all() and (res.out_len[sp] == -1).all()
+    summ = {"rate": rate, **res.summary(), "invalid": int(sp.size)}
+    return summ
+
+
 def run_serve(args, torch, b64):
-    """Poisson arrivals of mixed encode/decode requests at swept rates."""
+    """Poisson arrivals of mixed encode/decode requests through the native
+    continuous-batching server at swept rates (at least 100,000 requests or
+    10 s of arrivals per rate), payloads starting in pinned host memory."""
     from paper_1910_05109_amd import serve
+    count_max = args.requests
+    log("serve: making", count_max, "requests")
+    kinds, payload, off, sizes, spoil = serve_requests(torch, b64, count_max)
     out = []
-    for rate in args.rates:
-        count = int(min(args.requests, max(2000, rate * args.seconds)))
-        seed = workloads.SEED_BASE + 5
-        sizes = workloads.serve_sizes(seed, count)
-        is_dec, is_bad = workloads.serve_kinds(seed + 1, count)
-        arrival = workloads.serve_arrivals(seed + 2, count, rate)
-        kinds = is_dec.astype(np.int64)
-        enc_idx, dec_idx = np.nonzero(~is_dec)[0], np.nonzero(is_dec)[0]
-        pos = np.zeros(count, dtype=np.int64)
-        pos[enc_idx] = np.arange(enc_idx.size)
-        pos[dec_idx] = np.arange(dec_idx.size)
-        raw = workloads.random_bytes(seed + 3, int(sizes.sum()))
-        roff = workloads.offsets(sizes)
-        enc_lens = sizes[enc_idx]
-        enc_data = torch.from_numpy(np.concatenate([raw[roff[i]:roff[i + 1]] for i in enc_idx])
-                                    if enc_idx.size else np.zeros(1, np.uint8)).cuda()
-        # decode payloads: encodings of their raw bytes, 1% spoiled by one byte
-        dsrc = torch.from_numpy(np.concatenate([raw[roff[i]:roff[i + 1]] for i in dec_idx])
-                                if dec_idx.size else np.zeros(1, np.uint8)).cuda()
-        dtext, doff, _ = b64.encode_batch(dsrc, torch.from_numpy(workloads.offsets(sizes[dec_idx])).cuda())
-        doff_h = doff.cpu().numpy()
-        g = workloads.rng(seed + 4)
-        bad_bytes = workloads.non_alphabet_bytes(b64.STD)
-        spoil = np.nonzero(is_bad[dec_idx])[0]
-        for j in spoil:
-            p = int(doff_h[j] + g.integers(0, doff_h[j + 1] - doff_h[j]))
-            dtext[p] = int(bad_bytes[g.integers(0, bad_bytes.size)])
-        enc_pool = serve.make_pool(serve.ENC, enc_data, enc_lens)
-        dec_pool = serve.make_pool(serve.DEC, dtext, np.diff(doff_h))
-        srv = serve.Server(enc_pool, dec_pool, budget_bytes=32 << 30)
-        torch.cuda.synchronize()
-        stats = srv.run(kinds, arrival, pos)
-        dl, db = srv.results(serve.DEC)
-        assert (db[spoil] >= 0).all() and (np.delete(db, spoil) == -1).all()
-        summ = {"rate": rate, **stats.summary(), "invalid": int(spoil.size)}
-        log("serve", json.dumps(summ))
-        out.append(summ)
-    print(json.dumps({"workload": "serving", "sigma": workloads.SERVE_SIGMA, "rows": out}), flush=True)
+    with serve.Server(budget_bytes=32 << 30, nstreams=args.serve_streams,
+                      depth=args.serve_depth) as srv:
+        for rate in args.rates:
+            count = int(min(count_max, max(2000, rate * args.seconds)))
+            summ = serve_rate(srv, torch, b64, kinds, payload, off, sizes, spoil, rate, count)
+            log("serve", json.dumps(summ))
+            out.append(summ)
+    print(json.dumps({"workload": "serving", "sigma": workloads.SERVE_SIGMA,
+                      "streams": args.serve_streams, "depth": args.serve_depth, "rows": out}),
+          flush=True)
 
 
 def run_validate(args, torch, b64):
@@ -645,9 +677,12 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=512 << 20)
     ap.add_argument("--cpu-reps", type=int, default=5)
     ap.add_argument("--nbuf", type=int, default=workloads.BATCH_BUFFERS)
-    ap.add_argument("--rates", type=float, nargs="+", default=[1e3, 3e3, 1e4, 3e4, 1e5, 3e5])
+    ap.add_argument("--rates", type=float, nargs="+",
+                    default=[1e3, 3e3, 1e4, 3e4, 1e5, 2e5, 3e5, 5e5, 1e6, 2e6])
     ap.add_argument("--requests", type=int, default=100_000)
-    ap.add_argument("--seconds", type=float, default=2.0)
+    ap.add_argument("--seconds", type=float, default=10.0)
+    ap.add_argument("--serve-streams", type=int, default=2)
+    ap.add_argument("--serve-depth", type=int, default=2, help="launches in flight at most")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only; run it with --gpus 1", file=sys.stderr)

@@ -260,6 +260,57 @@ int64_t b64_pipeline_decode(b64_pipeline *p, const uint8_t *src, int64_t n, uint
                             const char *alphabet);
 const char *b64_pipeline_last_error(void);
 
+/* ------------------------------------------------------------- serving --
+ * A continuous-batching request server over the batched codec (the growth
+ * path that serves many small requests: requests that arrive while others
+ * are on the GPU join the next launch, and launches on different streams run
+ * at the same time).  b64_server_create allocates the device arena of
+ * `budget_bytes` (the HBM budget: every launch's payloads, offsets, outputs
+ * and statuses are allocated in it, and requests wait while it is full),
+ * `nstreams` HIP streams (1..16, default priority, launches go round robin)
+ * and events for up to `depth` launches in flight (nstreams..64); a launch
+ * coalesces up to `max_batch` queued requests of one kind and up to
+ * `max_batch_bytes` payload bytes (a single larger request still goes
+ * alone).  The server is bound to the device current at creation.  Returns
+ * NULL on error (message: b64_server_last_error()). */
+typedef struct b64_server b64_server;
+b64_server *b64_server_create(int64_t budget_bytes, int nstreams, int depth, int64_t max_batch,
+                              int64_t max_batch_bytes);
+void b64_server_destroy(b64_server *s);
+const char *b64_server_last_error(void);
+#define B64_SERVE_ENCODE 0
+#define B64_SERVE_DECODE 1
+/* stats[] entries written by b64_server_run                                  */
+#define B64_STAT_LAUNCHES 0        /* batched launches                          */
+#define B64_STAT_WALL_NS 1         /* first arrival window to last result, ns   */
+#define B64_STAT_PEAK_ARENA 2      /* most arena bytes held at once             */
+#define B64_STAT_MAX_INFLIGHT 3    /* most launches enqueued and not finished   */
+#define B64_STAT_MAX_CONCURRENT 4  /* most launches running on the device at once
+                                      (from device timestamps of their first and
+                                      last operation)                           */
+#define B64_STAT_OVERLAPPED 5      /* launches that ran at the same time as another */
+#define B64_STAT_ARENA 6           /* arena bytes                               */
+#define B64_STAT_COUNT 8
+/* Blocking.  Serves `nreq` requests on the calling thread and returns when
+ * all are done.  Request i (kind[i] = B64_SERVE_ENCODE or B64_SERVE_DECODE)
+ * arrives arrival_ns[i] nanoseconds after the call starts serving
+ * (non-decreasing); its payload is src[in_off[i] .. in_off[i+1]) in HOST
+ * memory (in_off: nreq+1 non-decreasing entries).  Before serving, the
+ * payloads are copied into pinned host pools (as a network stack would have
+ * left them); each request's bytes go to the device only when its launch is
+ * enqueued.  Results, in HOST memory: dst + out_off[i] receives the output
+ * (capacity b64_encoded_len / b64_decoded_max_len of the payload length),
+ * out_len[i] the output length (-1 for an invalid decode), first_bad[i] -1
+ * or the first invalid offset (decodes), done_ns[i] the time the request's
+ * results were in host memory (same clock as arrival_ns).  stats must hold
+ * B64_STAT_COUNT entries.  Returns 0, or B64_EARG / B64_EHIP (message:
+ * b64_server_last_error()).  One call at a time per server.
+ * (Section "Encoding" and Section "Decoding", per request.) */
+int64_t b64_server_run(b64_server *s, int64_t nreq, const int32_t *kind, const int64_t *arrival_ns,
+                       const uint8_t *src, const int64_t *in_off, uint8_t *dst,
+                       const int64_t *out_off, int64_t *out_len, int64_t *first_bad,
+                       int64_t *done_ns, const char *alphabet, int64_t *stats);
+
 /* Launch shape used by the kernels of operation `op` (0 encode, 1 decode,
  * 2 encode_batch, 3 decode_batch, 4 validate, 5 line-wrapped encode,
  * 6 whitespace-skipping decode / validate, 7 fused float32 -> bfloat16

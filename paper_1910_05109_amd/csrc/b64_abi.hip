@@ -51,35 +51,6 @@ int64_t hip_fail(hipError_t e, const char *where)
     return B64_EHIP;
 }
 
-// An alphabet must be invertible and may not contain the pad character.
-bool alphabet_ok(const char *alphabet)
-{
-    if (!alphabet) return false;
-    bool seen[256] = {false};
-    for (int v = 0; v < 64; ++v) {
-        const uint8_t c = (uint8_t)alphabet[v];
-        if (c == kPad || seen[c]) return false;
-        seen[c] = true;
-    }
-    return true;
-}
-
-EncTab make_enc(const char *alphabet)
-{
-    EncTab t;
-    memcpy(t.w, alphabet, 64);
-    return t;
-}
-
-DecMap make_dec(const char *alphabet)
-{
-    DecMap d;
-    uint8_t *b = (uint8_t *)d.w;
-    memset(b, (int)kBad, 256);
-    for (int v = 0; v < 64; ++v) b[(uint8_t)alphabet[v]] = (uint8_t)v;
-    return d;
-}
-
 bool is_ws(uint8_t c) { return c == ' ' || c == '\t' || c == '\r' || c == '\n'; }
 
 // Codes of the whitespace-skipping kernels: alphabet values, 0x40 for the four
@@ -139,6 +110,12 @@ Shape shape_of(int op, int64_t n)
     std::lock_guard<std::mutex> lk(g_mu);
     return g_shape[op][n < 0 ? kBuckets - 1 : bucket_of(n)];
 }
+
+}  // namespace
+
+Shape b64hip::batch_shape(int op) { return shape_of(op, -1); }
+
+namespace {
 
 constexpr int kMaxDevices = 64;
 // Compute units per device, asked once (threads may race to ask; they store
@@ -211,6 +188,12 @@ hipError_t scratch_ptr(void **out)
     *out = g_scratch_ptr[dev];
     return hipSuccess;
 }
+
+}  // namespace
+
+hipError_t b64hip::device_cus(int *cus) { return cu_count(cus); }
+
+namespace {
 
 const char *const kBadAlphabet = "alphabet must be 64 distinct bytes without '='";
 

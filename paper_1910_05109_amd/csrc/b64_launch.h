@@ -13,6 +13,48 @@ namespace b64hip {
 // whether streaming loads / stores carry the nontemporal hint.
 struct Shape { int unroll, bpc, nt; };
 
+// An alphabet must be invertible and may not contain the pad character.
+inline bool alphabet_ok(const char *alphabet)
+{
+    if (!alphabet) return false;
+    bool seen[256] = {false};
+    for (int v = 0; v < 64; ++v) {
+        const uint8_t c = (uint8_t)alphabet[v];
+        if (c == kPad || seen[c]) return false;
+        seen[c] = true;
+    }
+    return true;
+}
+
+// The kernel-argument tables of an alphabet: its 64 bytes (encode), and the
+// 256-entry map from byte to value or kBad (decode).
+inline EncTab make_enc(const char *alphabet)
+{
+    EncTab t;
+    for (int i = 0; i < 16; ++i)
+        t.w[i] = (uint32_t)(uint8_t)alphabet[4 * i] | (uint32_t)(uint8_t)alphabet[4 * i + 1] << 8 |
+                 (uint32_t)(uint8_t)alphabet[4 * i + 2] << 16 |
+                 (uint32_t)(uint8_t)alphabet[4 * i + 3] << 24;
+    return t;
+}
+
+inline DecMap make_dec(const char *alphabet)
+{
+    DecMap d;
+    uint8_t b[256];
+    for (int i = 0; i < 256; ++i) b[i] = (uint8_t)kBad;
+    for (int v = 0; v < 64; ++v) b[(uint8_t)alphabet[v]] = (uint8_t)v;
+    for (int i = 0; i < 64; ++i)
+        d.w[i] = (uint32_t)b[4 * i] | (uint32_t)b[4 * i + 1] << 8 | (uint32_t)b[4 * i + 2] << 16 |
+                 (uint32_t)b[4 * i + 3] << 24;
+    return d;
+}
+
+// Workgroups per CU of the batched launches (the shape the library holds for
+// op, in its largest size bucket); cus: compute units of the current device.
+Shape batch_shape(int op);
+hipError_t device_cus(int *cus);
+
 // Blocks for a grid-stride launch over `nch` lane chunks: enough to cover
 // them with `unroll` chunks per lane if that takes at most `bpc` per CU, else
 // `bpc` per CU; a whole number per XCD.

@@ -1,0 +1,512 @@
+// b64_serve.hip -- a continuous-batching request server over the batched
+// codec (host code; every codec step runs in the batch kernels).
+//
+// Requests (encode or decode) arrive over time with their payloads in host
+// memory.  One scheduler thread (the caller's, inside b64_server_run) loops:
+//
+//   1. it notes every launch whose work has finished (a HIP event per launch,
+//      polled); the launch's requests are then done -- their results are in
+//      pinned host memory -- and their latency is that moment minus their
+//      arrival.  Device arena space is given back in launch order;
+//   2. it admits every request whose arrival time has passed: the request
+//      joins the queue of its kind;
+//   3. while fewer than `depth` launches are in flight, it takes the queued
+//      requests of one kind (the kinds alternate), as many as `max_batch`
+//      requests and `max_batch_bytes` payload bytes allow and the device arena
+//      (the HBM budget) can hold -- inputs, offsets, outputs and statuses --
+//      and enqueues on the next of `nstreams` streams (round robin): two
+//      host-to-device copies (the payloads; their offsets with the initial
+//      first-invalid values), ONE batched encode / decode kernel, and two
+//      device-to-host copies (the outputs; the lengths and first invalid
+//      offsets, which the host turns into the public form when the launch is
+//      done).
+//
+// Requests that arrive while others are on the GPU join the next launch;
+// launches on different streams run at the same time on the device (a copy
+// of one overlaps the kernel of another).  Requests of one kind are packed in
+// arrival order in pinned host pools when the run starts (the payloads as a
+// network stack would have left them), so a batch is a contiguous range of
+// its pool and moves with one copy each way.
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <chrono>
+#include <deque>
+#include <thread>
+#include <vector>
+
+#include "b64_launch.h"
+#include "b64hip.h"
+
+using namespace b64hip;
+
+struct b64_server {
+    int device = 0;
+    int64_t budget = 0;          // bytes of device arena
+    uint8_t *arena = nullptr;
+    int nstreams = 0, depth = 0;
+    int64_t max_batch = 0, max_batch_bytes = 0;
+    std::vector<hipStream_t> streams;
+    std::vector<hipEvent_t> ev_start, ev_end;     // one pair per in-flight slot
+    // pinned staging per in-flight slot: the launch's offsets and status
+    // initial values going in (3 * max_batch + 1 words), its lengths and first
+    // invalid offsets coming back (2 * max_batch words)
+    std::vector<int64_t *> meta_in, stat_out;
+    hipEvent_t ref = nullptr;
+};
+
+namespace {
+
+thread_local char s_err[256];
+
+int64_t s_fail(int64_t code, const char *msg)
+{
+    snprintf(s_err, sizeof s_err, "%s", msg);
+    return code;
+}
+
+int64_t s_hip(hipError_t e, const char *where)
+{
+    snprintf(s_err, sizeof s_err, "%s: %s", where, hipGetErrorString(e));
+    return B64_EHIP;
+}
+
+constexpr int64_t kAlign = 256;
+
+int64_t align_up(int64_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+// The device arena as a ring: allocations are given back in the order they
+// were made, so the live region is one span (possibly wrapped); an allocation
+// that does not fit before the end skips the tail, which stays held until the
+// allocation is given back.
+struct Ring {
+    int64_t size = 0, head = 0, used = 0, live = 0;
+
+    bool alloc(int64_t n, int64_t *start, int64_t *held)
+    {
+        if (n > size) return false;
+        const int64_t tail = size - head;
+        int64_t waste = 0, at = head;
+        if (n > tail) {
+            waste = tail;
+            at = 0;
+        }
+        if (used + waste + n > size) return false;
+        head = at + n;
+        used += waste + n;
+        ++live;
+        *start = at;
+        *held = waste + n;
+        return true;
+    }
+    void release(int64_t held)
+    {
+        used -= held;
+        if (--live == 0) head = used = 0;
+    }
+};
+
+// Requests of one kind, packed in arrival order in pinned host memory.
+struct Pool {
+    int kind = 0;
+    std::vector<int64_t> req;            // request index of each entry
+    uint8_t *in = nullptr, *out = nullptr;
+    int64_t *in_off = nullptr;           // entries + 1 (relative to `in`)
+    int64_t *out_off = nullptr;          // entries + 1 (relative to `out`)
+    int64_t *len = nullptr, *bad = nullptr;
+    int64_t ready = 0, next = 0;         // admitted prefix, first not yet launched
+
+    int64_t n() const { return (int64_t)req.size(); }
+    // arena bytes of entries [f, f + c): payload, then one block of words
+    // (c + 1 input offsets, c output offsets, c first invalid offsets, c
+    // lengths), then outputs
+    int64_t need(int64_t f, int64_t c) const
+    {
+        return align_up(in_off[f + c] - in_off[f]) + align_up(8 * (4 * c + 1)) +
+               align_up(out_off[f + c] - out_off[f]);
+    }
+    void free_host()
+    {
+        for (void *p : {(void *)in, (void *)out, (void *)in_off, (void *)out_off, (void *)len,
+                        (void *)bad})
+            if (p) (void)hipHostFree(p);
+        in = out = nullptr;
+        in_off = out_off = len = bad = nullptr;
+    }
+};
+
+struct Launch {
+    int kind = 0, slot = 0;
+    int64_t first = 0, count = 0, held = 0;
+    bool done = false;
+};
+
+int64_t now_ns(std::chrono::steady_clock::time_point t0)
+{
+    return std::chrono::duration_cast<std::chrono::nanoseconds>(std::chrono::steady_clock::now() -
+                                                                 t0)
+        .count();
+}
+
+hipError_t host_alloc(void **p, int64_t bytes)
+{
+    return hipHostMalloc(p, (size_t)std::max<int64_t>(bytes, 64), hipHostMallocDefault);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *b64_server_last_error(void) { return s_err; }
+
+b64_server *b64_server_create(int64_t budget_bytes, int nstreams, int depth, int64_t max_batch,
+                              int64_t max_batch_bytes)
+{
+    if (budget_bytes < (1 << 20)) return s_fail(0, "budget_bytes must be at least 1 MiB"), nullptr;
+    if (nstreams < 1 || nstreams > 16) return s_fail(0, "nstreams must be 1..16"), nullptr;
+    if (depth < nstreams || depth > 64) return s_fail(0, "depth must be nstreams..64"), nullptr;
+    if (max_batch < 1 || max_batch_bytes < 1) return s_fail(0, "batch limits must be positive"), nullptr;
+    b64_server *s = new b64_server;
+    s->budget = align_up(budget_bytes);
+    s->nstreams = nstreams;
+    s->depth = depth;
+    s->max_batch = max_batch;
+    s->max_batch_bytes = max_batch_bytes;
+    hipError_t e = hipGetDevice(&s->device);
+    if (e == hipSuccess) e = hipMalloc((void **)&s->arena, (size_t)s->budget);
+    for (int i = 0; e == hipSuccess && i < nstreams; ++i) {
+        hipStream_t st = nullptr;
+        e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+        if (e == hipSuccess) s->streams.push_back(st);
+    }
+    for (int i = 0; e == hipSuccess && i < depth; ++i) {
+        hipEvent_t a = nullptr, b = nullptr;
+        e = hipEventCreate(&a);
+        if (e == hipSuccess) e = hipEventCreate(&b);
+        if (e == hipSuccess) {
+            s->ev_start.push_back(a);
+            s->ev_end.push_back(b);
+        }
+        int64_t *mi = nullptr, *so = nullptr;
+        if (e == hipSuccess) e = host_alloc((void **)&mi, 8 * (3 * max_batch + 1));
+        if (e == hipSuccess) s->meta_in.push_back(mi);
+        if (e == hipSuccess) e = host_alloc((void **)&so, 8 * (2 * max_batch));
+        if (e == hipSuccess) s->stat_out.push_back(so);
+    }
+    if (e == hipSuccess) e = hipEventCreate(&s->ref);
+    if (e != hipSuccess) {
+        s_hip(e, "server creation");
+        b64_server_destroy(s);
+        return nullptr;
+    }
+    return s;
+}
+
+void b64_server_destroy(b64_server *s)
+{
+    if (!s) return;
+    (void)hipSetDevice(s->device);
+    for (hipStream_t st : s->streams) {
+        (void)hipStreamSynchronize(st);
+        (void)hipStreamDestroy(st);
+    }
+    for (hipEvent_t ev : s->ev_start) (void)hipEventDestroy(ev);
+    for (hipEvent_t ev : s->ev_end) (void)hipEventDestroy(ev);
+    if (s->ref) (void)hipEventDestroy(s->ref);
+    for (int64_t *p : s->meta_in) (void)hipHostFree(p);
+    for (int64_t *p : s->stat_out) (void)hipHostFree(p);
+    if (s->arena) (void)hipFree(s->arena);
+    delete s;
+}
+
+int64_t b64_server_run(b64_server *s, int64_t nreq, const int32_t *kind, const int64_t *arrival_ns,
+                       const uint8_t *src, const int64_t *in_off, uint8_t *dst,
+                       const int64_t *out_off, int64_t *out_len, int64_t *first_bad,
+                       int64_t *done_ns, const char *alphabet, int64_t *stats)
+{
+    if (!s) return s_fail(B64_EARG, "null server");
+    if (nreq < 0) return s_fail(B64_EARG, "negative request count");
+    if (nreq > 0 && (!kind || !arrival_ns || !src || !in_off || !dst || !out_off || !out_len ||
+                     !first_bad || !done_ns))
+        return s_fail(B64_EARG, "null pointer");
+    if (!stats) return s_fail(B64_EARG, "null stats");
+    if (!alphabet) return s_fail(B64_EARG, "null alphabet");
+    // the batched entry points check the alphabet; check it here as well, so
+    // that a bad one fails before anything is enqueued
+    {
+        bool seen[256] = {false};
+        for (int v = 0; v < 64; ++v) {
+            const uint8_t c = (uint8_t)alphabet[v];
+            if (c == '=' || seen[c]) return s_fail(B64_EARG, "alphabet must be 64 distinct bytes without '='");
+            seen[c] = true;
+        }
+    }
+    hipError_t e = hipSetDevice(s->device);
+    if (e != hipSuccess) return s_hip(e, "set device");
+
+    // ---- untimed set-up: pack each kind's payloads in pinned pools
+    Pool pool[2];
+    pool[0].kind = B64_SERVE_ENCODE;
+    pool[1].kind = B64_SERVE_DECODE;
+    for (int64_t i = 0; i < nreq; ++i) {
+        if (kind[i] != B64_SERVE_ENCODE && kind[i] != B64_SERVE_DECODE)
+            return s_fail(B64_EARG, "request kind must be B64_SERVE_ENCODE or B64_SERVE_DECODE");
+        if (in_off[i + 1] < in_off[i] || in_off[i] < 0) return s_fail(B64_EARG, "in_off must be non-decreasing");
+        if (i > 0 && arrival_ns[i] < arrival_ns[i - 1]) return s_fail(B64_EARG, "arrivals must be non-decreasing");
+        pool[kind[i]].req.push_back(i);
+    }
+    auto cleanup = [&]() {
+        pool[0].free_host();
+        pool[1].free_host();
+    };
+    for (Pool &p : pool) {
+        const int64_t m = p.n();
+        int64_t in_bytes = 0, out_bytes = 0;
+        for (int64_t k = 0; k < m; ++k) {
+            const int64_t len = in_off[p.req[k] + 1] - in_off[p.req[k]];
+            in_bytes += len;
+            out_bytes += p.kind == B64_SERVE_ENCODE ? b64_encoded_len(len) : b64_decoded_max_len(len);
+        }
+        if ((e = host_alloc((void **)&p.in, in_bytes)) != hipSuccess ||
+            (e = host_alloc((void **)&p.out, out_bytes)) != hipSuccess ||
+            (e = host_alloc((void **)&p.in_off, 8 * (m + 1))) != hipSuccess ||
+            (e = host_alloc((void **)&p.out_off, 8 * (m + 1))) != hipSuccess ||
+            (e = host_alloc((void **)&p.len, 8 * m)) != hipSuccess ||
+            (e = host_alloc((void **)&p.bad, 8 * m)) != hipSuccess) {
+            cleanup();
+            return s_hip(e, "pinned pools");
+        }
+        p.in_off[0] = p.out_off[0] = 0;
+        for (int64_t k = 0; k < m; ++k) {
+            const int64_t i = p.req[k], len = in_off[i + 1] - in_off[i];
+            memcpy(p.in + p.in_off[k], src + in_off[i], (size_t)len);
+            p.in_off[k + 1] = p.in_off[k] + len;
+            p.out_off[k + 1] = p.out_off[k] + (p.kind == B64_SERVE_ENCODE ? b64_encoded_len(len)
+                                                                           : b64_decoded_max_len(len));
+            p.len[k] = -1;
+            p.bad[k] = -1;
+        }
+        for (int64_t k = 0; k < m; ++k)
+            if (p.need(k, 1) > s->budget) {
+                cleanup();
+                return s_fail(B64_EARG, "a request does not fit in the HBM budget");
+            }
+    }
+
+    // ---- the timed loop
+    Ring ring;
+    ring.size = s->budget;
+    std::deque<Launch> fifo;
+    std::vector<int> free_slots;
+    for (int i = s->depth - 1; i >= 0; --i) free_slots.push_back(i);
+    std::vector<std::pair<float, float>> spans;      // device start / end of each launch, ms
+    int64_t launches = 0, peak_used = 0, max_inflight = 0, retired = 0, next_arrival = 0;
+    int turn = 0, next_stream = 0;
+    int64_t err = 0;
+    e = hipEventRecord(s->ref, s->streams[0]);
+    if (e != hipSuccess) {
+        cleanup();
+        return s_hip(e, "reference event");
+    }
+    const auto t0 = std::chrono::steady_clock::now();
+
+    int cus = 0;
+    e = device_cus(&cus);
+    if (e != hipSuccess) {
+        cleanup();
+        return s_hip(e, "device query");
+    }
+    const EncTab tab = make_enc(alphabet);
+    const DecMap map = make_dec(alphabet);
+    const Shape enc_shape = batch_shape(2), dec_shape = batch_shape(3);
+
+    // Enqueue entries [f, f + c) of pool p on the next stream: two copies in
+    // (the payload; the offsets and the first-invalid initial values in one
+    // block), one batched kernel, two copies out (the outputs; the first
+    // invalid offsets and lengths in one block).
+    auto launch = [&](Pool &p, int64_t f, int64_t c, int64_t start, int64_t held, int slot) -> int64_t {
+        hipStream_t st = s->streams[next_stream];
+        next_stream = (next_stream + 1) % s->nstreams;
+        const int64_t nin = p.in_off[f + c] - p.in_off[f], nout = p.out_off[f + c] - p.out_off[f];
+        uint8_t *d_in = s->arena + start;
+        int64_t *d_ioff = (int64_t *)(d_in + align_up(nin));     // c + 1
+        int64_t *d_ooff = d_ioff + c + 1;                        // c
+        int64_t *d_bad = d_ooff + c;                             // c
+        int64_t *d_len = d_bad + c;                              // c
+        uint8_t *d_out = (uint8_t *)d_ioff + align_up(8 * (4 * c + 1));
+        int64_t *mi = s->meta_in[slot];
+        memcpy(mi, p.in_off + f, (size_t)(8 * (c + 1)));
+        memcpy(mi + c + 1, p.out_off + f, (size_t)(8 * c));
+        const bool dec = p.kind == B64_SERVE_DECODE;
+        if (dec)
+            for (int64_t k = 0; k < c; ++k) mi[2 * c + 1 + k] = kNoError;
+        const int64_t nmeta = dec ? 3 * c + 1 : 2 * c + 1;
+        hipError_t x = hipEventRecord(s->ev_start[slot], st);
+        if (x == hipSuccess)
+            x = hipMemcpyAsync(d_in, p.in + p.in_off[f], (size_t)nin, hipMemcpyHostToDevice, st);
+        if (x == hipSuccess)
+            x = hipMemcpyAsync(d_ioff, mi, (size_t)(8 * nmeta), hipMemcpyHostToDevice, st);
+        if (x != hipSuccess) return s_hip(x, "request copies");
+        // the batch kernels index src / dst with the pool offsets of these entries
+        const uint8_t *src_base = d_in - p.in_off[f];
+        uint8_t *dst_base = d_out - p.out_off[f];
+        x = dec ? launch_decode_batch(src_base, d_ioff, c, dst_base, d_ooff, d_len, d_bad, map, 0,
+                                      dec_shape, cus, st)
+                : launch_encode_batch(src_base, d_ioff, c, dst_base, d_ooff, d_len, tab, 0,
+                                      enc_shape, cus, st);
+        if (x != hipSuccess) return s_hip(x, "batch launch");
+        x = hipMemcpyAsync(p.out + p.out_off[f], d_out, (size_t)nout, hipMemcpyDeviceToHost, st);
+        if (x == hipSuccess)
+            x = dec ? hipMemcpyAsync(s->stat_out[slot], d_bad, (size_t)(16 * c), hipMemcpyDeviceToHost, st)
+                    : hipMemcpyAsync(s->stat_out[slot] + c, d_len, (size_t)(8 * c),
+                                     hipMemcpyDeviceToHost, st);
+        if (x == hipSuccess) x = hipEventRecord(s->ev_end[slot], st);
+        if (x != hipSuccess) return s_hip(x, "result copies");
+        Launch L;
+        L.kind = p.kind;
+        L.slot = slot;
+        L.first = f;
+        L.count = c;
+        L.held = held;
+        fifo.push_back(L);
+        ++launches;
+        max_inflight = std::max<int64_t>(max_inflight, (int64_t)fifo.size());
+        return 0;
+    };
+
+    while (retired < nreq && !err) {
+        bool progress = false;
+        // 1. launches that have finished
+        for (Launch &L : fifo) {
+            if (L.done) continue;
+            const hipError_t q = hipEventQuery(s->ev_end[L.slot]);
+            if (q == hipErrorNotReady) continue;
+            if (q != hipSuccess) {
+                err = s_hip(q, "event query");
+                break;
+            }
+            const int64_t t = now_ns(t0);
+            Pool &p = pool[L.kind];
+            // the kernel's raw status: first invalid offset kNoError for a
+            // valid decode (whose length the kernel wrote), else the offset
+            const int64_t *bad = s->stat_out[L.slot], *len = bad + L.count;
+            for (int64_t k = 0; k < L.count; ++k) {
+                const int64_t e_ = L.first + k;
+                done_ns[p.req[e_]] = t;
+                if (p.kind == B64_SERVE_DECODE && bad[k] != kNoError) {
+                    p.bad[e_] = bad[k];
+                    p.len[e_] = -1;
+                } else {
+                    p.bad[e_] = -1;
+                    p.len[e_] = len[k];
+                }
+            }
+            float a = 0.f, b = 0.f;
+            if (hipEventElapsedTime(&a, s->ref, s->ev_start[L.slot]) == hipSuccess &&
+                hipEventElapsedTime(&b, s->ref, s->ev_end[L.slot]) == hipSuccess)
+                spans.emplace_back(a, b);
+            L.done = true;
+            retired += L.count;
+            progress = true;
+        }
+        while (!fifo.empty() && fifo.front().done) {
+            ring.release(fifo.front().held);
+            free_slots.push_back(fifo.front().slot);
+            fifo.pop_front();
+        }
+        // 2. arrivals
+        const int64_t t = now_ns(t0);
+        while (next_arrival < nreq && arrival_ns[next_arrival] <= t) {
+            ++pool[kind[next_arrival]].ready;
+            ++next_arrival;
+            progress = true;
+        }
+        // 3. launches of queued requests, the kinds in turn
+        for (int pass = 0; pass < 2 && !err; ++pass) {
+            Pool &p = pool[(turn + pass) & 1];
+            if (free_slots.empty()) break;
+            int64_t c = std::min<int64_t>(p.ready - p.next, s->max_batch);
+            if (c <= 0) continue;
+            while (c > 1 && p.in_off[p.next + c] - p.in_off[p.next] > s->max_batch_bytes) c = (c + 1) / 2;
+            int64_t start = 0, held = 0;
+            while (c > 0 && !ring.alloc(p.need(p.next, c), &start, &held)) c /= 2;
+            if (c == 0) continue;               // waits for earlier launches to give space back
+            const int slot = free_slots.back();
+            free_slots.pop_back();
+            err = launch(p, p.next, c, start, held, slot);
+            if (err) break;
+            peak_used = std::max(peak_used, ring.used);
+            p.next += c;
+            progress = true;
+        }
+        turn ^= 1;
+        if (!progress) {
+            // nothing to do: wait for the next arrival if nothing is in flight
+            if (fifo.empty() && next_arrival < nreq) {
+                const int64_t wait = arrival_ns[next_arrival] - now_ns(t0);
+                if (wait > 200000) std::this_thread::sleep_for(std::chrono::nanoseconds(wait - 100000));
+            } else {
+                std::this_thread::yield();
+            }
+        }
+    }
+    const int64_t wall = now_ns(t0);
+    for (hipStream_t st : s->streams) {
+        const hipError_t x = hipStreamSynchronize(st);
+        if (x != hipSuccess && !err) err = s_hip(x, "stream synchronize");
+    }
+    if (err) {
+        cleanup();
+        return err;
+    }
+    // ---- untimed: results to the caller's arrays
+    for (const Pool &p : pool) {
+        for (int64_t k = 0; k < p.n(); ++k) {
+            const int64_t i = p.req[k];
+            const int64_t len = p.len[k];
+            out_len[i] = len;
+            first_bad[i] = p.kind == B64_SERVE_ENCODE ? -1 : p.bad[k];
+            if (len > 0) memcpy(dst + out_off[i], p.out + p.out_off[k], (size_t)len);
+        }
+    }
+    // launches that were running on the device at the same time
+    int64_t concurrent = 0, overlapped = 0;
+    {
+        std::vector<std::pair<float, int>> ev;
+        for (auto &sp : spans) {
+            ev.emplace_back(sp.first, +1);
+            ev.emplace_back(sp.second, -1);
+        }
+        std::sort(ev.begin(), ev.end(),
+                  [](const std::pair<float, int> &a, const std::pair<float, int> &b) {
+                      return a.first < b.first || (a.first == b.first && a.second < b.second);
+                  });
+        int64_t cur = 0;
+        for (auto &x : ev) concurrent = std::max(concurrent, cur += x.second);
+        // sorted by start, launch k overlaps an earlier one when it starts
+        // before the latest end so far, and a later one when the next launch
+        // starts before it ends
+        std::vector<std::pair<float, float>> sorted = spans;
+        std::sort(sorted.begin(), sorted.end());
+        float reach = -1.f;
+        for (size_t k = 0; k < sorted.size(); ++k) {
+            const bool with_earlier = k > 0 && sorted[k].first < reach;
+            const bool with_later = k + 1 < sorted.size() && sorted[k + 1].first < sorted[k].second;
+            overlapped += (with_earlier || with_later) ? 1 : 0;
+            reach = std::max(reach, sorted[k].second);
+        }
+    }
+    stats[B64_STAT_LAUNCHES] = launches;
+    stats[B64_STAT_WALL_NS] = wall;
+    stats[B64_STAT_PEAK_ARENA] = peak_used;
+    stats[B64_STAT_MAX_INFLIGHT] = max_inflight;
+    stats[B64_STAT_MAX_CONCURRENT] = concurrent;
+    stats[B64_STAT_OVERLAPPED] = overlapped;
+    stats[B64_STAT_ARENA] = s->budget;
+    stats[B64_STAT_ARENA + 1] = 0;
+    cleanup();
+    return 0;
+}
+
+}  // extern "C"

@@ -1,6 +1,15 @@
-"""The serving loop: every request's result in the coalesced mix equals its
-result alone (single-buffer entry points) and the oracle's, bit-exact; the
-loop coalesces, overlaps launches and respects its HBM budget."""
+"""The native serving loop (b64_server_run): every request's result in the
+coalesced, overlapping mix equals its result alone (the single-buffer entry
+points) and the oracle's, bit-exact; launches run at the same time on the
+device; the device arena (the HBM budget) bounds what is in flight, and
+requests wait when it is full.
+
+Requests follow the serving workload's law -- sizes log-normal with median
+8 KiB and sigma 1.5 clipped to [1 B, 16 MiB], 50/50 encode and decode, some
+decodes spoiled by one invalid byte -- and a second case adds requests of
+several MiB up to 16 MiB under a budget small enough that the arena wraps and
+admission waits.
+"""
 import numpy as np
 import pytest
 
@@ -20,79 +29,108 @@ def b64():
     return b64
 
 
-@pytest.mark.parametrize("budget,rate", [(1 << 30, 2e4), (96 << 10, 5e4)],
-                         ids=["roomy", "tight_budget"])
-def test_mix_equals_alone(b64, oracle, budget, rate):
-    import torch
-    from paper_1910_05109_amd import serve
-    seed = workloads.SEED_BASE + 140
-    count = 800
-    sizes = workloads.serve_sizes(seed, count, median=2048, sigma=1.5)
-    sizes = np.minimum(sizes, 40_000)
-    is_dec, is_bad = workloads.serve_kinds(seed + 1, count, invalid_frac=0.05)
+def _schedule(oracle, seed, sizes, rate, invalid_frac):
+    """kinds, arrivals, packed host payloads and offsets; decode requests
+    carry the oracle's encoding of their bytes, some spoiled by one byte
+    outside the alphabet."""
+    count = sizes.size
+    is_dec, is_bad = workloads.serve_kinds(seed + 1, count, invalid_frac=invalid_frac)
     arrival = workloads.serve_arrivals(seed + 2, count, rate)
-    kinds = is_dec.astype(np.int64)
-    enc_idx, dec_idx = np.nonzero(~is_dec)[0], np.nonzero(is_dec)[0]
-    pos = np.zeros(count, dtype=np.int64)
-    pos[enc_idx] = np.arange(enc_idx.size)
-    pos[dec_idx] = np.arange(dec_idx.size)
     raw = workloads.random_bytes(seed + 3, int(sizes.sum()))
     roff = workloads.offsets(sizes)
-    payload = [raw[roff[i]:roff[i + 1]] for i in range(count)]
-    # decode requests carry the oracle's encoding, some spoiled by one byte
     g = workloads.rng(seed + 4)
     bad_bytes = workloads.non_alphabet_bytes(oracle.STD)
-    for i in dec_idx:
-        t = oracle.encode(payload[i])
-        if is_bad[i] and t.size:
-            t = t.copy()
-            t[g.integers(0, t.size)] = bad_bytes[g.integers(0, bad_bytes.size)]
-        payload[i] = t
-    enc_data = np.concatenate([payload[i] for i in enc_idx])
-    dec_data = np.concatenate([payload[i] for i in dec_idx])
-    enc_pool = serve.make_pool(serve.ENC, to_dev(enc_data), sizes[enc_idx])
-    dec_pool = serve.make_pool(serve.DEC, to_dev(dec_data), np.array([payload[i].size for i in dec_idx]))
-
-    served = {}
-
-    def on_retire(L, srv):
-        pool = srv.pools[L.kind]
-        base = int(pool.out_rel[L.first])
-        n = int(pool.out_rel[L.first + L.count]) - base
-        region = to_host(srv.arena[L.start: L.start + n])
-        for k in range(L.first, L.first + L.count):
-            served[(L.kind, k)] = region[int(pool.out_rel[k]) - base: int(pool.out_rel[k + 1]) - base]
-
-    say("serve", budget, rate)
-    srv = serve.Server(enc_pool, dec_pool, budget_bytes=budget, max_inflight=3, max_batch=64,
-                       on_retire=on_retire)
-    stats = srv.run(kinds, arrival, pos)
-    torch.cuda.synchronize()
-    summ = stats.summary()
-    say("serve summary", summ)
-    assert np.isfinite(stats.latency).all() and (stats.latency >= 0).all()
-    assert summ["launches"] < count and summ["mean_batch"] > 1.0     # coalescing happened
-    assert summ["peak_arena_used"] <= srv.arena_bytes <= max(budget, 1 << 20)
-    enc_len, _ = srv.results(serve.ENC)
-    dec_len, dec_bad = srv.results(serve.DEC)
+    parts = []
     for i in range(count):
-        k = pos[i]
-        if kinds[i] == serve.ENC:
-            alone = to_host(b64.encode(to_dev(payload[i]))) if payload[i].size else np.zeros(0, np.uint8)
-            ref = oracle.encode(payload[i])
-            assert enc_len[k] == ref.size
-            mixed = served[(serve.ENC, k)][: ref.size]
-            assert first_mismatch(mixed, ref) is None, i
-            assert first_mismatch(alone, ref) is None, i
+        x = raw[roff[i]:roff[i + 1]]
+        if is_dec[i]:
+            x = oracle.encode(x)
+            if is_bad[i] and x.size:
+                x = x.copy()
+                x[int(g.integers(0, x.size))] = bad_bytes[int(g.integers(0, bad_bytes.size))]
+        parts.append(x)
+    payload = np.concatenate(parts) if parts else np.zeros(0, np.uint8)
+    in_off = workloads.offsets(np.array([p.size for p in parts], dtype=np.int64))
+    return is_dec.astype(np.int32), arrival, payload, in_off, parts
+
+
+def _check_mix_alone_oracle(b64, oracle, res, kinds, parts, label):
+    import torch
+    for i, x in enumerate(parts):
+        if kinds[i] == 0:
+            ref = oracle.encode(x)
+            alone = to_host(b64.encode(to_dev(x))) if x.size else np.zeros(0, np.uint8)
+            assert res.out_len[i] == ref.size and res.first_bad[i] == -1, (label, i)
+            assert first_mismatch(res.output(i), ref) is None, (label, i)
+            assert first_mismatch(alone, ref) is None, (label, i)
         else:
-            ref, ref_bad = oracle.decode(payload[i])
-            import torch as _t
-            dt = to_dev(payload[i]) if payload[i].size else _t.empty(0, dtype=_t.uint8, device="cuda")
-            alone, alone_bad = b64.decode(dt)
-            assert alone_bad == ref_bad
+            ref, ref_bad = oracle.decode(x)
+            dx = to_dev(x) if x.size else torch.empty(0, dtype=torch.uint8, device="cuda")
+            alone, alone_bad = b64.decode(dx)
+            assert alone_bad == ref_bad, (label, i)
             if ref_bad is None:
-                assert dec_bad[k] == -1 and dec_len[k] == ref.size, i
-                assert first_mismatch(served[(serve.DEC, k)][: ref.size], ref) is None, i
-                assert first_mismatch(to_host(alone), ref) is None, i
+                assert res.first_bad[i] == -1 and res.out_len[i] == ref.size, (label, i)
+                assert first_mismatch(res.output(i), ref) is None, (label, i)
+                assert first_mismatch(to_host(alone), ref) is None, (label, i)
             else:
-                assert dec_bad[k] == ref_bad and dec_len[k] == -1, i
+                assert res.first_bad[i] == ref_bad and res.out_len[i] == -1, (label, i)
+
+
+def test_mix_equals_alone_serving_law(b64, oracle):
+    """3,000 requests of the serving law at 200,000 per second: coalesced,
+    with launches overlapping on the device."""
+    from paper_1910_05109_amd import serve
+    seed = workloads.SEED_BASE + 140
+    sizes = workloads.serve_sizes(seed, 3000)
+    kinds, arrival, payload, in_off, parts = _schedule(oracle, seed, sizes, 2e5, 0.02)
+    say("serve law", sizes.size, int(sizes.sum()))
+    with serve.Server(budget_bytes=32 << 30, nstreams=4, depth=8) as srv:
+        res = srv.run(kinds, arrival, payload, in_off)
+    summ = res.summary()
+    say("serve summary", summ)
+    assert np.isfinite(res.latency).all() and (res.latency > 0).all()
+    assert summ["launches"] < sizes.size and summ["mean_batch"] > 1.0     # coalescing happened
+    assert summ["max_concurrent"] >= 2 and summ["overlapped_launches"] >= 2, summ
+    assert summ["peak_arena_bytes"] <= summ["arena_bytes"]
+    _check_mix_alone_oracle(b64, oracle, res, kinds, parts, "law")
+
+
+def test_large_requests_under_a_tight_budget(b64, oracle):
+    """Requests of 1..16 MiB among small ones, a 40 MiB arena: the ring wraps
+    and requests wait for space; every result still equals the oracle's."""
+    from paper_1910_05109_amd import serve
+    seed = workloads.SEED_BASE + 145
+    sizes = workloads.serve_sizes(seed, 400)
+    big = workloads.rng(seed + 9).choice(sizes.size, size=12, replace=False)
+    sizes[big] = np.array([1 << 20, 3 << 20, (5 << 20) + 1, 7 << 20, (9 << 20) + 2, 11 << 20,
+                           12 << 20, (13 << 20) + 1, 14 << 20, 15 << 20, 16 << 20,
+                           (16 << 20) - 1])[: big.size]
+    kinds, arrival, payload, in_off, parts = _schedule(oracle, seed, sizes, 5e4, 0.05)
+    budget = 40 << 20
+    say("serve tight", sizes.size, int(sizes.sum()), "budget", budget)
+    with serve.Server(budget_bytes=budget, nstreams=3, depth=6, max_batch=64,
+                      max_batch_bytes=4 << 20) as srv:
+        res = srv.run(kinds, arrival, payload, in_off)
+    summ = res.summary()
+    say("serve summary", summ)
+    assert summ["arena_bytes"] == budget and summ["peak_arena_bytes"] <= budget
+    assert summ["peak_arena_bytes"] > budget // 2          # the budget was the limit
+    _check_mix_alone_oracle(b64, oracle, res, kinds, parts, "tight")
+
+
+def test_server_argument_errors(b64):
+    from paper_1910_05109_amd import serve
+    from paper_1910_05109_amd._lib import B64Error
+    with pytest.raises(B64Error):
+        serve.Server(budget_bytes=1 << 10)
+    with pytest.raises(B64Error):
+        serve.Server(budget_bytes=1 << 20, nstreams=0)
+    with serve.Server(budget_bytes=1 << 20, nstreams=1, depth=1) as srv:
+        payload = np.zeros(4 << 20, dtype=np.uint8)
+        with pytest.raises(B64Error):          # one request larger than the budget
+            srv.run(np.zeros(1, np.int32), np.zeros(1), payload, np.array([0, payload.size]))
+        with pytest.raises(B64Error):          # arrivals out of order
+            srv.run(np.zeros(2, np.int32), np.array([1e-3, 0.0]), payload[:8],
+                    np.array([0, 4, 8]))
+        res = srv.run(np.zeros(0, np.int32), np.zeros(0), payload[:0], np.zeros(1, np.int64))
+        assert res.out_len.size == 0

@@ -1,51 +1,11 @@
-"""Host logic of the serving loop and the batch planner (CPU only)."""
+"""Host logic of the serving binding, the batch planner, the workload
+recipes and the host pipeline's buffer checks (CPU only)."""
 import numpy as np
 import pytest
 
 import workloads
 from paper_1910_05109_amd.batch import decoded_capacity, encoded_lengths, prefix
-from paper_1910_05109_amd.serve import OutputRing
-
-
-def _overlaps(a, b):
-    return a[0] < b[1] and b[0] < a[1]
-
-
-@pytest.mark.parametrize("seed", range(6))
-def test_ring_never_overlaps_and_frees_in_order(seed):
-    g = workloads.rng(seed)
-    size = int(g.integers(100, 5000))
-    ring = OutputRing(size)
-    live = []            # (start, end, held)
-    for _ in range(3000):
-        if live and (g.random() < 0.45 or len(live) > 20):
-            s, e, held = live.pop(0)           # retire in order
-            ring.release(held)
-            continue
-        n = int(g.integers(1, size // 3 + 2))
-        got = ring.alloc(n)
-        if got is None:
-            # must not fit: the contiguous free space is smaller than n
-            assert live, "an empty ring must accept any size up to its capacity"
-            continue
-        start, held = got
-        iv = (start, start + n)
-        assert 0 <= iv[0] and iv[1] <= size
-        for s, e, _ in live:
-            assert not _overlaps(iv, (s, e)), (iv, (s, e))
-        live.append((iv[0], iv[1], held))
-        assert ring.used <= size
-
-
-def test_ring_rejects_oversized_and_accepts_full_capacity():
-    ring = OutputRing(1000)
-    with pytest.raises(ValueError):
-        ring.alloc(1001)
-    start, held = ring.alloc(1000)
-    assert (start, held) == (0, 1000)
-    assert ring.alloc(1) is None
-    ring.release(held)
-    assert ring.alloc(1) == (0, 1)
+from paper_1910_05109_amd.serve import DEC, ENC, out_layout
 
 
 def test_layout_helpers():
@@ -53,6 +13,13 @@ def test_layout_helpers():
     assert encoded_lengths(lens).tolist() == [0, 4, 4, 4, 8, 8, 136]
     assert decoded_capacity(lens).tolist() == [0, 0, 0, 0, 3, 3, 75]
     assert prefix(lens).tolist() == [0, 0, 1, 3, 6, 10, 15, 115]
+
+
+def test_server_output_layout():
+    """Each request gets the output capacity of its kind, packed in order."""
+    kinds = np.array([ENC, DEC, ENC, DEC, DEC], dtype=np.int32)
+    lens = np.array([5, 9, 0, 4, 3], dtype=np.int64)
+    assert out_layout(kinds, lens).tolist() == [0, 8, 14, 14, 17, 17]
 
 
 def test_workload_recipes():
