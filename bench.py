@@ -10,10 +10,15 @@ paper does (Section "Experiments"): value = 2 * N / step time, N = 4*ceil(n/3).
 Also reported in the same line: each direction against a same-size
 device-to-device hipMemcpyAsync (the paper's memcpy yardstick), the roofline of
 the slower kernel (algorithmic bytes / average duration from HIP events on the
-launch stream, against the 8 TB/s HBM peak), and the oracle's CPU throughput
-on a bounded sample.
+launch stream, against the 8 TB/s HBM peak), the oracle's CPU throughput on a
+bounded sample, and the metric's other two parts: `batch` (the 100,000-buffer
+ragged workload, one graph-captured batched launch per direction against one
+launch per buffer) and `serve` (p50 / p99 latency of the continuous-batching
+server at 10^4 and 3 x 10^5 requests per second).
 
-Other modes (--mode): sweep (size sweep 2^k + r), batch (100,000 ragged
+Other modes (--mode): ceiling (streaming kernels with the codec's access
+patterns and grids but no arithmetic, and a same-size copy: the attainable
+bandwidth), sweep (size sweep 2^k + r), batch (100,000 ragged
 buffers, batched launch vs one launch per buffer), serve (continuous batching
 loop), small (the 3 MiB workload), validate (read-only validation of the
 1 GiB encoding), host (the 1 GiB workload in host memory through the chunked
@@ -141,6 +146,53 @@ def cpu_baseline(x: np.ndarray, sample_bytes: int, reps: int):
                       f"of 3-byte / 4-character multiples), single_thread on one"}
 
 
+YARD_KINDS = {"read_only": 0, "write_only": 1, "encode_pattern": 2, "decode_pattern": 3,
+              "copy_same_grid": 4}
+
+
+def ceiling_measure(torch, n: int, N: int, reps: int = 20) -> dict:
+    """Attainable bandwidth with the codec kernels' access patterns and grids
+    and none of their arithmetic (b64_yardstick), for the byte counts of an
+    n-byte encode / N-character decode: median ms, bytes moved and GB/s of
+    each pattern, and a hipMemcpyAsync of N bytes."""
+    import ctypes
+    from paper_1910_05109_amd import _lib
+    from paper_1910_05109_amd import stream_ptr
+    L = _lib.load()
+    a = torch.empty(N, dtype=torch.uint8, device="cuda").fill_(0x41)
+    b = torch.empty(N, dtype=torch.uint8, device="cuda")
+    st = stream_ptr()
+    cases = {  # kind: (lane chunks, bytes read per chunk, bytes written per chunk)
+        "encode_pattern": (n // 12, 12, 16), "decode_pattern": (N // 16, 16, 12),
+        "read_only": (N // 16, 16, 0), "write_only": (N // 16, 0, 16),
+        "copy_same_grid": (N // 16, 16, 16)}
+    out = {}
+    for name, (nch, rin, wout) in cases.items():
+        kind = YARD_KINDS[name]
+        fn = lambda: L.b64_yardstick(kind, a.data_ptr(), b.data_ptr(), nch, st)
+        for _ in range(3):
+            assert fn() == 0, name
+        t = _events_time(torch, fn, reps)["median"]
+        moved = nch * (rin + wout)
+        out[name] = {"ms": round(t, 4), "bytes": moved, "gbps": round(moved / t / 1e6, 1),
+                     "frac_of_peak": round(moved / t / 1e6 / HBM_PEAK_GBS, 4)}
+    t = _events_time(torch, lambda: b.copy_(a), reps)["median"]
+    out["memcpy_N"] = {"ms": round(t, 4), "bytes": 2 * N, "gbps": round(2 * N / t / 1e6, 1),
+                       "frac_of_peak": round(2 * N / t / 1e6 / HBM_PEAK_GBS, 4)}
+    del a, b
+    torch.cuda.empty_cache()
+    return out
+
+
+def run_ceiling(args, torch, b64):
+    """The attainable-bandwidth ceiling at the 1 GiB workload's sizes."""
+    n = workloads.SINGLE_1GIB[0]
+    N = 4 * ((n + 2) // 3)
+    res = {"workload": "bandwidth ceiling at the 1 GiB workload's sizes", "n_bytes": n,
+           "n_chars": N, **ceiling_measure(torch, n, N, args.steps)}
+    print(json.dumps(res), flush=True)
+
+
 def run_single(args, torch, b64):
     n = workloads.SINGLE_1GIB[0]
     N = 4 * ((n + 2) // 3)
@@ -192,6 +244,9 @@ def run_single(args, torch, b64):
     else:
         kname, kms = "k_decode", dec_avg
     achieved = alg / (kms * 1e-3) / 1e9
+    log("bandwidth ceiling (codec access patterns, no arithmetic)")
+    ceil = ceiling_measure(torch, n, N)
+    pat = ceil["encode_pattern" if kname == "k_encode" else "decode_pattern"]
     rec = {
         "metric": METRIC,
         "value": round(value, 2),
@@ -217,11 +272,39 @@ def run_single(args, torch, b64):
                    "gbps_N": round(2 * N / mc_N / 1e6, 1)},
         "roofline": {"bound": "hbm", "kernel": kname, "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": measured_traffic(kname, alg)},
+                     "traffic": measured_traffic(kname, alg),
+                     "ceiling": pat["gbps"], "frac_of_ceiling": round(achieved / pat["gbps"], 4)},
+        "ceiling": {k: {"ms": v["ms"], "gbps": v["gbps"]} for k, v in ceil.items()},
     }
     if not args.no_cpu:
         log("cpu baseline (oracle)")
         rec["cpu_baseline"] = cpu_baseline(x, args.cpu_sample, args.cpu_reps)
+    del dx, dtext, ddec
+    torch.cuda.empty_cache()
+    if not args.no_extras:
+        # the other two parts of the metric: batched vs per-buffer GB/s on the
+        # ragged-batch workload, and serving latency at two arrival rates
+        log("batch part of the metric")
+        bm = batch_measure(torch, b64, args.nbuf, 5, same_bytes=False)
+        rec["batch"] = {"workload": bm["workload"], "buffers": bm["buffers"], "chars": bm["chars"],
+                        **{k: {kk: bm[k][kk] for kk in ("batched_ms", "batched_gbps_b64",
+                                                        "per_buffer_gbps_b64", "speedup")}
+                           for k in ("encode", "decode")}}
+        log("serving part of the metric")
+        from paper_1910_05109_amd import serve
+        count = 20_000
+        kinds, payload, off, sizes, spoil = serve_requests(torch, b64, count)
+        rows = []
+        with serve.Server(budget_bytes=32 << 30, nstreams=args.serve_streams,
+                          depth=args.serve_depth) as srv:
+            for rate in (1e4, 3e5):
+                r = serve_rate(srv, torch, b64, kinds, payload, off, sizes, spoil, rate, count)
+                rows.append({k: (round(v, 2) if isinstance(v, float) else v)
+                             for k, v in r.items() if k in ("rate", "requests", "p50_us", "p99_us",
+                                                             "gbps_b64", "mean_batch",
+                                                             "max_concurrent")})
+        rec["serve"] = {"workload": "Poisson arrivals, log-normal sizes (median 8 KiB, sigma 1.5), "
+                                    "payloads from pinned host memory", "rows": rows}
     print(json.dumps(rec), flush=True)
 
 
@@ -331,18 +414,22 @@ def run_sweep(args, torch, b64):
     print(json.dumps({"workload": "size sweep", "rows": rows}), flush=True)
 
 
-def run_batch(args, torch, b64):
-    """100,000 ragged buffers (log-uniform 16 B .. 1 MiB): one graph-captured
-    batched launch per direction vs one launch per buffer on one stream."""
+def batch_measure(torch, b64, nbuf: int, steps: int, same_bytes: bool = True) -> dict:
+    """The ragged-batch workload: `nbuf` buffers with log-uniform lengths in
+    [16 B, 1 MiB) (uniform random bytes made on the device), one
+    graph-captured batched launch per direction against one launch per
+    buffer on one stream (no graph); every length and status is checked."""
     import ctypes
     from paper_1910_05109_amd import _lib
     from paper_1910_05109_amd.batch import GraphBatch
     seed = workloads.SEED_BASE + 4
-    lens = workloads.batch_lengths(seed, args.nbuf)
+    lens = workloads.batch_lengths(seed, nbuf)
     in_off = workloads.offsets(lens)
     total = int(in_off[-1])
     log("batch: generate", total, "bytes in", lens.size, "buffers")
-    src = torch.from_numpy(workloads.random_bytes(seed, total)).cuda()
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(seed)
+    src = torch.randint(0, 256, (total,), dtype=torch.uint8, device="cuda", generator=gen)
     genc = GraphBatch("encode", lens.size, total)
     genc.load(lens, src)
     genc.replay()
@@ -357,19 +444,18 @@ def run_batch(args, torch, b64):
     torch.cuda.synchronize()
     _, _, dlen, dbad = gdec.results()
     assert np.array_equal(dlen.cpu().numpy(), lens) and (dbad.cpu().numpy() == -1).all()
-    t_enc = _events_time(torch, genc.replay, args.steps)
-    t_dec = _events_time(torch, gdec.replay, args.steps)
+    t_enc = _events_time(torch, genc.replay, steps)
+    t_dec = _events_time(torch, gdec.replay, steps)
     # one launch per buffer, same stream, no graph
     L = _lib.load()
     alpha = ctypes.create_string_buffer(b64.STD, 64)
     stream = b64.stream_ptr()
     sp, dp = src.data_ptr(), enc_dst.data_ptr()
-    eo = genc.host_out_off
     per_dst = torch.empty(int(gdec.host_out_off[-1]) + 1, dtype=torch.uint8, device="cuda")
     stat = torch.empty(2 * lens.size, dtype=torch.int64, device="cuda")
     pp, stp = per_dst.data_ptr(), stat.data_ptr()
-    do = gdec.host_out_off
-    ioff = in_off.tolist(); eol = eo.tolist(); dol = do.tolist(); ll = lens.tolist(); tl = tlens.tolist()
+    ioff = in_off.tolist(); eol = genc.host_out_off.tolist(); dol = gdec.host_out_off.tolist()
+    ll = lens.tolist(); tl = tlens.tolist()
 
     def per_enc():
         for b in range(len(ll)):
@@ -380,7 +466,8 @@ def run_batch(args, torch, b64):
             L.b64_decode_async(dp + eol[b], tl[b], pp + dol[b], stp + 16 * b, stp + 16 * b + 8,
                                alpha, stream)
 
-    res = {"workload": "ragged batch", "buffers": int(lens.size), "bytes": total, "chars": ntext}
+    res = {"workload": "ragged batch: log-uniform 16 B .. 1 MiB", "buffers": int(lens.size),
+           "bytes": total, "chars": ntext}
     for name, fn, tb in (("encode", per_enc, t_enc), ("decode", per_dec, t_dec)):
         fn()
         torch.cuda.synchronize()
@@ -392,30 +479,40 @@ def run_batch(args, torch, b64):
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         gpu_ms = a.elapsed_time(b)
-        res[name] = {"batched_ms": tb["median"], "batched_gbps_b64": ntext / tb["median"] / 1e6,
-                     "batched_hbm_gbps": (total + ntext) / tb["median"] / 1e6,
-                     "per_buffer_ms": gpu_ms, "per_buffer_wall_ms": wall * 1e3,
-                     "per_buffer_gbps_b64": ntext / gpu_ms / 1e6,
-                     "speedup": gpu_ms / tb["median"]}
+        res[name] = {"batched_ms": round(tb["median"], 4),
+                     "batched_gbps_b64": round(ntext / tb["median"] / 1e6, 1),
+                     "batched_hbm_gbps": round((total + ntext) / tb["median"] / 1e6, 1),
+                     "per_buffer_ms": round(gpu_ms, 3), "per_buffer_wall_ms": round(wall * 1e3, 3),
+                     "per_buffer_gbps_b64": round(ntext / gpu_ms / 1e6, 2),
+                     "speedup": round(gpu_ms / tb["median"], 1)}
         log("batch", name, json.dumps(res[name]))
     st = stat.view(-1, 2).cpu().numpy()
     assert np.array_equal(st[:, 0], lens) and (st[:, 1] == -1).all()
     del per_dst, stat
-    # yardstick: the packed input as ONE buffer, the same bytes to move, so
-    # that the batched rates can be told apart from the cost of the footprint
-    text1 = b64.encode(src)
-    out1, st1 = b64.decode_async(text1)
-    torch.cuda.synchronize()
-    assert st1.cpu().tolist() == [total, -1]
-    t1e = _events_time(torch, lambda: b64.encode(src, out=text1), args.steps)
-    t1d = _events_time(torch, lambda: b64.decode_async(text1, out=out1, status=st1), args.steps)
-    n1 = int(text1.numel())
-    res["one_buffer_same_bytes"] = {
-        "chars": n1, "encode_ms": t1e["median"], "decode_ms": t1d["median"],
-        "encode_hbm_gbps": (total + n1) / t1e["median"] / 1e6,
-        "decode_hbm_gbps": (total + n1) / t1d["median"] / 1e6}
-    log("batch one buffer", json.dumps(res["one_buffer_same_bytes"]))
-    print(json.dumps(res), flush=True)
+    if same_bytes:
+        # yardstick: the packed input as ONE buffer, the same bytes to move, so
+        # that the batched rates can be told apart from the cost of the footprint
+        text1 = b64.encode(src)
+        out1, st1 = b64.decode_async(text1)
+        torch.cuda.synchronize()
+        assert st1.cpu().tolist() == [total, -1]
+        t1e = _events_time(torch, lambda: b64.encode(src, out=text1), steps)
+        t1d = _events_time(torch, lambda: b64.decode_async(text1, out=out1, status=st1), steps)
+        n1 = int(text1.numel())
+        res["one_buffer_same_bytes"] = {
+            "chars": n1, "encode_ms": t1e["median"], "decode_ms": t1d["median"],
+            "encode_hbm_gbps": (total + n1) / t1e["median"] / 1e6,
+            "decode_hbm_gbps": (total + n1) / t1d["median"] / 1e6}
+        log("batch one buffer", json.dumps(res["one_buffer_same_bytes"]))
+    del genc, gdec, src
+    torch.cuda.empty_cache()
+    return res
+
+
+def run_batch(args, torch, b64):
+    """100,000 ragged buffers (log-uniform 16 B .. 1 MiB): one graph-captured
+    batched launch per direction vs one launch per buffer on one stream."""
+    print(json.dumps(batch_measure(torch, b64, args.nbuf, args.steps)), flush=True)
 
 
 def serve_requests(torch, b64, count: int):
@@ -670,10 +767,12 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--mode", default="single",
-                    choices=["single", "small", "sweep", "batch", "serve", "validate", "host",
-                             "variants", "fused"])
+                    choices=["single", "ceiling", "small", "sweep", "batch", "serve", "validate",
+                             "host", "variants", "fused"])
     ap.add_argument("--chunk-mib", type=int, default=64)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="default line without its batch and serve objects")
     ap.add_argument("--cpu-sample", type=int, default=512 << 20)
     ap.add_argument("--cpu-reps", type=int, default=5)
     ap.add_argument("--nbuf", type=int, default=workloads.BATCH_BUFFERS)
@@ -693,7 +792,8 @@ def main():
     if not torch.cuda.is_available():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
-    {"single": run_single, "small": run_small, "sweep": run_sweep, "batch": run_batch,
+    {"single": run_single, "ceiling": run_ceiling, "small": run_small, "sweep": run_sweep,
+     "batch": run_batch,
      "serve": run_serve, "validate": run_validate, "host": run_host,
      "variants": run_variants, "fused": run_fused}[args.mode](args, torch, b64)
 

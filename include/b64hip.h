@@ -345,6 +345,17 @@ int64_t b64_tune_bucket(int64_t n);
  * change results.  Not a paper operation: a launch-policy knob.              */
 int64_t b64_tune_ws_guess_min(int64_t min_chars);
 
+/* Bandwidth yardstick (not a codec operation; Section "Experiments" measures
+ * the codec against a memory copy): streaming kernels with the codec kernels'
+ * access pattern and grid and none of their arithmetic, over nch lane
+ * chunks.  kind 0: reads 16*nch bytes of src (dst receives one word per
+ * workgroup: it must hold 65,536 bytes); 1: writes 16*nch bytes of dst; 2:
+ * encode's pattern, reads 12*nch and writes 16*nch; 3: decode's pattern,
+ * reads 16*nch and writes 12*nch; 4: copies 16*nch bytes.  Device pointers,
+ * caller-owned, sized as stated.  Asynchronous; returns 0, B64_EARG or
+ * B64_EHIP. */
+int64_t b64_yardstick(int kind, const uint8_t *src, uint8_t *dst, int64_t nch, hipStream_t stream);
+
 /* Message for the last B64_EARG / B64_EHIP returned on this thread.          */
 const char *b64_last_error(void);
 

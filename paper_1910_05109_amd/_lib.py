@@ -55,6 +55,7 @@ SIGNATURES = {
     "b64_tune_get": ([_INT], _I64),
     "b64_tune_bucket": ([_I64], _I64),
     "b64_tune_ws_guess_min": ([_I64], _I64),
+    "b64_yardstick": ([_INT, _P, _P, _I64, _P], _I64),
     "b64_last_error": ([], ctypes.c_char_p),
 }
 DATA_SYMBOLS = ("b64_alphabet_std", "b64_alphabet_url")

@@ -15,7 +15,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 SOURCES = [os.path.join(CSRC, f) for f in ("b64_single.hip", "b64_batch.hip", "b64_validate.hip",
                                             "b64_variants.hip", "b64_fused.hip", "b64_abi.hip",
-                                            "b64_pipeline.hip", "b64_serve.hip")]
+                                            "b64_pipeline.hip", "b64_serve.hip",
+                                            "b64_yardstick.hip")]
 LIB = os.path.join(HERE, "libb64hip.so")
 INCLUDE = os.path.join(ROOT, "include")
 ARCH = "gfx950"

@@ -113,7 +113,7 @@ Shape shape_of(int op, int64_t n)
 
 }  // namespace
 
-Shape b64hip::batch_shape(int op) { return shape_of(op, -1); }
+Shape b64hip::op_shape(int op, int64_t n) { return shape_of(op, n); }
 
 namespace {
 

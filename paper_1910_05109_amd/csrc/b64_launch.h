@@ -50,9 +50,10 @@ inline DecMap make_dec(const char *alphabet)
     return d;
 }
 
-// Workgroups per CU of the batched launches (the shape the library holds for
-// op, in its largest size bucket); cus: compute units of the current device.
-Shape batch_shape(int op);
+// The shape the library holds for operation `op` (the numbering of
+// b64_tune_set) and an input of n bytes (n < 0: the largest size bucket), and
+// the compute units of the current device.
+Shape op_shape(int op, int64_t n);
 hipError_t device_cus(int *cus);
 
 // Blocks for a grid-stride launch over `nch` lane chunks: enough to cover

@@ -319,7 +319,7 @@ int64_t b64_server_run(b64_server *s, int64_t nreq, const int32_t *kind, const i
     }
     const EncTab tab = make_enc(alphabet);
     const DecMap map = make_dec(alphabet);
-    const Shape enc_shape = batch_shape(2), dec_shape = batch_shape(3);
+    const Shape enc_shape = op_shape(2, -1), dec_shape = op_shape(3, -1);
 
     // Enqueue entries [f, f + c) of pool p on the next stream: two copies in
     // (the payload; the offsets and the first-invalid initial values in one
