@@ -33,7 +33,8 @@ import statistics
 import numpy as np
 
 from . import (BUCKETS, OPS, SKIP_WS, STD, decode_async, decode_batch, decode_f32_bf16, encode,
-               encode_batch, tune_get, tune_set, validate_async, workspace_size)
+               encode_batch, tune_get, tune_set, tune_ws_guess_min, validate_async,
+               workspace_size)
 
 UNROLLS = (1, 2, 4, 8)
 BLOCKS_PER_CU = (1, 2, 4, 8, 16, 32, 64)
@@ -208,8 +209,56 @@ def tune_op(op: str, bucket: int, nbytes: int | None = None, reps: int = 10, unr
             "previous": list(old), "grid": [[r[1], r[2], r[3], r[0]] for r in results]}
 
 
+# MIME text sizes at which the whitespace-skipping decode's two paths are
+# compared (payload bytes; the text is about 4/3 of that with line breaks)
+GUESS_SIZES = (1 << 20, 2 << 20, 4 << 20, 6 << 20, 8 << 20, 12 << 20, 16 << 20, 24 << 20,
+               32 << 20)
+
+
+def tune_ws_guess(reps: int = 10, sizes=GUESS_SIZES, verbose: bool = True) -> dict:
+    """The whitespace-skipping decode of text in regular lines either guesses
+    the line layout (a few more launches, one read of the text) or counts the
+    significant characters first (fewer launches, two reads).  Time both on
+    MIME text of each size and return the smallest text size from which the
+    guess is faster at that size and every larger one (applied with
+    b64_tune_ws_guess_min)."""
+    import torch
+    old = tune_ws_guess_min(-1)
+    rows = []
+    try:
+        for nbytes in sizes:
+            gen = torch.Generator(device="cuda")
+            gen.manual_seed(nbytes)
+            x = torch.randint(0, 256, (nbytes,), dtype=torch.uint8, device="cuda", generator=gen)
+            mime = encode(x, STD, line_len=76)
+            out = torch.empty(3 * (mime.numel() // 4), dtype=torch.uint8, device="cuda")
+            st = torch.empty(2, dtype=torch.int64, device="cuda")
+            ws = torch.empty(workspace_size(mime.numel(), SKIP_WS), dtype=torch.uint8, device="cuda")
+            fn = lambda: decode_async(mime, STD, out=out, status=st, flags=SKIP_WS, workspace=ws)
+            tune_ws_guess_min(0)
+            t_guess = _time(torch, fn, reps)
+            tune_ws_guess_min(1 << 62)
+            t_count = _time(torch, fn, reps)
+            rows.append((int(mime.numel()), t_guess, t_count))
+            if verbose:
+                print(f"[tune] decode_ws text {mime.numel():>10d} B: guess {t_guess * 1e3:8.2f} us, "
+                      f"counted {t_count * 1e3:8.2f} us", flush=True)
+    finally:
+        tune_ws_guess_min(old)
+    chosen = rows[-1][0] + 1 if rows else old
+    for n, tg, tc in reversed(rows):
+        if tg < tc:
+            chosen = n
+        else:
+            break
+    tune_ws_guess_min(chosen)
+    return {"min_chars": chosen, "previous": old,
+            "grid": [[n, tg, tc] for n, tg, tc in rows]}
+
+
 def save(entries: dict, path: str | None = None):
-    """Merge {op: {bucket: shape}} into the cache under the current device."""
+    """Merge {op: {bucket: shape}} (and "ws_guess_min": {"min_chars": n})
+    into the cache under the current device."""
     path = path or cache_path()
     if not path:
         return
@@ -238,6 +287,12 @@ def apply_cached(path: str | None = None) -> dict:
         data = json.load(f)
     ent = data.get(device_key(), {})
     for op, per_bucket in ent.items():
+        if op == "ws_guess_min":
+            n = int(per_bucket["min_chars"])
+            if n < 0:
+                raise ValueError(f"tune cache {path}: negative ws_guess_min")
+            tune_ws_guess_min(n)
+            continue
         if op not in OPS:
             raise ValueError(f"tune cache {path}: unknown operation {op!r}")
         for bucket, v in per_bucket.items():
@@ -256,6 +311,8 @@ def main():
     ap.add_argument("--reps", type=int, default=10)
     ap.add_argument("--out", default=None, help="cache file (default: the package's cache)")
     ap.add_argument("--json", default=None, help="also write the full sweep here")
+    ap.add_argument("--no-ws-guess", action="store_true",
+                    help="skip timing the whitespace decode's guess against its counted path")
     args = ap.parse_args()
     found = {}
     for op in args.ops:
@@ -268,8 +325,14 @@ def main():
                   f"blocks/cu={r['blocks_per_cu']} nt={r['nontemporal']} {r['ms'] * 1e3:.2f} us",
                   flush=True)
     keys = ("unroll", "blocks_per_cu", "nontemporal", "ms", "bytes")
-    save({op: {b: {k: r[k] for k in keys} for b, r in per.items()} for op, per in found.items()},
-         args.out)
+    entries = {op: {b: {k: r[k] for k in keys} for b, r in per.items()}
+               for op, per in found.items()}
+    if not args.no_ws_guess and "decode_ws" in args.ops:
+        g = tune_ws_guess(args.reps)
+        print(f"[tune] best ws_guess_min: {g['min_chars']} (was {g['previous']})", flush=True)
+        found["ws_guess_min"] = g
+        entries["ws_guess_min"] = {"min_chars": g["min_chars"]}
+    save(entries, args.out)
     if args.json:
         with open(args.json, "w") as f:
             json.dump(found, f, indent=1)

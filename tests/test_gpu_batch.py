@@ -4,8 +4,8 @@ against the oracle, bit-exact, buffer by buffer.
 Covers: small ragged batches with empty buffers, invalid bytes and '=' misuse;
 every string of length 0..8 over a 7-symbol set (each string one buffer);
 input offsets at every alignment and outputs with gaps; HIP-graph capture and
-replay; and the 100,000-buffer log-uniform workload at full size (sampled
-buffers against the oracle, properties on all buffers).
+replay; and the 100,000-buffer log-uniform workload at full size (every
+buffer against the oracle).
 """
 import numpy as np
 import pytest
@@ -212,9 +212,23 @@ def test_graph_capture_and_replay(b64, oracle):
             assert first_mismatch(dd[dec_off[b]: dec_off[b] + lens[b]], src[in_off[b]: in_off[b + 1]]) is None
 
 
+def _slices(nbuf, per=2000):
+    return [(b0, min(b0 + per, nbuf)) for b0 in range(0, nbuf, per)]
+
+
+def _pool():
+    import os
+    from concurrent.futures import ThreadPoolExecutor
+    n = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    return ThreadPoolExecutor(max_workers=max(1, min(16, n)))
+
+
 def test_batch_workload_full_size(b64, oracle):
     """100,000 buffers, log-uniform lengths in [16 B, 1 MiB]: one encode launch
-    and one decode launch; 0.5% of the decode buffers carry one invalid byte."""
+    and one decode launch; 0.5% of the decode buffers carry one invalid byte.
+    Every buffer's encoding and every valid buffer's decoded bytes are compared
+    with the oracle's (the oracle runs on slices of 2,000 buffers in parallel
+    host threads), and every length and first invalid offset too."""
     import torch
     seed = workloads.SEED_BASE + 4
     lens = workloads.batch_lengths(seed)
@@ -228,13 +242,20 @@ def test_batch_workload_full_size(b64, oracle):
     enc_off = to_host(d_enc_off)
     assert np.array_equal(to_host(d_enc_len), 4 * ((lens + 2) // 3))
     assert np.array_equal(enc_off, workloads.offsets(4 * ((lens + 2) // 3)))
-    sample = np.unique(np.concatenate([
-        workloads.pick_buffers(seed + 1, lens.size, 0.01),
-        np.argsort(lens)[:50], np.argsort(lens)[-20:], [0, lens.size - 1]]))
-    for b in sample:
-        got = to_host(d_enc[enc_off[b]: enc_off[b + 1]])
-        ref = oracle.encode(src[in_off[b]: in_off[b + 1]])
-        assert first_mismatch(got, ref) is None, b
+    h_enc = to_host(d_enc[: int(enc_off[-1])])
+    del d_src
+    say("batch full: oracle encode of every buffer")
+
+    def enc_slice(bounds):
+        b0, b1 = bounds
+        ref, ref_off, ref_len = oracle.encode_list(src[in_off[b0]: in_off[b1]],
+                                                   in_off[b0: b1 + 1] - in_off[b0])
+        assert np.array_equal(ref_off + enc_off[b0], enc_off[b0: b1 + 1]), (b0, b1)
+        return first_mismatch(h_enc[enc_off[b0]: enc_off[b1]], ref), b0
+
+    with _pool() as pool:
+        for mism, b0 in pool.map(enc_slice, _slices(lens.size)):
+            assert mism is None, (b0, mism)
     # plant one invalid byte in 0.5% of the buffers
     bad_bufs = workloads.pick_buffers(seed + 2, lens.size, 0.005)
     g = workloads.rng(seed + 3)
@@ -243,24 +264,41 @@ def test_batch_workload_full_size(b64, oracle):
     pos = np.array([g.integers(0, nchar[b]) for b in bad_bufs], dtype=np.int64)
     vals = outside[g.integers(0, outside.size, size=bad_bufs.size)]
     d_enc[to_dev(enc_off[bad_bufs] + pos)] = to_dev(vals)
+    h_enc[enc_off[bad_bufs] + pos] = vals
     say("batch full: decode_batch")
     d_dec, d_dec_off, d_len, d_bad = b64.decode_batch(d_enc, d_enc_off)
     dec_off = to_host(d_dec_off)
+    got_len, got_bad = to_host(d_len), to_host(d_bad)
+    h_dec = to_host(d_dec)
+    del d_enc, d_dec
+    torch.cuda.empty_cache()
     exp_bad = np.full(lens.size, -1, dtype=np.int64)
     exp_bad[bad_bufs] = pos
     exp_len = lens.copy()
     exp_len[bad_bufs] = -1
-    assert np.array_equal(to_host(d_bad), exp_bad)
-    assert np.array_equal(to_host(d_len), exp_len)
-    for b in sample:
-        if exp_len[b] >= 0:
-            got = to_host(d_dec[dec_off[b]: dec_off[b] + lens[b]])
-            assert first_mismatch(got, src[in_off[b]: in_off[b + 1]]) is None, b
-    for b in bad_bufs[:40]:
-        text = to_host(d_enc[enc_off[b]: enc_off[b + 1]])
-        assert oracle.decode_raw(text) == ~exp_bad[b]
-    del d_enc, d_dec, d_src
-    torch.cuda.empty_cache()
+    assert np.array_equal(got_bad, exp_bad)
+    assert np.array_equal(got_len, exp_len)
+    say("batch full: oracle decode of every buffer")
+
+    def dec_slice(bounds):
+        b0, b1 = bounds
+        ref, ref_off, res = oracle.decode_list(h_enc[enc_off[b0]: enc_off[b1]],
+                                               enc_off[b0: b1 + 1] - enc_off[b0])
+        wrong = []
+        for k in range(b1 - b0):
+            b = b0 + k
+            r = int(res[k])
+            if (r >= 0) != (got_len[b] >= 0) or (r >= 0 and r != got_len[b]) or \
+                    (r < 0 and ~r != got_bad[b]):
+                wrong.append(("status", b))
+            elif r >= 0 and not np.array_equal(h_dec[dec_off[b]: dec_off[b] + r],
+                                               ref[ref_off[k]: ref_off[k] + r]):
+                wrong.append(("bytes", b))
+        return wrong
+
+    with _pool() as pool:
+        for wrong in pool.map(dec_slice, _slices(lens.size)):
+            assert not wrong, wrong[:5]
 
 
 def test_layout_validation_rejects_out_of_bounds(b64):
