@@ -320,10 +320,10 @@ int64_t b64_server_run(b64_server *s, int64_t nreq, const int32_t *kind, const i
  * or 4, and 8 runs as 2), `blocks_per_cu` workgroups of 256 threads per
  * compute unit (1..64; an input that fewer workgroups cover in one round gets
  * just those), and `nontemporal` (0 or 1) for streaming loads and stores.
- * Size buckets of the input length n in bytes: 0 for n < 1 MiB, 1 for
- * n < 16 MiB, 2 for n < 128 MiB, 3 from 128 MiB; ops 2, 3 and 7 always use
- * bucket 3 (their total size lives in device memory); bucket -1 sets every
- * bucket.  Process-wide; meant for the autotuner.  Does not change results
+ * Size buckets of the input length n in bytes: 0 for n < 64 KiB, 1 for
+ * n < 1 MiB, 2 for n < 16 MiB, 3 for n < 128 MiB, 4 from 128 MiB; ops 2, 3
+ * and 7 always use bucket 4 (their total size lives in device memory);
+ * bucket -1 sets every bucket.  Process-wide; meant for the autotuner.  Does not change results
  * (every unroll x nontemporal pair is tested against the oracle at 1, 3, 8
  * and 64 workgroups per CU).  Returns 0 or B64_EARG. */
 int64_t b64_tune_set_bucket(int op, int bucket, int unroll, int blocks_per_cu, int nontemporal);
@@ -332,9 +332,9 @@ int64_t b64_tune_set(int op, int unroll, int blocks_per_cu, int nontemporal);
 /* Shape of `op` in `bucket` packed as nontemporal*10000 + unroll*100 +
  * blocks_per_cu, or B64_EARG.                                                */
 int64_t b64_tune_get_bucket(int op, int bucket);
-/* b64_tune_get_bucket(op, 3).                                                */
+/* b64_tune_get_bucket(op, 4): the shape of the largest inputs.              */
 int64_t b64_tune_get(int op);
-/* Size bucket (0..3) of an input of n bytes, or B64_EARG for n < 0.          */
+/* Size bucket (0..4) of an input of n bytes, or B64_EARG for n < 0.          */
 int64_t b64_tune_bucket(int64_t n);
 /* Whitespace-skipping decode (B64_SKIP_WS): texts of at least `min_chars`
  * bytes first try decoding as regular lines (the guess), shorter ones count

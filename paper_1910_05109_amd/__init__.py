@@ -403,7 +403,7 @@ def decode_f32_bf16(src, in_off, dim: int, alphabet=STD, dst=None, status=None, 
     return dst.reshape(-1)[: nrows * dim].view(nrows, dim), status[:nrows]
 
 
-BUCKETS = 4   # size buckets of the launch shapes: < 1 MiB, < 16 MiB, < 128 MiB, larger
+BUCKETS = 5   # size buckets of the launch shapes: < 64 KiB, < 1 MiB, < 16 MiB, < 128 MiB, larger
 
 
 def tune_set(op: str, unroll: int, blocks_per_cu: int, nontemporal: int = 1,

@@ -68,25 +68,27 @@ DecMap make_dec_ws(const char *alphabet, bool nopad)
 
 // Launch shapes per operation (encode, decode, encode_batch, decode_batch,
 // validate, line-wrapped encode, whitespace-skipping decode, fused float32 ->
-// bfloat16 decode) and size bucket of the operation's input: below 1 MiB
-// (launch-latency bound), below 16 MiB and below 128 MiB (resident in the
-// L2 and last-level caches), and from 128 MiB (HBM streaming).  The batched
+// bfloat16 decode) and size bucket of the operation's input: below 64 KiB
+// and below 1 MiB (launch-latency bound; the smallest inputs can take a grid
+// of one workgroup, which skips the decode status count), below 16 MiB and
+// below 128 MiB (resident in the L2 and last-level caches), and from 128 MiB
+// (HBM streaming).  The batched
 // and fused operations find their total size only on the device and always
 // take the last bucket's shape.  The defaults are the autotuner's choices on
-// MI355X (python -m paper_1910_05109_amd.tune: inputs of 256 KiB, 4 MiB,
-// 48 MiB and 1 GiB).
+// MI355X (python -m paper_1910_05109_amd.tune: inputs of 16 KiB, 256 KiB,
+// 4 MiB, 48 MiB and 1 GiB).
 constexpr int kOps = 8;
-constexpr int kBuckets = 4;
-constexpr int64_t kBucketLimit[kBuckets - 1] = {1 << 20, 16 << 20, 128 << 20};
+constexpr int kBuckets = 5;
+constexpr int64_t kBucketLimit[kBuckets - 1] = {64 << 10, 1 << 20, 16 << 20, 128 << 20};
 Shape g_shape[kOps][kBuckets] = {
-    {{1, 8, 1}, {2, 32, 0}, {1, 32, 0}, {8, 1, 1}},    // encode
-    {{1, 32, 1}, {2, 8, 1}, {1, 4, 0}, {2, 2, 1}},     // decode
-    {{2, 2, 1}, {2, 2, 1}, {2, 2, 1}, {2, 2, 1}},      // encode_batch
-    {{4, 16, 1}, {4, 16, 1}, {4, 16, 1}, {4, 16, 1}},  // decode_batch
-    {{1, 32, 0}, {2, 4, 0}, {1, 4, 1}, {8, 1, 1}},     // validate
-    {{1, 4, 0}, {1, 8, 0}, {1, 8, 0}, {8, 1, 0}},      // line-wrapped encode
-    {{1, 2, 0}, {1, 16, 0}, {4, 2, 1}, {2, 8, 1}},     // whitespace-skipping decode
-    {{2, 64, 1}, {2, 64, 1}, {2, 64, 1}, {2, 64, 1}},  // fused decode
+    {{1, 4, 0}, {1, 16, 1}, {2, 32, 0}, {1, 32, 0}, {8, 1, 1}},       // encode
+    {{1, 4, 1}, {1, 16, 1}, {1, 4, 1}, {1, 4, 0}, {2, 2, 1}},         // decode
+    {{2, 2, 1}, {2, 2, 1}, {2, 2, 1}, {2, 2, 1}, {2, 2, 1}},          // encode_batch
+    {{4, 16, 1}, {4, 16, 1}, {4, 16, 1}, {4, 16, 1}, {4, 16, 1}},     // decode_batch
+    {{1, 8, 0}, {1, 4, 1}, {1, 64, 0}, {1, 4, 1}, {8, 1, 1}},         // validate
+    {{1, 4, 1}, {1, 64, 0}, {1, 8, 0}, {1, 8, 0}, {8, 1, 0}},         // line-wrapped encode
+    {{1, 2, 0}, {4, 2, 1}, {1, 16, 0}, {4, 2, 1}, {2, 8, 1}},         // whitespace-skipping decode
+    {{2, 64, 1}, {2, 64, 1}, {2, 64, 1}, {2, 64, 1}, {2, 64, 1}},     // fused decode
 };
 std::mutex g_mu;
 

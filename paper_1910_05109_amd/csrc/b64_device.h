@@ -457,8 +457,19 @@ __device__ __forceinline__ void sink_finish(const DecSink &s, const SinkLane &l,
                                             int64_t n)
 {
     if (!s.slot) return;
-    const int any_bad = __syncthreads_or(l.bad);
+    // Whether any lane of the workgroup reported: a ballot per wave, one LDS
+    // word per wave, one barrier.  (__syncthreads_or reads the workgroup size
+    // from the dispatch packet and then waits for every memory operation the
+    // wave has issued, the output stores included: a full store round trip
+    // before the count.)
+    __shared__ uint32_t s_bad[kWaves];
+    const uint32_t wave_bad = __ballot(l.bad) != 0 ? 1u : 0u;
+    if ((threadIdx.x & 63) == 0) s_bad[threadIdx.x >> 6] = wave_bad;
+    __syncthreads();
     if ((int)threadIdx.x != (tail ? kThreads - 1 : 0)) return;
+    uint32_t any_bad = 0;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) any_bad |= s_bad[w];
     constexpr int64_t kOne = (int64_t)1 << 32;
     int64_t v = kOne | ((int64_t)l.nd << 24) | (any_bad ? 1 : 0);
     const int64_t G = gridDim.x;

@@ -6,9 +6,9 @@ encode and 16 characters -> 12 bytes for decode, so unroll 4 is the paper's
 48 -> 64 block) and `blocks_per_cu` workgroups of 256 threads per compute
 unit (an input that fewer workgroups cover in one round gets just those; the
 grid-stride and persistent kernels loop over the rest).  The library keeps one
-shape per operation and size bucket of the input (below 1 MiB, below 16 MiB,
-below 128 MiB, larger); the batched and fused operations use the last bucket
-only.
+shape per operation and size bucket of the input (below 64 KiB, below 1 MiB,
+below 16 MiB, below 128 MiB, larger); the batched and fused operations use
+the last bucket only.
 
 The tuner times every shape of a grid with HIP events on the launch stream
 on one input per bucket -- below 16 MiB per call replayed from a HIP graph
@@ -40,7 +40,7 @@ UNROLLS = (1, 2, 4, 8)
 BLOCKS_PER_CU = (1, 2, 4, 8, 16, 32, 64)
 NONTEMPORAL = (0, 1)
 # one representative input size per bucket (bytes of the operation's input)
-BUCKET_BYTES = (256 << 10, 4 << 20, 48 << 20, 1 << 30)
+BUCKET_BYTES = (16 << 10, 256 << 10, 4 << 20, 48 << 20, 1 << 30)
 # operations whose total size is known only on the device: last bucket only
 LAST_BUCKET_ONLY = ("encode_batch", "decode_batch", "decode_f32_bf16")
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "b64hip", "tune.json")
@@ -195,7 +195,7 @@ def tune_op(op: str, bucket: int, nbytes: int | None = None, reps: int = 10, unr
             for b in bpcs:
                 tune_set(op, u, b, nt, bucket=bucket)
                 # small calls: device time from graph replays; large ones: stream timing
-                ms = _graph_time(torch, fn, reps) if bucket < 2 else _time(torch, fn, reps)
+                ms = _graph_time(torch, fn, reps) if nbytes < (16 << 20) else _time(torch, fn, reps)
                 results.append((ms, u, b, nt))
                 if verbose:
                     print(f"[tune] {op:15s} bucket={bucket} unroll={u} blocks/cu={b:2d} nt={nt}: "

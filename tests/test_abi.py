@@ -182,8 +182,8 @@ def test_argument_errors_without_gpu(lib):
 
 def test_tuning_interface(lib):
     EARG = -(2 ** 63)
-    old = [lib.b64_tune_get_bucket(0, b) for b in range(4)]
-    assert lib.b64_tune_get(0) == old[3]
+    old = [lib.b64_tune_get_bucket(0, b) for b in range(5)]
+    assert lib.b64_tune_get(0) == old[4]
     assert lib.b64_tune_set(0, 3, 8, 0) == EARG
     assert lib.b64_tune_set(0, 4, 0, 0) == EARG
     assert lib.b64_tune_set(8, 4, 8, 0) == EARG
@@ -194,20 +194,21 @@ def test_tuning_interface(lib):
     assert lib.b64_tune_get(8) == EARG
     assert lib.b64_tune_set(0, 4, 8, 2) == EARG
     assert lib.b64_tune_set(0, 8, 16, 1) == 0
-    assert [lib.b64_tune_get_bucket(0, b) for b in range(4)] == [10816] * 4
+    assert [lib.b64_tune_get_bucket(0, b) for b in range(5)] == [10816] * 5
     # one bucket at a time
     assert lib.b64_tune_set_bucket(0, 2, 2, 3, 0) == 0
-    assert [lib.b64_tune_get_bucket(0, b) for b in range(4)] == [10816, 10816, 203, 10816]
-    assert lib.b64_tune_set_bucket(0, 4, 2, 3, 0) == EARG
+    assert [lib.b64_tune_get_bucket(0, b) for b in range(5)] == [10816, 10816, 203, 10816, 10816]
+    assert lib.b64_tune_set_bucket(0, 5, 2, 3, 0) == EARG
     assert lib.b64_tune_set_bucket(0, -2, 2, 3, 0) == EARG
-    assert lib.b64_tune_get_bucket(0, 4) == EARG
+    assert lib.b64_tune_get_bucket(0, 5) == EARG
     assert lib.b64_tune_get_bucket(0, -1) == EARG
     for b, v in enumerate(old):
         assert lib.b64_tune_set_bucket(0, b, (v // 100) % 100, v % 100, v // 10000) == 0
-    assert [lib.b64_tune_get_bucket(0, b) for b in range(4)] == old
-    # size buckets: < 1 MiB, < 16 MiB, < 128 MiB, larger
-    for n, b in ((0, 0), ((1 << 20) - 1, 0), (1 << 20, 1), ((16 << 20) - 1, 1), (16 << 20, 2),
-                 ((128 << 20) - 1, 2), (128 << 20, 3), (1 << 40, 3)):
+    assert [lib.b64_tune_get_bucket(0, b) for b in range(5)] == old
+    # size buckets: < 64 KiB, < 1 MiB, < 16 MiB, < 128 MiB, larger
+    for n, b in ((0, 0), ((64 << 10) - 1, 0), (64 << 10, 1), ((1 << 20) - 1, 1), (1 << 20, 2),
+                 ((16 << 20) - 1, 2), (16 << 20, 3), ((128 << 20) - 1, 3), (128 << 20, 4),
+                 (1 << 40, 4)):
         assert lib.b64_tune_bucket(n) == b, n
     assert lib.b64_tune_bucket(-1) == EARG
     # the whitespace decode's guess threshold: default, set, read, restore
