@@ -50,26 +50,38 @@ __all__ = ["STD", "URL", "NOPAD", "SKIP_WS", "B64Error", "load", "encoded_len", 
 
 # The wrappers below sit on the launch path of every call, so they keep their
 # own host work small: at a few MiB a call costs about as much on the host as
-# on the GPU.
+# on the GPU.  torch's types and stream accessors are looked up once, and the
+# single-buffer entry points go through the fast-call binding (_lib.fast).
 _torch_mod = None
+_Tensor = _U8 = _I64 = None
+_raw_stream = _cur_device = None
 
 
 def _torch():
-    global _torch_mod
+    global _torch_mod, _Tensor, _U8, _I64, _raw_stream, _cur_device
     if _torch_mod is None:
         import torch
+        _Tensor, _U8, _I64 = torch.Tensor, torch.uint8, torch.int64
+        c = torch._C
+        if hasattr(c, "_cuda_getCurrentRawStream"):
+            _raw_stream, _cur_device = c._cuda_getCurrentRawStream, c._cuda_getDevice
         _torch_mod = torch
     return _torch_mod
+
+
+def _fast():
+    if _lib.fast is None:
+        load()
+    return _lib.fast
 
 
 def stream_ptr(stream=None) -> int:
     """Raw HIP stream of `stream`, or of torch's current stream."""
     if stream is not None:
         return int(stream.cuda_stream)
-    c = _torch()._C
-    if hasattr(c, "_cuda_getCurrentRawStream"):
+    if _raw_stream is not None:
         # the raw accessor skips building a torch Stream object (about 3 us)
-        return c._cuda_getCurrentRawStream(c._cuda_getDevice())
+        return _raw_stream(_cur_device())
     return int(_torch().cuda.current_stream().cuda_stream)
 
 
@@ -90,17 +102,42 @@ def _alpha(alphabet) -> ctypes.Array:
     return buf
 
 
+_alpha_addrs: dict = {}
+
+
+def _alpha_addr(alphabet) -> int:
+    """Address of _alpha(alphabet)'s buffer, for the fast-call binding; the
+    buffer stays alive in _alpha_cache (or in `_alpha_addrs`' own entry for
+    alphabets that are not cached there)."""
+    hit = _alpha_addrs.get(alphabet) if isinstance(alphabet, bytes) else None
+    if hit is not None:
+        return hit[0]
+    buf = _alpha(alphabet)
+    addr = ctypes.addressof(buf)
+    if isinstance(alphabet, bytes) and len(_alpha_addrs) < 256:
+        _alpha_addrs[alphabet] = (addr, buf)
+    else:
+        _alpha_keep.append(buf)
+        del _alpha_keep[:-8]
+    return addr
+
+
+_alpha_keep: list = []
+
+
 def _check_u8(t, what):
-    torch = _torch()
-    if not isinstance(t, torch.Tensor) or t.dtype != torch.uint8 or not t.is_cuda:
+    if _Tensor is None:
+        _torch()
+    if not isinstance(t, _Tensor) or t.dtype is not _U8 or not t.is_cuda:
         raise TypeError(f"{what} must be a torch.uint8 CUDA tensor")
     if not t.is_contiguous():
         raise ValueError(f"{what} must be contiguous")
 
 
 def _check_i64(t, what):
-    torch = _torch()
-    if not isinstance(t, torch.Tensor) or t.dtype != torch.int64 or not t.is_cuda:
+    if _Tensor is None:
+        _torch()
+    if not isinstance(t, _Tensor) or t.dtype is not _I64 or not t.is_cuda:
         raise TypeError(f"{what} must be a torch.int64 CUDA tensor")
     if not t.is_contiguous():
         raise ValueError(f"{what} must be contiguous")
@@ -146,40 +183,40 @@ def _workspace(n, flags, workspace, device):
 
 def encode(x, alphabet=STD, out=None, stream=None, flags: int = 0, line_len: int = 0):
     """Encode a uint8 CUDA tensor; returns out[:encoded length] (asynchronous)."""
-    torch = _torch()
+    F = _fast()
     _check_u8(x, "x")
     n = x.numel()
     m = _plain_enc_len(n) if flags == 0 and line_len == 0 else encoded_len(n, flags, line_len)
     if out is None:
-        out = torch.empty(max(m, 1), dtype=torch.uint8, device=x.device)
+        out = _torch().empty(max(m, 1), dtype=_U8, device=x.device)
     else:
         _check_u8(out, "out")
         if out.numel() < m:
             raise ValueError("out too small")
     if flags == 0 and line_len == 0:
-        r = check(load().b64_encode(x.data_ptr(), n, out.data_ptr(), _alpha(alphabet),
-                                    stream_ptr(stream)), "b64_encode")
+        r = check(F.encode(x.data_ptr(), n, out.data_ptr(), _alpha_addr(alphabet),
+                           stream_ptr(stream)), "b64_encode")
     else:
-        r = check(load().b64_encode_mode(x.data_ptr(), n, out.data_ptr(), _alpha(alphabet), flags,
-                                         line_len, stream_ptr(stream)), "b64_encode_mode")
+        r = check(F.encode_mode(x.data_ptr(), n, out.data_ptr(), _alpha_addr(alphabet), flags,
+                                line_len, stream_ptr(stream)), "b64_encode_mode")
     return out if out.numel() == r else out[:r]
 
 
 def decode(s, alphabet=STD, out=None, stream=None, flags: int = 0):
     """Blocking decode: (bytes_tensor, None) if valid, (None, first_bad) if not."""
-    torch = _torch()
+    F = _fast()
     _check_u8(s, "s")
     n = s.numel()
     cap = _plain_dec_cap(n) if flags == 0 else decoded_max_len(n, flags)
     if out is None:
-        out = torch.empty(max(cap, 1), dtype=torch.uint8, device=s.device)
+        out = _torch().empty(max(cap, 1), dtype=_U8, device=s.device)
     else:
         _check_u8(out, "out")
         if out.numel() < cap:
             raise ValueError("out too small")
     if flags == 0:
-        r = check(load().b64_decode(s.data_ptr(), n, out.data_ptr(), _alpha(alphabet),
-                                    stream_ptr(stream)), "b64_decode")
+        r = check(F.decode(s.data_ptr(), n, out.data_ptr(), _alpha_addr(alphabet),
+                           stream_ptr(stream)), "b64_decode")
     else:
         r = check(load().b64_decode_mode(s.data_ptr(), n, out.data_ptr(), _alpha(alphabet), flags,
                                          stream_ptr(stream)), "b64_decode_mode")
@@ -194,22 +231,22 @@ def decode_async(s, alphabet=STD, out=None, status=None, stream=None, flags: int
     device: [decoded length or -1, -1 or first invalid offset].  With SKIP_WS a
     device workspace of workspace_size(n, flags) bytes is used (allocated here
     unless given)."""
-    torch = _torch()
+    F = _fast()
     _check_u8(s, "s")
     n = s.numel()
     cap = _plain_dec_cap(n) if flags == 0 else decoded_max_len(n, flags)
     if out is None:
-        out = torch.empty(max(cap, 1), dtype=torch.uint8, device=s.device)
+        out = _torch().empty(max(cap, 1), dtype=_U8, device=s.device)
     if status is None:
-        status = torch.empty(2, dtype=torch.int64, device=s.device)
+        status = _torch().empty(2, dtype=_I64, device=s.device)
     _check_u8(out, "out")
     _check_i64(status, "status")
     if out.numel() < cap or status.numel() < 2:
         raise ValueError("out or status too small")
     sp = status.data_ptr()
     if flags == 0:
-        check(load().b64_decode_async(s.data_ptr(), n, out.data_ptr(), sp, sp + 8, _alpha(alphabet),
-                                      stream_ptr(stream)), "b64_decode_async")
+        check(F.decode_async(s.data_ptr(), n, out.data_ptr(), sp, sp + 8, _alpha_addr(alphabet),
+                             stream_ptr(stream)), "b64_decode_async")
     else:
         wp, wn = _workspace(n, flags, workspace, s.device)
         check(load().b64_decode_mode_async(s.data_ptr(), n, out.data_ptr(), sp, sp + 8,
@@ -221,10 +258,11 @@ def decode_async(s, alphabet=STD, out=None, status=None, stream=None, flags: int
 def validate(s, alphabet=STD, stream=None, flags: int = 0):
     """Blocking, read-only: (decoded length, None) if s is a valid encoding,
     (None, first_invalid_offset) if not."""
+    F = _fast()
     _check_u8(s, "s")
     if flags == 0:
-        r = check(load().b64_validate(s.data_ptr(), s.numel(), _alpha(alphabet),
-                                      stream_ptr(stream)), "b64_validate")
+        r = check(F.validate(s.data_ptr(), s.numel(), _alpha_addr(alphabet), stream_ptr(stream)),
+                  "b64_validate")
     else:
         r = check(load().b64_validate_mode(s.data_ptr(), s.numel(), _alpha(alphabet), flags,
                                            stream_ptr(stream)), "b64_validate_mode")
@@ -234,15 +272,15 @@ def validate(s, alphabet=STD, stream=None, flags: int = 0):
 def validate_async(s, alphabet=STD, status=None, stream=None, flags: int = 0, workspace=None):
     """Asynchronous validation; status = int64[2] on the device:
     [decoded length or -1, -1 or first invalid offset]."""
-    torch = _torch()
+    F = _fast()
     _check_u8(s, "s")
     if status is None:
-        status = torch.empty(2, dtype=torch.int64, device=s.device)
+        status = _torch().empty(2, dtype=_I64, device=s.device)
     _check_i64(status, "status")
     sp = status.data_ptr()
     if flags == 0:
-        check(load().b64_validate_async(s.data_ptr(), s.numel(), sp, sp + 8, _alpha(alphabet),
-                                        stream_ptr(stream)), "b64_validate_async")
+        check(F.validate_async(s.data_ptr(), s.numel(), sp, sp + 8, _alpha_addr(alphabet),
+                               stream_ptr(stream)), "b64_validate_async")
     else:
         wp, wn = _workspace(s.numel(), flags, workspace, s.device)
         check(load().b64_validate_mode_async(s.data_ptr(), s.numel(), sp, sp + 8, _alpha(alphabet),

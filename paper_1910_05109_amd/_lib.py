@@ -2,6 +2,9 @@
 
 Argument marshalling only: pointers, sizes and the HIP stream go across; every
 step of encoding, decoding and validation runs in the library's HIP kernels.
+The single-buffer entry points are also reached through `fast`, a CPython
+fast-call module (csrc/b64_pyfast.c) that load() binds to the same loaded
+library: it marshals the same integers without ctypes' per-argument cost.
 The library must have been built (python -m paper_1910_05109_amd.build); if it
 is missing this module raises instead of falling back to anything else.
 """
@@ -79,9 +82,29 @@ def load() -> ctypes.CDLL:
             fn = getattr(L, name)
             fn.argtypes = args
             fn.restype = res
+        _bind_fast(L)
         _lib = L
         _apply_tune_cache()
     return _lib
+
+
+fast = None
+FAST_ENTRY_POINTS = ("b64_encode", "b64_encode_mode", "b64_decode", "b64_decode_async",
+                     "b64_validate", "b64_validate_async")
+
+
+def _bind_fast(L: ctypes.CDLL) -> None:
+    """Hand the fast-call binding (_b64fast, built beside the library) the
+    addresses of its entry points in this loaded copy of the library."""
+    global fast
+    try:
+        from . import _b64fast
+    except ImportError as e:
+        raise ImportError("the fast-call binding _b64fast is not built; run "
+                          "`python -m paper_1910_05109_amd.build`") from e
+    _b64fast.bind(*(ctypes.cast(getattr(L, name), ctypes.c_void_p).value
+                    for name in FAST_ENTRY_POINTS))
+    fast = _b64fast
 
 
 def _apply_tune_cache() -> None:

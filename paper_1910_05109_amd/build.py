@@ -1,4 +1,5 @@
-"""Build libb64hip.so in-tree with hipcc for gfx950.
+"""Build libb64hip.so in-tree with hipcc for gfx950, and its CPython
+fast-call binding (_b64fast) with the host C compiler.
 
 Usage: python -m paper_1910_05109_amd.build   (or call build()).
 """
@@ -7,6 +8,7 @@ from __future__ import annotations
 import os
 import subprocess
 import sys
+import sysconfig
 import tempfile
 from concurrent.futures import ThreadPoolExecutor
 
@@ -18,6 +20,7 @@ SOURCES = [os.path.join(CSRC, f) for f in ("b64_single.hip", "b64_batch.hip", "b
                                             "b64_pipeline.hip", "b64_serve.hip",
                                             "b64_yardstick.hip")]
 LIB = os.path.join(HERE, "libb64hip.so")
+FAST = os.path.join(HERE, "_b64fast" + (sysconfig.get_config_var("EXT_SUFFIX") or ".so"))
 INCLUDE = os.path.join(ROOT, "include")
 ARCH = "gfx950"
 
@@ -54,7 +57,24 @@ def build(extra: list[str] | None = None, out: str = LIB, jobs: int | None = Non
         subprocess.check_call([hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", *extra,
                                *objs, "-o", tmp])
     os.replace(tmp, out)
+    if out == LIB:
+        build_fast()
     return out
+
+
+def build_fast() -> str:
+    """The CPython fast-call binding (csrc/b64_pyfast.c), compiled for the host
+    with the interpreter's own headers; it needs libb64hip.so only at run time
+    (the ctypes binding hands it the entry points)."""
+    py_inc = sysconfig.get_paths()["include"]
+    rocm = os.environ.get("ROCM_PATH", "/opt/rocm")
+    tmp = FAST + ".tmp"
+    subprocess.check_call([os.environ.get("CC", "gcc"), "-O2", "-shared", "-fPIC", "-Wall", "-Wextra",
+                           "-Wno-unused-parameter", "-D__HIP_PLATFORM_AMD__",
+                           f"-I{py_inc}", f"-I{INCLUDE}", f"-I{os.path.join(rocm, 'include')}",
+                           os.path.join(CSRC, "b64_pyfast.c"), "-o", tmp])
+    os.replace(tmp, FAST)
+    return FAST
 
 
 if __name__ == "__main__":

@@ -331,9 +331,9 @@ int64_t decode_enqueue(const uint8_t *src, int64_t n, uint8_t *dst, bool write, 
     }
     const DecSink sink{out_len, first_bad, sslot};
     if (write)
-        e = launch_decode(src, n, dst, make_dec(alphabet), sink, flags, shape_of(1, n), cus, stream);
+        e = launch_decode(src, n, dst, make_enc(alphabet), sink, flags, shape_of(1, n), cus, stream);
     else
-        e = launch_validate(src, n, make_dec(alphabet), sink, flags, shape_of(4, n), cus, stream);
+        e = launch_validate(src, n, make_enc(alphabet), sink, flags, shape_of(4, n), cus, stream);
     if (e != hipSuccess) return hip_fail(e, write ? "decode launch" : "validate launch");
     if (!sslot) {
         e = launch_finish(out_len, first_bad, 1, stream);

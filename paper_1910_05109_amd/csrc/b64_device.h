@@ -137,6 +137,79 @@ __device__ inline void enc_scalar(const uint8_t *p, int64_t r, uint8_t *o, const
     }
 }
 
+// The r <= 11 bytes left after an encode's chunks (at most three whole groups
+// and a partial group), or one head group (r = 3), fetched early and encoded
+// later: a kernel issues the loads before it stages its table and encodes
+// from registers afterwards.  The loads are whole dwords of a 12-byte window
+// of the input that holds the bytes (starting at them, or else ending where
+// they end) and nothing is extracted from them here, so no instruction waits
+// for a load; inputs too short for either window load bytes.
+struct EncTailIn {
+    uint32_t w[3];
+    int off;          // window offset of the first byte
+};
+
+// p = input + before, in an input of n bytes.
+__device__ __forceinline__ EncTailIn enc_tail_load(const uint8_t *p, int r, int64_t before,
+                                                   int64_t n)
+{
+    EncTailIn ti = {{0u, 0u, 0u}, 0};
+    if (r <= 0) return ti;
+    if (before + 12 <= n) {                 // the window [p, p + 12)
+        ti.w[0] = *(const u32a1 *)p;
+        ti.w[1] = *(const u32a1 *)(p + 4);
+        ti.w[2] = *(const u32a1 *)(p + 8);
+    } else if (before + r >= 12) {          // the window [p + r - 12, p + r)
+        const uint8_t *wp = p + r - 12;
+        ti.w[0] = *(const u32a1 *)wp;
+        ti.w[1] = *(const u32a1 *)(wp + 4);
+        ti.w[2] = *(const u32a1 *)(wp + 8);
+        ti.off = 12 - r;
+    } else {
+#pragma unroll
+        for (int i = 0; i < 11; ++i)
+            if (i < r) ti.w[i >> 2] |= (uint32_t)p[i] << (8 * (i & 3));
+    }
+    return ti;
+}
+
+// enc_scalar on bytes fetched by enc_tail_load (r <= 11).
+__device__ __forceinline__ void enc_tail_regs(const EncTailIn &ti, int r, uint8_t *o,
+                                              const uint8_t *tab, bool pad = true)
+{
+    // shift the window right by off bytes: t0..t2 hold the r bytes in order
+    const int q = ti.off >> 2;
+    const uint32_t k = (uint32_t)(ti.off & 3);
+    const uint32_t x0 = __builtin_amdgcn_alignbyte(ti.w[1], ti.w[0], k);
+    const uint32_t x1 = __builtin_amdgcn_alignbyte(ti.w[2], ti.w[1], k);
+    const uint32_t x2 = __builtin_amdgcn_alignbyte(0u, ti.w[2], k);
+    const uint32_t t0 = q == 0 ? x0 : q == 1 ? x1 : q == 2 ? x2 : 0u;
+    const uint32_t t1 = q == 0 ? x1 : q == 1 ? x2 : 0u;
+    const uint32_t t2 = q == 0 ? x2 : 0u;
+    const uint32_t t[3] = {t0, t1, t2};
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+        const int i = 3 * g;
+        const uint32_t s1 = (t[i >> 2] >> (8 * (i & 3))) & 0xFF;
+        const uint32_t s2 = i + 1 < 12 ? (t[(i + 1) >> 2] >> (8 * ((i + 1) & 3))) & 0xFF : 0u;
+        const uint32_t s3 = i + 2 < 12 ? (t[(i + 2) >> 2] >> (8 * ((i + 2) & 3))) & 0xFF : 0u;
+        if (i + 3 <= r) {
+            *(u32a1 *)(o + 4 * g) = enc_group(s2 | (s1 << 8) | (s3 << 16) | (s2 << 24), tab);
+        } else if (i < r) {
+            const int kk = r - i;
+            uint32_t v = kk == 1 ? enc_group(s1 << 8, tab) : enc_group(s2 | (s1 << 8) | (s2 << 24), tab);
+            if (pad) {
+                v = kk == 1 ? (v & 0xFFFFu) | (kPad << 16) | (kPad << 24) : (v & 0xFFFFFFu) | (kPad << 24);
+                *(u32a1 *)(o + 4 * g) = v;
+            } else {
+                o[4 * g] = (uint8_t)v;
+                o[4 * g + 1] = (uint8_t)(v >> 8);
+                if (kk == 2) o[4 * g + 2] = (uint8_t)(v >> 16);
+            }
+        }
+    }
+}
+
 __device__ __forceinline__ void stage_enc_table(uint32_t *s_tab, const EncTab &tab)
 {
     if (threadIdx.x < 16) s_tab[threadIdx.x] = tab.w[threadIdx.x];
@@ -152,6 +225,16 @@ __device__ __forceinline__ int64_t logical_block()
     const int64_t G = gridDim.x, b = blockIdx.x;
     if (G % kXcds != 0) return b;
     return (b % kXcds) * (G / kXcds) + b / kXcds;
+}
+
+// Complete rounds of `rstep` lane chunks in `nch` chunks.  Both fit 32 bits
+// for every input below 64 GiB, and a 32-bit quotient is a short instruction
+// sequence where a 64-bit one is over a hundred scalar instructions.
+__device__ __forceinline__ int64_t full_rounds(int64_t nch, int64_t rstep)
+{
+    if ((uint64_t)nch <= 0xFFFFFFFFull && (uint64_t)rstep <= 0xFFFFFFFFull)
+        return (int64_t)((uint32_t)nch / (uint32_t)rstep);
+    return nch / rstep;
 }
 
 // ---------------------------------------------------------------- decode --
@@ -289,19 +372,23 @@ struct TailIn {
     uint32_t fq;
 };
 
+// Every value is kept as loaded (the shift that aligns the final quantum is
+// applied by dec_tail_regs), so no instruction here waits for a load.
 __device__ __forceinline__ TailIn tail_load(const uint8_t *p, int64_t len)
 {
     TailIn ti = {{0u, 0u, 0u}, 0u};
     if (len <= 0) return ti;
-    const int nb = (int)((len - 1) >> 2);                  // body quanta, 0..3
-    const int r = (int)(len - 4 * nb);                     // final quantum, 1..4
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-        if (i < nb) ti.q[i] = *(const u32a1 *)(p + 4 * i);
     if (len >= 4) {
-        ti.fq = *(const u32a1 *)(p + len - 4) >> (8 * (4 - r));
+        const int nb = (int)((len - 1) >> 2);              // body quanta, 0..3
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+            if (i < nb) ti.q[i] = *(const u32a1 *)(p + 4 * i);
+        ti.fq = *(const u32a1 *)(p + len - 4);             // the last four characters
     } else {
-        for (int i = 0; i < r; ++i) ti.fq |= (uint32_t)p[i] << (8 * i);
+        // no body quantum: q[i] holds character i of the final quantum
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+            if (i < len) ti.q[i] = p[i];
     }
     return ti;
 }
@@ -335,7 +422,9 @@ __device__ inline int64_t dec_tail_regs(const TailIn &ti, const uint8_t *p, int6
     }
     int nd = 0;
     uint32_t fv = 0;
-    const int fbad = final_quantum(ti.fq, r, map, nopad, &nd, &fv);
+    // the final quantum's r characters in bytes 0..r-1
+    const uint32_t fq = len >= 4 ? ti.fq >> (8 * (4 - r)) : ti.q[0] | (ti.q[1] << 8) | (ti.q[2] << 16);
+    const int fbad = final_quantum(fq, r, map, nopad, &nd, &fv);
     if (fbad >= 0) return 4 * nb + fbad;
     if (o) {
 #pragma unroll
@@ -365,6 +454,24 @@ __device__ inline int64_t dec_tail_fast(const uint8_t *p, int64_t len, int64_t n
 __device__ __forceinline__ void stage_dec_map(uint32_t *s_map, const DecMap &map)
 {
     if (threadIdx.x < 64) s_map[threadIdx.x] = map.w[threadIdx.x];
+    __syncthreads();
+}
+
+// The same map built in LDS from the alphabet (a 64-byte kernel argument in
+// place of the 256-byte map): every entry kBad, then entry alphabet[v] = v;
+// the host has checked that the 64 bytes are distinct.  The first barrier
+// passes while the caller's earlier loads are still in flight; only the
+// scatter and the second barrier wait for them.
+__device__ __forceinline__ void stage_dec_map_alpha(uint32_t *s_map, const EncTab &alpha)
+{
+    uint32_t w = 0;
+    if (threadIdx.x < 64) {
+        s_map[threadIdx.x] = kBad * 0x01010101u;
+        w = alpha.w[threadIdx.x >> 2];
+    }
+    __syncthreads();
+    if (threadIdx.x < 64)
+        ((uint8_t *)s_map)[(w >> (8 * (threadIdx.x & 3))) & 0xFF] = (uint8_t)threadIdx.x;
     __syncthreads();
 }
 
@@ -554,21 +661,33 @@ __device__ __forceinline__ void enc_stream(const uint8_t *s0, uint8_t *d0, int64
 // so the loads stay outside any branch and the compiler waits for each load
 // alone rather than for every earlier store.
 template <int U, bool NT>
-__device__ __forceinline__ void enc_round_tail(const uint8_t *s0, uint8_t *d0, int64_t c0,
-                                               int64_t stride, const uint8_t *tab, int64_t nch)
+__device__ __forceinline__ void enc_round_load(u32x3 (&in)[U], const uint8_t *s0, int64_t c0,
+                                               int64_t stride, int64_t nch)
 {
     if (nch <= 0) return;
-    u32x3 in[U];
 #pragma unroll
     for (int j = 0; j < U; ++j) {
         const int64_t c = c0 + j * stride;
         in[j] = load12<NT>(s0 + 12 * (c < nch ? c : nch - 1));
     }
+}
+template <int U, bool NT>
+__device__ __forceinline__ void enc_round_store(const u32x3 (&in)[U], uint8_t *d0, int64_t c0,
+                                                int64_t stride, const uint8_t *tab, int64_t nch)
+{
 #pragma unroll
     for (int j = 0; j < U; ++j) {
         const int64_t c = c0 + j * stride;
         if (c < nch) store16<NT>(d0 + 16 * c, enc_chunk(in[j], tab));
     }
+}
+template <int U, bool NT>
+__device__ __forceinline__ void enc_round_tail(const uint8_t *s0, uint8_t *d0, int64_t c0,
+                                               int64_t stride, const uint8_t *tab, int64_t nch)
+{
+    u32x3 in[U];
+    enc_round_load<U, NT>(in, s0, c0, stride, nch);
+    enc_round_store<U, NT>(in, d0, c0, stride, tab, nch);
 }
 
 template <int U, bool NT>

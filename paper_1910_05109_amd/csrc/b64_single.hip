@@ -21,16 +21,14 @@ int64_t *g_slots_base[64];
 // with U chunks in flight per lane.  Threads t < head encode one head group
 // each; the last thread encodes the at most three whole groups and the
 // partial group left after the chunks (padded, or cut short under
-// kFlagNoPad).
+// kFlagNoPad).  Loads that need no table are issued before the table is
+// staged, so that their latency overlaps the staging: when the input takes a
+// single round, that round's chunks, then the head groups and the tail.
 template <int U, bool NT>
 __global__ __launch_bounds__(kThreads) void k_encode(const uint8_t *__restrict__ src, int64_t n,
                                                      uint8_t *__restrict__ dst, EncTab tab,
                                                      uint32_t flags)
 {
-    __shared__ uint32_t s_tab[16];
-    stage_enc_table(s_tab, tab);
-    const uint8_t *a = (const uint8_t *)s_tab;
-
     const int64_t ng = n / 3;
     const uint64_t da = (uint64_t)(uintptr_t)dst;
     int64_t head = (da & 3) ? 0 : (int64_t)((((uint64_t)kLine - (da & (kLine - 1))) & (kLine - 1)) >> 2);
@@ -40,17 +38,27 @@ __global__ __launch_bounds__(kThreads) void k_encode(const uint8_t *__restrict__
     uint8_t *d0 = dst + 4 * head;
     const int64_t T = (int64_t)gridDim.x * kThreads;
     const int64_t t = logical_block() * kThreads + threadIdx.x;
-    // rounds of U*T chunks; all but the last are complete
-    const int64_t nfull = nch / (U * T);
-    int64_t c0 = t;
-    enc_stream<U, NT>(s0, d0, c0, T, U * T, nfull, a);
-    c0 += nfull * U * T;
-    enc_round_tail<U, NT>(s0, d0, c0, T, a, nch);
-    if (t < head) enc_scalar(src + 3 * t, 3, dst + 4 * t, a);
-    if (t == kThreads - 1) {
-        const int64_t g = head + 4 * nch;
-        enc_scalar(src + 3 * g, n - 3 * g, dst + 4 * g, a, !(flags & kFlagNoPad));
+    const int64_t rstep = U * T;
+    const bool single = nch < rstep;                // one round, all but the last lanes' chunks
+    const int64_t g = head + 4 * nch;               // first group of the tail
+    u32x3 first[U];
+    if (single) enc_round_load<U, NT>(first, s0, t, T, nch);
+    EncTailIn hin, tin;
+    if (t < head) hin = enc_tail_load(src + 3 * t, 3, 3 * t, n);
+    if (t == kThreads - 1) tin = enc_tail_load(src + 3 * g, (int)(n - 3 * g), 3 * g, n);
+
+    __shared__ uint32_t s_tab[16];
+    stage_enc_table(s_tab, tab);
+    const uint8_t *a = (const uint8_t *)s_tab;
+    if (single) {
+        enc_round_store<U, NT>(first, d0, t, T, a, nch);
+    } else {
+        const int64_t nfull = full_rounds(nch, rstep);
+        enc_stream<U, NT>(s0, d0, t, T, rstep, nfull, a);
+        enc_round_tail<U, NT>(s0, d0, t + nfull * rstep, T, a, nch);
     }
+    if (t < head) enc_tail_regs(hin, 3, dst + 4 * t, a);
+    if (t == kThreads - 1) enc_tail_regs(tin, (int)(n - 3 * g), dst + 4 * g, a, !(flags & kFlagNoPad));
 }
 
 // Single buffer.  The body is every quantum but the last (nbq quanta).
@@ -65,7 +73,7 @@ __global__ __launch_bounds__(kThreads) void k_encode(const uint8_t *__restrict__
 // characters; the body is the same.
 template <int U, bool NT>
 __global__ __launch_bounds__(kThreads) void k_decode(const uint8_t *__restrict__ src, int64_t n,
-                                                     uint8_t *__restrict__ dst, DecMap map,
+                                                     uint8_t *__restrict__ dst, EncTab alpha,
                                                      DecSink sink, uint32_t flags)
 {
     const bool nopad = (flags & kFlagNoPad) != 0;
@@ -78,29 +86,30 @@ __global__ __launch_bounds__(kThreads) void k_decode(const uint8_t *__restrict__
     uint8_t *d0 = dst + 3 * head;
     const int64_t T = (int64_t)gridDim.x * kThreads;
     const int64_t t = logical_block() * kThreads + threadIdx.x;
-    // rounds of U*T chunks; all but the last are complete
-    const int64_t nfull = nch / (U * T);
+    const int64_t rstep = U * T;
+    const bool single = nch < rstep;                // one round, all but the last lanes' chunks
     const int64_t q = head + 4 * nch;               // first quantum of the tail
     // Loads that need no map are issued before the map is staged, so that
-    // their latency overlaps the staging: the head quantum, the tail and, when
-    // the input takes a single round, that round's chunks.
+    // their latency overlaps the staging: when the input takes a single round,
+    // that round's chunks, then the head quantum and the tail.
+    u32x4 first[U];
+    if (single) dec_round_load<U, NT>(first, s0, t, T, nch);
     uint32_t hq = 0;
     if (t < head) hq = *(const u32a1 *)(src + 4 * t);
     TailIn tin = {{0u, 0u, 0u}, 0u};
     if (t == kThreads - 1) tin = tail_load(src + 4 * q, n - 4 * q);
-    u32x4 first[U];
-    if (nfull == 0) dec_round_load<U, NT>(first, s0, t, T, nch);
 
     __shared__ uint32_t s_map[64];
-    stage_dec_map(s_map, map);
+    stage_dec_map_alpha(s_map, alpha);
     const uint8_t *m = (const uint8_t *)s_map;
     uint32_t err = 0;
     SinkLane lane;
-    if (nfull == 0) {
+    if (single) {
         if (nch > 0) dec_round_store<U, NT>(first, d0, t, T, m, err, nch);
     } else {
-        dec_stream<U, NT>(s0, d0, t, T, U * T, nfull, m, err);
-        dec_round_tail<U, NT>(s0, d0, t + nfull * U * T, T, m, err, nch);
+        const int64_t nfull = full_rounds(nch, rstep);
+        dec_stream<U, NT>(s0, d0, t, T, rstep, nfull, m, err);
+        dec_round_tail<U, NT>(s0, d0, t + nfull * rstep, T, m, err, nch);
     }
     // One test per lane for its whole share (bit 7 is set only by kBad).
     if (__ballot(err & 0x80)) {
@@ -175,12 +184,12 @@ hipError_t launch_encode(const uint8_t *src, int64_t n, uint8_t *dst, const EncT
     return hipGetLastError();
 }
 
-hipError_t launch_decode(const uint8_t *src, int64_t n, uint8_t *dst, const DecMap &map,
+hipError_t launch_decode(const uint8_t *src, int64_t n, uint8_t *dst, const EncTab &alpha,
                          const DecSink &sink, uint32_t flags, Shape sh, int cus, hipStream_t stream)
 {
     const int64_t nbq = n >= 1 ? (n - 1) >> 2 : 0;
     const int64_t grid = grid_for(nbq >> 2, sh, cus);
-    B64_DISPATCH(k_decode, sh, grid, stream, src, n, dst, map, sink, flags);
+    B64_DISPATCH(k_decode, sh, grid, stream, src, n, dst, alpha, sink, flags);
     return hipGetLastError();
 }
 
@@ -206,7 +215,7 @@ hipError_t status_slot_addr(int idx, int64_t **out)
 hipError_t launch_fill(int64_t *p, int64_t count, int64_t value, hipStream_t stream)
 {
     const int64_t blocks = (count + kThreads - 1) / kThreads;
-    hipLaunchKernelGGL(k_fill_i64, dim3(blocks), dim3(kThreads), 0, stream, p, count, value);
+    (void)launch_args(&k_fill_i64, dim3(blocks), dim3(kThreads), stream, p, count, value);
     return hipGetLastError();
 }
 

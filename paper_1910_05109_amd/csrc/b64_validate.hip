@@ -67,42 +67,44 @@ __device__ __forceinline__ uint32_t val_stream(const uint8_t *s0, int64_t c0, in
 // rules.
 template <int U, bool NT>
 __global__ __launch_bounds__(kThreads) void k_validate(const uint8_t *__restrict__ src, int64_t n,
-                                                       DecMap map, DecSink sink, uint32_t flags)
+                                                       EncTab alpha, DecSink sink, uint32_t flags)
 {
     const bool nopad = (flags & kFlagNoPad) != 0;
     const int64_t nbq = n >= 1 ? (n - 1) >> 2 : 0;
     const int64_t nch = nbq >> 2;
     const int64_t T = (int64_t)gridDim.x * kThreads;
     const int64_t t = logical_block() * kThreads + threadIdx.x;
-    const int64_t nfull = nch / (U * T);
+    const int64_t rstep = U * T;
+    const bool single = nch < rstep;                // one round, all but the last lanes' chunks
     const int64_t q0 = 4 * nch;                     // first quantum after the chunks
     // Loads that need no map go first, overlapping the staging of the map:
-    // the tail and, when the input takes a single round, that round's chunks.
-    TailIn tin = {{0u, 0u, 0u}, 0u};
-    if (t == kThreads - 1) tin = tail_load(src + 4 * q0, n - 4 * q0);
+    // when the input takes a single round, that round's chunks, then the tail.
     u32x4 first[U];
-    if (nfull == 0 && nch > 0) {
+    if (single && nch > 0) {
 #pragma unroll
         for (int j = 0; j < U; ++j) {
             const int64_t c = t + j * T;
             first[j] = load16<NT>(src + 16 * (c < nch ? c : nch - 1));
         }
     }
+    TailIn tin = {{0u, 0u, 0u}, 0u};
+    if (t == kThreads - 1) tin = tail_load(src + 4 * q0, n - 4 * q0);
 
     __shared__ uint32_t s_map[64];
-    stage_dec_map(s_map, map);
+    stage_dec_map_alpha(s_map, alpha);
     const uint8_t *m = (const uint8_t *)s_map;
     SinkLane lane;
     uint32_t err = 0;
-    if (nfull == 0) {
+    if (single) {
         if (nch > 0) {
 #pragma unroll
             for (int j = 0; j < U; ++j)
                 if (t + j * T < nch) err |= val_chunk(first[j], m);
         }
     } else {
-        err = val_stream<U, NT>(src, t, T, U * T, nfull, m);
-        for (int64_t c = t + nfull * U * T; c < nch; c += T)
+        const int64_t nfull = full_rounds(nch, rstep);
+        err = val_stream<U, NT>(src, t, T, rstep, nfull, m);
+        for (int64_t c = t + nfull * rstep; c < nch; c += T)
             err |= val_chunk(load16<NT>(src + 16 * c), m);
     }
     if (__ballot(err & 0x80)) {
@@ -127,12 +129,12 @@ __global__ __launch_bounds__(kThreads) void k_validate(const uint8_t *__restrict
 
 }  // namespace
 
-hipError_t launch_validate(const uint8_t *src, int64_t n, const DecMap &map, const DecSink &sink,
+hipError_t launch_validate(const uint8_t *src, int64_t n, const EncTab &alpha, const DecSink &sink,
                            uint32_t flags, Shape sh, int cus, hipStream_t stream)
 {
     const int64_t nbq = n >= 1 ? (n - 1) >> 2 : 0;
     const int64_t grid = grid_for(nbq >> 2, sh, cus);
-    B64_DISPATCH(k_validate, sh, grid, stream, src, n, map, sink, flags);
+    B64_DISPATCH(k_validate, sh, grid, stream, src, n, alpha, sink, flags);
     return hipGetLastError();
 }
 

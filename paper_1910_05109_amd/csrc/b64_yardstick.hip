@@ -65,7 +65,7 @@ __global__ __launch_bounds__(kThreads) void k_yardstick(const uint8_t *__restric
     const int64_t T = (int64_t)gridDim.x * kThreads;
     const int64_t t = logical_block() * kThreads + threadIdx.x;
     const int64_t rstep = U * T;
-    const int64_t nfull = nch / rstep;
+    const int64_t nfull = full_rounds(nch, rstep);
     uint32_t acc = 0;
     int64_t c0 = t;
     if (nfull > 0) {
@@ -109,14 +109,14 @@ hipError_t launch_kind(const uint8_t *src, uint8_t *dst, int64_t nch, Shape sh, 
                        hipStream_t stream)
 {
     const int64_t grid = grid_for(nch, sh, cus);
-#define B64_YARD(U_)                                                                            \
-    do {                                                                                       \
-        if (sh.nt)                                                                             \
-            hipLaunchKernelGGL((k_yardstick<U_, true, RIN, WOUT>), dim3(grid), dim3(kThreads),  \
-                               0, stream, src, dst, nch);                                      \
-        else                                                                                   \
-            hipLaunchKernelGGL((k_yardstick<U_, false, RIN, WOUT>), dim3(grid), dim3(kThreads), \
-                               0, stream, src, dst, nch);                                      \
+#define B64_YARD(U_)                                                                         \
+    do {                                                                                    \
+        if (sh.nt)                                                                          \
+            (void)launch_args(&k_yardstick<U_, true, RIN, WOUT>, dim3(grid), dim3(kThreads), stream, \
+                        src, dst, nch);                                                     \
+        else                                                                                \
+            (void)launch_args(&k_yardstick<U_, false, RIN, WOUT>, dim3(grid), dim3(kThreads), stream, \
+                        src, dst, nch);                                                     \
     } while (0)
     switch (sh.unroll) {
     case 1: B64_YARD(1); break;

@@ -241,3 +241,44 @@ def test_binding_size_copies_match_the_library(lib):
     assert np.array_equal(b64._dec_cap(t).numpy(), dec)
     assert np.array_equal(b64._enc_cap_nopad(t).numpy(), enc_np)
     assert np.array_equal(b64._dec_cap_nopad(t).numpy(), dec_np)
+
+
+def test_fast_binding_reaches_the_same_library(lib):
+    """The fast-call binding (_b64fast) calls the entry points of the loaded
+    library: the same host-side argument errors as through ctypes, the error
+    message left in that library's b64_last_error, argument-count and type
+    errors raised in Python, and zero-size work done without a device."""
+    from paper_1910_05109_amd import _lib
+    F = _lib.fast
+    assert F is not None
+    EARG = -(2 ** 63)
+    std = ctypes.create_string_buffer(b"ABCDEFGHIJKLMNOPQRSTUVWXYZabcdefghijklmnopqrstuvwxyz0123456789+/", 64)
+    dup = ctypes.create_string_buffer(b"A" * 64, 64)
+    a_std, a_dup = ctypes.addressof(std), ctypes.addressof(dup)
+    fake = 0x1000
+    assert F.encode(fake, -1, fake, a_std, 0) == EARG
+    assert b"negative" in lib.b64_last_error()
+    assert F.encode(fake, 10, fake, a_dup, 0) == EARG
+    assert b"alphabet" in lib.b64_last_error()
+    assert F.encode(0, 10, fake, a_std, 0) == EARG
+    assert F.encode_mode(fake, 10, fake, a_std, 2, 0, 0) == EARG           # SKIP_WS
+    assert F.encode_mode(fake, 10, fake, a_std, 0, 2, 0) == EARG           # line_len 2
+    assert F.decode(fake, -3, fake, a_std, 0) == EARG
+    assert F.decode(fake, 10, fake, a_dup, 0) == EARG
+    assert F.decode_async(fake, 10, fake, 0, fake, a_std, 0) == EARG
+    assert F.validate(0, 10, a_std, 0) == EARG
+    assert F.validate_async(fake, 10, fake, 0, a_std, 0) == EARG
+    assert F.encode(0, 0, 0, a_std, 0) == 0
+    assert F.encode_mode(0, 0, 0, a_std, 1, 76, 0) == 0
+    with pytest.raises(TypeError):
+        F.encode(fake, 10, fake, a_std)
+    with pytest.raises(TypeError):
+        F.decode_async(fake, "10", fake, fake, fake, a_std, 0)
+    with pytest.raises(OverflowError):
+        F.validate(fake, 1 << 70, a_std, 0)
+    with pytest.raises(ValueError):
+        F.bind(0, 0, 0, 0, 0, 0)
+    # the binding's alphabet addresses point at the 64 bytes themselves
+    import paper_1910_05109_amd as b64
+    for alpha in (b64.STD, b64.URL, bytes(bytearray(b64.URL)[::-1])):
+        assert ctypes.string_at(b64._alpha_addr(alpha), 64) == alpha
