@@ -183,22 +183,26 @@ def _workspace(n, flags, workspace, device):
 
 def encode(x, alphabet=STD, out=None, stream=None, flags: int = 0, line_len: int = 0):
     """Encode a uint8 CUDA tensor; returns out[:encoded length] (asynchronous)."""
-    F = _fast()
+    F = _lib.fast or _fast()
     _check_u8(x, "x")
     n = x.numel()
-    m = _plain_enc_len(n) if flags == 0 and line_len == 0 else encoded_len(n, flags, line_len)
+    plain = flags == 0 and line_len == 0
+    m = _plain_enc_len(n) if plain else encoded_len(n, flags, line_len)
     if out is None:
-        out = _torch().empty(max(m, 1), dtype=_U8, device=x.device)
+        out = _torch_mod.empty(max(m, 1), dtype=_U8, device=x.device)
     else:
         _check_u8(out, "out")
         if out.numel() < m:
             raise ValueError("out too small")
-    if flags == 0 and line_len == 0:
-        r = check(F.encode(x.data_ptr(), n, out.data_ptr(), _alpha_addr(alphabet),
-                           stream_ptr(stream)), "b64_encode")
+    hit = _alpha_addrs.get(alphabet) if alphabet.__class__ is bytes else None
+    a = hit[0] if hit is not None else _alpha_addr(alphabet)
+    st = _raw_stream(_cur_device()) if stream is None and _raw_stream is not None else stream_ptr(stream)
+    if plain:
+        r = F.encode(x.data_ptr(), n, out.data_ptr(), a, st)
     else:
-        r = check(F.encode_mode(x.data_ptr(), n, out.data_ptr(), _alpha_addr(alphabet), flags,
-                                line_len, stream_ptr(stream)), "b64_encode_mode")
+        r = F.encode_mode(x.data_ptr(), n, out.data_ptr(), a, flags, line_len, st)
+    if r < 0:
+        check(r, "b64_encode" if plain else "b64_encode_mode")
     return out if out.numel() == r else out[:r]
 
 
@@ -231,26 +235,32 @@ def decode_async(s, alphabet=STD, out=None, status=None, stream=None, flags: int
     device: [decoded length or -1, -1 or first invalid offset].  With SKIP_WS a
     device workspace of workspace_size(n, flags) bytes is used (allocated here
     unless given)."""
-    F = _fast()
+    F = _lib.fast or _fast()
     _check_u8(s, "s")
     n = s.numel()
     cap = _plain_dec_cap(n) if flags == 0 else decoded_max_len(n, flags)
     if out is None:
-        out = _torch().empty(max(cap, 1), dtype=_U8, device=s.device)
+        out = _torch_mod.empty(max(cap, 1), dtype=_U8, device=s.device)
+    else:
+        _check_u8(out, "out")
     if status is None:
-        status = _torch().empty(2, dtype=_I64, device=s.device)
-    _check_u8(out, "out")
-    _check_i64(status, "status")
+        status = _torch_mod.empty(2, dtype=_I64, device=s.device)
+    else:
+        _check_i64(status, "status")
     if out.numel() < cap or status.numel() < 2:
         raise ValueError("out or status too small")
     sp = status.data_ptr()
+    st = _raw_stream(_cur_device()) if stream is None and _raw_stream is not None else stream_ptr(stream)
     if flags == 0:
-        check(F.decode_async(s.data_ptr(), n, out.data_ptr(), sp, sp + 8, _alpha_addr(alphabet),
-                             stream_ptr(stream)), "b64_decode_async")
+        hit = _alpha_addrs.get(alphabet) if alphabet.__class__ is bytes else None
+        a = hit[0] if hit is not None else _alpha_addr(alphabet)
+        r = F.decode_async(s.data_ptr(), n, out.data_ptr(), sp, sp + 8, a, st)
+        if r < 0:
+            check(r, "b64_decode_async")
     else:
         wp, wn = _workspace(n, flags, workspace, s.device)
         check(load().b64_decode_mode_async(s.data_ptr(), n, out.data_ptr(), sp, sp + 8,
-                                           _alpha(alphabet), flags, wp, wn, stream_ptr(stream)),
+                                           _alpha(alphabet), flags, wp, wn, st),
               "b64_decode_mode_async")
     return out, status
 
@@ -272,19 +282,26 @@ def validate(s, alphabet=STD, stream=None, flags: int = 0):
 def validate_async(s, alphabet=STD, status=None, stream=None, flags: int = 0, workspace=None):
     """Asynchronous validation; status = int64[2] on the device:
     [decoded length or -1, -1 or first invalid offset]."""
-    F = _fast()
+    F = _lib.fast or _fast()
     _check_u8(s, "s")
     if status is None:
-        status = _torch().empty(2, dtype=_I64, device=s.device)
-    _check_i64(status, "status")
+        status = _torch_mod.empty(2, dtype=_I64, device=s.device)
+    else:
+        _check_i64(status, "status")
+    if status.numel() < 2:
+        raise ValueError("status too small")
     sp = status.data_ptr()
+    st = _raw_stream(_cur_device()) if stream is None and _raw_stream is not None else stream_ptr(stream)
     if flags == 0:
-        check(F.validate_async(s.data_ptr(), s.numel(), sp, sp + 8, _alpha_addr(alphabet),
-                               stream_ptr(stream)), "b64_validate_async")
+        hit = _alpha_addrs.get(alphabet) if alphabet.__class__ is bytes else None
+        a = hit[0] if hit is not None else _alpha_addr(alphabet)
+        r = F.validate_async(s.data_ptr(), s.numel(), sp, sp + 8, a, st)
+        if r < 0:
+            check(r, "b64_validate_async")
     else:
         wp, wn = _workspace(s.numel(), flags, workspace, s.device)
         check(load().b64_validate_mode_async(s.data_ptr(), s.numel(), sp, sp + 8, _alpha(alphabet),
-                                             flags, wp, wn, stream_ptr(stream)),
+                                             flags, wp, wn, st),
               "b64_validate_mode_async")
     return status
 

@@ -81,14 +81,14 @@ constexpr int kOps = 8;
 constexpr int kBuckets = 5;
 constexpr int64_t kBucketLimit[kBuckets - 1] = {64 << 10, 1 << 20, 16 << 20, 128 << 20};
 Shape g_shape[kOps][kBuckets] = {
-    {{1, 4, 0}, {1, 16, 1}, {2, 32, 0}, {1, 32, 0}, {8, 1, 1}},       // encode
-    {{1, 4, 1}, {1, 16, 1}, {1, 4, 1}, {1, 4, 0}, {2, 2, 1}},         // decode
-    {{2, 2, 1}, {2, 2, 1}, {2, 2, 1}, {2, 2, 1}, {2, 2, 1}},          // encode_batch
-    {{4, 16, 1}, {4, 16, 1}, {4, 16, 1}, {4, 16, 1}, {4, 16, 1}},     // decode_batch
-    {{1, 8, 0}, {1, 4, 1}, {1, 64, 0}, {1, 4, 1}, {8, 1, 1}},         // validate
-    {{1, 4, 1}, {1, 64, 0}, {1, 8, 0}, {1, 8, 0}, {8, 1, 0}},         // line-wrapped encode
-    {{1, 2, 0}, {4, 2, 1}, {1, 16, 0}, {4, 2, 1}, {2, 8, 1}},         // whitespace-skipping decode
-    {{2, 64, 1}, {2, 64, 1}, {2, 64, 1}, {2, 64, 1}, {2, 64, 1}},     // fused decode
+    {{1, 32, 0}, {1, 4, 1}, {2, 16, 0}, {2, 32, 0}, {8, 1, 1}},   // encode
+    {{1, 8, 1}, {1, 64, 1}, {1, 8, 0}, {1, 4, 0}, {2, 2, 1}},     // decode
+    {{2, 2, 1}, {2, 2, 1}, {2, 2, 1}, {2, 2, 1}, {2, 2, 1}},      // encode_batch
+    {{4, 16, 1}, {4, 16, 1}, {4, 16, 1}, {4, 16, 1}, {4, 16, 1}}, // decode_batch
+    {{1, 1, 1}, {1, 8, 1}, {2, 32, 0}, {1, 4, 1}, {2, 2, 1}},     // validate
+    {{1, 16, 1}, {1, 4, 0}, {1, 16, 0}, {1, 8, 0}, {8, 1, 0}},    // line-wrapped encode
+    {{1, 2, 0}, {4, 4, 0}, {2, 8, 0}, {4, 2, 1}, {2, 8, 1}},      // whitespace-skipping decode
+    {{2, 64, 1}, {2, 64, 1}, {2, 64, 1}, {2, 64, 1}, {2, 64, 1}}, // fused decode
 };
 std::mutex g_mu;
 

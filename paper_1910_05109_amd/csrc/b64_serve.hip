@@ -154,6 +154,30 @@ hipError_t host_alloc(void **p, int64_t bytes)
     return hipHostMalloc(p, (size_t)std::max<int64_t>(bytes, 64), hipHostMallocDefault);
 }
 
+// The HIP runtime sets up a stream's DMA copy queues on first use, and the
+// hipMemcpyAsync that does it blocks the calling thread for milliseconds
+// (5-8 ms measured on MI355X, on the first host-to-device and device-to-host
+// copies of each stream).  The scheduler thread must not stall with requests
+// waiting, so every stream makes copies of both directions, small and large,
+// once here, at creation.
+hipError_t warm_copies(b64_server *s)
+{
+    const int64_t big = std::min<int64_t>(1 << 20, s->budget);
+    uint8_t *h = nullptr;
+    hipError_t e = host_alloc((void **)&h, big);
+    if (e != hipSuccess) return e;
+    memset(h, 0, (size_t)big);
+    for (hipStream_t st : s->streams) {
+        for (const int64_t bytes : {(int64_t)64, big}) {
+            if (e == hipSuccess) e = hipMemcpyAsync(s->arena, h, (size_t)bytes, hipMemcpyHostToDevice, st);
+            if (e == hipSuccess) e = hipMemcpyAsync(h, s->arena, (size_t)bytes, hipMemcpyDeviceToHost, st);
+        }
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+    }
+    (void)hipHostFree(h);
+    return e;
+}
+
 }  // namespace
 
 extern "C" {
@@ -195,6 +219,7 @@ b64_server *b64_server_create(int64_t budget_bytes, int nstreams, int depth, int
         if (e == hipSuccess) s->stat_out.push_back(so);
     }
     if (e == hipSuccess) e = hipEventCreate(&s->ref);
+    if (e == hipSuccess) e = warm_copies(s);
     if (e != hipSuccess) {
         s_hip(e, "server creation");
         b64_server_destroy(s);
