@@ -344,6 +344,15 @@ int64_t b64_tune_bucket(int64_t n);
  * autotuner and for tests that want either path on small texts.  Does not
  * change results.  Not a paper operation: a launch-policy knob.              */
 int64_t b64_tune_ws_guess_min(int64_t min_chars);
+/* Whitespace-skipping decode and validation (B64_SKIP_WS): texts of at most
+ * `max_chars` bytes (0 .. 65,536; default 65,536) run in one launch of one
+ * workgroup, which compacts the significant characters in LDS; longer texts
+ * take the multi-launch paths above.  max_chars >= 0 sets the size, a
+ * negative value only reads it; returns the size in force before the call,
+ * or B64_EARG above 65,536.  Process-wide, for tests that want the
+ * multi-launch paths on small texts.  Does not change results.  Not a paper
+ * operation: a launch-policy knob.                                           */
+int64_t b64_tune_ws_small_max(int64_t max_chars);
 
 /* Bandwidth yardstick (not a codec operation; Section "Experiments" measures
  * the codec against a memory copy): streaming kernels with the codec kernels'

@@ -45,7 +45,7 @@ __all__ = ["STD", "URL", "NOPAD", "SKIP_WS", "B64Error", "load", "encoded_len", 
            "workspace_size", "encode",
            "decode", "decode_async", "validate", "validate_async", "encode_batch", "decode_batch",
            "decode_f32_bf16", "tune_set", "tune_get", "tune_shapes", "tune_restore", "tune_bucket",
-           "tune_ws_guess_min", "stream_ptr", "BUCKETS"]
+           "tune_ws_guess_min", "tune_ws_small_max", "stream_ptr", "BUCKETS"]
 
 
 # The wrappers below sit on the launch path of every call, so they keep their
@@ -478,6 +478,13 @@ def tune_ws_guess_min(min_chars: int = -1) -> int:
     regular-line guess; sets it when min_chars >= 0.  Returns the previous
     size."""
     return int(load().b64_tune_ws_guess_min(int(min_chars)))
+
+
+def tune_ws_small_max(max_chars: int = -1) -> int:
+    """Size in bytes up to which the whitespace-skipping decode runs in one
+    launch of one workgroup (at most 65,536); sets it when max_chars >= 0.
+    Returns the previous size."""
+    return check(load().b64_tune_ws_small_max(int(max_chars)), "b64_tune_ws_small_max")
 
 
 def tune_get(op: str, bucket: int = BUCKETS - 1) -> tuple[int, int, int]:

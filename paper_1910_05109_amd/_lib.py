@@ -58,6 +58,7 @@ SIGNATURES = {
     "b64_tune_get": ([_INT], _I64),
     "b64_tune_bucket": ([_I64], _I64),
     "b64_tune_ws_guess_min": ([_I64], _I64),
+    "b64_tune_ws_small_max": ([_I64], _I64),
     "b64_yardstick": ([_INT, _P, _P, _I64, _P], _I64),
     "b64_last_error": ([], ctypes.c_char_p),
 }

@@ -105,6 +105,7 @@ int bucket_of(int64_t n)
 // only against 0.042 ms with the guess; 23 MB: 0.052 against 0.045 ms).
 constexpr int64_t kWsGuessMin = 14 << 20;
 std::atomic<int64_t> g_ws_guess_min{kWsGuessMin};
+std::atomic<int64_t> g_ws_small_max{kWsSmallMax};
 
 // Shape of `op` for an input of n bytes (n < 0: the last bucket).
 Shape shape_of(int op, int64_t n)
@@ -322,7 +323,8 @@ int64_t decode_enqueue(const uint8_t *src, int64_t n, uint8_t *dst, bool write, 
     if (flags & kFlagSkipWs) {
         e = launch_decode_ws(src, n, dst, write, make_dec_ws(alphabet, flags & kFlagNoPad), out_len,
                              first_bad, flags, workspace, shape_of(6, n), cus,
-                             g_ws_guess_min.load(std::memory_order_relaxed), stream);
+                             g_ws_guess_min.load(std::memory_order_relaxed),
+                             g_ws_small_max.load(std::memory_order_relaxed), stream);
         return e == hipSuccess ? 0 : hip_fail(e, "whitespace decode launch");
     }
     if (!sslot) {
@@ -441,6 +443,13 @@ int64_t b64_tune_bucket(int64_t n)
 {
     if (n < 0) return fail(B64_EARG, "negative length");
     return bucket_of(n);
+}
+
+int64_t b64_tune_ws_small_max(int64_t max_chars)
+{
+    if (max_chars > kWsSmallMax) return fail(B64_EARG, "max_chars above the one-workgroup limit (65,536)");
+    if (max_chars < 0) return g_ws_small_max.load(std::memory_order_relaxed);
+    return g_ws_small_max.exchange(max_chars, std::memory_order_relaxed);
 }
 
 int64_t b64_tune_ws_guess_min(int64_t min_chars)

@@ -104,9 +104,14 @@ hipError_t launch_decode_f32_bf16(const uint8_t *src, const int64_t *in_off, int
                                   uint32_t flags, Shape sh, int cus, hipStream_t stream);
 int64_t ws_tile_size(int64_t n);
 int64_t ws_workspace_bytes(int64_t n);
+// Texts of at most small_max (<= kWsSmallMax) characters take one launch of
+// one workgroup (k_ws_small); longer ones the counted path, after the guess
+// of regular lines from guess_min characters on.
+constexpr int64_t kWsSmallMax = 64 << 10;
 hipError_t launch_decode_ws(const uint8_t *src, int64_t n, uint8_t *dst, bool write, const DecMap &map,
                             int64_t *out_len, int64_t *first_bad, uint32_t flags, void *workspace,
-                            Shape sh, int cus, int64_t guess_min, hipStream_t stream);
+                            Shape sh, int cus, int64_t guess_min, int64_t small_max,
+                            hipStream_t stream);
 
 }  // namespace b64hip
 

@@ -261,8 +261,34 @@ __device__ __forceinline__ uint32_t codes4(uint32_t q, const uint8_t *map)
            ((uint32_t)map[(q >> 16) & 0xFF] << 16) | ((uint32_t)map[q >> 24] << 24);
 }
 
-// The 16 characters of thread `tid` in round `r` of a tile as packed codes;
-// characters at or past n read as whitespace.
+// Codes of the last r (1 .. 15) characters of an input, given the 16 bytes
+// that end the input (b), as the codes of a 16-character chunk that starts r
+// characters before the end: b is shifted down by 16 - r bytes, and the
+// positions from r on read as whitespace.
+__device__ __forceinline__ u32x4 ws_codes_window(u32x4 b, int r, const uint8_t *map)
+{
+    const int sh = 16 - r, q = sh >> 2;
+    const uint32_t k = (uint32_t)(sh & 3);
+    const uint32_t x0 = __builtin_amdgcn_alignbyte(b.y, b.x, k);
+    const uint32_t x1 = __builtin_amdgcn_alignbyte(b.z, b.y, k);
+    const uint32_t x2 = __builtin_amdgcn_alignbyte(b.w, b.z, k);
+    const uint32_t x3 = __builtin_amdgcn_alignbyte(0u, b.w, k);
+    const uint32_t t[4] = {q == 0 ? x0 : q == 1 ? x1 : q == 2 ? x2 : x3,
+                           q == 0 ? x1 : q == 1 ? x2 : q == 2 ? x3 : 0u,
+                           q == 0 ? x2 : q == 1 ? x3 : 0u, q == 0 ? x3 : 0u};
+    uint32_t w[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int keep = r - 4 * i;
+        const uint32_t msk = keep >= 4 ? 0xFFFFFFFFu : keep <= 0 ? 0u : (1u << (8 * keep)) - 1u;
+        w[i] = (codes4(t[i], map) & msk) | (0x40404040u & ~msk);
+    }
+    return u32x4{w[0], w[1], w[2], w[3]};
+}
+
+// The 16 characters at p as packed codes; characters at or past n read as
+// whitespace.  A partial chunk of an input of 16 bytes or more is one load of
+// the 16 bytes that end at n (byte loads would each wait for the one before).
 template <bool NT>
 __device__ __forceinline__ u32x4 ws_codes(const uint8_t *src, int64_t n, int64_t p,
                                           const uint8_t *map)
@@ -274,6 +300,8 @@ __device__ __forceinline__ u32x4 ws_codes(const uint8_t *src, int64_t n, int64_t
         c.y = codes4(q.y, map);
         c.z = codes4(q.z, map);
         c.w = codes4(q.w, map);
+    } else if (n >= 16) {
+        c = ws_codes_window(load16<NT>(src + n - 16), (int)(n - p), map);
     } else {
         uint32_t w[4] = {0, 0, 0, 0};
         for (int j = 0; j < 16; ++j) {
@@ -1462,6 +1490,215 @@ __global__ __launch_bounds__(kWsBlock) void k_ws_lines(const uint8_t *__restrict
         __hip_atomic_store(mode, kModeCounted, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// ------------------------------------------------ small texts, one workgroup --
+
+// k_ws_small: a text of at most kWsSmallMax characters decoded (or, !write,
+// validated) by one workgroup in one launch, where the counted path takes
+// five.  The text is read in rows of kSmallThreads lane chunks of 16
+// characters: thread t owns chunk t of every row (characters 16*(1024r + t)
+// onward), so every load of the workgroup is contiguous.  A thread counts
+// the significant characters of each of its chunks; a workgroup scan per row
+// gives each chunk the index of its first significant character, and the
+// thread writes the codes at their indices into an LDS array (chunks of
+// neighbouring lanes write neighbouring ranges).  The first invalid byte and
+// the first '=' (padded mode) are workgroup minima.  The '=' and
+// end-of-input rules then run on the array, as k_ws_finish runs them on the
+// prefix sums: the index E of the first '=', the value before it, and the
+// significant characters after it, whose offsets the threads that own them
+// report.  Then the quanta are decoded from the array, 3 bytes each (the last
+// one: the bytes its data values carry).  Nothing is shared between
+// workgroups, and every wait is a barrier of this one workgroup.
+constexpr int kSmallThreads = 1024;
+constexpr int kSmallPer = 4;                    // rows (16-character loads per thread) at most
+static_assert(kWsSmallMax == (int64_t)kSmallThreads * 16 * kSmallPer, "one workgroup's characters");
+
+__global__ __launch_bounds__(kSmallThreads) void k_ws_small(const uint8_t *__restrict__ src, int64_t n,
+                                                            uint8_t *__restrict__ dst, DecMap map,
+                                                            int64_t *__restrict__ out_len,
+                                                            int64_t *__restrict__ first_bad,
+                                                            uint32_t flags, int write)
+{
+    __shared__ uint32_t s_map[64];
+    __shared__ __align__(16) uint8_t vals[kWsSmallMax + 16];   // codes of the significant characters
+    __shared__ int s_wsum[kSmallPer][kSmallThreads / 64];
+    __shared__ uint32_t s_bad;                   // offset of the first invalid byte
+    __shared__ unsigned long long s_pad;         // first '=': offset << 32 | its index E
+    __shared__ uint32_t s_after[2];              // offsets of significant characters E+1, E+2
+    __shared__ int64_t s_len, s_err;
+    const int tid = threadIdx.x;
+    const bool nopad = (flags & kFlagNoPad) != 0;
+    const int K = (int)((n + 16 * kSmallThreads - 1) / (16 * kSmallThreads));   // rows, 0 .. kSmallPer
+    // the bulk loads first; the map is staged while they are in flight
+    u32x4 raw[kSmallPer];
+#pragma unroll
+    for (int j = 0; j < kSmallPer; ++j) {
+        const int p = 16 * (j * kSmallThreads + tid);
+        if (j < K && p + 16 <= n) raw[j] = load16<false>(src + p);
+        else if (j < K && p < n && n >= 16) raw[j] = load16<false>(src + n - 16);   // the last bytes
+    }
+    if (tid == 0) {
+        s_bad = 0xFFFFFFFFu;
+        s_pad = ~0ull;
+        s_after[0] = s_after[1] = 0xFFFFFFFFu;
+    }
+    stage_dec_map(s_map, map);
+    const uint8_t *m = (const uint8_t *)s_map;
+
+    const int lane = tid & 63, wv = tid >> 6;
+    u32x4 c[kSmallPer];
+    int cnt[kSmallPer], incl[kSmallPer];
+    uint32_t any = 0;
+#pragma unroll
+    for (int j = 0; j < kSmallPer; ++j) {
+        const int p = 16 * (j * kSmallThreads + tid);
+        if (j < K && p + 16 <= n) c[j] = codes16(raw[j], m);
+        else if (j < K && p < n && n >= 16) c[j] = ws_codes_window(raw[j], (int)(n - p), m);
+        else if (j < K && p < n) c[j] = ws_codes<false>(src, n, p, m);
+        else c[j] = u32x4{0x40404040u, 0x40404040u, 0x40404040u, 0x40404040u};
+        cnt[j] = sig_count(c[j]);
+        any |= c[j].x | c[j].y | c[j].z | c[j].w;
+        incl[j] = j < K ? wave_incl_scan(cnt[j]) : 0;
+        if (j < K && lane == 63) s_wsum[j][wv] = incl[j];
+    }
+    __syncthreads();
+    // index of the first significant character of each of this thread's
+    // chunks: the rows before, the waves before in the row, the lanes before
+    int excl[kSmallPer];
+    int total = 0;
+#pragma unroll
+    for (int j = 0; j < kSmallPer; ++j) {
+        int woff = 0, rsum = 0;
+        if (j < K)
+            for (int w = 0; w < kSmallThreads / 64; ++w) {
+                const int v = s_wsum[j][w];
+                woff += w < wv ? v : 0;
+                rsum += v;
+            }
+        excl[j] = total + woff + incl[j] - cnt[j];
+        total += rsum;
+    }
+    // The first invalid byte and the first '=' (with its index) of the
+    // threads that saw either, then every thread's significant codes at their
+    // indices.  Both loops are free of branches: a character's index is a
+    // running count, and a whitespace byte is written to a spare byte.
+    if (any & 0x80808080u) {
+        uint32_t pad_off = 0xFFFFFFFFu, pad_pos = 0, bad_off = 0xFFFFFFFFu;
+#pragma unroll
+        for (int j = 0; j < kSmallPer; ++j) {
+            if (j >= K) break;                   // uniform
+            const uint32_t w4[4] = {c[j].x, c[j].y, c[j].z, c[j].w};
+            int pos = excl[j];
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                const uint32_t code = (w4[i >> 2] >> (8 * (i & 3))) & 0xFFu;
+                const uint32_t off = (uint32_t)(16 * (j * kSmallThreads + tid) + i);
+                const bool first_pad = code == kPadCode && pad_off == 0xFFFFFFFFu;
+                pad_pos = first_pad ? (uint32_t)pos : pad_pos;
+                pad_off = first_pad ? off : pad_off;
+                const bool bad = (code & 0x80u) && code != kPadCode;
+                bad_off = bad && off < bad_off ? off : bad_off;
+                pos += is_sig(code) ? 1 : 0;
+            }
+        }
+        if (pad_off != 0xFFFFFFFFu) atomicMin(&s_pad, ((unsigned long long)pad_off << 32) | pad_pos);
+        if (bad_off != 0xFFFFFFFFu) atomicMin(&s_bad, bad_off);
+    }
+#pragma unroll
+    for (int j = 0; j < kSmallPer; ++j) {
+        if (j >= K) break;                       // uniform
+        const uint32_t w4[4] = {c[j].x, c[j].y, c[j].z, c[j].w};
+        int pos = excl[j];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const uint32_t code = (w4[i >> 2] >> (8 * (i & 3))) & 0xFFu;
+            const bool sg = is_sig(code);
+            vals[sg ? pos : kWsSmallMax + 8] = (uint8_t)code;
+            pos += sg ? 1 : 0;
+        }
+    }
+    __syncthreads();
+    const unsigned long long pad = s_pad;
+    const int E = pad == ~0ull ? -1 : (int)(pad & 0xFFFFFFFFu);
+    // offsets of significant characters E+1 and E+2, from the threads whose
+    // chunks hold them
+#pragma unroll
+    for (int j = 0; j < kSmallPer; ++j) {
+        if (j >= K) break;                       // uniform
+        if (E >= 0 && excl[j] < E + 3 && excl[j] + cnt[j] > E + 1) {
+            const uint32_t w4[4] = {c[j].x, c[j].y, c[j].z, c[j].w};
+            int pos = excl[j];
+            uint32_t o1 = 0xFFFFFFFFu, o2 = 0xFFFFFFFFu;
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                const uint32_t code = (w4[i >> 2] >> (8 * (i & 3))) & 0xFFu;
+                const uint32_t off = (uint32_t)(16 * (j * kSmallThreads + tid) + i);
+                const bool sg = is_sig(code);
+                o1 = sg && pos == E + 1 ? off : o1;
+                o2 = sg && pos == E + 2 ? off : o2;
+                pos += sg ? 1 : 0;
+            }
+            if (o1 != 0xFFFFFFFFu) s_after[0] = o1;
+            if (o2 != 0xFFFFFFFFu) s_after[1] = o2;
+        }
+    }
+    __syncthreads();
+    if (tid == 0) {
+        int64_t bad = s_bad == 0xFFFFFFFFu ? kNoError : (int64_t)s_bad;
+        const int64_t k = total;
+        const int r = (int)(k & 3);
+        int64_t len;
+        if (nopad) {
+            if (r == 1) bad = bad < n ? bad : n;
+            else if (r >= 2 && (vals[k - 1] & (r == 2 ? 15u : 3u))) bad = bad < n ? bad : n;
+            len = 3 * (k >> 2) + (r ? r - 1 : 0);
+        } else if (E < 0) {
+            if (r != 0) bad = bad < n ? bad : n;
+            len = 3 * (k >> 2);
+        } else {
+            const int64_t a = (int64_t)(pad >> 32);
+            const int pq = E & 3;
+            int64_t e = kNoError;
+            if (pq < 2) {
+                e = a;
+            } else {
+                const uint32_t prev = vals[E - 1];
+                if (prev & (pq == 2 ? 15u : 3u)) e = a;
+                else if (pq == 3) e = E + 1 < k ? (int64_t)s_after[0] : kNoError;
+                else if (E + 1 >= k) e = n;
+                else if (vals[E + 1] != kPadCode) e = (int64_t)s_after[0];
+                else e = E + 2 < k ? (int64_t)s_after[1] : kNoError;
+            }
+            bad = bad < e ? bad : e;
+            len = 3 * (k >> 2) - (k - E);
+        }
+        s_len = len;
+        s_err = bad;
+    }
+    __syncthreads();
+    const int64_t err = s_err, len = s_len;
+    if (err == kNoError && write) {
+        // quantum q: values 4q .. 4q+3 (those at D and past are zero), the
+        // bytes below len
+        const int D = nopad || E < 0 ? total : E;
+        const int nq = (D + 3) >> 2;
+        for (int q = tid; q < nq; q += kSmallThreads) {
+            uint32_t w = *(const uint32_t *)(vals + 4 * q);
+            const int have = D - 4 * q;
+            if (have < 4) w &= (1u << (8 * have)) - 1u;
+            const uint32_t b = ws_quantum(w);
+            const int64_t nb = len - 3 * (int64_t)q < 3 ? len - 3 * (int64_t)q : 3;
+            uint8_t *o = dst + 3 * (int64_t)q;
+            if (nb == 3) store3(o, b);
+            else
+                for (int i = 0; i < nb; ++i) o[i] = (uint8_t)(b >> (8 * i));
+        }
+    }
+    if (tid == 0) {
+        *out_len = err == kNoError ? len : -1;
+        *first_bad = err == kNoError ? -1 : err;
+    }
+}
+
 }  // namespace
 
 hipError_t launch_encode_wrap(const uint8_t *src, int64_t n, uint8_t *dst, const EncTab &tab,
@@ -1571,8 +1808,14 @@ void launch_ws_decode_shape(const uint8_t *src, int64_t n, uint8_t *dst, const D
 
 hipError_t launch_decode_ws(const uint8_t *src, int64_t n, uint8_t *dst, bool write, const DecMap &map,
                             int64_t *out_len, int64_t *first_bad, uint32_t flags, void *workspace,
-                            Shape sh, int cus, int64_t guess_min, hipStream_t stream)
+                            Shape sh, int cus, int64_t guess_min, int64_t small_max,
+                            hipStream_t stream)
 {
+    if (n <= small_max && n <= kWsSmallMax) {
+        (void)launch_args(&k_ws_small, dim3(1), dim3(kSmallThreads), stream, src, n, dst, map, out_len,
+                          first_bad, flags, write ? 1 : 0);
+        return hipGetLastError();
+    }
     const int64_t TS = ws_tile_size(n);
     const int64_t ntiles = n > 0 ? (n + TS - 1) / TS : 0;
     int64_t *prefix = (int64_t *)workspace;      // ntiles + 1 words

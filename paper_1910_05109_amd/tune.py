@@ -33,8 +33,8 @@ import statistics
 import numpy as np
 
 from . import (BUCKETS, OPS, SKIP_WS, STD, decode_async, decode_batch, decode_f32_bf16, encode,
-               encode_batch, tune_get, tune_set, tune_ws_guess_min, validate_async,
-               workspace_size)
+               encode_batch, tune_get, tune_set, tune_ws_guess_min, tune_ws_small_max,
+               validate_async, workspace_size)
 
 UNROLLS = (1, 2, 4, 8)
 BLOCKS_PER_CU = (1, 2, 4, 8, 16, 32, 64)
@@ -190,6 +190,24 @@ def tune_op(op: str, bucket: int, nbytes: int | None = None, reps: int = 10, unr
     fn = _workload(torch, op, nbytes)
     old = tune_get(op, bucket)
     results = []
+    # the whitespace-skipping decode's shape is the multi-launch path's: small
+    # texts would otherwise take the one-workgroup path, which has no shape
+    small_old = tune_ws_small_max(0) if op == "decode_ws" else None
+    try:
+        _sweep(torch, op, bucket, fn, reps, unrolls, bpcs, nts, nbytes, results, verbose)
+    finally:
+        if small_old is not None:
+            tune_ws_small_max(small_old)
+    results.sort()
+    ms, u, b, nt = results[0]
+    tune_set(op, u, b, nt, bucket=bucket)
+    del fn
+    torch.cuda.empty_cache()
+    return {"unroll": u, "blocks_per_cu": b, "nontemporal": nt, "ms": ms, "bytes": nbytes,
+            "previous": list(old), "grid": [[r[1], r[2], r[3], r[0]] for r in results]}
+
+
+def _sweep(torch, op, bucket, fn, reps, unrolls, bpcs, nts, nbytes, results, verbose):
     for nt in nts:
         for u in unrolls:
             for b in bpcs:
@@ -200,13 +218,6 @@ def tune_op(op: str, bucket: int, nbytes: int | None = None, reps: int = 10, unr
                 if verbose:
                     print(f"[tune] {op:15s} bucket={bucket} unroll={u} blocks/cu={b:2d} nt={nt}: "
                           f"{ms * 1e3:9.2f} us", flush=True)
-    results.sort()
-    ms, u, b, nt = results[0]
-    tune_set(op, u, b, nt, bucket=bucket)
-    del fn
-    torch.cuda.empty_cache()
-    return {"unroll": u, "blocks_per_cu": b, "nontemporal": nt, "ms": ms, "bytes": nbytes,
-            "previous": list(old), "grid": [[r[1], r[2], r[3], r[0]] for r in results]}
 
 
 # MIME text sizes at which the whitespace-skipping decode's two paths are

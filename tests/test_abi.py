@@ -43,7 +43,8 @@ def test_header_declares_the_boundary():
         "b64_pipeline_decode", "b64_pipeline_last_error",
         "b64_server_create", "b64_server_destroy", "b64_server_last_error", "b64_server_run",
         "b64_tune_set_bucket", "b64_tune_set", "b64_tune_get_bucket", "b64_tune_get",
-        "b64_tune_bucket", "b64_tune_ws_guess_min", "b64_yardstick", "b64_last_error"}
+        "b64_tune_bucket", "b64_tune_ws_guess_min", "b64_tune_ws_small_max", "b64_yardstick",
+        "b64_last_error"}
     assert set(data) == {"b64_alphabet_std", "b64_alphabet_url"}
 
 
@@ -282,3 +283,16 @@ def test_fast_binding_reaches_the_same_library(lib):
     import paper_1910_05109_amd as b64
     for alpha in (b64.STD, b64.URL, bytes(bytearray(b64.URL)[::-1])):
         assert ctypes.string_at(b64._alpha_addr(alpha), 64) == alpha
+
+
+def test_ws_small_max_knob(lib):
+    """The one-workgroup limit of the whitespace-skipping decode: read,
+    set, restored; above 65,536 rejected (no device needed)."""
+    EARG = -(2 ** 63)
+    old = lib.b64_tune_ws_small_max(-1)
+    assert old == 65536
+    assert lib.b64_tune_ws_small_max(65537) == EARG
+    assert lib.b64_tune_ws_small_max(1000) == old
+    assert lib.b64_tune_ws_small_max(-1) == 1000
+    assert lib.b64_tune_ws_small_max(old) == 1000
+    assert lib.b64_tune_ws_small_max(-1) == old

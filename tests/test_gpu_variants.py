@@ -561,3 +561,119 @@ def test_skip_ws_round_trip_many_tiles(b64, oracle):
     assert torch.equal(out[:n], x)
     del x, text, out
     torch.cuda.empty_cache()
+
+
+# ------------------------------------------ one-workgroup path for small texts --
+
+class _WsSmall:
+    """Sets the one-workgroup limit of the whitespace-skipping decode for a
+    block of code (0: small texts take the multi-launch paths)."""
+
+    def __init__(self, b64, max_chars):
+        self.b64, self.max_chars = b64, max_chars
+
+    def __enter__(self):
+        self.old = self.b64.tune_ws_small_max(self.max_chars)
+
+    def __exit__(self, *exc):
+        self.b64.tune_ws_small_max(self.old)
+
+
+def _ws_rows_on_gpu(b64, rows, flags):
+    """decode_async and validate_async of every row of `rows` (one launch
+    sequence per row, all enqueued, one synchronisation); returns the decode
+    statuses [nrows, 2], the validate statuses and the outputs."""
+    import torch
+    nrows, L = rows.shape
+    dev = torch.from_numpy(np.ascontiguousarray(rows).reshape(-1)).cuda() if rows.size else None
+    cap = max(b64.decoded_max_len(L, flags), 1)
+    out = torch.zeros((nrows, cap), dtype=torch.uint8, device="cuda")
+    st = torch.full((nrows, 2), 7, dtype=torch.int64, device="cuda")
+    vst = torch.full((nrows, 2), 7, dtype=torch.int64, device="cuda")
+    empty = torch.empty(0, dtype=torch.uint8, device="cuda")
+    for i in range(nrows):
+        s = dev[i * L:(i + 1) * L] if L else empty
+        b64.decode_async(s, STD, out=out[i], status=st[i], flags=flags)
+        b64.validate_async(s, STD, status=vst[i], flags=flags)
+    torch.cuda.synchronize()
+    return to_host(st), to_host(vst), to_host(out)
+
+
+def _check_rows(oracle, rows, flags, st, vst, out, label):
+    want = oracle.decode_mode_rows(rows, STD, flags)
+    for i in range(rows.shape[0]):
+        w = int(want[i])
+        exp = [w, -1] if w >= 0 else [-1, ~w]
+        assert st[i].tolist() == exp, (label, bytes(rows[i]), st[i].tolist(), exp)
+        assert vst[i].tolist() == exp, (label, "validate", bytes(rows[i]), vst[i].tolist(), exp)
+        if w > 0:
+            ref, _ = oracle.decode_mode(rows[i], STD, flags)
+            assert first_mismatch(out[i][:w], ref) is None, (label, bytes(rows[i]))
+
+
+@pytest.mark.parametrize("small", [True, False], ids=["one_workgroup", "multi_launch"])
+@pytest.mark.parametrize("flags", [SKIP_WS, SKIP_WS | NOPAD], ids=["padded", "nopad"])
+def test_skip_ws_brute_force_short(b64, oracle, small, flags):
+    """Every string of up to 5 characters over A, B, Q, '=', space, LF and
+    '*' (outside the alphabet): status, validate status and decoded bytes
+    against the oracle, through the one-workgroup path and through the
+    multi-launch paths.  A (value 0), Q (16) and B (1) make the canonical
+    rules before '=' hold or fail."""
+    import itertools
+    sym = np.frombuffer(b"ABQ= \n*", dtype=np.uint8)
+    with _WsSmall(b64, 65536 if small else 0):
+        for L in range(0, 6):
+            rows = (np.array(list(itertools.product(sym, repeat=L)), dtype=np.uint8) if L
+                    else np.zeros((1, 0), dtype=np.uint8))
+            say("brute force", "small" if small else "multi", flags, "L =", L, "rows", rows.shape[0])
+            st, vst, out = _ws_rows_on_gpu(b64, rows, flags)
+            _check_rows(oracle, rows, flags, st, vst, out, f"L={L}")
+
+
+@pytest.mark.parametrize("small", [True, False], ids=["one_workgroup", "multi_launch"])
+def test_skip_ws_random_short_strings(b64, oracle, small):
+    """Random strings of 6 .. 80 characters over the same symbols, weighted
+    towards valid text, and valid encodings with whitespace sprinkled in."""
+    g = workloads.rng(workloads.SEED_BASE + 190)
+    sym = np.frombuffer(b"ABQgw09+/= \n\r\t*", dtype=np.uint8)
+    weights = np.array([8, 2, 4, 4, 4, 4, 4, 2, 2, 2, 3, 2, 1, 1, 1], dtype=np.float64)
+    weights /= weights.sum()
+    with _WsSmall(b64, 65536 if small else 0):
+        for flags in (SKIP_WS, SKIP_WS | NOPAD):
+            for L in (6, 7, 9, 13, 16, 17, 31, 64, 80):
+                rows = g.choice(sym, size=(300, L), p=weights).astype(np.uint8)
+                say("random", "small" if small else "multi", flags, "L =", L)
+                st, vst, out = _ws_rows_on_gpu(b64, rows, flags)
+                _check_rows(oracle, rows, flags, st, vst, out, f"random L={L}")
+
+
+def test_skip_ws_one_workgroup_limits(b64, oracle):
+    """Texts around the one-workgroup path's limit (65,536 characters) and
+    its per-thread load counts (16,384, 32,768, 49,152), valid and with an
+    invalid byte, a misplaced '=' or a cut at the end: the same results as
+    the multi-launch paths and the oracle."""
+    x = workloads.random_bytes(workloads.SEED_BASE + 191, 60000)
+    g = workloads.rng(workloads.SEED_BASE + 192)
+    for target in (16383, 16384, 16385, 32768, 49151, 49153, 65535, 65536, 65537):
+        # MIME text of about `target` characters, padded out with spaces
+        text = _mime(oracle, x[: target * 57 // 78])[:target]
+        text = np.concatenate([text, np.full(max(target - text.size, 0), ord(" "), np.uint8)])
+        cases = [("valid", text)]
+        t = text.copy()
+        t[int(g.integers(0, t.size))] = ord("*")
+        cases.append(("invalid", t))
+        t = text.copy()
+        t[int(g.integers(0, t.size))] = ord("=")
+        cases.append(("misplaced =", t))
+        cases.append(("cut", text[:-3]))
+        for label, tx in cases:
+            for flags in (SKIP_WS, SKIP_WS | NOPAD):
+                ref = oracle.decode_mode_raw(tx, STD, flags)
+                for small in (True, False):
+                    with _WsSmall(b64, 65536 if small else 0):
+                        got = _dec(b64, oracle, tx, STD, flags, f"{target} {label} small={small}",
+                                   check_validate=True)
+                    assert got == ref
+    with pytest.raises(Exception):
+        b64.tune_ws_small_max(65537)
+    assert b64.tune_ws_small_max(-1) == 65536
