@@ -297,11 +297,13 @@ def run_single(args, torch, b64):
         rows = []
         with serve.Server(budget_bytes=32 << 30, nstreams=args.serve_streams,
                           depth=args.serve_depth) as srv:
-            # untimed warm-up traffic: in a server's first seconds the HIP
-            # runtime's DMA copies now and then block the scheduler thread
-            # for 5-8 ms (seen inside hipMemcpyAsync), which would decide the
-            # p99 of a 67 ms window by itself
-            serve_rate(srv, torch, b64, kinds, payload, off, sizes, spoil, 1e4, count)
+            # untimed warm-up traffic at both rates: in a server's first runs
+            # the HIP runtime's DMA copies now and then block the scheduler
+            # thread for 5-8 ms (seen inside hipMemcpyAsync, most often in the
+            # first run and the first run at a high rate), which would decide
+            # the p99 of a 67 ms window by itself
+            for rate in (1e4, 3e5):
+                serve_rate(srv, torch, b64, kinds, payload, off, sizes, spoil, rate, count)
             for rate in (1e4, 3e5):
                 r = serve_rate(srv, torch, b64, kinds, payload, off, sizes, spoil, rate, count)
                 rows.append({k: (round(v, 2) if isinstance(v, float) else v)
