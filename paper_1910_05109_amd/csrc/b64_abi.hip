@@ -252,7 +252,7 @@ hipError_t ws_cache(int64_t bytes, void **out)
 // a graph get a slot per capture and capturing stream: the nodes captured from
 // one stream run in order within a replay, and launches of one graph run one
 // after another, so they never overlap either.  Slots are never given back (a
-// slot is 2,176 bytes of device memory); once all kStatusSlots of a device are
+// slot is 4,224 bytes of device memory); once all kStatusSlots of a device are
 // taken, further streams and captures use the three-launch form.
 struct SlotTable {
     std::mutex mu;

@@ -517,7 +517,7 @@ __device__ __forceinline__ void consume(int64_t v) { asm volatile("" ::"v"(v)); 
 // device scope touch the slot, so no cache writeback is needed.  A grid of one
 // workgroup skips the count.  Calls that may run at the same time must use
 // different slots.
-constexpr int kSinkGroups = 16;
+constexpr int kSinkGroups = 32;
 constexpr int kSlotWords = 16 * (kSinkGroups + 1);   // line 0: key, total; then one line per group
 struct DecSink {
     int64_t *out_len, *first_bad, *slot;

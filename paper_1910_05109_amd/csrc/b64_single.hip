@@ -4,7 +4,7 @@
 namespace b64hip {
 
 // Status slots of the single-launch decode and validation (the slot form of
-// DecSink): kStatusSlots x kSlotWords int64 (2.1 MiB) per device, zero when
+// DecSink): kStatusSlots x kSlotWords int64 (4.1 MiB) per device, zero when
 // the code object is loaded and put back to zero by every call that uses one.
 // Kernels reach them through the address passed in DecSink only.
 __device__ __align__(256) int64_t g_status_slots[kStatusSlots * kSlotWords];
