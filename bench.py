@@ -630,7 +630,7 @@ def run_host(args, torch, b64):
     text = np.empty(N, dtype=np.uint8)
     dec = np.empty(n + 3, dtype=np.uint8)
     res = {"workload": "1 GiB in host memory, pipelined through the GPU", "n_bytes": n, "n_chars": N}
-    with HostPipeline(chunk_bytes=args.chunk_mib << 20, depth=3, host_threads=8) as p:
+    with HostPipeline(chunk_bytes=args.chunk_mib << 20, depth=args.host_depth, host_threads=8) as p:
         p.encode(x[: 64 << 20], out=text)            # warm-up
         te = []
         td = []
@@ -642,6 +642,24 @@ def run_host(args, torch, b64):
             out, bad = p.decode(text, out=dec)
             td.append(time.perf_counter() - t0)
             assert bad is None and out.size == n
+        # the same calls with source and destination in pinned host memory:
+        # the pipeline then copies straight between them and the device
+        px = torch.empty(n, dtype=torch.uint8, pin_memory=True).numpy()
+        ptext = torch.empty(N, dtype=torch.uint8, pin_memory=True).numpy()
+        pdec = torch.empty(n + 3, dtype=torch.uint8, pin_memory=True).numpy()
+        px[:] = x
+        tpe = []
+        tpd = []
+        for _ in range(3):
+            t0 = time.perf_counter()
+            p.encode(px, out=ptext)
+            tpe.append(time.perf_counter() - t0)
+            t0 = time.perf_counter()
+            out, bad = p.decode(ptext, out=pdec)
+            tpd.append(time.perf_counter() - t0)
+            assert bad is None and out.size == n
+        assert np.array_equal(ptext, text) and np.array_equal(pdec[:n], x)
+        del px, ptext, pdec, out
     # reference: the same bytes over PCIe with pinned torch copies (no codec)
     h_in = torch.empty(n, dtype=torch.uint8).pin_memory()
     h_out = torch.empty(N, dtype=torch.uint8).pin_memory()
@@ -655,10 +673,27 @@ def run_host(args, torch, b64):
     h_out.copy_(d_out, non_blocking=True)
     torch.cuda.synchronize()
     t_d2h = time.perf_counter() - t0
+    # both at once on two streams: the floor for a 1 GiB encode host -> host
+    # (a decode moves the same bytes the other way)
+    s_in, s_out = torch.cuda.Stream(), torch.cuda.Stream()
+    t_both = []
+    for _ in range(3):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        with torch.cuda.stream(s_in):
+            d_in.copy_(h_in, non_blocking=True)
+        with torch.cuda.stream(s_out):
+            h_out.copy_(d_out, non_blocking=True)
+        torch.cuda.synchronize()
+        t_both.append(time.perf_counter() - t0)
     res.update({"encode_s": min(te), "encode_gbps_b64": N / min(te) / 1e9,
                 "decode_s": min(td), "decode_gbps_b64": N / min(td) / 1e9,
+                "pinned_encode_s": min(tpe), "pinned_encode_gbps_b64": N / min(tpe) / 1e9,
+                "pinned_decode_s": min(tpd), "pinned_decode_gbps_b64": N / min(tpd) / 1e9,
                 "pcie_h2d_gbps": n / t_h2d / 1e9, "pcie_d2h_gbps": N / t_d2h / 1e9,
-                "chunk_mib": args.chunk_mib})
+                "pcie_both_s": min(t_both), "pcie_both_gbps_b64": N / min(t_both) / 1e9,
+                "pinned_encode_frac_of_both": min(t_both) / min(tpe),
+                "chunk_mib": args.chunk_mib, "depth": args.host_depth})
     print(json.dumps(res), flush=True)
 
 
@@ -777,6 +812,7 @@ def main():
                     choices=["single", "ceiling", "small", "sweep", "batch", "serve", "validate",
                              "host", "variants", "fused"])
     ap.add_argument("--chunk-mib", type=int, default=64)
+    ap.add_argument("--host-depth", type=int, default=3, help="host pipeline: chunks in flight")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-extras", action="store_true",
                     help="default line without its batch and serve objects")

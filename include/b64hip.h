@@ -237,25 +237,32 @@ int64_t b64_decode_f32_bf16(const uint8_t *src, const int64_t *in_off, int64_t n
 /* Host-memory pipeline (an opaque handle).  Encodes or decodes data that
  * lives in ordinary host memory by cutting it into chunks that stream through
  * pinned staging, host-to-device copies, the kernels and device-to-host
- * copies on `depth` streams at once.  The handle owns, until
- * b64_pipeline_destroy, depth x 2 pinned host buffers and depth x 2 device
- * buffers of 4/3 x chunk_bytes each (chunk_bytes is rounded up to a multiple
- * of 1536), and is bound to the HIP device current at creation.  One handle
- * serves one calling thread at a time.  (Section "Experiments": large inputs
- * are best processed in parts.)
- * b64_pipeline_create: chunk_bytes >= 48, 1 <= depth <= 16,
+ * copies, with up to `depth` chunks in flight (one stream per stage).  The
+ * handle owns, until b64_pipeline_destroy, slots x 2 pinned host buffers and
+ * slots x 2 device buffers of 4/3 x chunk_bytes each (chunk_bytes is rounded
+ * up to a multiple of 1536; slots = min(depth, 3)), and is bound to the HIP
+ * device current at creation.  One handle serves one calling thread at a
+ * time.  (Section "Experiments": large inputs are best processed in parts.)
+ * b64_pipeline_create: chunk_bytes >= 48, 1 <= depth <= 16 (values above 3
+ * act as 3: on MI355X, copies queued further ahead run slower),
  * 1 <= host_threads <= 64 (threads for the host-side copies); returns NULL on
  * error (message: b64_pipeline_last_error()). */
 typedef struct b64_pipeline b64_pipeline;
 b64_pipeline *b64_pipeline_create(int64_t chunk_bytes, int depth, int host_threads);
 void b64_pipeline_destroy(b64_pipeline *p);
 /* Blocking.  src / dst are HOST pointers (any memory).  Returns
- * 4*ceil(n/3), or B64_EARG / B64_EHIP.  dst holds b64_encoded_len(n) bytes. */
+ * 4*ceil(n/3), or B64_EARG / B64_EHIP.  dst holds b64_encoded_len(n) bytes.
+ * A src or dst in pinned host memory (hipHostMalloc, or registered) is copied
+ * to or from the device directly, with no staging copy on that side; this
+ * applies to decode as well.                                                */
 int64_t b64_pipeline_encode(b64_pipeline *p, const uint8_t *src, int64_t n, uint8_t *dst,
                             const char *alphabet);
 /* Blocking.  src / dst are HOST pointers; dst holds b64_decoded_max_len(n)
  * bytes.  Returns the decoded length, ~off (the first invalid offset of the
- * whole input, as b64_decode defines it), or B64_EARG / B64_EHIP. */
+ * whole input, as b64_decode defines it), or B64_EARG / B64_EHIP.  With a
+ * pinned dst, dst may also receive bytes past the decoded length (up to
+ * b64_decoded_max_len(n)), and, for an invalid input, bytes of chunks after
+ * the first invalid one. */
 int64_t b64_pipeline_decode(b64_pipeline *p, const uint8_t *src, int64_t n, uint8_t *dst,
                             const char *alphabet);
 const char *b64_pipeline_last_error(void);

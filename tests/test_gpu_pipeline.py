@@ -1,7 +1,8 @@
 """GPU parity of the host-memory pipeline (b64_pipeline_*) against the oracle:
 results must equal the single-call results bit for bit, whatever the chunking,
 including the first invalid offset when the fault lies in a middle chunk or
-when a middle chunk ends in padding."""
+when a middle chunk ends in padding, and whether the host buffers are pageable
+or pinned (pinned ones are copied to and from the device directly)."""
 import numpy as np
 import pytest
 
@@ -74,3 +75,40 @@ def test_large_default_chunks(oracle):
         ref[150_000_000] = ord("?")
         dec, bad = p.decode(ref)
         assert bad == 150_000_000
+
+
+def _pinned(torch, n):
+    return torch.empty(max(n, 1), dtype=torch.uint8, pin_memory=True).numpy()[:n]
+
+
+def test_pinned_buffers(pipe, oracle):
+    """Source and destination in pinned host memory, alone and together: the
+    same bytes and the same first invalid offset as the oracle."""
+    import torch
+    x = workloads.random_bytes(workloads.SEED_BASE + 163, 100_000)
+    text = oracle.encode(x)
+    for n in (1, 6144, 6145, 100_000):
+        N = 4 * ((n + 2) // 3)
+        ref = oracle.encode(x[:n])
+        for pin_src, pin_dst in ((True, False), (False, True), (True, True)):
+            say("pipeline pinned encode", n, pin_src, pin_dst)
+            src = _pinned(torch, n) if pin_src else x[:n].copy()
+            src[:] = x[:n]
+            dst = _pinned(torch, N) if pin_dst else None
+            got = pipe.encode(src, out=dst)
+            assert np.array_equal(got, ref), (n, pin_src, pin_dst)
+            say("pipeline pinned decode", n, pin_src, pin_dst)
+            s = _pinned(torch, N) if pin_src else ref.copy()
+            s[:] = ref
+            d = _pinned(torch, N // 4 * 3) if pin_dst else None
+            dec, bad = pipe.decode(s, out=d)
+            assert bad is None and np.array_equal(dec, x[:n]), (n, pin_src, pin_dst)
+    for pos in (3, 6144, 70_000, 133_330):
+        bad_text = text.copy()
+        bad_text[pos] = ord("*")
+        ref_dec, ref_bad = oracle.decode(bad_text)
+        s = _pinned(torch, bad_text.size)
+        s[:] = bad_text
+        say("pipeline pinned fault", pos)
+        dec, bad = pipe.decode(s, out=_pinned(torch, bad_text.size // 4 * 3))
+        assert bad == ref_bad == pos
