@@ -14,7 +14,8 @@
 // characters decodes to 12 bytes, exactly three floats, so lane chunk k of a
 // row yields floats 3k..3k+2: dec_chunk, then the rounding below; the even
 // lane of each pair takes its neighbour's three values and stores the pair's
-// 12 bytes with one store.  Validation is the decoder's own (the OR of map values
+// 12 bytes with one store.  A lane keeps two passes of U chunks in flight
+// (the next pass loaded before this one is decoded).  Validation is the decoder's own (the OR of map values
 // tested once per row with a wave ballot, a rescan for the first invalid
 // offset); the row's last quanta are decoded on registers by lanes 0..3.
 #include "b64_launch.h"
@@ -97,13 +98,16 @@ __global__ __launch_bounds__(kThreads) void k_decode_f32_bf16(
             }
         }
         uint32_t err = 0;
-        for (int64_t k0 = lane; k0 < nch; k0 += 64 * U) {
-            u32x4 in[U];
+        // U lane chunks per pass (chunks k0 + 64j), two passes in flight: the
+        // loads of the next pass are issued before this one is decoded
+        auto load = [&](u32x4 (&in)[U], int64_t k0) {
 #pragma unroll
             for (int j = 0; j < U; ++j) {
                 const int64_t k = k0 + 64 * j;
                 in[j] = load16<NT>(row + 16 * (k < nch ? k : nch - 1));
             }
+        };
+        auto work = [&](const u32x4 (&in)[U], int64_t k0) {
 #pragma unroll
             for (int j = 0; j < U; ++j) {
                 const int64_t k = k0 + 64 * j;
@@ -130,6 +134,21 @@ __global__ __launch_bounds__(kThreads) void k_decode_f32_bf16(
                         o[2] = (uint16_t)h2;
                     }
                 }
+            }
+        };
+        {
+            u32x4 A[U], B[U];
+            int64_t k0 = lane;
+            if (k0 < nch) load(A, k0);
+            while (k0 < nch) {
+                const int64_t k1 = k0 + 64 * U;
+                if (k1 < nch) load(B, k1);
+                work(A, k0);
+                if (k1 >= nch) break;
+                const int64_t k2 = k1 + 64 * U;
+                if (k2 < nch) load(A, k2);
+                work(B, k1);
+                k0 = k2;
             }
         }
         int64_t bad = kNoError;
