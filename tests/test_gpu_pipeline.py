@@ -14,11 +14,15 @@ pytestmark = pytest.mark.gpu
 STD = b"ABCDEFGHIJKLMNOPQRSTUVWXYZabcdefghijklmnopqrstuvwxyz0123456789+/"
 
 
-@pytest.fixture(scope="module")
-def pipe():
+def _need_gpu():
     import torch
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
+
+
+@pytest.fixture(scope="module")
+def pipe():
+    _need_gpu()
     from paper_1910_05109_amd.pipeline import HostPipeline
     p = HostPipeline(chunk_bytes=6144, depth=3, host_threads=2)   # 6144-byte chunks
     yield p
@@ -63,6 +67,7 @@ def test_faults_at_chunk_boundaries(pipe, oracle):
 
 
 def test_large_default_chunks(oracle):
+    _need_gpu()
     from paper_1910_05109_amd.pipeline import HostPipeline
     x = workloads.random_bytes(workloads.SEED_BASE + 162, (200 << 20) + 1)
     with HostPipeline() as p:
@@ -112,3 +117,17 @@ def test_pinned_buffers(pipe, oracle):
         say("pipeline pinned fault", pos)
         dec, bad = pipe.decode(s, out=_pinned(torch, bad_text.size // 4 * 3))
         assert bad == ref_bad == pos
+
+
+def test_depth_above_three(oracle):
+    """Depths above 3 run with 3 chunks in flight; results are unchanged."""
+    _need_gpu()
+    from paper_1910_05109_amd.pipeline import HostPipeline
+    x = workloads.random_bytes(workloads.SEED_BASE + 164, 90_001)
+    ref = oracle.encode(x)
+    for depth in (4, 16):
+        with HostPipeline(chunk_bytes=6144, depth=depth, host_threads=2) as p:
+            say("pipeline depth", depth)
+            assert np.array_equal(p.encode(x), ref), depth
+            dec, bad = p.decode(ref)
+            assert bad is None and np.array_equal(dec, x), depth
