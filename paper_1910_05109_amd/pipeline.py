@@ -1,7 +1,10 @@
 """Host-memory encode / decode through the library's chunked pipeline
 (b64_pipeline_* in the C ABI): chunks of the host input stream through pinned
-staging, host-to-device copies, the HIP kernels and device-to-host copies on
-several streams at once.  The Python side only passes numpy buffers."""
+staging, host-to-device copies, the HIP kernels and device-to-host copies,
+one stream per stage, up to three chunks in flight.  Arrays in pinned host
+memory (torch's pin_memory tensors, viewed with .numpy()) are copied to and
+from the device directly, without the staging copies.  The Python side only
+passes numpy buffers."""
 from __future__ import annotations
 
 import ctypes
