@@ -294,24 +294,34 @@ def run_single(args, torch, b64):
         from paper_1910_05109_amd import serve
         count = 20_000
         kinds, payload, off, sizes, spoil = serve_requests(torch, b64, count)
-        rows = []
-        with serve.Server(budget_bytes=32 << 30, nstreams=args.serve_streams,
-                          depth=args.serve_depth) as srv:
-            # untimed warm-up traffic at both rates: in a server's first runs
-            # the HIP runtime's DMA copies now and then block the scheduler
-            # thread for 5-8 ms (seen inside hipMemcpyAsync, most often in the
-            # first run and the first run at a high rate), which would decide
-            # the p99 of a 67 ms window by itself
-            for rate in (1e4, 3e5):
-                serve_rate(srv, torch, b64, kinds, payload, off, sizes, spoil, rate, count)
-            for rate in (1e4, 3e5):
-                r = serve_rate(srv, torch, b64, kinds, payload, off, sizes, spoil, rate, count)
-                rows.append({k: (round(v, 2) if isinstance(v, float) else v)
-                             for k, v in r.items() if k in ("rate", "requests", "p50_us", "p99_us",
-                                                             "gbps_b64", "mean_batch",
-                                                             "max_concurrent")})
+        keys = ("rate", "requests", "p50_us", "p99_us", "gbps_b64", "mean_batch", "max_concurrent",
+                "zero_copy_launches")
+
+        def serve_rows(zero_copy_max):
+            rows = []
+            with serve.Server(budget_bytes=32 << 30, nstreams=args.serve_streams,
+                              depth=args.serve_depth, zero_copy_max=zero_copy_max) as srv:
+                # untimed warm-up traffic at both rates: in a server's first
+                # runs the HIP runtime's DMA copies now and then block the
+                # scheduler thread for 5-8 ms (seen inside hipMemcpyAsync, most
+                # often in the first run and the first run at a high rate),
+                # which would decide the p99 of a 67 ms window by itself
+                for rate in (1e4, 3e5):
+                    serve_rate(srv, torch, b64, kinds, payload, off, sizes, spoil, rate, count)
+                for rate in (1e4, 3e5):
+                    r = serve_rate(srv, torch, b64, kinds, payload, off, sizes, spoil, rate, count)
+                    rows.append({k: (round(v, 2) if isinstance(v, float) else v)
+                                 for k, v in r.items() if k in keys})
+            return rows
+
         rec["serve"] = {"workload": "Poisson arrivals, log-normal sizes (median 8 KiB, sigma 1.5), "
-                                    "payloads from pinned host memory", "rows": rows}
+                                    "payloads from pinned host memory, staged in device memory "
+                                    "under the HBM budget", "rows": serve_rows(args.serve_zero_copy_max)}
+        if args.serve_zero_copy_max is None:
+            # the same requests with every launch zero-copy: the kernels work on
+            # the pinned host pools over PCIe, nothing staged in device memory
+            rec["serve_zero_copy"] = {"workload": "the same, every launch zero-copy (no DMA, no arena)",
+                                      "rows": serve_rows(64 << 20)}
     print(json.dumps(rec), flush=True)
 
 
@@ -587,14 +597,15 @@ def run_serve(args, torch, b64):
     kinds, payload, off, sizes, spoil = serve_requests(torch, b64, count_max)
     out = []
     with serve.Server(budget_bytes=32 << 30, nstreams=args.serve_streams,
-                      depth=args.serve_depth) as srv:
+                      depth=args.serve_depth, zero_copy_max=args.serve_zero_copy_max) as srv:
         for rate in args.rates:
             count = int(min(count_max, max(2000, rate * args.seconds)))
             summ = serve_rate(srv, torch, b64, kinds, payload, off, sizes, spoil, rate, count)
             log("serve", json.dumps(summ))
             out.append(summ)
     print(json.dumps({"workload": "serving", "sigma": workloads.SERVE_SIGMA,
-                      "streams": args.serve_streams, "depth": args.serve_depth, "rows": out}),
+                      "streams": args.serve_streams, "depth": args.serve_depth,
+                      "zero_copy_max": args.serve_zero_copy_max, "rows": out}),
           flush=True)
 
 
@@ -829,6 +840,8 @@ def main():
     ap.add_argument("--seconds", type=float, default=10.0)
     ap.add_argument("--serve-streams", type=int, default=2)
     ap.add_argument("--serve-depth", type=int, default=2, help="launches in flight at most")
+    ap.add_argument("--serve-zero-copy-max", type=int, default=None,
+                    help="payload bytes of a launch at most for zero-copy (0: off; default: the library's)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only; run it with --gpus 1", file=sys.stderr)

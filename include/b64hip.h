@@ -278,12 +278,20 @@ const char *b64_pipeline_last_error(void);
  * and events for up to `depth` launches in flight (nstreams..64); a launch
  * coalesces up to `max_batch` queued requests of one kind and up to
  * `max_batch_bytes` payload bytes (a single larger request still goes
- * alone).  The server is bound to the device current at creation.  Returns
- * NULL on error (message: b64_server_last_error()). */
+ * alone).  Launches can skip the arena (b64_server_set_zero_copy_max).  The
+ * server is bound to the device current at creation.  Returns NULL on error
+ * (message: b64_server_last_error()). */
 typedef struct b64_server b64_server;
 b64_server *b64_server_create(int64_t budget_bytes, int nstreams, int depth, int64_t max_batch,
                               int64_t max_batch_bytes);
 void b64_server_destroy(b64_server *s);
+/* Launches whose payload is at most `bytes` run zero-copy: their kernel reads
+ * the payloads from, and writes the outputs to, the pinned host pools (mapped
+ * into the device's address space) over PCIe, with no DMA copy and no arena
+ * space; larger launches stage through the arena.  0 (the default) turns
+ * zero-copy off: buffers then stay in device memory under the HBM budget.  Returns the previous value (bytes = -1 only reads
+ * it), or B64_EARG. */
+int64_t b64_server_set_zero_copy_max(b64_server *s, int64_t bytes);
 const char *b64_server_last_error(void);
 #define B64_SERVE_ENCODE 0
 #define B64_SERVE_DECODE 1
@@ -297,6 +305,7 @@ const char *b64_server_last_error(void);
                                       last operation)                           */
 #define B64_STAT_OVERLAPPED 5      /* launches that ran at the same time as another */
 #define B64_STAT_ARENA 6           /* arena bytes                               */
+#define B64_STAT_ZERO_COPY 7       /* launches that ran zero-copy               */
 #define B64_STAT_COUNT 8
 /* Blocking.  Serves `nreq` requests on the calling thread and returns when
  * all are done.  Request i (kind[i] = B64_SERVE_ENCODE or B64_SERVE_DECODE)
@@ -305,7 +314,7 @@ const char *b64_server_last_error(void);
  * memory (in_off: nreq+1 non-decreasing entries).  Before serving, the
  * payloads are copied into pinned host pools (as a network stack would have
  * left them); each request's bytes go to the device only when its launch is
- * enqueued.  Results, in HOST memory: dst + out_off[i] receives the output
+ * enqueued (or are read there by the kernel, for a zero-copy launch).  Results, in HOST memory: dst + out_off[i] receives the output
  * (capacity b64_encoded_len / b64_decoded_max_len of the payload length),
  * out_len[i] the output length (-1 for an invalid decode), first_bad[i] -1
  * or the first invalid offset (decodes), done_ns[i] the time the request's

@@ -23,7 +23,7 @@ from .batch import decoded_capacity, encoded_lengths
 
 ENC, DEC = 0, 1
 STATS = ("launches", "wall_ns", "peak_arena_bytes", "max_inflight", "max_concurrent",
-         "overlapped_launches", "arena_bytes")
+         "overlapped_launches", "arena_bytes", "zero_copy_launches")
 STAT_COUNT = 8
 
 
@@ -68,7 +68,8 @@ class Result:
                 "max_concurrent": self.stats["max_concurrent"],
                 "overlapped_launches": self.stats["overlapped_launches"],
                 "peak_arena_bytes": self.stats["peak_arena_bytes"],
-                "arena_bytes": self.stats["arena_bytes"], **self.extra}
+                "arena_bytes": self.stats["arena_bytes"],
+                "zero_copy_launches": self.stats["zero_copy_launches"], **self.extra}
 
 
 class Server:
@@ -77,18 +78,26 @@ class Server:
     budget_bytes: the device arena for everything in flight (HBM budget);
     nstreams: HIP streams the launches go to in turn; depth: launches in
     flight at most; max_batch / max_batch_bytes: requests / payload bytes per
-    launch at most.  The defaults (two streams, one launch in flight on each)
-    gave the lowest p99 on MI355X: a device has four hardware queues, and
-    more streams than the queues left beside the default stream stall now and
-    then for milliseconds."""
+    launch at most; zero_copy_max: launches with at most this many payload
+    bytes run zero-copy (the kernel works on the pinned host pools, no DMA
+    and no arena space; 0 turns it off, None keeps the library's default).
+    The defaults (two streams, one launch in flight on each) gave the lowest
+    p99 on MI355X: a device has four hardware queues, and more streams than
+    the queues left beside the default stream stall now and then for
+    milliseconds."""
 
     def __init__(self, budget_bytes: int = 32 << 30, nstreams: int = 2, depth: int = 2,
-                 max_batch: int = 8192, max_batch_bytes: int = 64 << 20):
+                 max_batch: int = 8192, max_batch_bytes: int = 64 << 20,
+                 zero_copy_max: int | None = None):
         L = load()
         self._h = L.b64_server_create(int(budget_bytes), int(nstreams), int(depth), int(max_batch),
                                       int(max_batch_bytes))
         if not self._h:
             raise B64Error("b64_server_create: " + (L.b64_server_last_error() or b"").decode())
+        if zero_copy_max is not None:
+            if zero_copy_max < 0 or L.b64_server_set_zero_copy_max(self._h, int(zero_copy_max)) < 0:
+                self.close()
+                raise ValueError("zero_copy_max must be >= 0")
 
     def close(self):
         if self._h:

@@ -8,7 +8,9 @@ Requests follow the serving workload's law -- sizes log-normal with median
 8 KiB and sigma 1.5 clipped to [1 B, 16 MiB], 50/50 encode and decode, some
 decodes spoiled by one invalid byte -- and a second case adds requests of
 several MiB up to 16 MiB under a budget small enough that the arena wraps and
-admission waits.
+admission waits.  Each case runs with every launch staged through the arena
+by DMA (the default), with launches of up to 1 MiB zero-copy (the kernel
+works on the pinned host pools), and with every launch zero-copy.
 """
 import numpy as np
 import pytest
@@ -76,18 +78,26 @@ def _check_mix_alone_oracle(b64, oracle, res, kinds, parts, label):
                 assert res.first_bad[i] == ref_bad and res.out_len[i] == -1, (label, i)
 
 
-def test_mix_equals_alone_serving_law(b64, oracle):
+ZERO_COPY = pytest.mark.parametrize("zc", [None, 1 << 20, 64 << 20], ids=["dma", "mixed", "zero-copy"])
+
+
+@ZERO_COPY
+def test_mix_equals_alone_serving_law(b64, oracle, zc):
     """3,000 requests of the serving law at 200,000 per second: coalesced,
     with launches overlapping on the device."""
     from paper_1910_05109_amd import serve
     seed = workloads.SEED_BASE + 140
     sizes = workloads.serve_sizes(seed, 3000)
     kinds, arrival, payload, in_off, parts = _schedule(oracle, seed, sizes, 2e5, 0.02)
-    say("serve law", sizes.size, int(sizes.sum()))
-    with serve.Server(budget_bytes=32 << 30, nstreams=4, depth=8) as srv:
+    say("serve law", sizes.size, int(sizes.sum()), "zero-copy max", zc)
+    with serve.Server(budget_bytes=32 << 30, nstreams=4, depth=8, zero_copy_max=zc) as srv:
         res = srv.run(kinds, arrival, payload, in_off)
     summ = res.summary()
     say("serve summary", summ)
+    if zc is None:                                   # the default: every launch staged
+        assert summ["zero_copy_launches"] == 0
+    else:
+        assert summ["zero_copy_launches"] > 0
     assert np.isfinite(res.latency).all() and (res.latency > 0).all()
     assert summ["launches"] < sizes.size and summ["mean_batch"] > 1.0     # coalescing happened
     assert summ["max_concurrent"] >= 2 and summ["overlapped_launches"] >= 2, summ
@@ -95,9 +105,12 @@ def test_mix_equals_alone_serving_law(b64, oracle):
     _check_mix_alone_oracle(b64, oracle, res, kinds, parts, "law")
 
 
-def test_large_requests_under_a_tight_budget(b64, oracle):
+@ZERO_COPY
+def test_large_requests_under_a_tight_budget(b64, oracle, zc):
     """Requests of 1..16 MiB among small ones, a 40 MiB arena: the ring wraps
-    and requests wait for space; every result still equals the oracle's."""
+    and requests wait for space; every result still equals the oracle's.
+    With zero-copy, launches of at most 1 MiB skip the arena and the larger
+    ones still go through it."""
     from paper_1910_05109_amd import serve
     seed = workloads.SEED_BASE + 145
     sizes = workloads.serve_sizes(seed, 400)
@@ -107,14 +120,17 @@ def test_large_requests_under_a_tight_budget(b64, oracle):
                            (16 << 20) - 1])[: big.size]
     kinds, arrival, payload, in_off, parts = _schedule(oracle, seed, sizes, 5e4, 0.05)
     budget = 40 << 20
-    say("serve tight", sizes.size, int(sizes.sum()), "budget", budget)
+    say("serve tight", sizes.size, int(sizes.sum()), "budget", budget, "zero-copy max", zc)
     with serve.Server(budget_bytes=budget, nstreams=3, depth=6, max_batch=64,
-                      max_batch_bytes=4 << 20) as srv:
+                      max_batch_bytes=4 << 20, zero_copy_max=zc) as srv:
         res = srv.run(kinds, arrival, payload, in_off)
     summ = res.summary()
     say("serve summary", summ)
     assert summ["arena_bytes"] == budget and summ["peak_arena_bytes"] <= budget
-    assert summ["peak_arena_bytes"] > budget // 2          # the budget was the limit
+    if zc is None or zc < (5 << 20):
+        assert summ["peak_arena_bytes"] > budget // 2      # the budget was the limit
+    else:
+        assert summ["peak_arena_bytes"] == 0 and summ["zero_copy_launches"] == summ["launches"]
     _check_mix_alone_oracle(b64, oracle, res, kinds, parts, "tight")
 
 
@@ -125,7 +141,9 @@ def test_server_argument_errors(b64):
         serve.Server(budget_bytes=1 << 10)
     with pytest.raises(B64Error):
         serve.Server(budget_bytes=1 << 20, nstreams=0)
-    with serve.Server(budget_bytes=1 << 20, nstreams=1, depth=1) as srv:
+    with pytest.raises(ValueError):
+        serve.Server(budget_bytes=1 << 20, zero_copy_max=-2)
+    with serve.Server(budget_bytes=1 << 20, nstreams=1, depth=1, zero_copy_max=0) as srv:
         payload = np.zeros(4 << 20, dtype=np.uint8)
         with pytest.raises(B64Error):          # one request larger than the budget
             srv.run(np.zeros(1, np.int32), np.zeros(1), payload, np.array([0, payload.size]))
@@ -134,3 +152,10 @@ def test_server_argument_errors(b64):
                     np.array([0, 4, 8]))
         res = srv.run(np.zeros(0, np.int32), np.zeros(0), payload[:0], np.zeros(1, np.int64))
         assert res.out_len.size == 0
+    with serve.Server(budget_bytes=1 << 20, nstreams=1, depth=1, zero_copy_max=4 << 20) as srv:
+        # the same request zero-copy: no arena space needed
+        payload = workloads.random_bytes(workloads.SEED_BASE + 146, 4 << 20)
+        res = srv.run(np.zeros(1, np.int32), np.zeros(1), payload, np.array([0, payload.size]))
+        assert res.summary()["zero_copy_launches"] == 1
+        import base64
+        assert res.output(0).tobytes() == base64.b64encode(payload.tobytes())
