@@ -29,7 +29,8 @@
 // most `zc_max` bytes moves no bytes by DMA and takes no arena space: the pools are pinned host
 // memory mapped into the device's address space, so its kernel reads the
 // payloads and offsets from them and writes the outputs and lengths to them
-// over PCIe.  The decode's first invalid offsets, which the kernel merges with
+// over PCIe (the pools' offsets are copied to device memory once, before
+// serving starts).  The decode's first invalid offsets, which the kernel merges with
 // device-scope atomics, go to a per-slot device array kept at "no error"; a
 // one-block kernel after the decode copies the launch's entries to the host
 // and resets them.  For small launches the copies cost more than the kernel:
@@ -139,10 +140,13 @@ struct Pool {
     int64_t *in_off = nullptr;           // entries + 1 (relative to `in`)
     int64_t *out_off = nullptr;          // entries + 1 (relative to `out`)
     int64_t *len = nullptr, *bad = nullptr;
-    // the same pools as the device sees them (zero-copy launches)
+    // for zero-copy launches: the payload pools as the device sees them, and
+    // the offsets copied to device memory before serving (the kernels look
+    // them up before they can load a payload byte; over PCIe each lookup is
+    // a round trip)
     const uint8_t *d_in = nullptr;
     uint8_t *d_out = nullptr;
-    const int64_t *d_in_off = nullptr, *d_out_off = nullptr;
+    int64_t *d_in_off = nullptr, *d_out_off = nullptr;
     int64_t ready = 0, next = 0;         // admitted prefix, first not yet launched
 
     int64_t n() const { return (int64_t)req.size(); }
@@ -159,8 +163,11 @@ struct Pool {
         for (void *p : {(void *)in, (void *)out, (void *)in_off, (void *)out_off, (void *)len,
                         (void *)bad})
             if (p) (void)hipHostFree(p);
+        for (void *p : {(void *)d_in_off, (void *)d_out_off})
+            if (p) (void)hipFree(p);
         in = out = nullptr;
         in_off = out_off = len = bad = nullptr;
+        d_in_off = d_out_off = nullptr;
     }
 };
 
@@ -385,15 +392,16 @@ int64_t b64_server_run(b64_server *s, int64_t nreq, const int32_t *kind, const i
                 return s_fail(B64_EARG, "a request does not fit in the HBM budget");
             }
         uint8_t *din = nullptr;
-        int64_t *dio = nullptr, *doo = nullptr;
+        const size_t ob = (size_t)(8 * (m + 1));
         if ((e = dev_view(p.in, &din)) != hipSuccess || (e = dev_view(p.out, &p.d_out)) != hipSuccess ||
-            (e = dev_view(p.in_off, &dio)) != hipSuccess || (e = dev_view(p.out_off, &doo)) != hipSuccess) {
+            (e = hipMalloc((void **)&p.d_in_off, ob)) != hipSuccess ||
+            (e = hipMalloc((void **)&p.d_out_off, ob)) != hipSuccess ||
+            (e = hipMemcpy(p.d_in_off, p.in_off, ob, hipMemcpyHostToDevice)) != hipSuccess ||
+            (e = hipMemcpy(p.d_out_off, p.out_off, ob, hipMemcpyHostToDevice)) != hipSuccess) {
             cleanup();
             return s_hip(e, "pool device views");
         }
         p.d_in = din;
-        p.d_in_off = dio;
-        p.d_out_off = doo;
     }
 
     // ---- the timed loop
