@@ -13,32 +13,36 @@
 //   3. while fewer than `depth` launches are in flight, it takes the queued
 //      requests of one kind (the kinds alternate), as many as `max_batch`
 //      requests and `max_batch_bytes` payload bytes allow and the device arena
-//      (the HBM budget) can hold -- inputs, offsets, outputs and statuses --
-//      and enqueues on the next of `nstreams` streams (round robin): two
-//      host-to-device copies (the payloads; their offsets with the initial
-//      first-invalid values), ONE batched encode / decode kernel, and two
-//      device-to-host copies (the outputs; the lengths and first invalid
-//      offsets, which the host turns into the public form when the launch is
-//      done).
+//      (the HBM budget) can hold -- payloads and outputs -- and enqueues on the
+//      next of `nstreams` streams (round robin): ONE host-to-device copy (the
+//      payloads), ONE batched encode / decode kernel (plus, for a decode, a
+//      one-block kernel that hands its first invalid offsets to the host),
+//      and ONE device-to-host copy (the outputs).
+//
+// The pools' offsets are copied to device memory once, before serving, and
+// the kernels read them there.  The pools and each slot's status words are
+// pinned host memory mapped into the device's address space: the kernels
+// write the lengths straight to the status words.  The decode's first
+// invalid offsets, which the kernel merges with device-scope atomics (not
+// used on host memory), go to a per-slot device array kept at "no error";
+// the one-block kernel after the decode copies the launch's entries to the
+// status words and resets them.  The host turns the raw statuses into the
+// public form when the launch is done.
 //
 // Requests that arrive while others are on the GPU join the next launch;
 // launches on different streams run at the same time on the device (a copy
 // of one overlaps the kernel of another).
 //
 // Optionally (b64_server_set_zero_copy_max), a launch whose payload is at
-// most `zc_max` bytes moves no bytes by DMA and takes no arena space: the pools are pinned host
-// memory mapped into the device's address space, so its kernel reads the
-// payloads and offsets from them and writes the outputs and lengths to them
-// over PCIe (the pools' offsets are copied to device memory once, before
-// serving starts).  The decode's first invalid offsets, which the kernel merges with
-// device-scope atomics, go to a per-slot device array kept at "no error"; a
-// one-block kernel after the decode copies the launch's entries to the host
-// and resets them.  For small launches the copies cost more than the kernel:
+// most `zc_max` bytes moves no bytes by DMA and takes no arena space: its
+// kernel reads the payloads from, and writes the outputs to, the mapped
+// pools over PCIe.  For small launches the copies cost more than the kernel:
 // on MI355X one request of 1 KB / 64 KB / 1 MB took 18.5 / 31 / 51 us
-// zero-copy against 26 / 51 / 92 us with DMA copies around the same kernel.  Requests of one kind are packed in
-// arrival order in pinned host pools when the run starts (the payloads as a
-// network stack would have left them), so a batch is a contiguous range of
-// its pool and moves with one copy each way.
+// zero-copy against 26 / 51 / 92 us with DMA copies around the same kernel.
+//
+// Requests of one kind are packed in arrival order in the pools when the run
+// starts (the payloads as a network stack would have left them), so a batch
+// is a contiguous range of its pool and moves with one copy each way.
 #include <stdio.h>
 #include <string.h>
 
@@ -71,10 +75,9 @@ struct b64_server {
     int64_t max_batch = 0, max_batch_bytes = 0;
     std::vector<hipStream_t> streams;
     std::vector<hipEvent_t> ev_start, ev_end;     // one pair per in-flight slot
-    // pinned staging per in-flight slot: the launch's offsets and status
-    // initial values going in (3 * max_batch + 1 words), its lengths and first
-    // invalid offsets coming back (2 * max_batch words)
-    std::vector<int64_t *> meta_in, stat_out;
+    // per in-flight slot: its launch's first invalid offsets and lengths
+    // (2 * max_batch words, pinned and mapped: the kernels write them there)
+    std::vector<int64_t *> stat_out;
     std::vector<int64_t *> stat_out_dev;          // stat_out as the device sees it
     std::vector<int64_t *> bad_dev;               // zero-copy decodes: first invalid offsets
     int64_t zc_max = kZeroCopyDefault;
@@ -150,13 +153,11 @@ struct Pool {
     int64_t ready = 0, next = 0;         // admitted prefix, first not yet launched
 
     int64_t n() const { return (int64_t)req.size(); }
-    // arena bytes of entries [f, f + c): payload, then one block of words
-    // (c + 1 input offsets, c output offsets, c first invalid offsets, c
-    // lengths), then outputs
+    // arena bytes of entries [f, f + c) when staged: payload, then outputs
+    // (offsets and statuses live outside the arena)
     int64_t need(int64_t f, int64_t c) const
     {
-        return align_up(in_off[f + c] - in_off[f]) + align_up(8 * (4 * c + 1)) +
-               align_up(out_off[f + c] - out_off[f]);
+        return align_up(in_off[f + c] - in_off[f]) + align_up(out_off[f + c] - out_off[f]);
     }
     void free_host()
     {
@@ -270,9 +271,7 @@ b64_server *b64_server_create(int64_t budget_bytes, int nstreams, int depth, int
             s->ev_start.push_back(a);
             s->ev_end.push_back(b);
         }
-        int64_t *mi = nullptr, *so = nullptr, *sod = nullptr, *bd = nullptr;
-        if (e == hipSuccess) e = host_alloc((void **)&mi, 8 * (3 * max_batch + 1));
-        if (e == hipSuccess) s->meta_in.push_back(mi);
+        int64_t *so = nullptr, *sod = nullptr, *bd = nullptr;
         if (e == hipSuccess) e = host_alloc((void **)&so, 8 * (2 * max_batch));
         if (e == hipSuccess) s->stat_out.push_back(so);
         if (e == hipSuccess) e = dev_view(so, &sod);
@@ -312,7 +311,6 @@ void b64_server_destroy(b64_server *s)
     for (hipEvent_t ev : s->ev_start) (void)hipEventDestroy(ev);
     for (hipEvent_t ev : s->ev_end) (void)hipEventDestroy(ev);
     if (s->ref) (void)hipEventDestroy(s->ref);
-    for (int64_t *p : s->meta_in) (void)hipHostFree(p);
     for (int64_t *p : s->stat_out) (void)hipHostFree(p);
     for (int64_t *p : s->bad_dev) (void)hipFree(p);
     if (s->arena) (void)hipFree(s->arena);
@@ -431,76 +429,45 @@ int64_t b64_server_run(b64_server *s, int64_t nreq, const int32_t *kind, const i
     const DecMap map = make_dec(alphabet);
     const Shape enc_shape = op_shape(2, -1), dec_shape = op_shape(3, -1);
 
-    // Enqueue entries [f, f + c) of pool p on the next stream: two copies in
-    // (the payload; the offsets and the first-invalid initial values in one
-    // block), one batched kernel, two copies out (the outputs; the first
-    // invalid offsets and lengths in one block).
+    // Enqueue entries [f, f + c) of pool p on the next stream.  The kernels
+    // take the entries' offsets from their device copy and write the lengths
+    // (and, through k_status_out, the first invalid offsets) straight to the
+    // slot's mapped status words.  Staged (held >= 0): the payload is copied
+    // into the arena, the kernel writes the outputs there, and they are
+    // copied back.  Zero-copy (held < 0): the kernel reads the payload from,
+    // and writes the outputs to, the mapped pools.
     auto launch = [&](Pool &p, int64_t f, int64_t c, int64_t start, int64_t held, int slot) -> int64_t {
         hipStream_t st = s->streams[next_stream];
         next_stream = (next_stream + 1) % s->nstreams;
-        if (held < 0) {
-            // zero-copy: the kernel works on the mapped pools (pool offsets)
-            const bool dec = p.kind == B64_SERVE_DECODE;
-            int64_t *hs = s->stat_out_dev[slot];      // first invalid offsets, then lengths
-            hipError_t x = hipEventRecord(s->ev_start[slot], st);
-            if (x == hipSuccess)
-                x = dec ? launch_decode_batch(p.d_in, p.d_in_off + f, c, p.d_out, p.d_out_off + f, hs + c,
-                                              s->bad_dev[slot], map, 0, dec_shape, cus, st)
-                        : launch_encode_batch(p.d_in, p.d_in_off + f, c, p.d_out, p.d_out_off + f, hs + c,
-                                              tab, 0, enc_shape, cus, st);
-            if (x == hipSuccess && dec) {
-                const int64_t g = std::min<int64_t>((c + kThreads - 1) / kThreads, 32);
-                x = launch_args(&k_status_out, dim3((unsigned)g), dim3(kThreads), st, hs, s->bad_dev[slot], c);
-            }
-            if (x == hipSuccess) x = hipEventRecord(s->ev_end[slot], st);
-            if (x != hipSuccess) return s_hip(x, "zero-copy launch");
-            Launch L;
-            L.kind = p.kind;
-            L.slot = slot;
-            L.first = f;
-            L.count = c;
-            L.held = -1;
-            fifo.push_back(L);
-            ++launches;
-            ++zc_launches;
-            max_inflight = std::max<int64_t>(max_inflight, (int64_t)fifo.size());
-            return 0;
-        }
+        const bool dec = p.kind == B64_SERVE_DECODE, zc = held < 0;
         const int64_t nin = p.in_off[f + c] - p.in_off[f], nout = p.out_off[f + c] - p.out_off[f];
-        uint8_t *d_in = s->arena + start;
-        int64_t *d_ioff = (int64_t *)(d_in + align_up(nin));     // c + 1
-        int64_t *d_ooff = d_ioff + c + 1;                        // c
-        int64_t *d_bad = d_ooff + c;                             // c
-        int64_t *d_len = d_bad + c;                              // c
-        uint8_t *d_out = (uint8_t *)d_ioff + align_up(8 * (4 * c + 1));
-        int64_t *mi = s->meta_in[slot];
-        memcpy(mi, p.in_off + f, (size_t)(8 * (c + 1)));
-        memcpy(mi + c + 1, p.out_off + f, (size_t)(8 * c));
-        const bool dec = p.kind == B64_SERVE_DECODE;
-        if (dec)
-            for (int64_t k = 0; k < c; ++k) mi[2 * c + 1 + k] = kNoError;
-        const int64_t nmeta = dec ? 3 * c + 1 : 2 * c + 1;
+        // entry k's bytes are at base + (pool offset of entry f + k)
+        const uint8_t *src_base = p.d_in;
+        uint8_t *dst_base = p.d_out;
+        uint8_t *d_in = nullptr, *d_out = nullptr;
+        if (!zc) {
+            d_in = s->arena + start;
+            d_out = d_in + align_up(nin);
+            src_base = d_in - p.in_off[f];
+            dst_base = d_out - p.out_off[f];
+        }
+        int64_t *hs = s->stat_out_dev[slot];      // first invalid offsets, then lengths
         hipError_t x = hipEventRecord(s->ev_start[slot], st);
-        if (x == hipSuccess)
+        if (x == hipSuccess && !zc)
             x = hipMemcpyAsync(d_in, p.in + p.in_off[f], (size_t)nin, hipMemcpyHostToDevice, st);
         if (x == hipSuccess)
-            x = hipMemcpyAsync(d_ioff, mi, (size_t)(8 * nmeta), hipMemcpyHostToDevice, st);
-        if (x != hipSuccess) return s_hip(x, "request copies");
-        // the batch kernels index src / dst with the pool offsets of these entries
-        const uint8_t *src_base = d_in - p.in_off[f];
-        uint8_t *dst_base = d_out - p.out_off[f];
-        x = dec ? launch_decode_batch(src_base, d_ioff, c, dst_base, d_ooff, d_len, d_bad, map, 0,
-                                      dec_shape, cus, st)
-                : launch_encode_batch(src_base, d_ioff, c, dst_base, d_ooff, d_len, tab, 0,
-                                      enc_shape, cus, st);
-        if (x != hipSuccess) return s_hip(x, "batch launch");
-        x = hipMemcpyAsync(p.out + p.out_off[f], d_out, (size_t)nout, hipMemcpyDeviceToHost, st);
-        if (x == hipSuccess)
-            x = dec ? hipMemcpyAsync(s->stat_out[slot], d_bad, (size_t)(16 * c), hipMemcpyDeviceToHost, st)
-                    : hipMemcpyAsync(s->stat_out[slot] + c, d_len, (size_t)(8 * c),
-                                     hipMemcpyDeviceToHost, st);
+            x = dec ? launch_decode_batch(src_base, p.d_in_off + f, c, dst_base, p.d_out_off + f, hs + c,
+                                          s->bad_dev[slot], map, 0, dec_shape, cus, st)
+                    : launch_encode_batch(src_base, p.d_in_off + f, c, dst_base, p.d_out_off + f, hs + c,
+                                          tab, 0, enc_shape, cus, st);
+        if (x == hipSuccess && dec) {
+            const int64_t g = std::min<int64_t>((c + kThreads - 1) / kThreads, 32);
+            x = launch_args(&k_status_out, dim3((unsigned)g), dim3(kThreads), st, hs, s->bad_dev[slot], c);
+        }
+        if (x == hipSuccess && !zc)
+            x = hipMemcpyAsync(p.out + p.out_off[f], d_out, (size_t)nout, hipMemcpyDeviceToHost, st);
         if (x == hipSuccess) x = hipEventRecord(s->ev_end[slot], st);
-        if (x != hipSuccess) return s_hip(x, "result copies");
+        if (x != hipSuccess) return s_hip(x, zc ? "zero-copy launch" : "staged launch");
         Launch L;
         L.kind = p.kind;
         L.slot = slot;
@@ -509,6 +476,7 @@ int64_t b64_server_run(b64_server *s, int64_t nreq, const int32_t *kind, const i
         L.held = held;
         fifo.push_back(L);
         ++launches;
+        zc_launches += zc ? 1 : 0;
         max_inflight = std::max<int64_t>(max_inflight, (int64_t)fifo.size());
         return 0;
     };
