@@ -272,8 +272,8 @@ const char *b64_pipeline_last_error(void);
  * path that serves many small requests: requests that arrive while others
  * are on the GPU join the next launch, and launches on different streams run
  * at the same time).  b64_server_create allocates the device arena of
- * `budget_bytes` (the HBM budget: every launch's payloads, offsets, outputs
- * and statuses are allocated in it, and requests wait while it is full),
+ * `budget_bytes` (the HBM budget: every staged launch's payloads and outputs
+ * are allocated in it, and requests wait while it is full),
  * `nstreams` HIP streams (1..16, default priority, launches go round robin)
  * and events for up to `depth` launches in flight (nstreams..64); a launch
  * coalesces up to `max_batch` queued requests of one kind and up to
