@@ -3,10 +3,11 @@
 The server itself is native (csrc/b64_serve.hip): one scheduler thread
 admits requests as they arrive, coalesces the queued requests of one kind
 into ONE batched launch while the device arena (the HBM budget) has room for
-their payloads, offsets, outputs and statuses, and enqueues each launch on
-the next of several HIP streams, so that launches run at the same time on the
-device; a launch's requests are done when its results are in pinned host
-memory.  This module only marshals arrays: a schedule (kind, arrival time,
+their payloads and outputs, and enqueues each launch on the next of several
+HIP streams, so that launches run at the same time on the device; a launch's
+requests are done when its results are in pinned host memory.  Optionally,
+launches run zero-copy: the kernels work on the pinned host pools directly,
+with no DMA and no arena space.  This module only marshals arrays: a schedule (kind, arrival time,
 payload of each request, in host memory) goes in; outputs, lengths, first
 invalid offsets, completion times and the run's counters come out.
 """
@@ -75,7 +76,7 @@ class Result:
 class Server:
     """A native continuous-batching server on the current device.
 
-    budget_bytes: the device arena for everything in flight (HBM budget);
+    budget_bytes: the device arena for the payloads and outputs in flight (HBM budget);
     nstreams: HIP streams the launches go to in turn; depth: launches in
     flight at most; max_batch / max_batch_bytes: requests / payload bytes per
     launch at most; zero_copy_max: launches with at most this many payload
