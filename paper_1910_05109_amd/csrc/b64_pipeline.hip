@@ -129,6 +129,18 @@ hipError_t store_chunk(b64_pipeline *p, b64_pipeline::Slot &s, uint8_t *h_out, i
     return hipEventRecord(s.done, p->s_out);
 }
 
+// An error after chunks were enqueued: let every copy and kernel in flight
+// finish (they may read the caller's source or write its destination, which
+// the caller may free once the call returns), and forget the slots' chunks,
+// so that the next call starts from empty slots.
+int64_t p_abort(b64_pipeline *p, int64_t code)
+{
+    for (hipStream_t st : {p->s_in, p->s_code, p->s_out}) (void)hipStreamSynchronize(st);
+    (void)hipGetLastError();
+    for (auto &s : p->slots) s.busy = false;
+    return code;
+}
+
 void release(b64_pipeline *p)
 {
     for (hipStream_t st : {p->s_in, p->s_code, p->s_out})
@@ -222,7 +234,7 @@ int64_t b64_pipeline_encode(b64_pipeline *p, const uint8_t *src, int64_t n, uint
     for (int64_t k = 0; k < nchunks + depth; ++k) {
         b64_pipeline::Slot &s = p->slots[k % depth];
         if (s.busy) {   // collect this slot's previous chunk
-            if ((e = hipEventSynchronize(s.done)) != hipSuccess) return p_hip(e, "pipeline wait");
+            if ((e = hipEventSynchronize(s.done)) != hipSuccess) return p_abort(p, p_hip(e, "pipeline wait"));
             if (!dst_pinned) par_copy(dst + s.out_off, s.h_out, s.out_len, p->host_threads);
             s.busy = false;
         }
@@ -233,11 +245,12 @@ int64_t b64_pipeline_encode(b64_pipeline *p, const uint8_t *src, int64_t n, uint
         s.out_len = (s.in_len + 2) / 3 * 4;
         if (!src_pinned) par_copy(s.h_in, src + s.in_off, s.in_len, p->host_threads);
         const uint8_t *h_in = src_pinned ? src + s.in_off : s.h_in;
-        if ((e = load_chunk(p, s, h_in)) != hipSuccess) return p_hip(e, "pipeline H2D");
+        if ((e = load_chunk(p, s, h_in)) != hipSuccess) return p_abort(p, p_hip(e, "pipeline H2D"));
         const int64_t r = b64_encode(s.d_in, s.in_len, s.d_out, alphabet, p->s_code);
-        if (r < 0) return r;
+        if (r < 0) return p_abort(p, r);
         uint8_t *h_out = dst_pinned ? dst + s.out_off : s.h_out;
-        if ((e = store_chunk(p, s, h_out, s.out_len, nullptr)) != hipSuccess) return p_hip(e, "pipeline D2H");
+        if ((e = store_chunk(p, s, h_out, s.out_len, nullptr)) != hipSuccess)
+            return p_abort(p, p_hip(e, "pipeline D2H"));
         s.busy = true;
     }
     return 4 * ((n + 2) / 3);
@@ -261,7 +274,7 @@ int64_t b64_pipeline_decode(b64_pipeline *p, const uint8_t *src, int64_t n, uint
     for (int64_t k = 0; k < nchunks + depth; ++k) {
         b64_pipeline::Slot &s = p->slots[k % depth];
         if (s.busy) {
-            if ((e = hipEventSynchronize(s.done)) != hipSuccess) return p_hip(e, "pipeline wait");
+            if ((e = hipEventSynchronize(s.done)) != hipSuccess) return p_abort(p, p_hip(e, "pipeline wait"));
             s.busy = false;
             const int64_t len = s.h_status[0], bad = s.h_status[1];
             const bool last = s.in_off + s.in_len == n;
@@ -281,13 +294,13 @@ int64_t b64_pipeline_decode(b64_pipeline *p, const uint8_t *src, int64_t n, uint
         s.out_off = s.in_off / 4 * 3;
         if (!src_pinned) par_copy(s.h_in, src + s.in_off, s.in_len, p->host_threads);
         const uint8_t *h_in = src_pinned ? src + s.in_off : s.h_in;
-        if ((e = load_chunk(p, s, h_in)) != hipSuccess) return p_hip(e, "pipeline H2D");
+        if ((e = load_chunk(p, s, h_in)) != hipSuccess) return p_abort(p, p_hip(e, "pipeline H2D"));
         const int64_t r = b64_decode_async(s.d_in, s.in_len, s.d_out, s.d_status, s.d_status + 1,
                                            alphabet, p->s_code);
-        if (r < 0) return r;
+        if (r < 0) return p_abort(p, r);
         uint8_t *h_out = dst_pinned ? dst + s.out_off : s.h_out;
         if ((e = store_chunk(p, s, h_out, s.in_len / 4 * 3, s.h_status)) != hipSuccess)
-            return p_hip(e, "pipeline D2H");
+            return p_abort(p, p_hip(e, "pipeline D2H"));
         s.busy = true;
     }
     return first_bad >= 0 ? ~first_bad : total;

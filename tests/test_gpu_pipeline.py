@@ -131,3 +131,19 @@ def test_depth_above_three(oracle):
             assert np.array_equal(p.encode(x), ref), depth
             dec, bad = p.decode(ref)
             assert bad is None and np.array_equal(dec, x), depth
+
+
+def test_error_then_valid_call(pipe, oracle):
+    """A call that fails (an alphabet with a repeated byte) drains what it
+    enqueued and leaves the pipeline ready: the next calls are exact."""
+    from paper_1910_05109_amd._lib import B64Error
+    x = workloads.random_bytes(workloads.SEED_BASE + 165, 40_000)
+    text = oracle.encode(x)
+    bad_alpha = b"A" * 64
+    with pytest.raises(B64Error):
+        pipe.encode(x, alphabet=bad_alpha)
+    assert np.array_equal(pipe.encode(x), text)
+    with pytest.raises(B64Error):
+        pipe.decode(text, alphabet=bad_alpha)
+    dec, bad = pipe.decode(text)
+    assert bad is None and np.array_equal(dec, x)
