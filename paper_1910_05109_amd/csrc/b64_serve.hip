@@ -569,6 +569,11 @@ int64_t b64_server_run(b64_server *s, int64_t nreq, const int32_t *kind, const i
         if (x != hipSuccess && !err) err = s_hip(x, "stream synchronize");
     }
     if (err) {
+        // a decode whose status hand-over never ran leaves its entries in the
+        // slot's device array: set them all back to "no error" for the next run
+        for (int64_t *bd : s->bad_dev) (void)launch_fill(bd, s->max_batch, kNoError, s->streams[0]);
+        (void)hipStreamSynchronize(s->streams[0]);
+        (void)hipGetLastError();
         cleanup();
         return err;
     }
