@@ -300,7 +300,8 @@ def run_single(args, torch, b64):
         def serve_rows(zero_copy_max):
             rows = []
             with serve.Server(budget_bytes=32 << 30, nstreams=args.serve_streams,
-                              depth=args.serve_depth, zero_copy_max=zero_copy_max) as srv:
+                              depth=args.serve_depth, zero_copy_max=zero_copy_max,
+                              staging=args.serve_staging) as srv:
                 # untimed warm-up traffic at both rates: in a server's first
                 # runs the HIP runtime's DMA copies now and then block the
                 # scheduler thread for 5-8 ms (seen inside hipMemcpyAsync, most
@@ -597,7 +598,8 @@ def run_serve(args, torch, b64):
     kinds, payload, off, sizes, spoil = serve_requests(torch, b64, count_max)
     out = []
     with serve.Server(budget_bytes=32 << 30, nstreams=args.serve_streams,
-                      depth=args.serve_depth, zero_copy_max=args.serve_zero_copy_max) as srv:
+                      depth=args.serve_depth, zero_copy_max=args.serve_zero_copy_max,
+                      staging=args.serve_staging) as srv:
         for rate in args.rates:
             count = int(min(count_max, max(2000, rate * args.seconds)))
             summ = serve_rate(srv, torch, b64, kinds, payload, off, sizes, spoil, rate, count)
@@ -605,7 +607,8 @@ def run_serve(args, torch, b64):
             out.append(summ)
     print(json.dumps({"workload": "serving", "sigma": workloads.SERVE_SIGMA,
                       "streams": args.serve_streams, "depth": args.serve_depth,
-                      "zero_copy_max": args.serve_zero_copy_max, "rows": out}),
+                      "zero_copy_max": args.serve_zero_copy_max, "staging": args.serve_staging,
+                      "rows": out}),
           flush=True)
 
 
@@ -840,6 +843,9 @@ def main():
     ap.add_argument("--seconds", type=float, default=10.0)
     ap.add_argument("--serve-streams", type=int, default=2)
     ap.add_argument("--serve-depth", type=int, default=2, help="launches in flight at most")
+    ap.add_argument("--serve-staging", choices=["auto", "kernels", "dma"], default=None,
+                    help="staged launches: copy kernels up to 1 MiB then DMA (auto, the default), "
+                         "copy kernels or DMA")
     ap.add_argument("--serve-zero-copy-max", type=int, default=None,
                     help="payload bytes of a launch at most for zero-copy (0: off; default: the library's)")
     args = ap.parse_args()

@@ -292,6 +292,16 @@ void b64_server_destroy(b64_server *s);
  * zero-copy off: buffers then stay in device memory under the HBM budget.  Returns the previous value (bytes = -1 only reads
  * it), or B64_EARG. */
 int64_t b64_server_set_zero_copy_max(b64_server *s, int64_t bytes);
+/* How staged launches move payloads into the arena and outputs out of it:
+ * B64_STAGE_KERNELS -- copy kernels that read or write the pinned host
+ * pools, mapped into the device's address space; B64_STAGE_DMA --
+ * hipMemcpyAsync; B64_STAGE_AUTO (the default) -- kernels for launches of
+ * at most 1 MiB of payload, DMA for larger ones.  Returns the previous mode
+ * (mode = -1 only reads it), or B64_EARG. */
+#define B64_STAGE_KERNELS 0
+#define B64_STAGE_DMA 1
+#define B64_STAGE_AUTO 2
+int64_t b64_server_set_staging(b64_server *s, int mode);
 const char *b64_server_last_error(void);
 #define B64_SERVE_ENCODE 0
 #define B64_SERVE_DECODE 1

@@ -51,6 +51,7 @@ SIGNATURES = {
     "b64_server_create": ([_I64, _INT, _INT, _I64, _I64], _P),
     "b64_server_destroy": ([_P], None),
     "b64_server_set_zero_copy_max": ([_P, _I64], _I64),
+    "b64_server_set_staging": ([_P, _INT], _I64),
     "b64_server_last_error": ([], ctypes.c_char_p),
     "b64_server_run": ([_P, _I64, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P], _I64),
     "b64_tune_set_bucket": ([_INT, _INT, _INT, _INT, _INT], _I64),

@@ -14,10 +14,13 @@
 //      requests of one kind (the kinds alternate), as many as `max_batch`
 //      requests and `max_batch_bytes` payload bytes allow and the device arena
 //      (the HBM budget) can hold -- payloads and outputs -- and enqueues on the
-//      next of `nstreams` streams (round robin): ONE host-to-device copy (the
-//      payloads), ONE batched encode / decode kernel (plus, for a decode, a
-//      one-block kernel that hands its first invalid offsets to the host),
-//      and ONE device-to-host copy (the outputs).
+//      next of `nstreams` streams (round robin): ONE copy of the payloads
+//      into the arena, ONE batched encode / decode kernel (plus, for a
+//      decode, a one-block kernel that hands its first invalid offsets to the
+//      host), and ONE copy of the outputs back.  The copies of launches up to
+//      1 MiB of payload are kernels that read or write the mapped host pools,
+//      larger ones are DMA (hipMemcpyAsync); b64_server_set_staging can make
+//      them all one or the other.
 //
 // The pools' offsets are copied to device memory once, before serving, and
 // the kernels read them there.  The pools and each slot's status words are
@@ -65,6 +68,13 @@ namespace b64hip {
 // rates measured worse than either alone on MI355X (launches of up to 4 MiB
 // zero-copy beside staged ones fell below an offered 10^6 requests/s).
 constexpr int64_t kZeroCopyDefault = 0;
+// Staged launches with payloads up to this size copy by kernels by default
+// (B64_STAGE_AUTO): for small launches a copy kernel answers sooner than a
+// DMA copy and never meets the runtime's DMA stalls; large launches, at high
+// request rates, need both copy directions at once, which DMA gives and
+// copy kernels, one direction per launch, did not (28 GB/s of base64 at 10^6
+// requests/s against 33-38 GB/s).
+constexpr int64_t kKernelCopyAuto = 1 << 20;
 }  // namespace b64hip
 
 struct b64_server {
@@ -81,6 +91,9 @@ struct b64_server {
     std::vector<int64_t *> stat_out_dev;          // stat_out as the device sees it
     std::vector<int64_t *> bad_dev;               // zero-copy decodes: first invalid offsets
     int64_t zc_max = kZeroCopyDefault;
+    // staged launches with at most this many payload bytes copy with kernels,
+    // larger ones by DMA (b64_server_set_staging)
+    int64_t kcopy_max = kKernelCopyAuto;
     hipEvent_t ref = nullptr;
 };
 
@@ -177,6 +190,41 @@ struct Launch {
     int64_t first = 0, count = 0, held = 0;     // held < 0: zero-copy, no arena space
     bool done = false;
 };
+
+// n bytes from src to dst (any alignment): each thread loads four 16-byte
+// chunks, a grid apart, before it stores them, so that four loads per thread
+// are in flight (over PCIe a load is a round trip); the last partial chunk
+// goes byte by byte.  The staged launches' payloads go into the arena and
+// their outputs out of it this way, between device memory and the mapped
+// host pools.
+__global__ __launch_bounds__(kThreads) void k_copy_bytes(uint8_t *__restrict__ dst,
+                                                         const uint8_t *__restrict__ src, int64_t n)
+{
+    const int64_t T = (int64_t)gridDim.x * kThreads;
+    const int64_t full = n >> 4;
+    for (int64_t i0 = (int64_t)blockIdx.x * kThreads + threadIdx.x; i0 < full; i0 += 4 * T) {
+        u32x4 v[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int64_t i = i0 + j * T;
+            v[j] = load16<true>(src + 16 * (i < full ? i : i0));
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int64_t i = i0 + j * T;
+            if (i < full) store16<true>(dst + 16 * i, v[j]);
+        }
+    }
+    if (blockIdx.x == 0 && threadIdx.x < (n & 15)) dst[16 * full + threadIdx.x] = src[16 * full + threadIdx.x];
+}
+
+hipError_t copy_bytes(uint8_t *dst, const uint8_t *src, int64_t n, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    const int64_t per = (int64_t)kThreads * 4 * 16;          // four chunks per thread
+    const int64_t g = std::max<int64_t>(1, std::min<int64_t>((n + per - 1) / per, 16384));
+    return launch_args(&k_copy_bytes, dim3((unsigned)g), dim3(kThreads), st, dst, src, n);
+}
 
 // Entries [0, c) of a zero-copy decode's first invalid offsets: to the host
 // (mapped) array, and the device array back to "no error" for the slot's
@@ -289,6 +337,21 @@ b64_server *b64_server_create(int64_t budget_bytes, int nstreams, int depth, int
         return nullptr;
     }
     return s;
+}
+
+int64_t b64_server_set_staging(b64_server *s, int mode)
+{
+    if (!s) return s_fail(B64_EARG, "null server");
+    const int64_t old = s->kcopy_max == 0 ? B64_STAGE_DMA
+                        : s->kcopy_max == INT64_MAX ? B64_STAGE_KERNELS : B64_STAGE_AUTO;
+    switch (mode) {
+    case B64_STAGE_AUTO: s->kcopy_max = kKernelCopyAuto; break;
+    case B64_STAGE_KERNELS: s->kcopy_max = INT64_MAX; break;
+    case B64_STAGE_DMA: s->kcopy_max = 0; break;
+    case -1: break;
+    default: return s_fail(B64_EARG, "mode must be B64_STAGE_AUTO, B64_STAGE_KERNELS, B64_STAGE_DMA or -1");
+    }
+    return old;
 }
 
 int64_t b64_server_set_zero_copy_max(b64_server *s, int64_t bytes)
@@ -454,7 +517,8 @@ int64_t b64_server_run(b64_server *s, int64_t nreq, const int32_t *kind, const i
         int64_t *hs = s->stat_out_dev[slot];      // first invalid offsets, then lengths
         hipError_t x = hipEventRecord(s->ev_start[slot], st);
         if (x == hipSuccess && !zc)
-            x = hipMemcpyAsync(d_in, p.in + p.in_off[f], (size_t)nin, hipMemcpyHostToDevice, st);
+            x = nin > s->kcopy_max ? hipMemcpyAsync(d_in, p.in + p.in_off[f], (size_t)nin, hipMemcpyHostToDevice, st)
+                                   : copy_bytes(d_in, p.d_in + p.in_off[f], nin, st);
         if (x == hipSuccess)
             x = dec ? launch_decode_batch(src_base, p.d_in_off + f, c, dst_base, p.d_out_off + f, hs + c,
                                           s->bad_dev[slot], map, 0, dec_shape, cus, st)
@@ -465,7 +529,8 @@ int64_t b64_server_run(b64_server *s, int64_t nreq, const int32_t *kind, const i
             x = launch_args(&k_status_out, dim3((unsigned)g), dim3(kThreads), st, hs, s->bad_dev[slot], c);
         }
         if (x == hipSuccess && !zc)
-            x = hipMemcpyAsync(p.out + p.out_off[f], d_out, (size_t)nout, hipMemcpyDeviceToHost, st);
+            x = nin > s->kcopy_max ? hipMemcpyAsync(p.out + p.out_off[f], d_out, (size_t)nout, hipMemcpyDeviceToHost, st)
+                                   : copy_bytes(p.d_out + p.out_off[f], d_out, nout, st);
         if (x == hipSuccess) x = hipEventRecord(s->ev_end[slot], st);
         if (x != hipSuccess) return s_hip(x, zc ? "zero-copy launch" : "staged launch");
         Launch L;

@@ -81,7 +81,11 @@ class Server:
     flight at most; max_batch / max_batch_bytes: requests / payload bytes per
     launch at most; zero_copy_max: launches with at most this many payload
     bytes run zero-copy (the kernel works on the pinned host pools, no DMA
-    and no arena space; 0 turns it off, None keeps the library's default).
+    and no arena space; 0 turns it off, None keeps the library's default);
+    staging: how staged launches move bytes between the host pools and the
+    arena: "auto" (the default: copy kernels on the mapped pools for
+    launches up to 1 MiB of payload, DMA above), "kernels" or "dma"
+    (hipMemcpyAsync).
     The defaults (two streams, one launch in flight on each) gave the lowest
     p99 on MI355X: a device has four hardware queues, and more streams than
     the queues left beside the default stream stall now and then for
@@ -89,7 +93,7 @@ class Server:
 
     def __init__(self, budget_bytes: int = 32 << 30, nstreams: int = 2, depth: int = 2,
                  max_batch: int = 8192, max_batch_bytes: int = 64 << 20,
-                 zero_copy_max: int | None = None):
+                 zero_copy_max: int | None = None, staging: str | None = None):
         L = load()
         self._h = L.b64_server_create(int(budget_bytes), int(nstreams), int(depth), int(max_batch),
                                       int(max_batch_bytes))
@@ -99,6 +103,12 @@ class Server:
             if zero_copy_max < 0 or L.b64_server_set_zero_copy_max(self._h, int(zero_copy_max)) < 0:
                 self.close()
                 raise ValueError("zero_copy_max must be >= 0")
+        if staging is not None:
+            modes = {"kernels": 0, "dma": 1, "auto": 2}
+            if staging not in modes:
+                self.close()
+                raise ValueError("staging must be 'auto', 'kernels' or 'dma'")
+            L.b64_server_set_staging(self._h, modes[staging])
 
     def close(self):
         if self._h:

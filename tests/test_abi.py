@@ -42,7 +42,7 @@ def test_header_declares_the_boundary():
         "b64_pipeline_create", "b64_pipeline_destroy", "b64_pipeline_encode",
         "b64_pipeline_decode", "b64_pipeline_last_error",
         "b64_server_create", "b64_server_destroy", "b64_server_last_error", "b64_server_run",
-        "b64_server_set_zero_copy_max",
+        "b64_server_set_zero_copy_max", "b64_server_set_staging",
         "b64_tune_set_bucket", "b64_tune_set", "b64_tune_get_bucket", "b64_tune_get",
         "b64_tune_bucket", "b64_tune_ws_guess_min", "b64_tune_ws_small_max", "b64_yardstick",
         "b64_last_error"}

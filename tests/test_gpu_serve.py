@@ -9,7 +9,8 @@ Requests follow the serving workload's law -- sizes log-normal with median
 decodes spoiled by one invalid byte -- and a second case adds requests of
 several MiB up to 16 MiB under a budget small enough that the arena wraps and
 admission waits.  Each case runs with every launch staged through the arena
-by DMA (the default), with launches of up to 1 MiB zero-copy (the kernel
+(copies by kernels up to 1 MiB and by DMA above, the default; all by
+kernels; all by DMA), with launches of up to 1 MiB zero-copy (the kernel
 works on the pinned host pools), and with every launch zero-copy.
 """
 import numpy as np
@@ -78,11 +79,13 @@ def _check_mix_alone_oracle(b64, oracle, res, kinds, parts, label):
                 assert res.first_bad[i] == ref_bad and res.out_len[i] == -1, (label, i)
 
 
-ZERO_COPY = pytest.mark.parametrize("zc", [None, 1 << 20, 64 << 20], ids=["dma", "mixed", "zero-copy"])
+ZERO_COPY = pytest.mark.parametrize(
+    "zc,staging", [(None, None), (None, "kernels"), (None, "dma"), (1 << 20, None), (64 << 20, None)],
+    ids=["staged", "staged-kernels", "staged-dma", "mixed", "zero-copy"])
 
 
 @ZERO_COPY
-def test_mix_equals_alone_serving_law(b64, oracle, zc):
+def test_mix_equals_alone_serving_law(b64, oracle, zc, staging):
     """3,000 requests of the serving law at 200,000 per second: coalesced,
     with launches overlapping on the device."""
     from paper_1910_05109_amd import serve
@@ -90,7 +93,8 @@ def test_mix_equals_alone_serving_law(b64, oracle, zc):
     sizes = workloads.serve_sizes(seed, 3000)
     kinds, arrival, payload, in_off, parts = _schedule(oracle, seed, sizes, 2e5, 0.02)
     say("serve law", sizes.size, int(sizes.sum()), "zero-copy max", zc)
-    with serve.Server(budget_bytes=32 << 30, nstreams=4, depth=8, zero_copy_max=zc) as srv:
+    with serve.Server(budget_bytes=32 << 30, nstreams=4, depth=8, zero_copy_max=zc,
+                      staging=staging) as srv:
         res = srv.run(kinds, arrival, payload, in_off)
     summ = res.summary()
     say("serve summary", summ)
@@ -106,7 +110,7 @@ def test_mix_equals_alone_serving_law(b64, oracle, zc):
 
 
 @ZERO_COPY
-def test_large_requests_under_a_tight_budget(b64, oracle, zc):
+def test_large_requests_under_a_tight_budget(b64, oracle, zc, staging):
     """Requests of 1..16 MiB among small ones, a 40 MiB arena: the ring wraps
     and requests wait for space; every result still equals the oracle's.
     With zero-copy, launches of at most 1 MiB skip the arena and the larger
@@ -122,7 +126,7 @@ def test_large_requests_under_a_tight_budget(b64, oracle, zc):
     budget = 40 << 20
     say("serve tight", sizes.size, int(sizes.sum()), "budget", budget, "zero-copy max", zc)
     with serve.Server(budget_bytes=budget, nstreams=3, depth=6, max_batch=64,
-                      max_batch_bytes=4 << 20, zero_copy_max=zc) as srv:
+                      max_batch_bytes=4 << 20, zero_copy_max=zc, staging=staging) as srv:
         res = srv.run(kinds, arrival, payload, in_off)
     summ = res.summary()
     say("serve summary", summ)
@@ -143,6 +147,8 @@ def test_server_argument_errors(b64):
         serve.Server(budget_bytes=1 << 20, nstreams=0)
     with pytest.raises(ValueError):
         serve.Server(budget_bytes=1 << 20, zero_copy_max=-2)
+    with pytest.raises(ValueError):
+        serve.Server(budget_bytes=1 << 20, staging="pigeon")
     with serve.Server(budget_bytes=1 << 20, nstreams=1, depth=1, zero_copy_max=0) as srv:
         payload = np.zeros(4 << 20, dtype=np.uint8)
         with pytest.raises(B64Error):          # one request larger than the budget
