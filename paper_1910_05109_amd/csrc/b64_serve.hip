@@ -314,11 +314,9 @@ b64_server *b64_server_create(int64_t budget_bytes, int nstreams, int depth, int
     for (int i = 0; e == hipSuccess && i < depth; ++i) {
         hipEvent_t a = nullptr, b = nullptr;
         e = hipEventCreate(&a);
+        if (e == hipSuccess) s->ev_start.push_back(a);
         if (e == hipSuccess) e = hipEventCreate(&b);
-        if (e == hipSuccess) {
-            s->ev_start.push_back(a);
-            s->ev_end.push_back(b);
-        }
+        if (e == hipSuccess) s->ev_end.push_back(b);
         int64_t *so = nullptr, *sod = nullptr, *bd = nullptr;
         if (e == hipSuccess) e = host_alloc((void **)&so, 8 * (2 * max_batch));
         if (e == hipSuccess) s->stat_out.push_back(so);
