@@ -152,6 +152,25 @@ def test_argument_errors_without_gpu(lib):
     assert lib.b64_pipeline_encode(None, fake, 10, fake, std) == EARG
     assert lib.b64_pipeline_decode(None, fake, 10, fake, std) == EARG
     lib.b64_pipeline_destroy(None)
+    # server: limits checked before any device call
+    assert lib.b64_server_create(1 << 19, 1, 2, 64, 1 << 20) is None    # budget below 1 MiB
+    assert b"budget_bytes" in lib.b64_server_last_error()
+    assert lib.b64_server_create(1 << 20, 0, 2, 64, 1 << 20) is None    # no stream
+    assert lib.b64_server_create(1 << 20, 17, 17, 64, 1 << 20) is None  # more than 16 streams
+    assert b"nstreams" in lib.b64_server_last_error()
+    assert lib.b64_server_create(1 << 20, 2, 1, 64, 1 << 20) is None    # depth below nstreams
+    assert lib.b64_server_create(1 << 20, 2, 65, 64, 1 << 20) is None   # depth above 64
+    assert b"depth" in lib.b64_server_last_error()
+    assert lib.b64_server_create(1 << 20, 2, 2, 0, 1 << 20) is None
+    assert lib.b64_server_create(1 << 20, 2, 2, 64, 0) is None
+    assert b"batch limits" in lib.b64_server_last_error()
+    assert lib.b64_server_set_zero_copy_max(None, 0) == EARG
+    assert lib.b64_server_set_staging(None, 0) == EARG
+    stats = (ctypes.c_int64 * 8)()
+    assert lib.b64_server_run(None, 0, None, None, None, None, None, None, None, None, None,
+                              std, stats) == EARG
+    assert b"null server" in lib.b64_server_last_error()
+    lib.b64_server_destroy(None)
     # variants
     with_space = ctypes.create_string_buffer(b" " + std.raw[1:], 64)
     assert lib.b64_encode_mode(fake, 10, fake, std, 2, 0, None) == EARG          # SKIP_WS
