@@ -50,9 +50,6 @@ typedef uint16_t u16a1 __attribute__((aligned(1)));
 
 // ------------------------------------------------------------ wrapped encode --
 
-// Output position of character j of the unwrapped encoding for lines of L.
-__device__ __forceinline__ int64_t wrap_pos(int64_t j, int64_t L) { return j + 2 * (j / L); }
-
 // Characters [j0, j0+4k) of the unwrapped encoding, given as k words of four,
 // stored for lines of L; (line, col) are those of character j0 (col a
 // multiple of 4, col < L).
@@ -72,31 +69,55 @@ __device__ __forceinline__ void store_wrapped(uint8_t *dst, int64_t j0, int64_t 
     }
 }
 
-// Scalar tail: input bytes p[0..r) whose first character has index j0; the
-// last group is padded or, with !pad, cut to the characters that carry bits.
-__device__ void enc_scalar_wrap(const uint8_t *p, int64_t r, int64_t j0, uint8_t *dst, int64_t L,
-                                const uint8_t *tab, bool pad)
+// The r <= 11 input bytes after the chunks, fetched early by enc_tail_load,
+// encoded from registers and stored for lines of L; j0 is the index of their
+// first character in the unwrapped encoding.  L is a multiple of 4, so each
+// group (the padded or, with !pad, cut last one included) lands whole in one
+// line; the line and column of j0 come from one division and are stepped per
+// group.
+__device__ __forceinline__ void enc_tail_wrap(const EncTailIn &ti, int r, int64_t j0, uint8_t *dst,
+                                              int64_t L, const uint8_t *tab, bool pad)
 {
-    uint8_t ch[16];
-    int m = 0;
-    for (int64_t i = 0; i < r; i += 3) {
-        const int64_t k = r - i < 3 ? r - i : 3;
-        const uint32_t s1 = p[i], s2 = k > 1 ? p[i + 1] : 0u, s3 = k > 2 ? p[i + 2] : 0u;
-        const uint32_t q = enc_group(s2 | (s1 << 8) | (s3 << 16) | (s2 << 24), tab);
-        const int keep = k == 3 ? 4 : (int)k + 1;
-        for (int c = 0; c < 4; ++c) {
-            if (c < keep) ch[m++] = (uint8_t)(q >> (8 * c));
-            else if (pad) ch[m++] = (uint8_t)kPad;
+    if (r <= 0) return;
+    // shift the window right by off bytes: t[0..2] hold the r bytes in order
+    const int q = ti.off >> 2;
+    const uint32_t k = (uint32_t)(ti.off & 3);
+    const uint32_t x0 = __builtin_amdgcn_alignbyte(ti.w[1], ti.w[0], k);
+    const uint32_t x1 = __builtin_amdgcn_alignbyte(ti.w[2], ti.w[1], k);
+    const uint32_t x2 = __builtin_amdgcn_alignbyte(0u, ti.w[2], k);
+    const uint32_t t[3] = {q == 0 ? x0 : q == 1 ? x1 : q == 2 ? x2 : 0u,
+                           q == 0 ? x1 : q == 1 ? x2 : 0u, q == 0 ? x2 : 0u};
+    int64_t line = j0 / L, col = j0 - line * L;
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+        const int i = 3 * g;
+        if (i >= r) break;
+        const int kk = r - i < 3 ? r - i : 3;              // input bytes of the group
+        const uint32_t s1 = (t[i >> 2] >> (8 * (i & 3))) & 0xFF;
+        const uint32_t s2 = kk > 1 ? (t[(i + 1) >> 2] >> (8 * ((i + 1) & 3))) & 0xFF : 0u;
+        const uint32_t s3 = kk > 2 ? (t[(i + 2) >> 2] >> (8 * ((i + 2) & 3))) & 0xFF : 0u;
+        uint32_t v = enc_group(s2 | (s1 << 8) | (s3 << 16) | (s2 << 24), tab);
+        int nc = kk + 1;                                   // characters that carry bits
+        if (kk == 3) nc = 4;
+        else if (pad) {
+            v = kk == 1 ? (v & 0xFFFFu) | (kPad << 16) | (kPad << 24) : (v & 0xFFFFFFu) | (kPad << 24);
+            nc = 4;
         }
-    }
-    for (int c = 0; c < m; ++c) {
-        const int64_t j = j0 + c;
-        const int64_t pos = wrap_pos(j, L);
-        if (j % L == 0 && j > 0) {
-            dst[pos - 2] = '\r';
-            dst[pos - 1] = '\n';
+        const int64_t j = j0 + 4 * g;
+        uint8_t *o = dst + j + 2 * line;                   // j + 2 * floor(j / L)
+        if (col == 0 && j > 0) *(u16a1 *)(o - 2) = (uint16_t)('\r' | ('\n' << 8));
+        if (nc == 4) {
+            *(u32a1 *)o = v;
+        } else {
+            o[0] = (uint8_t)v;
+            o[1] = (uint8_t)(v >> 8);
+            if (nc == 3) o[2] = (uint8_t)(v >> 16);
         }
-        dst[pos] = ch[c];
+        col += 4;
+        if (col == L) {
+            col = 0;
+            ++line;
+        }
     }
 }
 
@@ -195,13 +216,17 @@ __global__ __launch_bounds__(kThreads) void k_encode_wrap(const uint8_t *__restr
                                                           uint8_t *__restrict__ dst, EncTab tab,
                                                           uint32_t flags, int64_t L)
 {
+    const int64_t nch = n / 12;
+    const int64_t T = (int64_t)gridDim.x * kThreads;
+    const int64_t t = logical_block() * kThreads + threadIdx.x;
+    // the bytes after the chunks: loaded now, encoded last (from registers)
+    EncTailIn tin;
+    if (t == kThreads - 1) tin = enc_tail_load(src + 12 * nch, (int)(n - 12 * nch), 12 * nch, n);
+
     __shared__ uint32_t s_tab[16];
     stage_enc_table(s_tab, tab);
     const uint8_t *a = (const uint8_t *)s_tab;
 
-    const int64_t nch = n / 12;
-    const int64_t T = (int64_t)gridDim.x * kThreads;
-    const int64_t t = logical_block() * kThreads + threadIdx.x;
     const int64_t nfull = nch / (U * T);
     const int64_t c0 = t + nfull * U * T;
     // complete rounds, then the partial round with clamped loads
@@ -232,7 +257,7 @@ __global__ __launch_bounds__(kThreads) void k_encode_wrap(const uint8_t *__restr
         run(sink);
     }
     if (t == kThreads - 1)
-        enc_scalar_wrap(src + 12 * nch, n - 12 * nch, 16 * nch, dst, L, a, !(flags & kFlagNoPad));
+        enc_tail_wrap(tin, (int)(n - 12 * nch), 16 * nch, dst, L, a, !(flags & kFlagNoPad));
 }
 
 // ------------------------------------------------ whitespace-skipping decode --
@@ -806,6 +831,20 @@ __device__ __forceinline__ void ws_round(u32x4 raw, int64_t p0, int64_t end, uin
     S.Qb += 4 * nfull;
 }
 
+// The first invalid character and the first '=' among the 16 packed codes of
+// the characters at p, each kept only if none was found before (callers pass
+// their chunks in increasing position).
+__device__ __forceinline__ void ws_firsts(u32x4 cw, int64_t p, int64_t &first_pad, int64_t &first_bad)
+{
+    const uint32_t w[4] = {cw.x, cw.y, cw.z, cw.w};
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        const uint32_t code = (w[j >> 2] >> (8 * (j & 3))) & 0xFFu;
+        if (code == kBadCode && first_bad == kNoError) first_bad = p + j;
+        else if (code == kPadCode && first_pad == kNoError) first_pad = p + j;
+    }
+}
+
 // The first invalid character and the first '=' (padded mode) of the tile
 // [base, end), by atomic minimum, as k_ws_count records them; each lane scans
 // its own 16 characters of every 1,024 (wave-cooperative).
@@ -1230,7 +1269,7 @@ __global__ __launch_bounds__(kWsBlock) void k_ws_predict(const uint8_t *__restri
                                                          int64_t *__restrict__ first_bad)
 {
     __shared__ uint32_t s_map[64];
-    __shared__ int s_first, s_ok, s_cnt, s_err;
+    __shared__ int s_first, s_ok, s_cnt;
     const int tid = threadIdx.x;
     if (blockIdx.x == 0 && tid == 0) {          // the status reset of k_ws_init
         *first_bad = kNoError;
@@ -1244,13 +1283,14 @@ __global__ __launch_bounds__(kWsBlock) void k_ws_predict(const uint8_t *__restri
         s_first = INT_MAX;
         s_ok = 1;
         s_cnt = 0;
-        s_err = 0;
     }
     __syncthreads();
     if (ntiles < 2) return;
-    // block 0: the last tile's significant characters, and whether it holds
-    // a '=' or an invalid byte (loaded first, to overlap the line search)
+    // block 0: the last tile's significant characters, and each thread's
+    // first invalid character and '=' in it (loaded first, to overlap the
+    // line search)
     const int64_t lb = (ntiles - 1) * TS;
+    int64_t my_bad = kNoError, my_pad = kNoError;
     if (blockIdx.x == 0) {
         // all of a thread's loads first (the tile is at most kMaxRounds rounds)
         u32x4 q[kMaxRounds];
@@ -1260,18 +1300,16 @@ __global__ __launch_bounds__(kWsBlock) void k_ws_predict(const uint8_t *__restri
             q[k] = p + 16 <= n ? load16<false>(src + p) : u32x4{0u, 0u, 0u, 0u};
         }
         int c = 0;
-        uint32_t err = 0;
 #pragma unroll
         for (int k = 0; k < kMaxRounds; ++k) {
             const int64_t p = lb + 16 * tid + (int64_t)k * kRound;
             if (p < n) {
                 const u32x4 cw = p + 16 <= n ? codes16(q[k], m) : ws_codes<false>(src, n, p, m);
                 c += sig_count(cw);
-                err |= cw.x | cw.y | cw.z | cw.w;
+                if ((cw.x | cw.y | cw.z | cw.w) & 0x80808080u) ws_firsts(cw, p, my_pad, my_bad);
             }
         }
         atomicAdd(&s_cnt, c);
-        if (err & 0x80808080u) s_err = 1;
     }
     // the first whitespace byte of the first 4 KiB: 16 bytes per thread
     const int64_t look = n < 4096 ? n : 4096;
@@ -1291,8 +1329,10 @@ __global__ __launch_bounds__(kWsBlock) void k_ws_predict(const uint8_t *__restri
         if (first != INT_MAX) atomicMin(&s_first, first);
     }
     __syncthreads();
-    // the last tile's first invalid byte and '=', as k_ws_count records them
-    if (blockIdx.x == 0 && s_err && tid < 64) ws_rescan(src, lb, n, m, first_pad, first_bad);
+    // the last tile's first invalid character and '=', as k_ws_count records
+    // them (after the barrier, so after the reset above)
+    if (my_bad != kNoError) atomic_min_i64(first_bad, my_bad);
+    if (my_pad != kNoError) atomic_min_i64(first_pad, my_pad);
     const int64_t L = s_first;                   // the first line's length (uniform)
     if (L == INT_MAX || L < 4 || L + 3 > look) return;
     const bool w1 = !is_sig(m[src[L + 1]]), w2 = !is_sig(m[src[L + 2]]);   // src[L] is whitespace
@@ -1313,14 +1353,36 @@ __global__ __launch_bounds__(kWsBlock) void k_ws_predict(const uint8_t *__restri
         }
     }
     __syncthreads();
-    if (!s_ok) return;
+    if (!s_ok || tid >= 64) return;              // wave 0 decides the path
+    const int64_t total = lined_before(lb, L, P) + s_cnt;
+    // the final quantum's first character, where the layout puts it
+    const int64_t ql = (flags & kFlagNoPad) ? total / 4 : (total >= 4 ? total / 4 - 1 : 0);
+    const int64_t jq = 4 * ql;
+    const int64_t at = (jq / L) * P + jq % L;
+    // The line decode checks the layout up to the separator before the final
+    // quantum, and this kernel counted the last tile, so the prefix sums are
+    // exact when the layout also holds from that separator to the last tile.
+    // That stretch is empty unless the last tile is only a few bytes long
+    // (the final quantum then starts in the tile before it); up to 64 bytes of
+    // it are checked here, one per lane: whitespace exactly at separator
+    // positions.  Neither the line decode nor the last tile's scan looks at
+    // these bytes for '=' or invalid characters (the final quantum's '=' may
+    // lie here), so they are recorded here as k_ws_count records them.
+    const int64_t from = at - sep;
+    bool lines = L % 4 == 0 && L >= 16 && lb - from <= 64;
+    if (lines && from < lb) {
+        const int64_t x = from + tid;
+        bool off = false;
+        if (x >= 0 && x < lb) {
+            const uint32_t code = m[src[x]];
+            off = is_sig(code) != (x % P < L);
+            if (code == kBadCode) atomic_min_i64(first_bad, x);
+            else if (code == kPadCode) atomic_min_i64(first_pad, x);
+        }
+        if (__ballot(off)) lines = false;
+    }
     if (tid == 0) {
-        const int64_t total = lined_before(lb, L, P) + s_cnt;
         prefix[ntiles] = total;
-        // the final quantum's first character, where the layout puts it
-        const int64_t ql = (flags & kFlagNoPad) ? total / 4 : (total >= 4 ? total / 4 - 1 : 0);
-        const int64_t jq = 4 * ql;
-        const bool lines = L % 4 == 0 && L >= 16 && (jq / L) * P + jq % L >= lb;
         *mode = lines ? (kModeLines | sep << 2 | L << 4) : kModeChecked;
     }
 }
@@ -1335,12 +1397,12 @@ __global__ __launch_bounds__(kWsBlock) void k_ws_predict(const uint8_t *__restri
 // kernel checks what the layout claims, byte by byte: every character of a
 // quantum below qlimit decodes to a value (no whitespace, '=' or invalid
 // byte), and the s bytes after every line end it passes are whitespace.
-// k_ws_predict chose this path only when quantum qlimit lies at or past the
-// last tile, so these bytes are all of the text before the last tile, which
-// k_ws_predict counted exactly: when no check fails, every guessed prefix sum
-// is exact, the output is the plain decode's, and k_ws_finish adds the final
-// quantum.  Any failure sets *mode to kModeCounted, and the counted path
-// decodes everything again.
+// k_ws_predict chose this path only when these bytes, with those it checked
+// itself from the separator before quantum qlimit up to the last tile, are
+// all of the text before the last tile, which k_ws_predict counted exactly:
+// when no check fails, every guessed prefix sum is exact, the output is the
+// plain decode's, and k_ws_finish adds the final quantum.  Any failure sets
+// *mode to kModeCounted, and the counted path decodes everything again.
 //
 // Group g covers quanta 4g - h .. 4g - h + 3 and writes 12 bytes at
 // dst + 12g - 3h; h < 128 makes that 128-byte aligned for g a multiple of 32,

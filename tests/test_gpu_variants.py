@@ -545,6 +545,66 @@ def test_skip_ws_input_ends_on_a_tile_boundary(b64, oracle):
                     assert first_mismatch(got[off:off + ref.size], ref) is None, (n, flags, cut, off)
 
 
+def test_skip_ws_last_tile_of_a_few_bytes(b64, oracle):
+    """MIME text whose last decode tile (4 KiB at these sizes) holds only 1 to
+    3 bytes, so that the final quantum starts in the tile before it: the line
+    decode still takes it (the mode word the decoder leaves in its workspace
+    names the path that ran), with the oracle's result.  (Padded MIME text has
+    an even length; a trailing LF gives the odd cases.)  A byte changed just
+    before the last tile breaks the layout there, and the decoder must leave
+    the line decode, again with the oracle's result."""
+    import torch
+    TS, LINES = 4096, 2                       # tile size at these lengths; mode word: line decode
+    x = workloads.random_bytes(workloads.SEED_BASE + 197, 200_000)
+    for flags in (SKIP_WS, SKIP_WS | NOPAD):
+        nopad = bool(flags & NOPAD)
+        want = {1: [], 2: [], 3: []}          # (payload length, trailing LF) by bytes in the last tile
+        P = workloads.MIME_LINE + 2
+        for k in range(100_000, 200_000):
+            c = (4 * k + 2) // 3 if nopad else 4 * ((k + 2) // 3)
+            size = c + 2 * ((c - 1) // workloads.MIME_LINE)
+            jq = 4 * (c // 4) if nopad else c - 4          # the final quantum's first character
+            at = (jq // workloads.MIME_LINE) * P + jq % workloads.MIME_LINE
+            for lf in (0, 1):
+                r = (size + lf) % TS
+                # only texts whose final quantum starts before the last tile
+                if r in want and len(want[r]) < 2 and at < size + lf - r:
+                    want[r].append((k, lf))
+            if all(len(v) == 2 for v in want.values()):
+                break
+        # (unpadded text has no such case with 3 bytes in the last tile)
+        assert sum(len(v) for v in want.values()) >= 4, (flags, want)
+        for r, ks in want.items():
+            for k, lf in ks:
+                text = _mime(oracle, x[:k], STD, flags & NOPAD)
+                if lf:
+                    text = np.concatenate([text, np.frombuffer(b"\n", np.uint8)])
+                assert text.size % TS == r
+                lb = text.size - r                # the last tile's first byte
+                cases = [("regular", text)]
+                for back in (1, 2, 3):
+                    u = text.copy()
+                    u[lb - back] = ord("A") if u[lb - back] in b"\r\n" else ord(" ")
+                    cases.append((f"changed at tile end - {back}", u))
+                for label, u in cases:
+                    say("ws last tile of", r, "bytes, payload", k, "LF", lf, "flags", flags, label)
+                    ref_raw = oracle.decode_mode_raw(u, STD, flags)
+                    ntiles = -(-u.size // TS)
+                    ws = torch.zeros(b64.workspace_size(u.size, flags), dtype=torch.uint8, device="cuda")
+                    out = torch.zeros(b64.decoded_max_len(u.size, flags) + 8, dtype=torch.uint8,
+                                      device="cuda")
+                    _, st = b64.decode_async(_dev(u), STD, out=out, flags=flags, workspace=ws)
+                    s = to_host(st).tolist()
+                    if ref_raw >= 0:
+                        ref, _ = oracle.decode_mode(u, STD, flags)
+                        assert s == [ref.size, -1], (label, s)
+                        assert first_mismatch(to_host(out)[:ref.size], ref) is None, label
+                    else:
+                        assert s == [-1, ~ref_raw], (label, s, ~ref_raw)
+                    mode = int(to_host(ws.view(torch.int64))[ntiles + 2])
+                    assert ((mode & 3) == LINES) == (label == "regular"), (label, mode)
+
+
 def test_skip_ws_round_trip_many_tiles(b64, oracle):
     """A 1.3 GB payload as MIME text (about 1.78 GB, more than 49,152 tiles of
     32 KiB, so the tile scan takes two passes): the whitespace-skipping decode
