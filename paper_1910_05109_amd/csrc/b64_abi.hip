@@ -75,19 +75,22 @@ DecMap make_dec_ws(const char *alphabet, bool nopad)
 // (HBM streaming).  The batched
 // and fused operations find their total size only on the device and always
 // take the last bucket's shape.  The defaults are the autotuner's choices on
-// MI355X (python -m paper_1910_05109_amd.tune: inputs of 16 KiB, 256 KiB,
-// 4 MiB, 48 MiB and 1 GiB).
+// MI355X (python -m paper_1910_05109_amd.tune: each shape timed on three
+// sizes spread over each of the first four buckets -- 4 / 16 / 48 KiB,
+// 96 / 256 / 768 KiB, 2 / 4 / 12 MiB, 24 / 48 / 96 MiB -- and on 1 GiB for
+// the last; the lowest mean time relative to the fastest shape at each size,
+// averaged over two sweeps where the code was the same in both).
 constexpr int kOps = 8;
 constexpr int kBuckets = 5;
 constexpr int64_t kBucketLimit[kBuckets - 1] = {64 << 10, 1 << 20, 16 << 20, 128 << 20};
 Shape g_shape[kOps][kBuckets] = {
-    {{1, 32, 0}, {1, 4, 1}, {2, 16, 0}, {2, 32, 0}, {8, 1, 1}},   // encode
-    {{1, 8, 1}, {1, 64, 1}, {1, 8, 0}, {1, 4, 0}, {2, 2, 1}},     // decode
+    {{1, 4, 0}, {1, 4, 0}, {2, 4, 0}, {1, 8, 0}, {8, 1, 1}},      // encode
+    {{1, 2, 1}, {1, 32, 0}, {1, 4, 0}, {1, 4, 0}, {2, 2, 1}},     // decode
     {{2, 2, 1}, {2, 2, 1}, {2, 2, 1}, {2, 2, 1}, {2, 2, 1}},      // encode_batch
     {{4, 16, 1}, {4, 16, 1}, {4, 16, 1}, {4, 16, 1}, {4, 16, 1}}, // decode_batch
-    {{1, 1, 1}, {1, 8, 1}, {2, 32, 0}, {1, 4, 1}, {2, 2, 1}},     // validate
-    {{1, 16, 1}, {1, 4, 0}, {1, 16, 0}, {1, 8, 0}, {8, 1, 0}},    // line-wrapped encode
-    {{1, 2, 0}, {4, 4, 0}, {2, 8, 0}, {4, 2, 1}, {2, 8, 1}},      // whitespace-skipping decode
+    {{2, 64, 0}, {2, 32, 0}, {1, 4, 0}, {1, 4, 0}, {2, 2, 1}},    // validate
+    {{1, 8, 0}, {1, 64, 0}, {1, 8, 0}, {2, 64, 0}, {8, 1, 0}},    // line-wrapped encode
+    {{2, 12, 0}, {2, 8, 0}, {2, 16, 0}, {1, 2, 1}, {2, 8, 1}},    // whitespace-skipping decode
     {{2, 64, 1}, {2, 64, 1}, {2, 64, 1}, {2, 64, 1}, {2, 64, 1}}, // fused decode
 };
 std::mutex g_mu;

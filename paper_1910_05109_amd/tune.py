@@ -11,11 +11,15 @@ below 16 MiB, below 128 MiB, larger); the batched and fused operations use
 the last bucket only.
 
 The tuner times every shape of a grid with HIP events on the launch stream
-on one input per bucket -- below 16 MiB per call replayed from a HIP graph
-(the device time, which the host's launch cost would otherwise hide), above
-it per call in groups of back-to-back calls -- keeps the fastest, applies it
-with b64_tune_set_bucket and stores it in a JSON cache keyed by device,
-operation and bucket.  The package applies
+on three input sizes spread over each bucket (one for the last) -- below
+16 MiB per call replayed from a HIP graph (the device time, which the host's
+launch cost would otherwise hide), above it per call in groups of
+back-to-back calls.  A bucket spans up to 16x in size and the best shape
+moves within it (more workgroups pay off at its small end, fewer at its
+large end), so each shape is scored by its time relative to the fastest
+shape at each size, averaged over the sizes, and the lowest score is kept.
+It is applied with b64_tune_set_bucket and stored in a JSON cache keyed by
+device, operation and bucket.  The package applies
 the cache of the current device when it loads the library (load()), from
 $B64HIP_TUNE_CACHE or ~/.cache/b64hip/tune.json; B64HIP_TUNE_CACHE=off
 skips it.  Every shape the grid holds is covered by the launch-shape parity
@@ -39,8 +43,10 @@ from . import (BUCKETS, OPS, SKIP_WS, STD, decode_async, decode_batch, decode_f3
 UNROLLS = (1, 2, 4, 8)
 BLOCKS_PER_CU = (1, 2, 4, 8, 16, 32, 64)
 NONTEMPORAL = (0, 1)
-# one representative input size per bucket (bytes of the operation's input)
-BUCKET_BYTES = (16 << 10, 256 << 10, 4 << 20, 48 << 20, 1 << 30)
+# input sizes timed per bucket (bytes of the operation's input), spread over
+# the bucket's range: < 64 KiB, < 1 MiB, < 16 MiB, < 128 MiB, larger
+BUCKET_SIZES = ((4 << 10, 16 << 10, 48 << 10), (96 << 10, 256 << 10, 768 << 10),
+                (2 << 20, 4 << 20, 12 << 20), (24 << 20, 48 << 20, 96 << 20), (1 << 30,))
 # operations whose total size is known only on the device: last bucket only
 LAST_BUCKET_ONLY = ("encode_batch", "decode_batch", "decode_f32_bf16")
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "b64hip", "tune.json")
@@ -180,44 +186,52 @@ def buckets_of(op: str) -> tuple[int, ...]:
 
 def tune_op(op: str, bucket: int, nbytes: int | None = None, reps: int = 10, unrolls=UNROLLS,
             bpcs=BLOCKS_PER_CU, nts=NONTEMPORAL, verbose: bool = True) -> dict:
-    """Time every shape of the grid for `op` in size `bucket` (on an input of
-    `nbytes`, by default the bucket's representative size), apply the fastest
-    and return it with the whole grid."""
+    """Time every shape of the grid for `op` in size `bucket` (on inputs of
+    the bucket's sizes, or of `nbytes` alone), apply the shape with the lowest
+    mean time relative to the fastest shape at each size, and return it with
+    the whole grid."""
     import torch
     unrolls = GRIDS.get(op, {}).get("unrolls", unrolls)
     bpcs = GRIDS.get(op, {}).get("bpcs", bpcs)
-    nbytes = BUCKET_BYTES[bucket] if nbytes is None else nbytes
-    fn = _workload(torch, op, nbytes)
+    sizes = BUCKET_SIZES[bucket] if nbytes is None else (nbytes,)
     old = tune_get(op, bucket)
-    results = []
+    times = {}                                   # shape -> ms per size
     # the whitespace-skipping decode's shape is the multi-launch path's: small
     # texts would otherwise take the one-workgroup path, which has no shape
     small_old = tune_ws_small_max(0) if op == "decode_ws" else None
     try:
-        _sweep(torch, op, bucket, fn, reps, unrolls, bpcs, nts, nbytes, results, verbose)
+        for size in sizes:
+            fn = _workload(torch, op, size)
+            try:
+                _sweep(torch, op, bucket, fn, reps, unrolls, bpcs, nts, size, times, verbose)
+            finally:
+                del fn
+                torch.cuda.empty_cache()
     finally:
         if small_old is not None:
             tune_ws_small_max(small_old)
-    results.sort()
-    ms, u, b, nt = results[0]
+    best_at = [min(ms[i] for ms in times.values()) for i in range(len(sizes))]
+    scored = sorted((statistics.fmean(t / b for t, b in zip(ms, best_at)), sh, ms)
+                    for sh, ms in times.items())
+    score, (u, b, nt), ms = scored[0]
     tune_set(op, u, b, nt, bucket=bucket)
-    del fn
-    torch.cuda.empty_cache()
-    return {"unroll": u, "blocks_per_cu": b, "nontemporal": nt, "ms": ms, "bytes": nbytes,
-            "previous": list(old), "grid": [[r[1], r[2], r[3], r[0]] for r in results]}
+    return {"unroll": u, "blocks_per_cu": b, "nontemporal": nt, "ms": list(ms),
+            "bytes": list(sizes), "score": score, "best_ms": best_at, "previous": list(old),
+            "previous_ms": list(times.get(tuple(old), [])),
+            "grid": [[sh[0], sh[1], sh[2], sc] + list(t) for sc, sh, t in scored]}
 
 
-def _sweep(torch, op, bucket, fn, reps, unrolls, bpcs, nts, nbytes, results, verbose):
+def _sweep(torch, op, bucket, fn, reps, unrolls, bpcs, nts, nbytes, times, verbose):
     for nt in nts:
         for u in unrolls:
             for b in bpcs:
                 tune_set(op, u, b, nt, bucket=bucket)
                 # small calls: device time from graph replays; large ones: stream timing
                 ms = _graph_time(torch, fn, reps) if nbytes < (16 << 20) else _time(torch, fn, reps)
-                results.append((ms, u, b, nt))
+                times.setdefault((u, b, nt), []).append(ms)
                 if verbose:
-                    print(f"[tune] {op:15s} bucket={bucket} unroll={u} blocks/cu={b:2d} nt={nt}: "
-                          f"{ms * 1e3:9.2f} us", flush=True)
+                    print(f"[tune] {op:15s} bucket={bucket} bytes={nbytes} unroll={u} "
+                          f"blocks/cu={b:2d} nt={nt}: {ms * 1e3:9.2f} us", flush=True)
 
 
 # MIME text sizes at which the whitespace-skipping decode's two paths are
@@ -332,10 +346,11 @@ def main():
                 continue
             r = tune_op(op, bucket, reps=args.reps)
             found.setdefault(op, {})[bucket] = r
+            us = " / ".join(f"{m * 1e3:.2f}" for m in r["ms"])
             print(f"[tune] best {op} bucket {bucket}: unroll={r['unroll']} "
-                  f"blocks/cu={r['blocks_per_cu']} nt={r['nontemporal']} {r['ms'] * 1e3:.2f} us",
-                  flush=True)
-    keys = ("unroll", "blocks_per_cu", "nontemporal", "ms", "bytes")
+                  f"blocks/cu={r['blocks_per_cu']} nt={r['nontemporal']} {us} us "
+                  f"(x{r['score']:.3f} of the best per size)", flush=True)
+    keys = ("unroll", "blocks_per_cu", "nontemporal", "ms", "bytes", "score")
     entries = {op: {b: {k: r[k] for k in keys} for b, r in per.items()}
                for op, per in found.items()}
     if not args.no_ws_guess and "decode_ws" in args.ops:
