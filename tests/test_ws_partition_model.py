@@ -329,28 +329,36 @@ def test_line_decode_split(L, s):
 
 def test_line_decode_eligibility_is_safe():
     """When the guess picks the line decode (L a multiple of 4, at least 16,
-    and the final quantum at or past the last tile as far as the guessed total
-    goes), the bytes the line decode checks (every character of a quantum
-    below qlimit and the separator after every line end it passes) cover all
-    of the text before the last tile.  So either they all fit the layout and
-    the guessed total is the true one, or one of them does not and the kernel
-    falls back.  Regular texts followed by whitespace runs of every size
-    around a tile, some with an extra space inside, and tiles of 4 KiB."""
+    and at most 64 bytes from the separator before the final quantum, as far
+    as the guessed total goes, to the last tile), the bytes the line decode
+    checks (every character of a quantum below qlimit and the separator after
+    every line end it passes) and the bytes k_ws_predict checks itself (that
+    stretch before the last tile, against the layout) cover all of the text
+    before the last tile.  So either they all fit the layout and the guessed
+    total is the true one, or one of them does not and the kernel falls back.
+    Regular texts followed by whitespace runs of every size around a tile,
+    texts whose last tile holds 1 to 3 bytes, some with an extra space
+    inside, and tiles of 4 KiB."""
     g = workloads.rng(workloads.SEED_BASE + 199)
     alpha = b"ABCDEFGHIJKLMNOPQRSTUVWXYZabcdefghijklmnopqrstuvwxyz0123456789+/"
-    picked = fell_back = 0
-    for trial in range(300):
+    picked = fell_back = short_last = 0
+    ts = 4096
+    for trial in range(400):
         L = int(g.choice([16, 20, 64, 76]))
         s = int(g.integers(1, 3))
         sep = b"\r\n"[2 - s:]
         n_sig = int(g.integers(1500, 4000)) * 4
+        if trial % 4 == 1:                      # a last tile of 1 to 3 bytes
+            while (n_sig + s * ((n_sig - 1) // L)) % ts not in (1, 2, 3):
+                n_sig += 4
         body = bytes(alpha[int(c)] for c in g.integers(0, 64, n_sig))
         text = sep.join(body[i:i + L] for i in range(0, n_sig, L))
-        text += b" " * int(g.choice([0, 1, 2, 100, 4000, 4096, 5000, 9000, 20000]))
+        if trial % 4 != 1:
+            text += b" " * int(g.choice([0, 1, 2, 3, 100, 4000, 4093, 4096, 5000, 9000, 20000]))
         if trial % 3 == 0:                      # a break in the layout
-            at = int(g.integers(0, len(text) // 2))
+            at = int(g.integers(0, len(text) // 2)) if trial % 2 else len(text) - int(g.integers(1, 80))
             text = text[:at] + b" " + text[at:]
-        n, P, ts = len(text), L + s, 4096
+        n, P = len(text), L + s
         ntiles = (n + ts - 1) // ts
         if ntiles < 2:
             continue
@@ -358,9 +366,12 @@ def test_line_decode_eligibility_is_safe():
         total = lined_before(lb, L, P) + sum(1 for c in text[lb:] if c not in WS)
         ql = total // 4 - 1
         jq = 4 * ql
-        if not ((jq // L) * P + jq % L >= lb):
+        at_q = (jq // L) * P + jq % L
+        frm = at_q - s
+        if lb - frm > 64:
             continue
         picked += 1
+        short_last += frm < lb
         checked = {}
         for j in range(4 * ql):
             p = (j // L) * P + j % L
@@ -368,6 +379,8 @@ def test_line_decode_eligibility_is_safe():
             if j % L == L - 1:
                 for k in range(s):
                     checked[p + 1 + k] = "sep"
+        for p in range(max(frm, 0), lb):        # k_ws_predict's own check
+            checked[p] = "char" if p % P < L else "sep"
         assert all(p in checked for p in range(lb)), (L, s, trial)
         fits = all(p < n and ((text[p] in WS) == (kind == "sep")) for p, kind in checked.items())
         true_total = sum(1 for c in text if c not in WS)
@@ -375,4 +388,4 @@ def test_line_decode_eligibility_is_safe():
             assert total == true_total, (L, s, trial)
         else:
             fell_back += 1
-    assert picked > 100 and fell_back > 0
+    assert picked > 100 and fell_back > 0 and short_last > 20, (picked, fell_back, short_last)
