@@ -210,15 +210,27 @@ def tune_op(op: str, bucket: int, nbytes: int | None = None, reps: int = 10, unr
     finally:
         if small_old is not None:
             tune_ws_small_max(small_old)
-    best_at = [min(ms[i] for ms in times.values()) for i in range(len(sizes))]
-    scored = sorted((statistics.fmean(t / b for t, b in zip(ms, best_at)), sh, ms)
-                    for sh, ms in times.items())
+    scored, best_at = rank_shapes(times)
     score, (u, b, nt), ms = scored[0]
     tune_set(op, u, b, nt, bucket=bucket)
     return {"unroll": u, "blocks_per_cu": b, "nontemporal": nt, "ms": list(ms),
             "bytes": list(sizes), "score": score, "best_ms": best_at, "previous": list(old),
             "previous_ms": list(times.get(tuple(old), [])),
             "grid": [[sh[0], sh[1], sh[2], sc] + list(t) for sc, sh, t in scored]}
+
+
+def rank_shapes(times: dict) -> tuple[list, list]:
+    """Shapes ranked by their mean time relative to the fastest shape at each
+    size: `times` maps a shape to its times at the same sizes, in order.
+    Returns ([(score, shape, times)], fastest time at each size), best first;
+    ties go to the smaller shape tuple."""
+    nsizes = len(next(iter(times.values())))
+    if any(len(ms) != nsizes for ms in times.values()):
+        raise ValueError("every shape needs a time at every size")
+    best_at = [min(ms[i] for ms in times.values()) for i in range(nsizes)]
+    scored = sorted((statistics.fmean(t / b for t, b in zip(ms, best_at)), sh, list(ms))
+                    for sh, ms in times.items())
+    return scored, best_at
 
 
 def _sweep(torch, op, bucket, fn, reps, unrolls, bpcs, nts, nbytes, times, verbose):
