@@ -719,10 +719,11 @@ def run_variants(args, torch, b64):
     decode (one read of the text); the same text with one space inserted near
     its start takes the counted path, which reads the text twice by design
     (count pass, then decode pass)."""
-    n = workloads.SINGLE_1GIB[0]
+    n = args.variants_bytes or workloads.SINGLE_1GIB[0]
     L = workloads.MIME_LINE
     x = torch.from_numpy(workloads.random_bytes(workloads.SEED_BASE + 2, n)).cuda()
-    res = {"workload": "1 GiB payload: unpadded; MIME text (76-char lines, CR LF)", "n_bytes": n}
+    size = "1 GiB payload" if n == workloads.SINGLE_1GIB[0] else f"{n}-byte payload"
+    res = {"workload": f"{size}: unpadded; MIME text (76-char lines, CR LF)", "n_bytes": n}
     # unpadded
     Nn = b64.encoded_len(n, b64.NOPAD)
     tn = torch.empty(Nn, dtype=torch.uint8, device="cuda")
@@ -830,6 +831,8 @@ def main():
                     choices=["single", "ceiling", "small", "sweep", "batch", "serve", "validate",
                              "host", "variants", "fused"])
     ap.add_argument("--chunk-mib", type=int, default=64)
+    ap.add_argument("--variants-bytes", type=int, default=0,
+                    help="variants: payload bytes (default: the 1 GiB workload)")
     ap.add_argument("--host-depth", type=int, default=3, help="host pipeline: chunks in flight")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-extras", action="store_true",
