@@ -35,8 +35,8 @@
 // word.  For lines whose length is a multiple of 4 (16 or more), k_ws_lines
 // reads every quantum at its closed-form position and checks each byte
 // against the layout; other line lengths take k_ws_decode<.., true>, which
-// decodes on the guessed sums and checks every tile's count, with k_ws_check
-// covering the tiles it leaves.  A failed check sets the mode word back to
+// decodes on the guessed sums and checks every tile's count (the tiles with
+// no quantum of their own are only counted).  A failed check sets the mode word back to
 // the counted path, and k_ws_count, k_ws_scan and k_ws_decode then run as
 // above (every launch returns at once unless the mode word names its path).  Tiles are dealt grid-stride (to blocks in
 // k_ws_count, to waves in k_ws_decode), so the grid streams through one
@@ -272,7 +272,7 @@ constexpr int kMaxRounds = 8;            // rounds per tile at most (tiles of 4 
 
 // The mode word in the decode workspace: kModeCounted, the counted path
 // (k_ws_count, k_ws_scan, k_ws_decode) runs; kModeChecked, k_ws_decode<.., true>
-// and k_ws_check run on guessed prefix sums; kModeLines | s << 2 | L << 4,
+// runs on guessed prefix sums; kModeLines | s << 2 | L << 4,
 // k_ws_lines runs for lines of L significant characters and s separator
 // bytes.  A failed check sets it back to kModeCounted.
 constexpr int64_t kModeCounted = 0, kModeChecked = 1, kModeLines = 2;
@@ -870,9 +870,9 @@ __device__ void ws_rescan(const uint8_t *src, int64_t base, int64_t end, const u
     }
 }
 
-// k_ws_check's work on a tile: count its significant characters against the
-// guessed count C (unless it is the last tile) and record its first invalid
-// character and '=' (wave-cooperative).
+// The checked decode's work on a tile with no quantum of its own: count its
+// significant characters against the guessed count C (when check_count) and
+// record its first invalid character and '=' (wave-cooperative).
 __device__ void ws_check_tile(const uint8_t *src, int64_t base, int64_t end, const uint8_t *m,
                               bool check_count, int64_t C, int64_t *mode, int64_t *first_pad,
                               int64_t *first_bad)
@@ -909,8 +909,9 @@ __device__ void ws_check_tile(const uint8_t *src, int64_t base, int64_t end, con
 // (*mode == kModeChecked; it returns at once otherwise).  Every tile it decodes, but the
 // last, compares the significant characters it saw with its guessed count,
 // and clears *mode on a difference or on any '=' or invalid character (the
-// counting path then finds them).  The last tile and the tiles with no
-// quantum of their own are left to k_ws_check.  When every count holds, the
+// counting path then finds them).  Tiles with no quantum of their own are
+// only counted and scanned (ws_check_tile), and the last tile is
+// k_ws_predict's.  When every count holds, the
 // guessed sums are the exact ones, so its output is the output of the plain
 // decode on exact sums.  Without CHECK the kernel runs only when *mode is 0
 // (no guess, or a check failed).
@@ -952,7 +953,14 @@ __global__ __launch_bounds__(kWsBlock) void k_ws_decode(const uint8_t *__restric
         const int64_t K0 = prefix[tile], C = prefix[tile + 1] - K0;
         const int64_t skip = (4 - (K0 & 3)) & 3;
         const int64_t Q0 = (K0 + skip) >> 2;
-        if (C <= skip || Q0 >= qlimit) continue;    // wave-uniform: no quantum of its own
+        if (C <= skip || Q0 >= qlimit) {            // wave-uniform: no quantum of its own
+            // checked: such a tile (but the last, which k_ws_predict scanned)
+            // is counted against its guess and scanned for '=' and invalid
+            // characters here, as k_ws_count would
+            if (CHECK && tile + 1 < ntiles)
+                ws_check_tile(src, base, end, m, true, C, mode, first_pad, first_bad);
+            continue;
+        }
         const int64_t h = (Q0 + 3 * dmod) & 3;
         // what the last quantum may borrow from the next tile, fetched early
         const bool has_next = tile + 1 < ntiles;
@@ -1037,49 +1045,6 @@ __global__ __launch_bounds__(kWsBlock) void k_ws_decode(const uint8_t *__restric
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    }
-}
-
-// k_ws_check: after the checked decode (only when *mode is still kModeChecked), the
-// tiles it left other than the last (k_ws_predict scans that one): those with
-// no quantum of their own are counted against their guessed counts and
-// scanned for the first invalid character and '=', as k_ws_count would.  A wave looks at
-// 64 tiles at once, one per lane, and works through the ones that qualify.
-__global__ __launch_bounds__(kWsBlock) void k_ws_check(const uint8_t *__restrict__ src, int64_t n,
-                                                       DecMap map, const int64_t *__restrict__ prefix,
-                                                       int64_t TS, uint32_t flags,
-                                                       int64_t *__restrict__ mode,
-                                                       int64_t *__restrict__ first_pad,
-                                                       int64_t *__restrict__ first_bad)
-{
-    __shared__ uint32_t s_map[64];
-    if (*mode != kModeChecked) return;            // uniform
-    stage_dec_map(s_map, map);
-    const uint8_t *m = (const uint8_t *)s_map;
-    const int64_t ntiles = ws_tiles(n, TS);
-    if (ntiles == 0) return;
-    const int64_t total = prefix[ntiles];
-    const bool nopad = (flags & kFlagNoPad) != 0;
-    const int64_t qlimit = nopad ? total / 4 : (total >= 4 ? total / 4 - 1 : 0);
-    const int lane = threadIdx.x & 63;
-    const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-    const int64_t nwaves = (int64_t)gridDim.x * (kWsBlock / 64);
-    for (int64_t t0 = ((int64_t)blockIdx.x * (kWsBlock / 64) + wv) * 64; t0 < ntiles; t0 += nwaves * 64) {
-        const int64_t t = t0 + lane;
-        int64_t C = 0;
-        bool want = false;
-        if (t < ntiles) {
-            const int64_t K0 = prefix[t];
-            C = prefix[t + 1] - K0;
-            const int64_t skip = (4 - (K0 & 3)) & 3;
-            want = t + 1 < ntiles && (C <= skip || ((K0 + skip) >> 2) >= qlimit);
-        }
-        for (uint64_t b = __builtin_amdgcn_ballot_w64(want); b; b &= b - 1) {
-            const int l = __builtin_ctzll(b);
-            const int64_t tile = t0 + l;
-            const int64_t base = tile * TS, end = base + TS < n ? base + TS : n;
-            ws_check_tile(src, base, end, m, true, readlane_i64(C, l), mode, first_pad, first_bad);
-        }
     }
 }
 
@@ -1898,9 +1863,6 @@ hipError_t launch_decode_ws(const uint8_t *src, int64_t n, uint8_t *dst, bool wr
         launch_ws_lines(src, n, dst, map, prefix, TS, flags, mode, cus, sh.nt, stream);
         launch_ws_decode_shape<true>(src, n, dst, map, prefix, TS, ntiles, flags, mode, first_pad,
                                      first_bad, sh, cus, stream);
-        const int64_t cgrid = std::min<int64_t>((ntiles + kWsBlock - 1) / kWsBlock, (int64_t)cus);
-        hipLaunchKernelGGL(k_ws_check, dim3(cgrid), dim3(kWsBlock), 0, stream, src, n, map, prefix, TS,
-                           flags, mode, first_pad, first_bad);
     }
     int64_t grid = (int64_t)cus * sh.bpc;
     if (grid > ntiles) grid = ntiles;
