@@ -831,18 +831,24 @@ __device__ __forceinline__ void ws_round(u32x4 raw, int64_t p0, int64_t end, uin
     S.Qb += 4 * nfull;
 }
 
-// The first invalid character and the first '=' among the 16 packed codes of
-// the characters at p, each kept only if none was found before (callers pass
-// their chunks in increasing position).
-__device__ __forceinline__ void ws_firsts(u32x4 cw, int64_t p, int64_t &first_pad, int64_t &first_bad)
+// The indexes (0..15) of the first invalid character and the first '=' among
+// the 16 packed codes of a chunk, as bad | pad << 8, 0xFF for none.  Only
+// bytes with bit 7 set are looked at, lowest first.
+__device__ __forceinline__ uint32_t ws_firsts16(u32x4 cw)
 {
+    uint32_t bad = 0xFFu, pad = 0xFFu;
     const uint32_t w[4] = {cw.x, cw.y, cw.z, cw.w};
 #pragma unroll
-    for (int j = 0; j < 16; ++j) {
-        const uint32_t code = (w[j >> 2] >> (8 * (j & 3))) & 0xFFu;
-        if (code == kBadCode && first_bad == kNoError) first_bad = p + j;
-        else if (code == kPadCode && first_pad == kNoError) first_pad = p + j;
+    for (int d = 3; d >= 0; --d) {
+        for (uint32_t hi = w[d] & 0x80808080u; hi; hi &= hi - 1) {
+            const uint32_t b = (uint32_t)__builtin_ctz(hi) >> 3;
+            const uint32_t code = (w[d] >> (8 * b)) & 0xFFu;
+            const uint32_t i = 4 * (uint32_t)d + b;
+            if (code == kBadCode && i < bad) bad = i;
+            else if (code == kPadCode && i < pad) pad = i;
+        }
     }
+    return bad | pad << 8;
 }
 
 // The first invalid character and the first '=' (padded mode) of the tile
@@ -872,8 +878,9 @@ __device__ void ws_rescan(const uint8_t *src, int64_t base, int64_t end, const u
 
 // The checked decode's work on a tile with no quantum of its own: count its
 // significant characters against the guessed count C (when check_count) and
-// record its first invalid character and '=' (wave-cooperative).
-__device__ void ws_check_tile(const uint8_t *src, int64_t base, int64_t end, const uint8_t *m,
+// record its first invalid character and '=' (wave-cooperative).  Inlined: a
+// call left 8 bytes of stack per lane in the checked decode and was no faster.
+__device__ __forceinline__ void ws_check_tile(const uint8_t *src, int64_t base, int64_t end, const uint8_t *m,
                               bool check_count, int64_t C, int64_t *mode, int64_t *first_pad,
                               int64_t *first_bad)
 {
@@ -1255,7 +1262,7 @@ __global__ __launch_bounds__(kWsBlock) void k_ws_predict(const uint8_t *__restri
     // first invalid character and '=' in it (loaded first, to overlap the
     // line search)
     const int64_t lb = (ntiles - 1) * TS;
-    int64_t my_bad = kNoError, my_pad = kNoError;
+    int my_bad = INT_MAX, my_pad = INT_MAX;      // offsets from lb
     if (blockIdx.x == 0) {
         // all of a thread's loads first (the tile is at most kMaxRounds rounds)
         u32x4 q[kMaxRounds];
@@ -1271,7 +1278,13 @@ __global__ __launch_bounds__(kWsBlock) void k_ws_predict(const uint8_t *__restri
             if (p < n) {
                 const u32x4 cw = p + 16 <= n ? codes16(q[k], m) : ws_codes<false>(src, n, p, m);
                 c += sig_count(cw);
-                if ((cw.x | cw.y | cw.z | cw.w) & 0x80808080u) ws_firsts(cw, p, my_pad, my_bad);
+                if ((cw.x | cw.y | cw.z | cw.w) & 0x80808080u) {
+                    // rounds go in increasing position: the first found is the lane's first
+                    const uint32_t f = ws_firsts16(cw);
+                    const int off = (int)(p - lb);
+                    if (my_bad == INT_MAX && (f & 0xFFu) != 0xFFu) my_bad = off + (int)(f & 0xFFu);
+                    if (my_pad == INT_MAX && (f >> 8) != 0xFFu) my_pad = off + (int)(f >> 8);
+                }
             }
         }
         atomicAdd(&s_cnt, c);
@@ -1296,8 +1309,8 @@ __global__ __launch_bounds__(kWsBlock) void k_ws_predict(const uint8_t *__restri
     __syncthreads();
     // the last tile's first invalid character and '=', as k_ws_count records
     // them (after the barrier, so after the reset above)
-    if (my_bad != kNoError) atomic_min_i64(first_bad, my_bad);
-    if (my_pad != kNoError) atomic_min_i64(first_pad, my_pad);
+    if (my_bad != INT_MAX) atomic_min_i64(first_bad, lb + my_bad);
+    if (my_pad != INT_MAX) atomic_min_i64(first_pad, lb + my_pad);
     const int64_t L = s_first;                   // the first line's length (uniform)
     if (L == INT_MAX || L < 4 || L + 3 > look) return;
     const bool w1 = !is_sig(m[src[L + 1]]), w2 = !is_sig(m[src[L + 2]]);   // src[L] is whitespace
