@@ -44,6 +44,34 @@ def assemble(src: str, workdir: str) -> str:
         return f.read()
 
 
+def scratch_sizes(threads: int = 4) -> dict:
+    """Scratch memory per lane of every kernel in the library's sources,
+    {mangled kernel name: bytes}, from the device assembly's kernel
+    descriptors (.amdhsa_private_segment_fixed_size).  Scratch is where the
+    compiler puts what does not fit in registers or is indexed dynamically;
+    every access to it is a round trip to memory."""
+    from concurrent.futures import ThreadPoolExecutor
+    srcs = sorted(f for f in os.listdir(CSRC) if f.endswith(".hip"))
+    flags = [f for f in FLAGS if f not in ("-shared", "-fPIC")]
+
+    def one(src: str, wd: str) -> str:
+        out = os.path.join(wd, src + ".s")
+        subprocess.check_call([hipcc(), *flags, "--offload-device-only", "-S",
+                               os.path.join(CSRC, src), "-o", out],
+                              cwd=wd, stdout=subprocess.DEVNULL, stderr=subprocess.DEVNULL)
+        with open(out) as f:
+            return f.read()
+
+    sizes = {}
+    with tempfile.TemporaryDirectory() as wd, ThreadPoolExecutor(threads) as pool:
+        for asm in pool.map(lambda s: one(s, wd), srcs):
+            for m in re.finditer(r"^\s*\.amdhsa_kernel (\S+)(.*?)^\s*\.end_amdhsa_kernel", asm,
+                                 flags=re.M | re.S):
+                fixed = re.search(r"\.amdhsa_private_segment_fixed_size (\d+)", m.group(2))
+                sizes[m.group(1)] = int(fixed.group(1)) if fixed else 0
+    return sizes
+
+
 def kernel_body(asm: str, fragment: str) -> list[str]:
     m = re.search(r"^(_Z\S*" + re.escape(fragment) + r"\S*):[^\n]*$", asm, flags=re.M)
     if not m:

@@ -38,3 +38,15 @@ def test_compute_per_block_within_bound(rows):
     assert rows["k_encode<4, nt>"]["compute_instr_per_64B"] < 6.0
     assert rows["k_decode<8, nt>"]["compute_instr_per_64B"] < 5.0
     assert rows["k_validate<8, nt>"]["compute_instr_per_64B"] < 3.5
+
+
+def test_no_kernel_uses_scratch_memory():
+    # A kernel's scratch is per-lane memory the compiler falls back to (an
+    # indexed local array, state it cannot keep in registers); each access is
+    # a memory round trip and its writes are HBM traffic.  One slipped into
+    # the whitespace decode's prediction once and tripled its writes.
+    sizes = isa_count.scratch_sizes()
+    assert len(sizes) > 50, len(sizes)             # the descriptors were found
+    assert any("k_ws_predict" in k for k in sizes) and any("k_encode" in k for k in sizes)
+    used = {k: v for k, v in sizes.items() if v}
+    assert not used, used
