@@ -384,6 +384,70 @@ def run_small(args, torch, b64):
         r = b64.decode(text, out=dec)
     res["decode_blocking_us"] = (time.perf_counter() - t0) / 200 * 1e6
     assert r[1] is None
+    # Bursts of 200 back-to-back calls at 16 KiB, 256 KiB and 3 MiB of raw
+    # bytes -- encode, decode, torch's device copy of the text and the
+    # decode-pattern yardstick (decode's access pattern and grid, no
+    # arithmetic) -- whose kernel durations a kernel trace of this run gives.
+    import ctypes
+    from paper_1910_05109_amd import _lib, stream_ptr
+    L = _lib.load()
+    sp = stream_ptr()
+    bursts = {}
+    for m in (16 << 10, 256 << 10, n):
+        Nm = 4 * ((m + 2) // 3)
+        xm, tm = x[:m], text[:Nm]
+        cp = torch.empty(Nm, dtype=torch.uint8, device="cuda")
+        fns = {"encode": lambda: b64.encode(xm, out=tm),
+               "decode": lambda: b64.decode_async(tm, out=dec, status=st),
+               "copy": lambda: cp.copy_(tm),
+               "yardstick_decode_pattern": lambda: L.b64_yardstick(
+                   YARD_KINDS["decode_pattern"], tm.data_ptr(), cp.data_ptr(), Nm // 16, sp)}
+        row = {}
+        for name, fn in fns.items():
+            fn()                                  # a kernel's first launch loads its code
+            torch.cuda.synchronize()
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            for _ in range(200):
+                fn()
+            b.record()
+            torch.cuda.synchronize()
+            row[name + "_us_per_call"] = a.elapsed_time(b) * 1e3 / 200
+        b64.encode(xm, out=tm)
+        bursts[str(m)] = row
+    res["bursts"] = bursts
+    # Host time per call with the GPU idle between groups: 1,000 calls on 48
+    # bytes back to back, best of 5 (the device finishes a call sooner than
+    # the host issues the next, so this is the host's cost).
+    m = 48
+    xm, tm = x[:m], text[:64]
+    b64.encode(xm, out=tm)
+    a_std = b64._alpha(b64.STD)
+    tp, dp, stp = tm.data_ptr(), dec.data_ptr(), st.data_ptr()
+    cp = torch.empty(64, dtype=torch.uint8, device="cuda")
+    calls = {"decode_async": lambda: b64.decode_async(tm, out=dec, status=st),
+             "encode": lambda: b64.encode(xm, out=tm),
+             "validate_async": lambda: b64.validate_async(tm, status=st),
+             "copy_": lambda: cp.copy_(tm),
+             "raw_decode_async": lambda: L.b64_decode_async(tp, 64, dp, stp, stp + 8, a_std, sp)}
+    if _lib.fast is not None:
+        calls["fast_decode_async"] = lambda: _lib.fast.decode_async(
+            tp, 64, dp, stp, stp + 8, ctypes.addressof(a_std), sp)
+    host = {}
+    for name, fn in calls.items():
+        for _ in range(500):
+            fn()
+        torch.cuda.synchronize()
+        best = []
+        for _ in range(5):
+            t0 = time.perf_counter()
+            for _ in range(1000):
+                fn()
+            best.append((time.perf_counter() - t0) / 1000 * 1e6)
+            torch.cuda.synchronize()
+        host[name] = min(best)
+    res["host_us_per_call"] = host
+    assert b64.decode(text, out=dec)[1] is None
     print(json.dumps(res), flush=True)
 
 
