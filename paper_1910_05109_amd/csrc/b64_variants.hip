@@ -1320,6 +1320,36 @@ __global__ __launch_bounds__(kWsBlock) void k_ws_predict(const uint8_t *__restri
     for (int64_t t = (int64_t)blockIdx.x * kWsBlock + tid; t < ntiles; t += (int64_t)gridDim.x * kWsBlock)
         prefix[t] = lined_before(t * TS, L, P);
     if (blockIdx.x != 0) return;
+    const int64_t total = lined_before(lb, L, P) + s_cnt;
+    // the final quantum's first character, where the layout puts it
+    const int64_t ql = (flags & kFlagNoPad) ? total / 4 : (total >= 4 ? total / 4 - 1 : 0);
+    const int64_t jq = 4 * ql;
+    const int64_t at = (jq / L) * P + jq % L;
+    // The line decode checks the layout up to the separator before the final
+    // quantum, and this kernel counted the last tile, so the prefix sums are
+    // exact when the layout also holds from that separator to the last tile.
+    // That stretch is empty unless the last tile is only a few bytes long
+    // (the final quantum then starts in the tile before it); up to 64 bytes of
+    // it are checked here, one per lane of wave 0, with their loads issued
+    // beside the line-end samples': whitespace exactly at separator
+    // positions.  Neither the line decode nor the last tile's scan looks at
+    // these bytes for '=' or invalid characters (the final quantum's '=' may
+    // lie here), so they are recorded here as k_ws_count records them (true
+    // positions, so also right when the samples below send the decode to the
+    // counted path).
+    const int64_t from = at - sep;
+    bool lines = L % 4 == 0 && L >= 16 && lb - from <= 64;
+    const bool gap = lines && from < lb;
+    bool off = false;
+    if (gap && tid < 64) {
+        const int64_t x = from + tid;
+        if (x >= 0 && x < lb) {
+            const uint32_t code = m[src[x]];
+            off = is_sig(code) != (x % P < L);
+            if (code == kBadCode) atomic_min_i64(first_bad, x);
+            else if (code == kPadCode) atomic_min_i64(first_pad, x);
+        }
+    }
     {   // line k's separator, and the characters on either side of it
         const int64_t k = (n / P) * tid / kWsBlock;
         const int64_t q = k * P + L;
@@ -1332,33 +1362,7 @@ __global__ __launch_bounds__(kWsBlock) void k_ws_predict(const uint8_t *__restri
     }
     __syncthreads();
     if (!s_ok || tid >= 64) return;              // wave 0 decides the path
-    const int64_t total = lined_before(lb, L, P) + s_cnt;
-    // the final quantum's first character, where the layout puts it
-    const int64_t ql = (flags & kFlagNoPad) ? total / 4 : (total >= 4 ? total / 4 - 1 : 0);
-    const int64_t jq = 4 * ql;
-    const int64_t at = (jq / L) * P + jq % L;
-    // The line decode checks the layout up to the separator before the final
-    // quantum, and this kernel counted the last tile, so the prefix sums are
-    // exact when the layout also holds from that separator to the last tile.
-    // That stretch is empty unless the last tile is only a few bytes long
-    // (the final quantum then starts in the tile before it); up to 64 bytes of
-    // it are checked here, one per lane: whitespace exactly at separator
-    // positions.  Neither the line decode nor the last tile's scan looks at
-    // these bytes for '=' or invalid characters (the final quantum's '=' may
-    // lie here), so they are recorded here as k_ws_count records them.
-    const int64_t from = at - sep;
-    bool lines = L % 4 == 0 && L >= 16 && lb - from <= 64;
-    if (lines && from < lb) {
-        const int64_t x = from + tid;
-        bool off = false;
-        if (x >= 0 && x < lb) {
-            const uint32_t code = m[src[x]];
-            off = is_sig(code) != (x % P < L);
-            if (code == kBadCode) atomic_min_i64(first_bad, x);
-            else if (code == kPadCode) atomic_min_i64(first_pad, x);
-        }
-        if (__ballot(off)) lines = false;
-    }
+    if (gap && __ballot(off)) lines = false;
     if (tid == 0) {
         prefix[ntiles] = total;
         *mode = lines ? (kModeLines | sep << 2 | L << 4) : kModeChecked;
